@@ -1,0 +1,485 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every expected value is a
+closed form, an identity of Section 2, a published test vector, a textbook
+special case that reduces to a LAPACK/ARPACK routine, or brute force.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.csgraph as csgraph
+import scipy.sparse.linalg as sla
+
+import oracle
+from paper_1311_1695_amd import graphgen as gg
+from tests._lapcheck import check_against_reference, residuals, sin_largest_angle
+
+
+# ---------------------------------------------------------------------------
+# Closed-form Laplacian spectra (standard spectral graph theory, e.g.
+# Brouwer & Haemers, "Spectra of Graphs", Section 1.4)
+# ---------------------------------------------------------------------------
+
+def path_spectrum(n):
+    return np.sort(2 - 2 * np.cos(np.pi * np.arange(n) / n))
+
+
+def cycle_spectrum(n):
+    return np.sort(2 - 2 * np.cos(2 * np.pi * np.arange(n) / n))
+
+
+def star_spectrum(n):
+    return np.array([0.0] + [1.0] * (n - 2) + [float(n)])
+
+
+def complete_spectrum(n):
+    return np.array([0.0] + [float(n)] * (n - 1))
+
+
+def kab_spectrum(a, b):
+    return np.sort(np.array([0.0] + [float(a)] * (b - 1) + [float(b)] * (a - 1) + [float(a + b)]))
+
+
+def hypercube_spectrum(d):
+    return np.sort(np.concatenate([[2.0 * i] * math.comb(d, i) for i in range(d + 1)]))
+
+
+def grid_spectrum(a, b):
+    pa, pb = path_spectrum(a), path_spectrum(b)
+    return np.sort((pa[:, None] + pb[None, :]).ravel())
+
+
+CLOSED = [
+    (gg.path_graph(17), path_spectrum(17)),
+    (gg.cycle_graph(12), cycle_spectrum(12)),
+    (gg.star_graph(9), star_spectrum(9)),
+    (gg.complete_graph(7), complete_spectrum(7)),
+    (gg.complete_bipartite_graph(3, 5), kab_spectrum(3, 5)),
+    (gg.hypercube_graph(4), hypercube_spectrum(4)),
+    (gg.grid_graph(4, 6), grid_spectrum(4, 6)),
+]
+
+
+# ---------------------------------------------------------------------------
+# Laplacian product and eq. (1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L", [g for g, _ in CLOSED] + [gg.workload("pa5k", 3)], ids=lambda g: g.name)
+def test_spmv_annihilates_constant(L):
+    # Section 2: G e = 0 because D e = A e
+    y = oracle.spmv(L, np.ones(L.n))
+    assert np.all(y == 0.0)
+
+
+def test_spmv_integer_vectors_exact():
+    # integer data: every partial sum is exact in FP64, so the result must
+    # equal numpy's dense product bit for bit whatever the order
+    L = gg.workload("pa5k", 5)
+    rng = np.random.default_rng(0)
+    x = rng.integers(-1000, 1000, size=L.n).astype(np.float64)
+    assert np.array_equal(oracle.spmv(L, x), L.to_scipy() @ x)
+    Lw = gg.workload("cl30k_w", 5)
+    x = rng.integers(-1000, 1000, size=Lw.n).astype(np.float64)
+    assert np.array_equal(oracle.spmv(Lw, x), Lw.to_scipy() @ x)
+
+
+def test_quadform_hand_examples():
+    # eq. (1) on a path 0-1-2 with x = (1, 2, 4): (1-2)^2 + (2-4)^2 = 5
+    assert oracle.quadform(gg.path_graph(3), np.array([1.0, 2.0, 4.0])) == 5.0
+    # weighted triangle, weights 1, 2, 3 on edges 01, 12, 02; x = (0, 1, 3):
+    # 1*(0-1)^2 + 2*(1-3)^2 + 3*(0-3)^2 = 1 + 8 + 27 = 36
+    L = gg.laplacian_from_edges(3, [0, 1, 0], [1, 2, 2], [1.0, 2.0, 3.0])
+    assert oracle.quadform(L, np.array([0.0, 1.0, 3.0])) == 36.0
+    # cut size interpretation (Section 2): x_i = +-1/2 on a 2-partition counts
+    # the weight of the cut edges; the 4-cycle split {0,1}|{2,3} cuts 2 edges
+    C = gg.cycle_graph(4)
+    assert oracle.quadform(C, np.array([0.5, 0.5, -0.5, -0.5])) == 2.0
+
+
+def test_quadform_equals_xGx_and_is_nonnegative():
+    L = gg.workload("cl30k_w", 9)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        x = rng.standard_normal(L.n)
+        q = oracle.quadform(L, x)
+        assert q >= 0.0
+        assert abs(q - x @ (L.to_scipy() @ x)) <= 1e-11 * abs(q)
+
+
+def test_components_count_and_partition():
+    G = gg.disjoint_union(gg.path_graph(5), gg.cycle_graph(6), gg.star_graph(4), gg.complete_graph(3))
+    nc, lab = oracle.components(G)
+    assert nc == 4
+    nref, labref = csgraph.connected_components(G.to_scipy(), directed=False)
+    assert nref == nc
+    # same partition (labels may be permuted)
+    pairs = set(zip(lab.tolist(), labref.tolist()))
+    assert len(pairs) == nc
+    # numbering by smallest vertex
+    assert lab[0] == 0 and lab[5] == 1 and lab[11] == 2 and lab[15] == 3
+
+
+# ---------------------------------------------------------------------------
+# Dense eigensolver (H in Algorithm 2 step 5; brute force for tiny graphs)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,spec", CLOSED, ids=[g.name for g, _ in CLOSED])
+def test_dense_eig_closed_forms(L, spec):
+    w, V = oracle.dense_eig(L.dense())
+    assert np.allclose(w, spec, atol=1e-12 * max(1.0, spec.max()))
+    # trace and Frobenius identities: sum lambda = sum d_i, sum lambda^2 = ||G||_F^2
+    G = L.dense()
+    assert abs(w.sum() - np.trace(G)) <= 1e-11 * np.trace(G)
+    assert abs((w ** 2).sum() - (G ** 2).sum()) <= 1e-11 * (G ** 2).sum()
+    assert np.allclose(V.T @ V, np.eye(L.n), atol=1e-13)
+    assert np.linalg.norm(G @ V - V * w) <= 1e-12 * np.linalg.norm(G)
+
+
+def test_dense_eig_path_eigenvectors():
+    # simple spectrum: eigenvector j of the path is cos(pi j (i + 1/2) / n)
+    n = 13
+    w, V = oracle.dense_eig(gg.path_graph(n).dense())
+    i = np.arange(n)
+    for j in range(n):
+        x = np.cos(np.pi * j * (i + 0.5) / n)
+        x /= np.linalg.norm(x)
+        assert abs(abs(x @ V[:, j]) - 1.0) <= 1e-12
+
+
+def test_dense_eig_vs_lapack_random_symmetric():
+    rng = np.random.default_rng(7)
+    for n in (1, 2, 5, 31, 64):
+        B = rng.standard_normal((n, n))
+        A = B + B.T
+        A[:2, :2] += 5.0  # asymmetry in the diagonal scale
+        w, V = oracle.dense_eig(A)
+        wl = np.linalg.eigvalsh(A)
+        assert np.allclose(w, wl, atol=1e-12 * np.abs(wl).max())
+        assert np.allclose(V.T @ V, np.eye(n), atol=1e-13)
+        assert np.linalg.norm(A @ V - V * w) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_dense_eig_repeated_eigenvalues():
+    # exact multiplicities: the complete graph K_n has eigenvalue n, n-1 times
+    w, V = oracle.dense_eig(gg.complete_graph(10).dense())
+    assert np.allclose(w[1:], 10.0, atol=1e-12)
+    assert abs(w[0]) <= 1e-12
+    e = np.ones(10) / math.sqrt(10)
+    assert abs(abs(V[:, 0] @ e) - 1.0) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Modified Gram-Schmidt (Algorithm 2 step 2)
+# ---------------------------------------------------------------------------
+
+def test_mgs_projects_out_and_pythagoras():
+    rng = np.random.default_rng(3)
+    n, q = 400, 7
+    Q, _ = np.linalg.qr(rng.standard_normal((n, q)))
+    v = rng.standard_normal(n)
+    w, nrm = oracle.mgs(Q, v)
+    assert np.abs(Q.T @ w).max() <= 1e-14 * np.linalg.norm(v)
+    assert abs(nrm - np.linalg.norm(w)) <= 1e-14 * nrm
+    assert abs(nrm ** 2 - (v @ v - np.sum((Q.T @ v) ** 2))) <= 1e-12 * (v @ v)
+    assert np.allclose(w, v - Q @ (Q.T @ v), atol=1e-13)
+
+
+def test_mgs_nearly_dependent_vector_second_pass():
+    rng = np.random.default_rng(4)
+    n, q = 300, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((n, q)))
+    v = Q @ rng.standard_normal(q) + 1e-9 * rng.standard_normal(n)
+    w, nrm = oracle.mgs(Q, v)
+    # one classical pass would leave O(eps * ||v||) = 1e-16 relative to 1e-9
+    assert np.abs(Q.T @ w).max() <= 1e-14 * nrm
+
+
+# ---------------------------------------------------------------------------
+# IC(0), Section 4
+# ---------------------------------------------------------------------------
+
+def test_ic0_tree_in_natural_order_is_exact_cholesky():
+    # a path in natural order has no fill, so IC(0) of the SPD matrix
+    # G + I is its exact Cholesky factor: applying it solves the system
+    n = 50
+    L = gg.path_graph(n)
+    A = L.dense() + np.eye(n)
+    M = gg.LaplacianCSR(n, L.rowptr, L.col, L.val + (L.col == np.repeat(np.arange(n), np.diff(L.rowptr))))
+    K = oracle.IC0(M)
+    assert K.nfloor == 0
+    r = np.random.default_rng(0).standard_normal(n)
+    assert np.allclose(K.apply(r), np.linalg.solve(A, r), rtol=1e-12, atol=1e-12)
+
+
+def test_ic0_matches_matrix_on_its_pattern():
+    # the defining property of IC(0): (K K')_ij = G_ij on the sparsity
+    # pattern of G (lower triangle), fill outside the pattern dropped
+    L = gg.workload("pa5k", 11)
+    n = 600
+    sub = L.to_scipy()[:n, :n].tocsr()
+    rows = np.repeat(np.arange(n), np.diff(sub.indptr))
+    diag_fix = np.asarray(-sub.sum(axis=1)).ravel()  # make rows of the sub-block diagonally dominant
+    A = sub.toarray() + np.diag(np.abs(diag_fix) + 1.0)
+    M = gg.LaplacianCSR(n, sub.indptr.astype(np.int32), sub.indices.astype(np.int32),
+                        A[rows, sub.indices])
+    K = oracle.IC0(M)
+    # recover K densely by applying K K' to unit vectors: (KK')^-1 e_j
+    inv = np.stack([K.apply(np.eye(n)[:, j]) for j in range(n)], axis=1)
+    KKt = np.linalg.inv(inv)
+    mask = (A != 0)
+    assert np.allclose(KKt[mask], A[mask], rtol=1e-9, atol=1e-9)
+
+
+def test_ic0_singular_laplacian_is_finite():
+    L = gg.workload("cl30k", 13)
+    K = oracle.IC0(L)
+    z = K.apply(np.random.default_rng(2).standard_normal(L.n))
+    assert np.all(np.isfinite(z))
+
+
+# ---------------------------------------------------------------------------
+# PCG on the projected correction equation (Algorithm 2 step 8)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [oracle.PREC_NONE, oracle.PREC_JACOBI, oracle.PREC_IC0])
+def test_pcg_without_projection_solves_spd_system(prec):
+    # Q empty and theta below the spectrum: (G - theta I) is SPD and PCG run
+    # to convergence must give numpy's dense solution
+    L = gg.workload("pa5k", 17)
+    n = 500
+    sub = L.to_scipy()[:n, :n].tocsr()
+    A = sub.toarray()
+    A = A - np.diag(A.sum(axis=1))  # back to a Laplacian of the induced subgraph
+    from paper_1311_1695_amd.graphgen import LaplacianCSR
+    import scipy.sparse as sp
+    As = sp.csr_matrix(A)
+    As.sort_indices()
+    M = LaplacianCSR(n, As.indptr.astype(np.int32), As.indices.astype(np.int32), As.data)
+    theta = -0.5
+    r = np.random.default_rng(5).standard_normal(n)
+    t, mvp, br = oracle.pcg_correction(M, theta, np.zeros((n, 0)), r, precond=prec, itmax=2000, rtol=1e-13)
+    exact = np.linalg.solve(A - theta * np.eye(n), -r)
+    assert not br
+    assert np.allclose(t, exact, rtol=1e-9, atol=1e-9 * np.abs(exact).max())
+
+
+@pytest.mark.parametrize("prec", [oracle.PREC_JACOBI, oracle.PREC_IC0])
+def test_pcg_projected_system_solution(prec):
+    # with Q = [e/sqrt(n), x2] and theta below lambda_3 the projected operator
+    # is SPD on Q-perp; the exact solution t = B y with B an orthonormal basis
+    # of Q-perp and (B'(G - theta I)B) y = -B'r comes from LAPACK
+    L = gg.workload("pa5k", 19)
+    G = L.dense()[:400, :400]
+    G = G - np.diag(G.sum(axis=1))
+    import scipy.sparse as sp
+    As = sp.csr_matrix(G); As.sort_indices()
+    M = gg.LaplacianCSR(400, As.indptr.astype(np.int32), As.indices.astype(np.int32), As.data)
+    nc, lab = oracle.components(M)
+    w, V = np.linalg.eigh(G)
+    q = nc + 1
+    Q = V[:, :q]
+    theta = 0.5 * w[q]
+    r = np.random.default_rng(6).standard_normal(400)
+    r -= Q @ (Q.T @ r)
+    t, mvp, br = oracle.pcg_correction(M, theta, Q, r, precond=prec, itmax=3000, rtol=1e-12)
+    B = V[:, q:]
+    y = np.linalg.solve(B.T @ (G - theta * np.eye(400)) @ B, -B.T @ r)
+    assert not br
+    assert np.abs(Q.T @ t).max() <= 1e-10 * np.linalg.norm(t)
+    assert np.allclose(t, B @ y, rtol=1e-8, atol=1e-8 * np.abs(B @ y).max())
+
+
+def test_pcg_stops_at_itmax_and_tolerance():
+    L = gg.workload("cl30k", 21)
+    nc, lab = oracle.components(L)
+    Q = np.ones((L.n, 1)) / math.sqrt(L.n)
+    r = np.random.default_rng(8).standard_normal(L.n)
+    r -= Q @ (Q.T @ r)
+    t, mvp, br = oracle.pcg_correction(L, 0.01, Q, r, precond=oracle.PREC_JACOBI, itmax=20, rtol=1e-2)
+    assert 1 <= mvp <= 20
+    # the returned correction is orthogonal to Q and reduces the projected residual
+    Gs = L.to_scipy()
+    res = -r - (Gs @ t - 0.01 * t)
+    res -= Q @ (Q.T @ res)
+    assert np.abs(Q.T @ t).max() <= 1e-12 * np.linalg.norm(t)
+    if mvp < 20 and not br:
+        assert np.linalg.norm(res) <= 1e-2 * np.linalg.norm(r) * (1 + 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Start vectors: SplitMix64 published outputs for seed 0
+# ---------------------------------------------------------------------------
+
+def test_start_values_follow_splitmix64():
+    published = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for i, z in enumerate(published):
+        expect = (z >> 11) * 2.0 ** -53 * 2.0 - 1.0
+        assert oracle.start_value(0, i) == expect
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 end to end
+# ---------------------------------------------------------------------------
+
+def _check_jd(L, k, ref_w, ref_V=None, tol=1e-10, **kw):
+    res = oracle.jd(L, k, tol, **kw)
+    assert res.status == 0 and res.nconv == k
+    Gs = L.to_scipy()
+    rr = residuals(Gs, res.evals, res.evecs)
+    # the certificate: ||G x - theta x|| <= tol * min(theta, 1) (zero pairs: <= tol)
+    assert np.all(rr <= tol * np.maximum(np.minimum(res.evals, 1.0), 1.0 * (res.evals == 0)) * (1 + 1e-6) + 1e-14)
+    assert np.allclose(res.evecs.T @ res.evecs, np.eye(k), atol=1e-10)
+    assert np.all(np.diff(res.evals) >= -1e-14)
+    if ref_V is not None:
+        check_against_reference(res.evals, res.evecs, ref_w, ref_V, val_rtol=1e-8, angle_tol=1e-6)
+    else:
+        assert np.allclose(res.evals, ref_w[:k], rtol=1e-8, atol=1e-12)
+    return res
+
+
+@pytest.mark.parametrize("prec", [oracle.PREC_IC0, oracle.PREC_JACOBI])
+def test_jd_path_closed_form(prec):
+    n = 40
+    L = gg.path_graph(n)
+    res = _check_jd(L, 6, path_spectrum(n), precond=prec)
+    i = np.arange(n)
+    for j in range(6):
+        x = np.cos(np.pi * j * (i + 0.5) / n)
+        assert sin_largest_angle(res.evecs[:, [j]], x[:, None]) <= 1e-6
+
+
+def test_jd_cycle_double_eigenvalues():
+    n = 30
+    L = gg.cycle_graph(n)
+    i = np.arange(n)
+    # eigenspace of 2-2cos(2 pi j/n) is spanned by cos and sin of 2 pi j i/n
+    basis = [np.ones(n)]
+    for j in (1, 2):
+        basis += [np.cos(2 * np.pi * j * i / n), np.sin(2 * np.pi * j * i / n)]
+    ref_V = np.stack(basis, axis=1)
+    ref_V /= np.linalg.norm(ref_V, axis=0)
+    ref_w = cycle_spectrum(n)[:5]
+    # compare the full j=1 and j=2 clusters (k = 5 covers both pairs)
+    res = oracle.jd(L, 5, 1e-10, precond=oracle.PREC_IC0)
+    assert res.nconv == 5
+    assert np.allclose(res.evals, ref_w, rtol=1e-8)
+    assert sin_largest_angle(res.evecs[:, 1:3], ref_V[:, 1:3]) <= 1e-6
+    assert sin_largest_angle(res.evecs[:, 3:5], ref_V[:, 3:5]) <= 1e-6
+
+
+def test_jd_star_and_complete_multiplicities():
+    L = gg.star_graph(20)
+    res = oracle.jd(L, 2, 1e-10)
+    assert np.allclose(res.evals, [0.0, 1.0], atol=1e-10)
+    L = gg.complete_graph(12)
+    res = oracle.jd(L, 3, 1e-10)
+    assert np.allclose(res.evals, [0.0, 12.0, 12.0], rtol=1e-10, atol=1e-10)
+
+
+def test_jd_exact_invariant_subspace_pairs_stay_certified():
+    # single-vector JD builds its basis from one start vector; on the star the
+    # basis can close up into an exactly invariant subspace, and then a member
+    # of the 18-fold eigenvalue 1 is skipped and the next pair locked is 20.
+    # What the method still guarantees: every returned pair is a certified
+    # eigenpair whose value lies in the true spectrum.
+    L = gg.star_graph(20)
+    res = oracle.jd(L, 3, 1e-10)
+    spec = star_spectrum(20)
+    assert all(np.min(np.abs(spec - lam)) <= 1e-9 for lam in res.evals)
+    rr = residuals(L.to_scipy(), res.evals, res.evecs)
+    assert np.all(rr <= 1e-10 * np.maximum(np.minimum(res.evals, 1.0), 1.0))
+
+
+def test_jd_disjoint_union_zero_multiplicity():
+    G = gg.disjoint_union(gg.path_graph(10), gg.cycle_graph(8), gg.star_graph(5))
+    nc, lab = oracle.components(G)
+    w = np.sort(np.concatenate([path_spectrum(10), cycle_spectrum(8), star_spectrum(5)]))
+    res = oracle.jd(G, 5, 1e-10)
+    assert res.ncomp == 3 and res.nconv == 5
+    assert np.allclose(res.evals, w[:5], rtol=1e-8, atol=1e-12)
+    # zero eigenvectors are the normalized component indicators
+    for c in range(3):
+        ind = (lab == c).astype(float)
+        ind /= np.linalg.norm(ind)
+        assert abs(res.evecs[:, c] @ ind - 1.0) <= 1e-14
+    # more components than requested pairs
+    res = oracle.jd(G, 2, 1e-10)
+    assert res.nconv == 2 and np.all(res.evals == 0.0)
+
+
+def test_jd_pendant_structures():
+    # hub 0 with two leaves (1, 2) and three pendant 2-paths (0-3-4, 0-5-6,
+    # 0-7-8): the leaf difference vector gives eigenvalue 1 exactly, the
+    # differences of identical pendant paths give (3 - sqrt 5)/2 twice
+    L = gg.laplacian_from_edges(9, [0, 0, 0, 3, 0, 5, 0, 7], [1, 2, 3, 4, 5, 6, 7, 8], None)
+    w, V = np.linalg.eigh(L.dense())
+    assert np.sum(np.abs(w - 1.0) < 1e-12) >= 1
+    assert np.sum(np.abs(w - (3 - math.sqrt(5)) / 2) < 1e-12) == 2
+    res = oracle.jd(L, 3, 1e-10)
+    assert res.ncomp == 1
+    check_against_reference(res.evals, res.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
+
+
+@functools.lru_cache(maxsize=None)
+def _pa5k_dense():
+    L = gg.workload("pa5k", 1001)
+    w, V = np.linalg.eigh(L.dense())
+    return L, w[:40].copy(), V[:, :40].copy()
+
+
+@pytest.mark.parametrize("prec", [oracle.PREC_IC0, oracle.PREC_JACOBI])
+def test_jd_pa5k_vs_dense_brute_force(prec):
+    L, w, V = _pa5k_dense()
+    _check_jd(L, 10, w, V, tol=1e-8, precond=prec)
+
+
+def test_jd_chung_lu_vs_dense_brute_force():
+    u, v = gg.chung_lu_edges(4000, 2.2, 4.0, 77)
+    n, u, v, _ = gg.largest_component(4000, u, v)
+    L = gg.laplacian_from_edges(n, u, v)
+    w, V = np.linalg.eigh(L.dense())
+    _check_jd(L, 12, w, V, tol=1e-9)
+
+
+def test_jd_weighted_vs_dense_brute_force():
+    u, v = gg.chung_lu_edges(3000, 2.2, 4.0, 78)
+    wts = gg.integer_weights(u.shape[0], 5)
+    n, u, v, wts = gg.largest_component(3000, u, v, wts)
+    L = gg.laplacian_from_edges(n, u, v, wts)
+    w, V = np.linalg.eigh(L.dense())
+    _check_jd(L, 8, w, V, tol=1e-9)
+
+
+def test_jd_chung_lu_vs_arpack_shift_invert():
+    u, v = gg.chung_lu_edges(8000, 2.2, 4.0, 77)
+    n, u, v, _ = gg.largest_component(8000, u, v)
+    L = gg.laplacian_from_edges(n, u, v)
+    w, V = sla.eigsh(L.to_scipy().tocsc(), k=14, sigma=-1e-2, which="LM", tol=1e-13)
+    o = np.argsort(w)
+    _check_jd(L, 10, w[o], V[:, o], tol=1e-9)
+
+
+def test_jd_paper_criterion():
+    # Section 4 exit test ||Au - theta u|| / theta < delta at delta = 1e-6
+    L = gg.workload("pa5k", 23)
+    res = oracle.jd(L, 6, 1e-6, criterion=1)
+    rr = residuals(L.to_scipy(), res.evals, res.evecs)
+    assert np.all(rr[1:] / res.evals[1:] < 1e-6)
+
+
+def test_jd_kmax_exhaustion_returns_certified_prefix():
+    L = gg.workload("pa5k", 29)
+    res = oracle.jd(L, 10, 1e-10, kmax=40)
+    assert res.status == 1
+    assert res.nconv < 10
+    rr = residuals(L.to_scipy(), res.evals, res.evecs)
+    assert np.all(rr[1:] <= 1e-10 * np.minimum(res.evals[1:], 1.0) * (1 + 1e-6))
+
+
+def test_jd_seed_independence_of_the_answer():
+    L = gg.workload("pa5k", 31)
+    a = oracle.jd(L, 6, 1e-10, seed=1)
+    b = oracle.jd(L, 6, 1e-10, seed=2)
+    assert np.allclose(a.evals, b.evals, rtol=1e-8)
