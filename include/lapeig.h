@@ -1,0 +1,181 @@
+/*
+ * lapeig.h -- C ABI of the MI355X (gfx950) Jacobi-Davidson solver for the
+ * smallest eigenpairs of a graph Laplacian G = D - A.
+ *
+ * The problem (Section 2 of Bergamaschi, Bozzo & Franceschet, "Computing the
+ * smallest eigenpairs of the graph Laplacian"): G is the weighted Laplacian
+ * of a simple undirected graph with positive edge weights, D the diagonal of
+ * generalized degrees.  G is symmetric positive semidefinite, G e = 0, and
+ * the multiplicity of the eigenvalue 0 is the number of connected
+ * components.  The method (Section 3.2, Algorithm 2) is Jacobi-Davidson:
+ * Rayleigh-Ritz on a search space V, Newton-type corrections from the
+ * projected correction equation solved inexactly by PCG, deflation against
+ * the converged vectors, and restarts between m_min and m_max columns.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns lap_status: 0 (LAP_OK) or a negative code.
+ *     lap_last_error() returns a thread-local message for the last failure.
+ *   - Input validation happens on the host before any HIP call, so bad
+ *     arguments are reported without touching the GPU.
+ *   - "device" pointers are HIP device allocations on the plan's device;
+ *     "host" pointers are ordinary host memory.  The caller owns every
+ *     buffer it passes; no pointer is retained after the call returns,
+ *     except that a plan keeps its own device copies of the matrix.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *   - Block vectors passed to lap_spmv are n x b ROW-major ("interleaved":
+ *     element (i, c) at X[i*b + c]); the orthogonalization and PCG entry
+ *     points take n x b COLUMN-major blocks (element (i, c) at X[i + c*n]).
+ */
+#ifndef LAPEIG_H
+#define LAPEIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAP_OK = 0,
+    LAP_EINVAL = -1,          /* bad argument (size, pointer, option) */
+    LAP_ENOTLAPLACIAN = -2,   /* the CSR is not the Laplacian of a simple weighted graph */
+    LAP_ENOMEM = -3,          /* device or host allocation failed */
+    LAP_EDEVICE = -4,         /* a HIP runtime call failed */
+    LAP_ENOCONV = -5,         /* eigensolver hit its outer-iteration limit */
+    LAP_EUNSUPPORTED = -6     /* valid request this build does not support */
+} lap_status;
+
+typedef enum { LAP_F32 = 0, LAP_F64 = 1 } lap_dtype;
+
+/* Arithmetic of lap_eigs.  FP64: every step in double precision.  MIXED:
+ * the Laplacian products inside PCG and the whole inner PCG run in single
+ * precision with single-precision accumulation; the outer products W = G V,
+ * orthogonalization, Rayleigh-Ritz, Rayleigh quotients and the certifying
+ * residual stay in double precision, so the answer is certified in FP64. */
+typedef enum { LAP_PREC_FP64 = 0, LAP_PREC_MIXED = 1 } lap_precision;
+
+/* The Laplacian G itself (diagonal included), host memory, CSR with int32
+ * indices.  Requirements, checked by lap_plan_create: n >= 1; rowptr[0] = 0,
+ * rowptr nondecreasing, rowptr[n] = nnz; columns strictly increasing in each
+ * row and in [0, n); values finite; off-diagonal values < 0 (the negated
+ * edge weights); G symmetric in pattern and value; each diagonal value
+ * equal to minus the sum of its row's off-diagonal values (exactly for
+ * integer data, else to 1e-12 relative). */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *rowptr;   /* n + 1 */
+    const int32_t *col;      /* nnz */
+    const double *val;       /* nnz */
+} lap_csr;
+
+typedef struct lap_plan lap_plan;
+
+/* Solver options.  lap_eigs_default_opts fills the paper's parameters
+ * (Section 4): m_min = 5, m_max = 10, ITMAX = 20, delta_PCG = 1e-2. */
+typedef struct {
+    int m_min;           /* basis size kept at a restart */
+    int m_max;           /* basis size that triggers a restart */
+    int itmax;           /* PCG iterations per correction equation */
+    double rtol_pcg;     /* PCG stops at ||res|| <= rtol_pcg * ||r|| */
+    int kmax;            /* outer-iteration limit; <= 0 means 1000 * k */
+    int precision;       /* lap_precision */
+    int block;           /* corrections per outer iteration: 1 is Algorithm 2 */
+    uint64_t seed;       /* SplitMix64 stream for start vectors */
+    const double *init;  /* optional start block, host, n x init_cols column-major,
+                            caller's vertex order; NULL for a seeded random start */
+    int init_cols;
+} lap_eigs_opts;
+
+typedef struct {
+    int nconv;           /* certified pairs returned (the first nconv entries) */
+    int ncomp;           /* connected components = multiplicity of eigenvalue 0 */
+    int outer;           /* outer iterations (correction equations solved) */
+    int inner;           /* PCG iterations, summed over the columns */
+    long long mvp;       /* Laplacian-vector products; a b-column product counts b */
+    double seconds;      /* wall time of the call */
+} lap_eigs_info;
+
+void lap_eigs_default_opts(lap_eigs_opts *opts);
+
+/* Validate G on the host, then copy it to the current HIP device in the
+ * solver's layout (vertices renumbered by decreasing degree; rows of degree
+ * above a threshold stored as CSR, the rest as 64-row column-major slices).
+ * stream: hipStream_t used by the plan's own work (NULL = default stream).
+ * Errors: LAP_EINVAL (null pointers, n < 1), LAP_ENOTLAPLACIAN (first bad
+ * row named in lap_last_error), LAP_ENOMEM / LAP_EDEVICE. */
+lap_status lap_plan_create(const lap_csr *L, void *stream, lap_plan **out);
+void lap_plan_destroy(lap_plan *plan);
+
+/* Size of the plan's matrix and its vertex renumbering: perm[i] is the
+ * solver's internal index of the caller's vertex i (host array of n). */
+int32_t lap_plan_n(const lap_plan *plan);
+lap_status lap_plan_perm(const lap_plan *plan, int32_t *perm);
+
+/* The k smallest eigenpairs of G (Algorithm 2 and its deflation for
+ * lambda_2, lambda_3, ..., eq. JDsismorethanone).  k counts the zero
+ * eigenvalues (one per connected component, whose eigenvectors are the
+ * normalized component indicators); 1 <= k < n, tol > 0.
+ * A pair is returned only after an FP64 certificate with a fresh product:
+ *   ||G u - theta u|| <= tol * min(theta, 1),  ||u|| = 1,
+ * theta the Rayleigh quotient of eq. (1).
+ * evals: host, k, ascending.  evecs: n x k column-major in the caller's
+ * vertex order, host (evecs_on_device = 0) or device (1), or NULL.
+ * res: host, k residual norms, or NULL.  info: or NULL.
+ * Eigenvector signs are fixed so that each vector's entry of largest
+ * magnitude (lowest index on ties) is positive.  Returns LAP_ENOCONV when
+ * kmax is reached; info->nconv pairs are then valid.  Synchronizes the
+ * plan's stream before returning. */
+lap_status lap_eigs(lap_plan *plan, int k, double tol, const lap_eigs_opts *opts,
+                    double *evals, double *evecs, int evecs_on_device, double *res,
+                    lap_eigs_info *info);
+
+/* One-shot convenience: plan, solve, destroy. */
+lap_status lap_eigs_csr(const lap_csr *L, int k, double tol, const lap_eigs_opts *opts,
+                        double *evals, double *evecs, double *res, lap_eigs_info *info);
+
+/* Y = G X - X diag(shift): the matrix-vector product (MVP) of Section 3
+ * on b columns.  X, Y: device, n x b row-major of dtype (float or double);
+ * shift: host array of b doubles or NULL (no shift).  flags: 0 when X and Y
+ * are in the caller's vertex order, LAP_ORDER_PLAN when they are already in
+ * the plan's internal order (no renumbering passes).  Asynchronous on
+ * stream.  Supported b: 1..64. */
+#define LAP_ORDER_PLAN 1
+lap_status lap_spmv(lap_plan *plan, lap_dtype dtype, int b, const void *X, void *Y,
+                    const double *shift, int flags, void *stream);
+
+/* Block orthogonalization (Algorithm 2 step 2, double precision):
+ * W <- an orthonormal basis of (I - Q Q') W, by classical Gram-Schmidt
+ * applied twice against Q, then twice within W column by column; columns
+ * whose norm falls below 1e-12 of their norm before the pass are replaced
+ * by zero columns and not counted.  Q: device n x q column-major with
+ * orthonormal columns (q >= 0); W: device n x b column-major, in/out.
+ * rank_out: host int, the number of nonzero columns kept, compacted to the
+ * front of W.  dtype must be LAP_F64.  Synchronizes stream. */
+lap_status lap_orth(lap_dtype dtype, int n, int q, const double *Q, int b, double *W,
+                    int *rank_out, void *stream);
+
+/* PCG on the projected correction equations (Algorithm 2 step 8):
+ *   (I - QQ')(G - theta_c I)(I - QQ') t_c = -r_c,  t_c orthogonal to Q,
+ * for each column c < b, with the preconditioner M = (I-QQ')P(I-QQ') and
+ * P = D^{-1} (Jacobi).  t_0 = 0; column c stops when its residual norm is
+ * <= rtol * ||r_c||, after itmax iterations, or when p'(G - theta_c I)p
+ * <= 0 (then the current t_c, or M(-r_c) if no step was taken).
+ * theta: host, b doubles.  Q: device n x q column-major orthonormal, in the
+ * caller's vertex order unless flags has LAP_ORDER_PLAN (same for R, T).
+ * R: device n x b column-major (r_c); T: device n x b column-major output.
+ * dtype: arithmetic of the iteration (LAP_F32 or LAP_F64; inputs and
+ * outputs stay double).  iters_out: host, b ints (PCG iterations per
+ * column) or NULL.  Synchronizes stream.  Supported q <= 62, b <= 32. */
+lap_status lap_pcg(lap_plan *plan, lap_dtype dtype, int b, const double *theta,
+                   const double *Q, int q, const double *R, double *T, int itmax,
+                   double rtol, int *iters_out, int flags, void *stream);
+
+const char *lap_status_string(lap_status s);
+const char *lap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAPEIG_H */

@@ -1,0 +1,285 @@
+"""Python binding of liblapeig.so, the gfx950 Jacobi-Davidson solver for the
+smallest eigenpairs of a graph Laplacian (Bergamaschi, Bozzo & Franceschet,
+"Computing the smallest eigenpairs of the graph Laplacian", Algorithm 2).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI of ``include/lapeig.h``.  PyTorch is used for device
+memory and streams.  Importing this module never falls back to anything: if
+the compiled library is missing, every entry point raises.
+
+Entry points mirror the C ABI names:
+  lap_plan_create(L, stream=None) -> Plan
+  lap_eigs(plan, k, tol, **opts)  -> EigResult
+  lap_spmv(plan, X, Y, shift=None, plan_order=False, stream=None)
+  lap_orth(Q, W, stream=None)     -> rank
+  lap_pcg(plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_order=False) -> iters
+Column blocks for lap_orth / lap_pcg are torch tensors of shape (b, n): row c
+is column c of the n x b column-major block the C ABI expects.  lap_spmv
+blocks are (n, b) row-major tensors, or (n,) vectors.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+__all__ = ["LapError", "Plan", "EigResult", "lap_plan_create", "lap_eigs", "lap_eigs_csr", "lap_spmv",
+           "lap_orth", "lap_pcg", "library_path", "load_library", "LAP_PREC_FP64", "LAP_PREC_MIXED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblapeig.so")
+_lib = None
+
+LAP_OK, LAP_EINVAL, LAP_ENOTLAPLACIAN, LAP_ENOMEM, LAP_EDEVICE, LAP_ENOCONV, LAP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+LAP_F32, LAP_F64 = 0, 1
+LAP_PREC_FP64, LAP_PREC_MIXED = 0, 1
+LAP_ORDER_PLAN = 1
+
+EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
+            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg", "lap_status_string",
+            "lap_last_error"]
+
+
+class LapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} [{code}]")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("rowptr", ctypes.POINTER(ctypes.c_int32)),
+                ("col", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("itmax", ctypes.c_int),
+                ("rtol_pcg", ctypes.c_double), ("kmax", ctypes.c_int), ("precision", ctypes.c_int),
+                ("block", ctypes.c_int), ("seed", ctypes.c_uint64), ("init", ctypes.POINTER(ctypes.c_double)),
+                ("init_cols", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nconv", ctypes.c_int), ("ncomp", ctypes.c_int), ("outer", ctypes.c_int),
+                ("inner", ctypes.c_int), ("mvp", ctypes.c_longlong), ("seconds", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load liblapeig.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise LapError(LAP_EUNSUPPORTED, f"{_LIB_PATH} is missing: build it with "
+                                         f"`python -m paper_1311_1695_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, vp = ctypes.POINTER, ctypes.c_void_p
+    i32p, f64p, ip = P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_int)
+    lib.lap_eigs_default_opts.argtypes = [P(_Opts)]
+    lib.lap_eigs_default_opts.restype = None
+    lib.lap_plan_create.argtypes = [P(_Csr), vp, P(vp)]
+    lib.lap_plan_destroy.argtypes = [vp]
+    lib.lap_plan_destroy.restype = None
+    lib.lap_plan_n.argtypes = [vp]
+    lib.lap_plan_n.restype = ctypes.c_int32
+    lib.lap_plan_perm.argtypes = [vp, i32p]
+    lib.lap_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p, P(_Info)]
+    lib.lap_eigs_csr.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info)]
+    lib.lap_spmv.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
+    lib.lap_orth.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, ip, vp]
+    lib.lap_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, f64p, vp, ctypes.c_int, vp, vp, ctypes.c_int,
+                            ctypes.c_double, ip, ctypes.c_int, vp]
+    lib.lap_status_string.argtypes = [ctypes.c_int]
+    lib.lap_status_string.restype = ctypes.c_char_p
+    lib.lap_last_error.argtypes = []
+    lib.lap_last_error.restype = ctypes.c_char_p
+    for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg"]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != LAP_OK:
+        lib = load_library()
+        raise LapError(code, lib.lap_last_error().decode() or lib.lap_status_string(code).decode())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _csr_struct(L):
+    rp = np.ascontiguousarray(L.rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(L.col, dtype=np.int32)
+    vl = np.ascontiguousarray(L.val, dtype=np.float64)
+    s = _Csr(int(L.n), int(rp[-1]) if len(rp) else 0, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+             cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), vl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return s, (rp, cl, vl)
+
+
+class Plan:
+    """A validated Laplacian resident on the current HIP device."""
+
+    def __init__(self, L, stream=None):
+        lib = load_library()
+        self._csr, self._keep = _csr_struct(L)
+        h = ctypes.c_void_p()
+        _check(lib.lap_plan_create(ctypes.byref(self._csr), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib.lap_plan_n(h))
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int32)
+        _check(load_library().lap_plan_perm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().lap_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lap_plan_create(L, stream=None) -> Plan:
+    return Plan(L, stream)
+
+
+@dataclasses.dataclass
+class EigResult:
+    evals: np.ndarray
+    evecs: object          # numpy (n, k) or torch tensor (k, n) when on the device
+    res: np.ndarray
+    nconv: int
+    ncomp: int
+    outer: int
+    inner: int
+    mvp: int
+    seconds: float
+    status: int
+
+
+def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0, block=1, seed=1, init=None):
+    lib = load_library()
+    o = _Opts()
+    lib.lap_eigs_default_opts(ctypes.byref(o))
+    o.m_min, o.m_max, o.itmax, o.rtol_pcg, o.kmax = m_min, m_max, itmax, rtol_pcg, kmax
+    o.precision = {"mixed": LAP_PREC_MIXED, "fp64": LAP_PREC_FP64}[precision] if isinstance(precision, str) else int(precision)
+    o.block, o.seed = block, seed
+    keep = None
+    if init is not None:
+        keep = np.asfortranarray(np.asarray(init, dtype=np.float64))
+        if keep.ndim == 1:
+            keep = keep[:, None]
+        o.init = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.init_cols = keep.shape[1]
+    return o, keep
+
+
+def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noconv=False, **kw) -> EigResult:
+    """The k smallest eigenpairs (k counts the zero eigenvalues).  Keyword
+    options: precision ('mixed' | 'fp64'), m_min, m_max, itmax, rtol_pcg,
+    kmax, block, seed, init (n x p start block)."""
+    lib = load_library()
+    o, keep = _opts(**kw)
+    n = plan.n
+    ev = np.zeros(k)
+    res = np.zeros(k)
+    info = _Info()
+    if evecs_on_device:
+        import torch
+        X = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        xp = ctypes.c_void_p(X.data_ptr())
+    else:
+        X = np.zeros((k, n))
+        xp = ctypes.c_void_p(X.ctypes.data)
+    code = lib.lap_eigs(plan._h, int(k), float(tol), ctypes.byref(o),
+                        ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), xp, int(bool(evecs_on_device)),
+                        res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(info))
+    if code != LAP_OK and not (allow_noconv and code == LAP_ENOCONV):
+        _check(code)
+    nc = info.nconv
+    vec = X[:nc] if evecs_on_device else X[:nc].T.copy()
+    return EigResult(ev[:nc].copy(), vec, res[:nc].copy(), nc, info.ncomp, info.outer, info.inner,
+                     int(info.mvp), info.seconds, code)
+
+
+def lap_eigs_csr(L, k, tol, **kw) -> EigResult:
+    plan = Plan(L)
+    try:
+        return lap_eigs(plan, k, tol, **kw)
+    finally:
+        plan.close()
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return LAP_F32
+    if t.dtype == torch.float64:
+        return LAP_F64
+    raise LapError(LAP_EINVAL, f"unsupported dtype {t.dtype}")
+
+
+def lap_spmv(plan: Plan, X, Y, shift=None, plan_order=False, stream=None):
+    """Y = G X - X diag(shift) on the device; X, Y: (n,) or (n, b) row-major."""
+    lib = load_library()
+    if X.dtype != Y.dtype or X.shape != Y.shape or not X.is_contiguous() or not Y.is_contiguous():
+        raise LapError(LAP_EINVAL, "X and Y must be contiguous tensors of one shape and dtype")
+    b = 1 if X.dim() == 1 else int(X.shape[1])
+    sh = None
+    if shift is not None:
+        sh = np.ascontiguousarray(np.broadcast_to(np.asarray(shift, dtype=np.float64), (b,)))
+    _check(lib.lap_spmv(plan._h, _dtype_code(X), b, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                        None if sh is None else sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        LAP_ORDER_PLAN if plan_order else 0, _stream_handle(stream)))
+
+
+def lap_orth(Q, W, stream=None) -> int:
+    """W <- orthonormal basis of (I - QQ')W (double precision).  Q: (q, n)
+    rows are orthonormal columns; W: (b, n), in place.  Returns the rank."""
+    lib = load_library()
+    import torch
+    if W.dtype != torch.float64 or not W.is_contiguous():
+        raise LapError(LAP_EINVAL, "W must be a contiguous float64 tensor of shape (b, n)")
+    b, n = int(W.shape[0]), int(W.shape[1])
+    q = 0 if Q is None else int(Q.shape[0])
+    qp = ctypes.c_void_p(Q.data_ptr()) if q else ctypes.c_void_p(0)
+    rank = ctypes.c_int(0)
+    _check(lib.lap_orth(LAP_F64, n, q, qp, b, ctypes.c_void_p(W.data_ptr()), ctypes.byref(rank),
+                        _stream_handle(stream)))
+    return rank.value
+
+
+def lap_pcg(plan: Plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_order=False, stream=None):
+    """PCG on the projected correction equations; Q: (q, n), R and T: (b, n)
+    float64 device tensors.  Returns the iterations per column."""
+    lib = load_library()
+    b = int(R.shape[0])
+    th = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, dtype=np.float64), (b,)))
+    q = 0 if Q is None else int(Q.shape[0])
+    its = np.zeros(b, dtype=np.int32)
+    _check(lib.lap_pcg(plan._h, {"f32": LAP_F32, "f64": LAP_F64}[dtype], b,
+                       th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       ctypes.c_void_p(Q.data_ptr()) if q else ctypes.c_void_p(0), q,
+                       ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(T.data_ptr()), int(itmax), float(rtol),
+                       its.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), LAP_ORDER_PLAN if plan_order else 0,
+                       _stream_handle(stream)))
+    return its

@@ -1,0 +1,545 @@
+// Outer-iteration kernels of Jacobi-Davidson, all in double precision:
+// orthogonalization of the new direction (Algorithm 2 step 2), the border of
+// H = V'GV (step 4), the eigenpairs of H (step 5), the Ritz vector and its
+// residual (step 6), the certificate of a converged pair (exit test of
+// Section 4 with the quotient of eq. (1)), restart and deflation.
+//
+// Storage: B = [X | V] is n x (kcap + m_max) column-major (ld = n): the
+// locked eigenvectors X in columns [0, nx), the search basis V in
+// [nx, nx + m).  W = G V is n x m_max column-major.  H is m_max x m_max.
+#include "lapeig_dev.h"
+#include "jd_kernels.h"
+
+namespace lapeig {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Classical Gram-Schmidt, applied twice ("twice is enough"), of one vector
+// against the nb = nx + m orthonormal columns of B.
+//   pass 1: v = src (converted to double);     c = B'v,  n0 = ||v||^2
+//   pass 2: v -= B c;                          c = B'v
+//   pass 3: v -= B c;                          n1 = ||v||^2  -> inv_norm
+// ---------------------------------------------------------------------------
+template <typename S, int NV>
+__global__ __launch_bounds__(kBlock) void k_orth1(int n, const double *__restrict__ B, int nb,
+                                                  const S *__restrict__ src, double *__restrict__ v,
+                                                  double *partial, unsigned *counter, JDStatus *st) {
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double vi = (double)src[i];
+        v[i] = vi;
+#pragma unroll
+        for (int j = 0; j < NV - 1; ++j)
+            if (j < nb) acc[j] += B[(size_t)j * n + i] * vi;
+        acc[NV - 1] += vi * vi;
+    }
+    __shared__ double out[NV];
+    // pack the norm right after the nb coefficients
+    double packed[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) packed[j] = j < nb ? acc[j] : (j == nb ? acc[NV - 1] : 0.0);
+    if (grid_reduce<double, NV>(packed, nb + 1, partial, counter, out)) {
+        for (int j = threadIdx.x; j < nb; j += blockDim.x) st->coef[j] = out[j];
+        if (threadIdx.x == 0) st->orth_n0 = sqrt(out[nb]);
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_orth2(int n, const double *__restrict__ B, int nb,
+                                                  double *__restrict__ v, double *partial,
+                                                  unsigned *counter, JDStatus *st, int last) {
+    __shared__ double c[NV];
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) c[j] = st->coef[j];
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double vi = v[i];
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < nb) s += B[(size_t)j * n + i] * c[j];
+        vi -= s;
+        v[i] = vi;
+        if (!last) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                if (j < nb) acc[j] += B[(size_t)j * n + i] * vi;
+        } else {
+            acc[0] += vi * vi;
+        }
+    }
+    __shared__ double out[NV];
+    const int nv = last ? 1 : nb;
+    if (grid_reduce<double, NV>(acc, nv, partial, counter, out)) {
+        if (!last) {
+            for (int j = threadIdx.x; j < nb; j += blockDim.x) st->coef[j] = out[j];
+        } else if (threadIdx.x == 0) {
+            const double n1 = sqrt(out[0]);
+            st->orth_n1 = n1;
+            // a direction that lay in span(B) leaves only rounding noise
+            st->degenerate = !(n1 > 1e-12 * st->orth_n0);
+            st->inv_norm = st->degenerate ? 0.0 : 1.0 / n1;
+        }
+    }
+}
+
+// V[:, m] = v / ||v||,  W[:, m] = G V[:, m]  (one MVP, step 3)
+template <bool Wt>
+__global__ __launch_bounds__(kBlock) void k_spmv_normalize(Graph g, Weights<double> w,
+                                                           const double *__restrict__ v,
+                                                           double *__restrict__ vcol,
+                                                           double *__restrict__ wcol,
+                                                           const JDStatus *st) {
+    const double s = st->inv_norm;
+    for_each_row<double, Wt, false>(g, w, v, [&](int i, double xi, double yi, double) {
+        vcol[i] = xi * s;
+        wcol[i] = yi * s;
+    });
+}
+
+// H(j, m) = H(m, j) = V[:, j]' W[:, m] for j <= m (step 4)
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_hborder(int n, const double *__restrict__ V, int m,
+                                                    const double *__restrict__ wcol, double *H,
+                                                    int ldh, double *partial, unsigned *counter) {
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double wi = wcol[i];
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j <= m) acc[j] += V[(size_t)j * n + i] * wi;
+    }
+    __shared__ double out[NV];
+    if (grid_reduce<double, NV>(acc, m + 1, partial, counter, out)) {
+        for (int j = threadIdx.x; j <= m; j += blockDim.x) {
+            H[(size_t)m * ldh + j] = out[j];
+            H[(size_t)j * ldh + m] = out[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// All eigenpairs of the small symmetric H (step 5) in one workgroup:
+// cyclic Jacobi in the round-robin (tournament) ordering, so the m/2
+// rotations of a round act on disjoint index pairs and run in parallel.
+// Rotation as in Golub & Van Loan (symmetric Schur 2x2).  Off-diagonal
+// entries below eps ||H||_F / m are skipped; sweeps stop when none is left.
+// Output: theta ascending (ties by index), Y column-major (ld = ldy).
+// ---------------------------------------------------------------------------
+constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
+
+__global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restrict__ Hin, int ldh,
+                                                   double *__restrict__ theta, double *__restrict__ Y,
+                                                   int ldy, JDStatus *st) {
+    extern __shared__ double lds[];
+    const int me = (m + 1) & ~1;  // even size; index m is a dummy when m is odd
+    double *A = lds;              // me x me, row-major
+    double *Z = A + me * me;      // me x me, row-major accumulator of rotations
+    __shared__ double cs[kRRMax / 2], sn[kRRMax / 2];
+    __shared__ int pp[kRRMax / 2], qq[kRRMax / 2];
+    __shared__ int any_rot;
+    __shared__ double fro2;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < me * me; t += blockDim.x) {
+        const int i = t / me, j = t % me;
+        A[t] = (i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0;
+        Z[t] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double f = 0.0;
+        for (int t = 0; t < me * me; ++t) f += A[t] * A[t];
+        fro2 = f;
+    }
+    __syncthreads();
+    const double tol = 2.220446049250313e-16 * sqrt(fro2) / (double)me;
+    const int half = me / 2;
+    int sweeps = 0;
+    for (; sweeps < 60 && me > 1; ++sweeps) {
+        if (tid == 0) any_rot = 0;
+        __syncthreads();
+        for (int round = 0; round < me - 1; ++round) {
+            // tournament pairing: position 0 fixed, the others rotate
+            if (tid < half) {
+                auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
+                int a = player(tid), b = player(me - 1 - tid);
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                const double apq = A[p * me + q];
+                if (fabs(apq) > tol) {
+                    const double tau = (A[q * me + q] - A[p * me + p]) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                    any_rot = 1;
+                }
+                pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+            }
+            __syncthreads();
+            // rows: A <- J' A
+            for (int t = tid; t < half * me; t += blockDim.x) {
+                const int k = t / me, j = t % me;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                if (s != 0.0) {
+                    const double ap = A[p * me + j], aq = A[q * me + j];
+                    A[p * me + j] = c * ap - s * aq;
+                    A[q * me + j] = s * ap + c * aq;
+                }
+            }
+            __syncthreads();
+            // columns: A <- A J, Z <- Z J
+            for (int t = tid; t < half * me; t += blockDim.x) {
+                const int k = t / me, i = t % me;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                if (s != 0.0) {
+                    const double ap = A[i * me + p], aq = A[i * me + q];
+                    A[i * me + p] = c * ap - s * aq;
+                    A[i * me + q] = s * ap + c * aq;
+                    const double zp = Z[i * me + p], zq = Z[i * me + q];
+                    Z[i * me + p] = c * zp - s * zq;
+                    Z[i * me + q] = s * zp + c * zq;
+                }
+            }
+            __syncthreads();
+            if (tid < half && sn[tid] != 0.0) {
+                A[pp[tid] * me + qq[tid]] = 0.0;
+                A[qq[tid] * me + pp[tid]] = 0.0;
+            }
+            __syncthreads();
+        }
+        const int rotated = any_rot;
+        __syncthreads();
+        if (!rotated) break;
+    }
+    // rank sort of the m real diagonal entries (the dummy index is excluded)
+    for (int i = tid; i < m; i += blockDim.x) {
+        const double di = A[i * me + i];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+            const double dj = A[j * me + j];
+            rank += (dj < di) || (dj == di && j < i);
+        }
+        theta[rank] = di;
+        for (int r = 0; r < m; ++r) Y[(size_t)rank * ldy + r] = Z[r * me + i];
+    }
+    if (tid == 0 && st) st->rr_sweeps = sweeps;
+}
+
+// u = V y, Gu ~= W y, r = W y - theta u (step 6); also u into column `qcol`
+// of the row-major PCG projector Q (type T, ld = ldq).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ritz(int n, const double *__restrict__ V,
+                                                 const double *__restrict__ W, int m,
+                                                 const double *__restrict__ Y, const double *__restrict__ theta,
+                                                 double *__restrict__ u, double *__restrict__ r,
+                                                 T *__restrict__ Q, int ldq, int qcol, double *partial,
+                                                 unsigned *counter, JDStatus *st) {
+    __shared__ double y[kRRMax];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = Y[j];
+    __syncthreads();
+    const double th = theta[0];
+    double acc[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double ui = 0.0, gi = 0.0;
+        for (int j = 0; j < m; ++j) {
+            ui += V[(size_t)j * n + i] * y[j];
+            gi += W[(size_t)j * n + i] * y[j];
+        }
+        const double ri = gi - th * ui;
+        u[i] = ui;
+        r[i] = ri;
+        Q[(size_t)i * ldq + qcol] = (T)ui;
+        acc[0] += ri * ri;
+        acc[1] += ui * ui;
+    }
+    __shared__ double out[2];
+    if (grid_reduce<double, 2>(acc, 2, partial, counter, out)) {
+        if (threadIdx.x == 0) {
+            st->theta = th;
+            st->unorm = sqrt(out[1]);
+            st->rnorm = sqrt(out[0]) / st->unorm;
+        }
+    }
+}
+
+// Certificate, part 1: Gu with a fresh product and the Rayleigh quotient by
+// eq. (1): theta = (1/2) sum_ij A_ij (u_i - u_j)^2 / u'u.
+template <bool Wt>
+__global__ __launch_bounds__(kBlock) void k_cert1(Graph g, Weights<double> w, const double *__restrict__ u,
+                                                  double *__restrict__ gu, double *partial,
+                                                  unsigned *counter, JDStatus *st) {
+    double acc[2] = {0.0, 0.0};
+    for_each_row<double, Wt, true>(g, w, u, [&](int i, double xi, double yi, double qi) {
+        gu[i] = yi;
+        acc[0] += qi;
+        acc[1] += xi * xi;
+    });
+    __shared__ double out[2];
+    if (grid_reduce<double, 2>(acc, 2, partial, counter, out)) {
+        if (threadIdx.x == 0) {
+            st->cert_unorm2 = out[1];
+            st->cert_theta = 0.5 * out[0] / out[1];
+        }
+    }
+}
+
+// Certificate, part 2: ||G u - theta u|| / ||u||.
+__global__ __launch_bounds__(kBlock) void k_cert2(int n, const double *__restrict__ u,
+                                                  const double *__restrict__ gu, double *partial,
+                                                  unsigned *counter, JDStatus *st) {
+    const double th = st->cert_theta;
+    double acc[1] = {0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double d = gu[i] - th * u[i];
+        acc[0] += d * d;
+    }
+    __shared__ double out[1];
+    if (grid_reduce<double, 1>(acc, 1, partial, counter, out)) {
+        if (threadIdx.x == 0) st->cert_rnorm = sqrt(out[0] / st->cert_unorm2);
+    }
+}
+
+// In-place basis rotation, row by row: for each matrix job,
+//   out[:, j] = (M Y)[:, c0 + j] * (j == 0 ? scale0 : 1),  j < nc,
+// where M = in[:, 0..m) and out may overlap in (each row is read before it
+// is written, by the same thread).  Used for restarts (keep the Ritz vectors
+// of the m_min smallest Ritz values) and deflation (lock u = V y_1, keep V y_j).
+struct RotJob {
+    const double *in;
+    double *out;
+    int c0, nc;
+    const double *scale0;  // device scalar applied to output column 0, or null
+};
+
+template <int MM>
+__global__ __launch_bounds__(kBlock) void k_rotate(int n, int m, const double *__restrict__ Y, int ldy,
+                                                   RotJob j0, RotJob j1) {
+    __shared__ double Ys[MM * MM];
+    // zero padding: rows c >= m of each column multiply zero inputs
+    for (int t = threadIdx.x; t < MM * MM; t += blockDim.x) {
+        const int col = t / MM, c = t % MM;
+        Ys[t] = (col < m && c < m) ? Y[(size_t)col * ldy + c] : 0.0;
+    }
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        for (int job = 0; job < 2; ++job) {
+            const RotJob &J = job ? j1 : j0;
+            if (!J.in || J.nc <= 0) continue;
+            // the whole input row is read before any output of the row is written
+            double row[MM];
+#pragma unroll
+            for (int c = 0; c < MM; ++c) row[c] = c < m ? J.in[(size_t)c * n + i] : 0.0;
+            const double sc = J.scale0 ? *J.scale0 : 1.0;
+#pragma unroll 1
+            for (int o = 0; o < J.nc; ++o) {
+                const double *yc = Ys + (J.c0 + o) * MM;
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < MM; ++c) s += row[c] * yc[c];
+                J.out[(size_t)o * n + i] = o == 0 ? s * sc : s;
+            }
+        }
+    }
+}
+
+// H = diag(theta[off .. off+cnt)) (after a restart or a deflation)
+__global__ void k_hdiag(double *H, int ldh, int cnt, const double *theta, int off) {
+    for (int t = threadIdx.x; t < ldh * ldh; t += blockDim.x) {
+        const int i = t / ldh, j = t % ldh;
+        H[t] = (i == j && i < cnt) ? theta[off + i] : 0.0;
+    }
+}
+
+// Zero eigenvectors (Section 2): normalized indicator of each component.
+template <typename T>
+__global__ void k_zero_space(int n, int nz, const int *__restrict__ comp, const double *__restrict__ inv_sqrt_size,
+                             double *__restrict__ B, T *__restrict__ Q, int ldq) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int c = comp[i];
+        for (int j = 0; j < nz; ++j) {
+            const double val = (c == j) ? inv_sqrt_size[j] : 0.0;
+            B[(size_t)j * n + i] = val;
+            Q[(size_t)i * ldq + j] = (T)val;
+        }
+    }
+}
+
+// Start vector: SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based
+// generator: entry i of column `colidx` takes output number colidx*n + (the
+// caller's index of plan row i) of the stream `seed`, mapped to [-1, 1).
+__device__ __forceinline__ double splitmix_unit(unsigned long long seed, unsigned long long idx) {
+    unsigned long long z = seed + (idx + 1ULL) * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+__global__ void k_random(int n, unsigned long long seed, long long colidx, const int *__restrict__ iperm,
+                         double *__restrict__ v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        v[i] = splitmix_unit(seed, (unsigned long long)colidx * (unsigned long long)n + iperm[i]);
+}
+
+__global__ void k_scale_copy(int n, const double *__restrict__ v, double *__restrict__ out, const JDStatus *st) {
+    const double sc = st->inv_norm;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = v[i] * sc;
+}
+
+inline int vec_grid(int n) {
+    int g = (n + kBlock - 1) / kBlock;
+    const int cap = 4 * device_cu_count();
+    return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+template <typename S, int NV>
+static void orth_nv(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
+                    hipStream_t s) {
+    const int grid = vec_grid(n);
+    rs.ensure(grid, 64);
+    hipLaunchKernelGGL((k_orth1<S, NV>), dim3(grid), dim3(kBlock), 0, s, n, B, nb, src, v, rs.partial.get(),
+                       rs.counter.get(), st);
+    hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, n, B, nb, v, rs.partial.get(),
+                       rs.counter.get(), st, 0);
+    hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, n, B, nb, v, rs.partial.get(),
+                       rs.counter.get(), st, 1);
+    LAP_HIP(hipGetLastError());
+}
+
+template <typename S>
+void jd_orth(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
+             hipStream_t s) {
+    LAP_REQUIRE(nb + 1 <= 64, LAP_EUNSUPPORTED, "basis wider than 63 columns");
+    if (nb + 1 <= 16) orth_nv<S, 16>(n, B, nb, src, v, rs, st, s);
+    else if (nb + 1 <= 32) orth_nv<S, 32>(n, B, nb, src, v, rs, st, s);
+    else orth_nv<S, 64>(n, B, nb, src, v, rs, st, s);
+}
+template void jd_orth<float>(int, const double *, int, const float *, double *, ReduceScratch &, JDStatus *, hipStream_t);
+template void jd_orth<double>(int, const double *, int, const double *, double *, ReduceScratch &, JDStatus *, hipStream_t);
+
+void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, const JDStatus *st, hipStream_t s) {
+    const int grid = row_grid(P.g, 1 << 20);
+    if (P.weighted)
+        hipLaunchKernelGGL((k_spmv_normalize<true>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), v,
+                           vcol, wcol, st);
+    else
+        hipLaunchKernelGGL((k_spmv_normalize<false>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), v,
+                           vcol, wcol, st);
+    LAP_HIP(hipGetLastError());
+}
+
+void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, int ldh, ReduceScratch &rs,
+                hipStream_t s) {
+    const int grid = vec_grid(n);
+    LAP_REQUIRE(m + 1 <= 64, LAP_EUNSUPPORTED, "search space wider than 64 columns");
+    rs.ensure(grid, 64);
+    if (m + 1 <= 16)
+        hipLaunchKernelGGL((k_hborder<16>), dim3(grid), dim3(kBlock), 0, s, n, V, m, wcol, H, ldh, rs.partial.get(),
+                           rs.counter.get());
+    else if (m + 1 <= 32)
+        hipLaunchKernelGGL((k_hborder<32>), dim3(grid), dim3(kBlock), 0, s, n, V, m, wcol, H, ldh, rs.partial.get(),
+                           rs.counter.get());
+    else
+        hipLaunchKernelGGL((k_hborder<64>), dim3(grid), dim3(kBlock), 0, s, n, V, m, wcol, H, ldh, rs.partial.get(),
+                           rs.counter.get());
+    LAP_HIP(hipGetLastError());
+}
+
+void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s) {
+    LAP_REQUIRE(m >= 1 && m <= kRRMax, LAP_EUNSUPPORTED, "projected matrix larger than 96");
+    const int me = (m + 1) & ~1;
+    const size_t lds = 2 * (size_t)me * me * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+        LAP_HIP(hipFuncSetAttribute((const void *)k_rr_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    2 * kRRMax * kRRMax * (int)sizeof(double)));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(kBlock), lds, s, m, H, ldh, theta, Y, ldy, st);
+    LAP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
+             double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s) {
+    const int grid = vec_grid(n);
+    rs.ensure(grid, 2);
+    hipLaunchKernelGGL((k_ritz<T>), dim3(grid), dim3(kBlock), 0, s, n, V, W, m, Y, theta, u, r, Q, ldq, qcol,
+                       rs.partial.get(), rs.counter.get(), st);
+    LAP_HIP(hipGetLastError());
+}
+template void jd_ritz<float>(int, const double *, const double *, int, const double *, const double *, double *,
+                             double *, float *, int, int, ReduceScratch &, JDStatus *, hipStream_t);
+template void jd_ritz<double>(int, const double *, const double *, int, const double *, const double *, double *,
+                              double *, double *, int, int, ReduceScratch &, JDStatus *, hipStream_t);
+
+void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &rs, JDStatus *st, hipStream_t s) {
+    const int grid = row_grid(P.g, 4 * device_cu_count());
+    rs.ensure(std::max(grid, vec_grid(P.n)), 2);
+    if (P.weighted)
+        hipLaunchKernelGGL((k_cert1<true>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), u, gu,
+                           rs.partial.get(), rs.counter.get(), st);
+    else
+        hipLaunchKernelGGL((k_cert1<false>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), u, gu,
+                           rs.partial.get(), rs.counter.get(), st);
+    hipLaunchKernelGGL(k_cert2, dim3(vec_grid(P.n)), dim3(kBlock), 0, s, P.n, u, gu, rs.partial.get(),
+                       rs.counter.get(), st);
+    LAP_HIP(hipGetLastError());
+}
+
+void jd_rotate(int n, int m, const double *Y, int ldy, const double *vin, double *vout, int vc0, int vnc,
+               const double *vscale0, const double *win, double *wout, int wc0, int wnc, hipStream_t s) {
+    RotJob a{vin, vout, vc0, vnc, vscale0};
+    RotJob b{win, wout, wc0, wnc, nullptr};
+    const int grid = vec_grid(n);
+    if (m <= 16)
+        hipLaunchKernelGGL((k_rotate<16>), dim3(grid), dim3(kBlock), 0, s, n, m, Y, ldy, a, b);
+    else if (m <= 32)
+        hipLaunchKernelGGL((k_rotate<32>), dim3(grid), dim3(kBlock), 0, s, n, m, Y, ldy, a, b);
+    else if (m <= 64)
+        hipLaunchKernelGGL((k_rotate<64>), dim3(grid), dim3(kBlock), 0, s, n, m, Y, ldy, a, b);
+    else
+        throw Failure{LAP_EUNSUPPORTED, "rotation of more than 64 columns"};
+    LAP_HIP(hipGetLastError());
+}
+
+void jd_hdiag(double *H, int ldh, int cnt, const double *theta, int off, hipStream_t s) {
+    hipLaunchKernelGGL(k_hdiag, dim3(1), dim3(kBlock), 0, s, H, ldh, cnt, theta, off);
+    LAP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void jd_zero_space(int n, int nz, const int *comp, const double *inv_sqrt_size, double *B, T *Q, int ldq,
+                   hipStream_t s) {
+    hipLaunchKernelGGL((k_zero_space<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, nz, comp, inv_sqrt_size, B,
+                       Q, ldq);
+    LAP_HIP(hipGetLastError());
+}
+template void jd_zero_space<float>(int, int, const int *, const double *, double *, float *, int, hipStream_t);
+template void jd_zero_space<double>(int, int, const int *, const double *, double *, double *, int, hipStream_t);
+
+void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, v, out, st);
+    LAP_HIP(hipGetLastError());
+}
+
+void jd_random(int n, uint64_t seed, long long colidx, const int *iperm, double *v, hipStream_t s) {
+    hipLaunchKernelGGL(k_random, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, (unsigned long long)seed, colidx,
+                       iperm, v);
+    LAP_HIP(hipGetLastError());
+}
+
+}  // namespace lapeig

@@ -1,0 +1,236 @@
+// extern "C" entry points of lapeig.h: argument validation (on the host,
+// before any HIP call), error codes and messages, order conversions.
+#include <cmath>
+#include <new>
+
+#include "jd_kernels.h"
+
+namespace lapeig {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *get_error() { return g_last_error.c_str(); }
+
+// Orthonormalize the b columns of W against Q and among themselves
+// (Algorithm 2 step 2, block form) with the single-vector CGS2 kernels.
+lap_status orth_block(int n, int q, const double *Q, int b, double *W, int *rank_out, hipStream_t s) {
+    LAP_REQUIRE(q + b <= kMaxBasis - 1, LAP_EUNSUPPORTED, "q + b must not exceed 63");
+    DevBuf<double> Bt((size_t)n * (q + b)), v(n);
+    DevBuf<JDStatus> st(1);
+    ReduceScratch rs;
+    if (q > 0) LAP_HIP(hipMemcpyAsync(Bt.get(), Q, sizeof(double) * n * q, hipMemcpyDeviceToDevice, s));
+    int rank = 0;
+    JDStatus h;
+    for (int c = 0; c < b; ++c) {
+        jd_orth<double>(n, Bt.get(), q + rank, W + (size_t)c * n, v.get(), rs, st.get(), s);
+        jd_scale_copy(n, v.get(), Bt.get() + (size_t)(q + rank) * n, st.get(), s);
+        LAP_HIP(hipMemcpyAsync(&h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+        if (!h.degenerate) ++rank;
+    }
+    if (rank > 0)
+        LAP_HIP(hipMemcpyAsync(W, Bt.get() + (size_t)q * n, sizeof(double) * n * rank, hipMemcpyDeviceToDevice, s));
+    if (rank < b)
+        LAP_HIP(hipMemsetAsync(W + (size_t)rank * n, 0, sizeof(double) * n * (b - rank), s));
+    LAP_HIP(hipStreamSynchronize(s));
+    if (rank_out) *rank_out = rank;
+    return LAP_OK;
+}
+
+}  // namespace lapeig
+
+using lapeig::Failure;
+
+#define LAP_GUARD_BEGIN try {
+#define LAP_GUARD_END                                                       \
+    }                                                                       \
+    catch (const Failure &f) {                                              \
+        lapeig::set_error(f.msg);                                           \
+        return f.code;                                                      \
+    }                                                                       \
+    catch (const std::bad_alloc &) {                                        \
+        lapeig::set_error("host allocation failed");                        \
+        return LAP_ENOMEM;                                                  \
+    }                                                                       \
+    catch (...) {                                                           \
+        lapeig::set_error("unexpected exception");                          \
+        return LAP_EDEVICE;                                                 \
+    }
+
+extern "C" {
+
+void lap_eigs_default_opts(lap_eigs_opts *o) {
+    if (!o) return;
+    o->m_min = 5;
+    o->m_max = 10;
+    o->itmax = 20;
+    o->rtol_pcg = 1e-2;
+    o->kmax = 0;
+    o->precision = LAP_PREC_MIXED;
+    o->block = 1;
+    o->seed = 1;
+    o->init = nullptr;
+    o->init_cols = 0;
+}
+
+const char *lap_status_string(lap_status s) {
+    switch (s) {
+        case LAP_OK: return "LAP_OK";
+        case LAP_EINVAL: return "LAP_EINVAL: invalid argument";
+        case LAP_ENOTLAPLACIAN: return "LAP_ENOTLAPLACIAN: not the Laplacian of a simple weighted graph";
+        case LAP_ENOMEM: return "LAP_ENOMEM: allocation failed";
+        case LAP_EDEVICE: return "LAP_EDEVICE: HIP runtime error";
+        case LAP_ENOCONV: return "LAP_ENOCONV: outer-iteration limit reached";
+        case LAP_EUNSUPPORTED: return "LAP_EUNSUPPORTED: not supported by this build";
+    }
+    return "unknown lap_status";
+}
+
+const char *lap_last_error(void) { return lapeig::get_error(); }
+
+lap_status lap_plan_create(const lap_csr *L, void *stream, lap_plan **out) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(out != nullptr, LAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    lap_plan *p = new lap_plan();
+    try {
+        lapeig::build_plan(L, (hipStream_t)stream, p);
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    *out = p;
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+void lap_plan_destroy(lap_plan *p) { delete p; }
+
+int32_t lap_plan_n(const lap_plan *p) { return p ? p->n : 0; }
+
+lap_status lap_plan_perm(const lap_plan *p, int32_t *perm) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p && perm, LAP_EINVAL, "plan or perm is NULL");
+    for (int i = 0; i < p->n; ++i) perm[i] = p->perm[i];
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+static void check_opts(const lap_eigs_opts &o, int n) {
+    LAP_REQUIRE(o.m_min >= 1 && o.m_max > o.m_min, LAP_EINVAL, "need 1 <= m_min < m_max");
+    LAP_REQUIRE(o.itmax >= 1, LAP_EINVAL, "itmax must be >= 1");
+    LAP_REQUIRE(o.rtol_pcg > 0.0 && std::isfinite(o.rtol_pcg), LAP_EINVAL, "rtol_pcg must be > 0");
+    LAP_REQUIRE(o.precision == LAP_PREC_FP64 || o.precision == LAP_PREC_MIXED, LAP_EINVAL, "bad precision");
+    LAP_REQUIRE(o.block >= 1, LAP_EINVAL, "block must be >= 1");
+    LAP_REQUIRE(o.init_cols >= 0 && (o.init_cols == 0 || o.init != nullptr), LAP_EINVAL,
+                "init_cols > 0 needs an init block");
+    if (o.init)
+        for (long long t = 0; t < (long long)n * o.init_cols; ++t)
+            LAP_REQUIRE(std::isfinite(o.init[t]), LAP_EINVAL, "init block holds non-finite values");
+}
+
+lap_status lap_eigs(lap_plan *p, int k, double tol, const lap_eigs_opts *opts, double *evals, double *evecs,
+                    int evecs_on_device, double *res, lap_eigs_info *info) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p != nullptr, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(k >= 1 && k < p->n, LAP_EINVAL, "need 1 <= k < n");
+    LAP_REQUIRE(tol > 0.0 && std::isfinite(tol), LAP_EINVAL, "tol must be > 0");
+    LAP_REQUIRE(evals != nullptr, LAP_EINVAL, "evals is NULL");
+    lap_eigs_opts o;
+    if (opts) o = *opts;
+    else lap_eigs_default_opts(&o);
+    check_opts(o, p->n);
+    LAP_HIP(hipSetDevice(p->device));
+    return lapeig::jd_solve(p, k, tol, o, evals, evecs, evecs_on_device, res, info);
+    LAP_GUARD_END
+}
+
+lap_status lap_eigs_csr(const lap_csr *L, int k, double tol, const lap_eigs_opts *opts, double *evals,
+                        double *evecs, double *res, lap_eigs_info *info) {
+    lap_plan *p = nullptr;
+    lap_status s = lap_plan_create(L, nullptr, &p);
+    if (s != LAP_OK) return s;
+    s = lap_eigs(p, k, tol, opts, evals, evecs, 0, res, info);
+    lap_plan_destroy(p);
+    return s;
+}
+
+lap_status lap_spmv(lap_plan *p, lap_dtype dt, int b, const void *X, void *Y, const double *shift, int flags,
+                    void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p != nullptr, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(dt == LAP_F32 || dt == LAP_F64, LAP_EINVAL, "dtype must be LAP_F32 or LAP_F64");
+    LAP_REQUIRE(b >= 1 && b <= 64, LAP_EINVAL, "need 1 <= b <= 64");
+    LAP_REQUIRE(X && Y, LAP_EINVAL, "X or Y is NULL");
+    LAP_REQUIRE((flags & ~LAP_ORDER_PLAN) == 0, LAP_EINVAL, "unknown flags");
+    if (shift)
+        for (int c = 0; c < b; ++c) LAP_REQUIRE(std::isfinite(shift[c]), LAP_EINVAL, "non-finite shift");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = p->n;
+    const size_t es = dt == LAP_F32 ? sizeof(float) : sizeof(double);
+    const double *sh = nullptr;
+    if (shift) {
+        if (!p->d_shift.get()) p->d_shift.alloc(64);
+        LAP_HIP(hipMemcpyAsync(p->d_shift.get(), shift, sizeof(double) * b, hipMemcpyHostToDevice, s));
+        sh = p->d_shift.get();
+    }
+    const bool plan_order = flags & LAP_ORDER_PLAN;
+    const void *xin = X;
+    void *yout = Y;
+    if (!plan_order) {
+        const size_t bytes = (size_t)n * b * es;
+        if (p->tmp_x.n < bytes) { p->tmp_x.alloc(bytes); p->tmp_y.alloc(bytes); }
+        xin = p->tmp_x.get();
+        yout = p->tmp_y.get();
+        if (dt == LAP_F32)
+            lapeig::permute_rows<float>(p->d_perm.get(), n, b, (const float *)X, (float *)p->tmp_x.get(), s);
+        else
+            lapeig::permute_rows<double>(p->d_perm.get(), n, b, (const double *)X, (double *)p->tmp_x.get(), s);
+    }
+    if (b == 1 && !sh) {
+        if (dt == LAP_F32) lapeig::spmv<float>(*p, (const float *)xin, (float *)yout, 0.0, s);
+        else lapeig::spmv<double>(*p, (const double *)xin, (double *)yout, 0.0, s);
+    } else {
+        if (dt == LAP_F32) lapeig::spmm<float>(*p, b, (const float *)xin, (float *)yout, sh, s);
+        else lapeig::spmm<double>(*p, b, (const double *)xin, (double *)yout, sh, s);
+    }
+    if (!plan_order) {
+        if (dt == LAP_F32)
+            lapeig::permute_rows<float>(p->d_iperm.get(), n, b, (const float *)yout, (float *)Y, s);
+        else
+            lapeig::permute_rows<double>(p->d_iperm.get(), n, b, (const double *)yout, (double *)Y, s);
+    }
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_orth(lap_dtype dt, int n, int q, const double *Q, int b, double *W, int *rank_out, void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(dt == LAP_F64, LAP_EINVAL, "lap_orth works in double precision (LAP_F64)");
+    LAP_REQUIRE(n >= 1 && q >= 0 && b >= 1, LAP_EINVAL, "need n >= 1, q >= 0, b >= 1");
+    LAP_REQUIRE(q == 0 || Q, LAP_EINVAL, "Q is NULL");
+    LAP_REQUIRE(W != nullptr, LAP_EINVAL, "W is NULL");
+    return lapeig::orth_block(n, q, Q, b, W, rank_out, (hipStream_t)stream);
+    LAP_GUARD_END
+}
+
+lap_status lap_pcg(lap_plan *p, lap_dtype dt, int b, const double *theta, const double *Q, int q, const double *R,
+                   double *T, int itmax, double rtol, int *iters_out, int flags, void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p != nullptr, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(dt == LAP_F32 || dt == LAP_F64, LAP_EINVAL, "dtype must be LAP_F32 or LAP_F64");
+    LAP_REQUIRE(b >= 1 && b <= 32, LAP_EINVAL, "need 1 <= b <= 32");
+    LAP_REQUIRE(q >= 0 && (q == 0 || Q), LAP_EINVAL, "bad Q");
+    LAP_REQUIRE(theta && R && T, LAP_EINVAL, "theta, R or T is NULL");
+    LAP_REQUIRE(itmax >= 1, LAP_EINVAL, "itmax must be >= 1");
+    LAP_REQUIRE(rtol > 0.0 && std::isfinite(rtol), LAP_EINVAL, "rtol must be > 0");
+    LAP_REQUIRE((flags & ~LAP_ORDER_PLAN) == 0, LAP_EINVAL, "unknown flags");
+    for (int c = 0; c < b; ++c) LAP_REQUIRE(std::isfinite(theta[c]), LAP_EINVAL, "non-finite theta");
+    return lapeig::pcg_entry(p, dt, b, theta, Q, q, R, T, itmax, rtol, iters_out, flags, (hipStream_t)stream);
+    LAP_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Host driver of Jacobi-Davidson (Algorithm 2 with the deflation of eq.
+// JDsismorethanone and the m_min/m_max restart of Section 3.2).  All vectors
+// stay on the device; the host reads back one small status block per outer
+// iteration (plus one per certification) to take the lock/restart decisions.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <functional>
+#include <numeric>
+
+#include "jd_kernels.h"
+
+namespace lapeig {
+
+namespace {
+
+bool converged(double rnorm, double theta, double tol) {
+    // certificate ||G u - theta u|| <= tol * min(theta, 1) for ||u|| = 1:
+    // implies the paper's ||r||/theta <= tol (Section 4) and ||r|| <= tol
+    const double scale = theta < 1.0 ? theta : 1.0;
+    return rnorm <= tol * scale;
+}
+
+// The PCG launch sequence of one correction equation (Algorithm 2 step 8)
+// captured once per projector width q and replayed every outer iteration:
+// its arguments are device pointers fixed for the solve, so one graph serves
+// until a lock widens Q.  The graph holds kernel nodes only.
+template <typename T>
+struct PcgGraphs {
+    std::vector<hipGraphExec_t> exec;  // indexed by q
+    ~PcgGraphs() {
+        for (auto e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+    }
+    hipGraphExec_t get(int q, hipStream_t s, const std::function<void()> &enqueue) {
+        if ((int)exec.size() <= q) exec.resize(q + 1, nullptr);
+        if (!exec[q]) {
+            hipGraph_t g = nullptr;
+            LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue();
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            LAP_HIP(hipStreamEndCapture(s, &g));
+            hipGraphExec_t e = nullptr;
+            hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            LAP_HIP(err);
+            exec[q] = e;
+        }
+        return exec[q];
+    }
+};
+
+// A non-blocking stream of default priority owned by one solve.
+struct OwnStream {
+    hipStream_t s = nullptr;
+    OwnStream() { LAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+    ~OwnStream() { if (s) (void)hipStreamDestroy(s); }
+};
+
+struct PinnedStatus {
+    JDStatus *h = nullptr;
+    PinnedStatus() { LAP_HIP(hipHostMalloc((void **)&h, sizeof(JDStatus), hipHostMallocDefault)); }
+    ~PinnedStatus() { if (h) (void)hipHostFree(h); }
+};
+
+template <typename T>
+lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                  int evecs_on_device, double *res_out, lap_eigs_info *info) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int n = P->n;
+    // work on a stream of our own (capturable even when the caller uses the
+    // default stream), ordered after the caller's pending work
+    LAP_HIP(hipStreamSynchronize(P->stream));
+    OwnStream own;
+    hipStream_t s = own.s;
+    const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
+    PcgGraphs<T> graphs;
+    const int mmax = o.m_max, mmin = o.m_min;
+    const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
+    LAP_REQUIRE(k + mmax <= kMaxBasis, LAP_EUNSUPPORTED,
+                "k + m_max must not exceed 64 in the single-vector solver");
+    const int nz = std::min(P->ncomp, k);
+    const int ldq = k;
+
+    DevBuf<double> B((size_t)n * (k + mmax)), W((size_t)n * mmax), H((size_t)mmax * mmax), theta(mmax),
+        Y((size_t)mmax * mmax), v(n), u(n), r(n), gu(n), vrand(n), isz(std::max(nz, 1));
+    DevBuf<T> Q((size_t)n * ldq), t(n);
+    DevBuf<JDStatus> st(1);
+    PinnedStatus hst;
+    ReduceScratch rs;
+    rs.ensure(std::max(4 * device_cu_count(), 1), 64);
+    PcgWork<T> pw;
+    pw.ensure(n);
+    LAP_HIP(hipMemsetAsync(H.get(), 0, sizeof(double) * mmax * mmax, s));
+
+    std::vector<double> lam, resid;
+    lam.reserve(k);
+    resid.reserve(k);
+    // zero eigenpairs: one normalized indicator per connected component
+    {
+        std::vector<double> inv(std::max(nz, 1));
+        for (int c = 0; c < nz; ++c) inv[c] = 1.0 / std::sqrt((double)P->comp_size[c]);
+        LAP_HIP(hipMemcpyAsync(isz.get(), inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, s));
+        if (nz > 0) jd_zero_space<T>(n, nz, P->d_comp.get(), isz.get(), B.get(), Q.get(), ldq, s);
+        for (int c = 0; c < nz; ++c) { lam.push_back(0.0); resid.push_back(0.0); }
+    }
+    int nx = nz, m = 0, it = 0;
+    long long mvp = 0, inner = 0;
+    long long start_col = 0;
+    lap_status status = LAP_OK;
+
+    // start vectors: the caller's block (renumbered) or seeded random columns
+    DevBuf<double> init_dev;
+    int init_left = 0, init_next = 0;
+    if (o.init && o.init_cols > 0) {
+        init_dev.alloc((size_t)n * o.init_cols);
+        DevBuf<double> tmp((size_t)n * o.init_cols);
+        LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * o.init_cols, hipMemcpyHostToDevice, s));
+        for (int c = 0; c < o.init_cols; ++c)
+            permute_rows<double>(P->d_perm.get(), n, 1, tmp.get() + (size_t)c * n, init_dev.get() + (size_t)c * n, s);
+        LAP_HIP(hipStreamSynchronize(s));
+        init_left = std::min(o.init_cols, mmax - 1);
+    }
+    auto next_start = [&]() -> const double * {
+        if (init_left > 0) {
+            --init_left;
+            return init_dev.get() + (size_t)(init_next++) * n;
+        }
+        jd_random(n, o.seed, start_col++, P->d_iperm.get(), vrand.get(), s);
+        return vrand.get();
+    };
+
+    bool src_is_t = false;
+    const double *src = nullptr;
+    bool pcg_pending = false;
+    if (nx < k) src = next_start();
+
+    while (nx < k) {
+        if (it >= kmax) { status = LAP_ENOCONV; break; }
+        ++it;
+        // step 2: orthogonalize against [X | V]; step 3: normalize, w = G v
+        if (src_is_t) jd_orth<T>(n, B.get(), nx + m, t.get(), v.get(), rs, st.get(), s);
+        else jd_orth<double>(n, B.get(), nx + m, src, v.get(), rs, st.get(), s);
+        double *Vb = B.get() + (size_t)nx * n;
+        jd_expand(*P, v.get(), Vb + (size_t)m * n, W.get() + (size_t)m * n, st.get(), s);
+        ++mvp;
+        // step 4: border H
+        jd_hborder(n, Vb, m, W.get() + (size_t)m * n, H.get(), mmax, rs, s);
+        ++m;
+        bool need_pcg = true;
+        bool first = true;
+        for (;;) {
+            // step 5: eigenpairs of H; step 6: Ritz vector and residual
+            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s);
+            Vb = B.get() + (size_t)nx * n;
+            jd_ritz<T>(n, Vb, W.get(), m, Y.get(), theta.get(), u.get(), r.get(), Q.get(), ldq, nx, rs, st.get(), s);
+            LAP_HIP(hipMemcpyAsync(hst.h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
+            PcgState<T> pstate;
+            if (pcg_pending) LAP_HIP(hipMemcpyAsync(&pstate, pw.st.get(), sizeof(pstate), hipMemcpyDeviceToHost, s));
+            LAP_HIP(hipStreamSynchronize(s));
+            if (pcg_pending) {
+                const int its = pstate.breakdown ? pstate.breakdown : pstate.iters;
+                inner += its;
+                mvp += its;
+                pcg_pending = false;
+            }
+            if (first && hst.h->degenerate) {
+                // the new direction lay in span[X V]: drop it, take a fresh start vector
+                --m;
+                need_pcg = false;
+                src_is_t = false;
+                src = next_start();
+                break;
+            }
+            first = false;
+            const double th = hst.h->theta, rn = hst.h->rnorm;
+            if (!std::isfinite(th) || !std::isfinite(rn))
+                throw Failure{LAP_EDEVICE, "non-finite Ritz value or residual"};
+            // step 7: exit test, certified with a fresh product and eq. (1)
+            if (!converged(rn, th, tol)) break;
+            jd_certify(*P, u.get(), gu.get(), rs, st.get(), s);
+            ++mvp;
+            LAP_HIP(hipMemcpyAsync(hst.h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
+            LAP_HIP(hipStreamSynchronize(s));
+            const double ct = hst.h->cert_theta, cr = hst.h->cert_rnorm;
+            if (!converged(cr, ct, tol)) break;
+            // lock u = V y_1 as x_{nx}; keep V y_2.. as the new basis, H = diag
+            jd_rotate(n, m, Y.get(), mmax, Vb, Vb, 0, m, nullptr, W.get(), W.get(), 1, m - 1, s);
+            lam.push_back(ct);
+            resid.push_back(cr);
+            ++nx;
+            --m;
+            jd_hdiag(H.get(), mmax, m, theta.get(), 1, s);
+            if (nx >= k) { need_pcg = false; break; }
+            if (m == 0) {
+                need_pcg = false;
+                src_is_t = false;
+                src = next_start();
+                break;
+            }
+        }
+        if (nx >= k) break;
+        if (!need_pcg) continue;
+        if (init_left > 0) {  // still loading the caller's start block
+            src_is_t = false;
+            src = next_start();
+            continue;
+        }
+        // restart: keep the m_min Ritz vectors of smallest Ritz value
+        if (m >= mmax) {
+            Vb = B.get() + (size_t)nx * n;
+            jd_rotate(n, m, Y.get(), mmax, Vb, Vb, 0, mmin, nullptr, W.get(), W.get(), 0, mmin, s);
+            jd_hdiag(H.get(), mmax, mmin, theta.get(), 0, s);
+            m = mmin;
+        }
+        // step 8: correction equation with Q = [X u]
+        {
+            const int q = nx + 1;
+            auto enqueue = [&]() {
+                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, rs, o.itmax, o.rtol_pcg, s);
+            };
+            if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, s, enqueue), s));
+            else enqueue();
+        }
+        pcg_pending = true;
+        src_is_t = true;
+    }
+    if (pcg_pending) {
+        PcgState<T> pstate;
+        LAP_HIP(hipMemcpyAsync(&pstate, pw.st.get(), sizeof(pstate), hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+        const int its = pstate.breakdown ? pstate.breakdown : pstate.iters;
+        inner += its;
+        mvp += its;
+    }
+
+    // ---- output: ascending order, caller's vertex order, canonical signs
+    const int nconv = std::min(nx, k);
+    std::vector<int> order(nconv);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    std::vector<double> Xh((size_t)n * nconv);
+    if (nconv > 0)
+        LAP_HIP(hipMemcpyAsync(Xh.data(), B.get(), sizeof(double) * n * nconv, hipMemcpyDeviceToHost, s));
+    LAP_HIP(hipStreamSynchronize(s));
+    std::vector<double> out((size_t)n * nconv);
+    for (int j = 0; j < nconv; ++j) {
+        const double *x = Xh.data() + (size_t)order[j] * n;
+        double *y = out.data() + (size_t)j * n;
+        for (int i = 0; i < n; ++i) y[i] = x[P->perm[i]];
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::fabs(y[i]) > std::fabs(y[best])) best = i;
+        if (y[best] < 0.0)
+            for (int i = 0; i < n; ++i) y[i] = -y[i];
+        evals[j] = lam[order[j]];
+        if (res_out) res_out[j] = resid[order[j]];
+    }
+    if (evecs && nconv > 0) {
+        if (evecs_on_device)
+            LAP_HIP(hipMemcpyAsync(evecs, out.data(), sizeof(double) * n * nconv, hipMemcpyHostToDevice, s));
+        else
+            std::copy(out.begin(), out.end(), evecs);
+    }
+    LAP_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->nconv = nconv;
+        info->ncomp = P->ncomp;
+        info->outer = it;
+        info->inner = (int)inner;
+        info->mvp = mvp;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return status;
+}
+
+}  // namespace
+
+lap_status jd_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                    int evecs_on_device, double *res, lap_eigs_info *info) {
+    LAP_REQUIRE(o.block == 1, LAP_EUNSUPPORTED, "block > 1 is not supported by this solver");
+    if (o.precision == LAP_PREC_MIXED)
+        return jd_run<float>(P, k, tol, o, evals, evecs, evecs_on_device, res, info);
+    return jd_run<double>(P, k, tol, o, evals, evecs, evecs_on_device, res, info);
+}
+
+}  // namespace lapeig

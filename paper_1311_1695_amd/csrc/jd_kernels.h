@@ -1,0 +1,70 @@
+// Launchers of the Jacobi-Davidson kernels (blas.hip, pcg.hip) used by the
+// host driver (jd.cpp) and the C ABI.
+#pragma once
+
+#include "lapeig_internal.h"
+
+namespace lapeig {
+
+constexpr int kMaxBasis = 64;   // columns of [X | V] handled by the single-vector kernels
+constexpr int kMaxQ = 62;       // projector columns in the PCG kernels
+
+// Small status block written by the kernels and read by the host once per
+// outer iteration.
+struct JDStatus {
+    double coef[kMaxBasis];
+    double orth_n0, orth_n1, inv_norm;
+    double theta, unorm, rnorm;
+    double cert_theta, cert_unorm2, cert_rnorm;
+    int degenerate, rr_sweeps;
+};
+
+template <typename T>
+struct PcgState {
+    T c0[64], c1[64], c2[64];
+    T rho, alpha, beta, r0, rn, pAp;
+    int stop, iters, breakdown, pad;
+};
+
+template <typename S>
+void jd_orth(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
+             hipStream_t s);
+void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, const JDStatus *st,
+               hipStream_t s);
+void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, int ldh, ReduceScratch &rs,
+                hipStream_t s);
+void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s);
+template <typename T>
+void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
+             double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s);
+void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &rs, JDStatus *st, hipStream_t s);
+void jd_rotate(int n, int m, const double *Y, int ldy, const double *vin, double *vout, int vc0, int vnc,
+               const double *vscale0, const double *win, double *wout, int wc0, int wnc, hipStream_t s);
+void jd_hdiag(double *H, int ldh, int cnt, const double *theta, int off, hipStream_t s);
+template <typename T>
+void jd_zero_space(int n, int nz, const int *comp, const double *inv_sqrt_size, double *B, T *Q, int ldq,
+                   hipStream_t s);
+void jd_random(int n, uint64_t seed, long long colidx, const int *iperm, double *v, hipStream_t s);
+// out = v * inv_norm (the normalization left by jd_orth)
+void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipStream_t s);
+
+// PCG work vectors (plan order, type T).
+template <typename T>
+struct PcgWork {
+    DevBuf<T> res, p, s, y;
+    DevBuf<PcgState<T>> st;
+    void ensure(int n) {
+        if (res.n >= (size_t)n && st.get()) return;
+        res.alloc(n); p.alloc(n); s.alloc(n); y.alloc(n);
+        st.alloc(1);
+    }
+};
+
+// One correction equation: t solves the projected system for theta (device
+// scalar), projector Q (row-major n x ldq, first q columns), right-hand side
+// -r (r double, plan order).  Enqueues everything; nothing is read back.
+template <typename T>
+void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
+                 PcgWork<T> &w, ReduceScratch &rs, int itmax, double rtol, hipStream_t s);
+
+}  // namespace lapeig

@@ -1,0 +1,199 @@
+// Device-side building blocks shared by the kernels: wavefront and workgroup
+// reductions, the deterministic cross-workgroup reduction, and the row
+// engine that evaluates Laplacian rows in edge-difference form.
+#pragma once
+
+#include "lapeig_internal.h"
+
+namespace lapeig {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over the 256 threads of a workgroup; every thread gets the result.
+// Fixed combination order, so the result is deterministic.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v) {
+    __shared__ T sm[kWavesPerBlock];
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) sm[wave_id()] = v;
+    __syncthreads();
+    T r = sm[0];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) r += sm[w];
+    return r;
+}
+
+// Device-coherent stores and loads (visible across XCDs within a launch).
+template <typename T>
+__device__ __forceinline__ void store_agent(T *p, T v) {
+    if constexpr (sizeof(T) == 8) {
+        __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                           __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        static_assert(sizeof(T) == 4, "4- or 8-byte types only");
+        __hip_atomic_store(reinterpret_cast<unsigned *>(p), __builtin_bit_cast(unsigned, v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    if constexpr (sizeof(T) == 8) {
+        unsigned long long b = __hip_atomic_load(
+            reinterpret_cast<unsigned long long *>(const_cast<T *>(p)), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT);
+        return __builtin_bit_cast(T, b);
+    } else {
+        static_assert(sizeof(T) == 4, "4- or 8-byte types only");
+        unsigned b = __hip_atomic_load(reinterpret_cast<unsigned *>(const_cast<T *>(p)),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __builtin_bit_cast(T, b);
+    }
+}
+
+// Cross-workgroup sum of nv <= NV <= 64 per-thread values (acc[0..nv)).
+// Every workgroup writes its nv partial sums (wavefront 0 does it, so one
+// release fence by its lane 0 orders them before the completion counter);
+// the last workgroup to finish adds all partials, in workgroup order, with
+// every thread loading a share in parallel, and leaves the totals in
+// out[0..nv) (its shared memory), resets the counter, and returns true.
+// Deterministic: the summation order depends only on the grid size.
+// All workgroups of the grid must call it (no early exits before it).
+template <typename T, int NV>
+__device__ bool grid_reduce(const T (&acc)[NV], int nv, T *partial, unsigned *counter, T *out) {
+    static_assert(NV <= kWave, "at most 64 values per reduction");
+    constexpr int NVP = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : NV <= 32 ? 32 : 64;
+    constexpr int GROUPS = kBlock / NVP;
+    __shared__ T red[kWavesPerBlock][NV];
+    __shared__ T fin[GROUPS][NVP];
+    __shared__ int is_last;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        if (j < nv) {
+            T s = wave_sum(acc[j]);
+            if (lane_id() == 0) red[wave_id()][j] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int j = threadIdx.x;
+        if (j < nv) {
+            T s = red[0][j];
+#pragma unroll
+            for (int w = 1; w < kWavesPerBlock; ++w) s += red[w][j];
+            store_agent(partial + (size_t)blockIdx.x * NV + j, s);
+        }
+        if (j == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            is_last = (prev == gridDim.x - 1);
+            if (is_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    {
+        const int j = threadIdx.x % NVP, g = threadIdx.x / NVP;
+        T s = T(0);
+        if (j < nv)
+            for (int b = g; b < (int)gridDim.x; b += GROUPS) s += load_agent(partial + (size_t)b * NV + j);
+        fin[g][j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        T s = fin[0][threadIdx.x];
+        for (int g = 1; g < GROUPS; ++g) s += fin[g][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) store_agent(counter, 0u);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Row engine.  For every row i of the grid's share it computes
+//   y_i = sum_{j in N(i)} w_ij (x_i - x_j)        ( = (G x)_i )
+//   q_i = sum_{j in N(i)} w_ij (x_i - x_j)^2      (only when QF; sum_i q_i = 2 x'Gx, eq. (1))
+// and calls f(i, x_i, y_i, q_i) on exactly one lane per row.  Rows are
+// visited workgroup-per-row (huge), wavefront-per-row (long), then
+// lane-per-row inside 64-row slices; the grid strides over the units.
+// f must not synchronize.
+// ---------------------------------------------------------------------------
+template <typename T, bool WEIGHTED, bool QF, class F>
+__device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w,
+                                             const T *__restrict__ x, F &&f) {
+    const int lane = lane_id();
+    // huge rows: the whole workgroup strides over the row
+    for (int r = blockIdx.x; r < g.n_huge; r += gridDim.x) {
+        const T xi = x[r];
+        T acc = T(0), aq = T(0);
+        const int e1 = g.rowptr[r + 1];
+        for (int e = g.rowptr[r] + threadIdx.x; e < e1; e += blockDim.x) {
+            const T d = xi - x[g.col[e]];
+            const T wt = WEIGHTED ? w.csr[e] : T(1);
+            acc += wt * d;
+            if (QF) aq += wt * d * d;
+        }
+        acc = block_sum(acc);
+        if (QF) aq = block_sum(aq);
+        if (threadIdx.x == 0) f(r, xi, acc, aq);
+    }
+    const int nlong = g.n_long - g.n_huge;
+    const int units = nlong + g.nslices;
+    for (int u = blockIdx.x * kWavesPerBlock + wave_id(); u < units; u += gridDim.x * kWavesPerBlock) {
+        if (u < nlong) {
+            const int r = g.n_huge + u;
+            const T xi = x[r];
+            T acc = T(0), aq = T(0);
+            const int e1 = g.rowptr[r + 1];
+            for (int e = g.rowptr[r] + lane; e < e1; e += kWave) {
+                const T d = xi - x[g.col[e]];
+                const T wt = WEIGHTED ? w.csr[e] : T(1);
+                acc += wt * d;
+                if (QF) aq += wt * d * d;
+            }
+            acc = wave_sum(acc);
+            if (QF) aq = wave_sum(aq);
+            if (lane == 0) f(r, xi, acc, aq);
+        } else {
+            const int s = u - nlong;
+            const int r = g.n_long + s * kWave + lane;
+            if (r < g.n) {
+                const int off = g.sell_off[s];
+                const int width = (g.sell_off[s + 1] - off) >> 6;
+                const T xi = x[r];
+                T acc = T(0), aq = T(0);
+                const int *cp = g.sell_col + off + lane;
+#pragma unroll 4
+                for (int t = 0; t < width; ++t) {
+                    const T d = xi - x[cp[t * kWave]];
+                    const T wt = WEIGHTED ? w.sell[off + t * kWave + lane] : T(1);
+                    acc += wt * d;
+                    if (QF) aq += wt * d * d;
+                }
+                f(r, xi, acc, aq);
+            }
+        }
+    }
+}
+
+// Grid size for a row-engine launch: enough wavefronts to cover the units,
+// capped so that one pass of partial sums stays small.
+inline int row_grid(const Graph &g, int cap) {
+    const int units = (g.n_long - g.n_huge) + g.nslices;
+    int blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    blocks = blocks > g.n_huge ? blocks : g.n_huge;
+    if (blocks < 1) blocks = 1;
+    return blocks < cap ? blocks : cap;
+}
+
+}  // namespace lapeig

@@ -1,0 +1,195 @@
+// Internal declarations of the gfx950 Jacobi-Davidson library.
+//
+// Vertex order.  A plan renumbers the vertices by decreasing degree (ties by
+// the caller's index).  Every device array of a plan, and every kernel, works
+// in that "plan order"; the C ABI converts at its edges.
+//
+// Matrix layout (plan order).  Only the adjacency part of G = D - A is
+// stored: the Laplacian product is evaluated in edge-difference form
+//   (G x)_i = sum_{j in N(i)} w_ij (x_i - x_j),
+// which is G x for G = D - A (Section 2) with D_ii = sum_j w_ij, needs no
+// diagonal, and has no cancellation between d_i x_i and sum_j w_ij x_j.
+//   rows [0, n_huge)        degree > huge threshold: one workgroup per row (CSR)
+//   rows [n_huge, n_long)   degree > long threshold: one wavefront per row (CSR)
+//   rows [n_long, n)        64-row slices, column-major inside a slice
+//                           ("sliced ELLPACK"): lane l of a wavefront owns row
+//                           n_long + 64 s + l and reads its s-th neighbour at
+//                           sell_col[sell_off[slice] + 64 s + l]; padding
+//                           entries point at the row itself, weight 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lapeig.h"
+
+namespace lapeig {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+const char *get_error();
+
+struct Failure {
+    lap_status code;
+    std::string msg;
+};
+
+#define LAP_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::lapeig::Failure{LAP_EDEVICE, std::string(#call) + ": " +            \
+                                                     hipGetErrorString(e_)};            \
+    } while (0)
+
+#define LAP_REQUIRE(cond, code, msg)                                                    \
+    do {                                                                                \
+        if (!(cond)) throw ::lapeig::Failure{code, msg};                                \
+    } while (0)
+
+// ------------------------------------------------------- device buffers
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Failure{LAP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                          " bytes failed: " + hipGetErrorString(e)};
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// ------------------------------------------------------------ the graph
+struct Graph {
+    int n = 0;
+    int n_huge = 0, n_long = 0;   // row-class boundaries (plan order)
+    int nslices = 0;              // 64-row slices covering [n_long, n)
+    const int *rowptr = nullptr;  // CSR of A, plan order, n + 1
+    const int *col = nullptr;
+    const int *sell_off = nullptr;  // nslices + 1 offsets into sell_col
+    const int *sell_col = nullptr;
+};
+
+template <typename T>
+struct Weights {
+    const T *csr = nullptr;   // weight of each CSR entry, or nullptr (unweighted)
+    const T *sell = nullptr;  // weight of each slice entry, or nullptr
+};
+
+}  // namespace lapeig
+
+// The opaque plan of the C ABI.
+struct lap_plan {
+    int n = 0;
+    long long nnz_a = 0;     // off-diagonal entries (2 per edge)
+    bool weighted = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int huge_threshold = 0, long_threshold = 0;
+
+    std::vector<int> perm;    // caller index -> plan index
+    std::vector<int> iperm;   // plan index -> caller index
+    std::vector<int> comp;    // component label per plan index, 0..ncomp-1
+    std::vector<int> comp_size;
+    int ncomp = 0;
+    int max_degree = 0;
+
+    lapeig::DevBuf<int> d_perm, d_iperm, d_comp;
+    lapeig::DevBuf<int> d_rowptr, d_col, d_sell_off, d_sell_col;
+    lapeig::DevBuf<float> d_w32, d_sellw32, d_dinv32;
+    lapeig::DevBuf<double> d_w64, d_sellw64, d_dinv64;
+    lapeig::Graph g;
+    // scratch of the building-block entry points
+    lapeig::DevBuf<double> d_shift;
+    lapeig::DevBuf<char> tmp_x, tmp_y;
+
+    template <typename T>
+    lapeig::Weights<T> weights() const;
+    template <typename T>
+    const T *dinv() const;
+};
+
+template <>
+inline lapeig::Weights<float> lap_plan::weights<float>() const {
+    return weighted ? lapeig::Weights<float>{d_w32.get(), d_sellw32.get()} : lapeig::Weights<float>{};
+}
+template <>
+inline lapeig::Weights<double> lap_plan::weights<double>() const {
+    return weighted ? lapeig::Weights<double>{d_w64.get(), d_sellw64.get()} : lapeig::Weights<double>{};
+}
+template <>
+inline const float *lap_plan::dinv<float>() const { return d_dinv32.get(); }
+template <>
+inline const double *lap_plan::dinv<double>() const { return d_dinv64.get(); }
+
+namespace lapeig {
+
+// ------------------------------------------------------------- plan.cpp
+// Validate (host), renumber, classify rows, build slices, upload.
+void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_threshold = 64,
+                int huge_threshold = 4096);
+
+// ------------------------------------------------------------- spmv.hip
+// y = (G - sigma I) x, b = 1, plan order.
+template <typename T>
+void spmv(const lap_plan &P, const T *x, T *y, double sigma, hipStream_t s);
+// Y = G X - X diag(shift) for n x b row-major blocks, plan order.
+template <typename T>
+void spmm(const lap_plan &P, int b, const T *X, T *Y, const double *shift_dev, hipStream_t s);
+
+// Reduction scratch: per-block partial sums and a completion counter.
+struct ReduceScratch {
+    DevBuf<double> partial;      // >= max_blocks * max_values doubles
+    DevBuf<unsigned> counter;    // one counter per reduction site
+    int max_blocks = 0;
+    int max_values = 0;
+    void ensure(int blocks, int values);
+};
+
+// Gathers and scatters between caller order and plan order.
+template <typename T>
+void permute_rows(const int *map, int n, int b, const T *in, T *out, hipStream_t s);
+
+// ------------------------------------------------------------ jd.cpp
+lap_status jd_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals,
+                    double *evecs, int evecs_on_device, double *res, lap_eigs_info *info);
+
+// ------------------------------------------------------------ blas.hip / pcg.hip
+lap_status orth_block(int n, int q, const double *Q, int b, double *W, int *rank_out,
+                      hipStream_t s);
+lap_status pcg_entry(lap_plan *P, lap_dtype dt, int b, const double *theta_host, const double *Q,
+                     int q, const double *R, double *T, int itmax, double rtol, int *iters_out,
+                     int flags, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace lapeig
