@@ -1,0 +1,85 @@
+// Launchers and state of the block Jacobi-Davidson path (block.hip,
+// jd_block.cpp).  Block vectors are row-major with an explicit leading
+// dimension; the basis [X | V] is one row-major n x (k + m_max) array.
+#pragma once
+
+#include "jd_kernels.h"
+
+namespace lapeig {
+
+constexpr int kMaxBlock = 32;
+
+// Partial tiles of the tall-skinny products: up to 2 x CUs workgroups,
+// 128 x 32 entries each.
+struct BlockScratch {
+    DevBuf<double> part;
+    void ensure() {
+        if (part.get()) return;
+        part.alloc((size_t)2 * device_cu_count() * 128 * 32);
+    }
+};
+
+struct BlockStatus {
+    double theta[kMaxBlock], rnorm[kMaxBlock], unorm[kMaxBlock];
+    int kept;
+};
+
+template <typename T>
+struct BPcgState {
+    T rho[kMaxBlock], alpha[kMaxBlock], beta[kMaxBlock], r0[kMaxBlock], rn[kMaxBlock];
+    int active[kMaxBlock], its[kMaxBlock], brk[kMaxBlock], copy_p[kMaxBlock];
+    int nactive, nactive_step;
+};
+
+template <typename T>
+struct BPcgWork {
+    DevBuf<T> res, p, s, y, C;
+    DevBuf<BPcgState<T>> st;
+    void ensure(int n, int b, int qmax) {
+        if (res.get()) return;
+        res.alloc((size_t)n * b); p.alloc((size_t)n * b); s.alloc((size_t)n * b); y.alloc((size_t)n * b);
+        C.alloc((size_t)(qmax + 1) * b);
+        st.alloc(1);
+    }
+};
+
+// C (ka x kb, column-major ldc) = alpha A'B  (A n x ka, B n x kb, row-major); when
+// mirror is given, also mirror[j + i ldm] = C(i, j) for i < ka - kb (the
+// border of a symmetric matrix whose new kb x kb corner C already holds).
+// kb <= 32, ka <= 128.
+template <typename T>
+void ts_tn(int n, const T *A, int lda, int ka, const T *B, int ldb, int kb, T *out, int ldc, T *mirror, int ldm,
+           T alpha, BlockScratch &bs, hipStream_t s);
+// Out = alpha A C + (addend if given, else beta Out); C ka x kb column-major.
+// Out may be the same rows as A (in-place rotation).  ka, kb <= 128.
+template <typename T>
+void ts_prepare();
+template <typename T>
+void ts_nn(int n, const T *A, int lda, int ka, const T *C, int ldc, int kb, T *Out, int ldo, const T *addend,
+           int ldadd, T alpha, T beta, hipStream_t s);
+
+// SVQB scaling: keep eigenvalues above max(rel lam_max, abs_thr)
+void blk_svqb(int b, const double *lam, const double *Z, int ldz, double rel, double abs_thr, double *M, int ldm,
+              BlockStatus *st, hipStream_t s);
+template <typename T>
+void blk_zero_space(int n, int nz, const int *comp, const double *isz, double *XV, int ldb, T *Q, int ldq,
+                    hipStream_t s);
+void blk_extract(int n, int nc, const double *in, int ldi, double *out, hipStream_t s);
+// out[map[i] * ldo + c] = in[i + c n] (map NULL: identity)
+void blk_cm_to_rm(int n, int b, const double *in, const int *map, double *out, int ldo, hipStream_t s);
+template <typename T>
+void blk_resid(int n, int bu, const double *U, const double *GU, int ldu, const double *theta, double *R, T *Q,
+               int ldq, int qoff, double *u0, ReduceScratch &rs, BlockStatus *st, hipStream_t s);
+template <typename S>
+void blk_to_f64(int n, int b, const S *in, int ldi, double *out, int ldo, hipStream_t s);
+void blk_random(int n, int b, uint64_t seed, long long colbase, const int *iperm, double *out, int ldo,
+                hipStream_t s);
+template <typename T>
+void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q, int ldq, int q, const double *R,
+                  int ldr, T *X, BPcgWork<T> &w, ReduceScratch &rs, BlockScratch &bs, int itmax, double rtol,
+                  hipStream_t s);
+
+lap_status jd_block_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                          int evecs_on_device, double *res, lap_eigs_info *info);
+
+}  // namespace lapeig

@@ -2,8 +2,9 @@
 // before any HIP call), error codes and messages, order conversions.
 #include <cmath>
 #include <new>
+#include <vector>
 
-#include "jd_kernels.h"
+#include "block_kernels.h"
 
 namespace lapeig {
 
@@ -15,24 +16,59 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 const char *get_error() { return g_last_error.c_str(); }
 
 // Orthonormalize the b columns of W against Q and among themselves
-// (Algorithm 2 step 2, block form) with the single-vector CGS2 kernels.
+// (Algorithm 2 step 2, block form).  Against Q: classical Gram-Schmidt twice,
+// as one block product per pass (W -= Q (Q'W), on the matrix cores when
+// b >= 2); within W: the single-vector CGS2 kernels column by column.
 lap_status orth_block(int n, int q, const double *Q, int b, double *W, int *rank_out, hipStream_t s) {
-    LAP_REQUIRE(q + b <= kMaxBasis - 1, LAP_EUNSUPPORTED, "q + b must not exceed 63");
-    DevBuf<double> Bt((size_t)n * (q + b)), v(n);
+    LAP_REQUIRE(b <= kMaxBasis - 1, LAP_EUNSUPPORTED, "b must not exceed 63");
+    LAP_REQUIRE(q + b <= 160, LAP_EUNSUPPORTED, "q + b must not exceed 160");
+    DevBuf<double> v(n);
     DevBuf<JDStatus> st(1);
     ReduceScratch rs;
-    if (q > 0) LAP_HIP(hipMemcpyAsync(Bt.get(), Q, sizeof(double) * n * q, hipMemcpyDeviceToDevice, s));
+    bool projected = false;
+    std::vector<double> norm0(b, 0.0);
+    if (q > 0 && b >= 2 && q <= 128 && b <= 32) {
+        // column norms before the projection: the reference of the drop test
+        {
+            std::vector<double> hw((size_t)n * b);
+            LAP_HIP(hipMemcpyAsync(hw.data(), W, sizeof(double) * n * b, hipMemcpyDeviceToHost, s));
+            LAP_HIP(hipStreamSynchronize(s));
+            for (int c = 0; c < b; ++c) {
+                double acc = 0.0;
+                for (int i = 0; i < n; ++i) acc += hw[(size_t)c * n + i] * hw[(size_t)c * n + i];
+                norm0[c] = std::sqrt(acc);
+            }
+        }
+        DevBuf<double> Qr((size_t)n * q), Wr((size_t)n * b), C((size_t)q * b);
+        BlockScratch bs;
+        bs.ensure();
+        blk_cm_to_rm(n, q, Q, nullptr, Qr.get(), q, s);
+        blk_cm_to_rm(n, b, W, nullptr, Wr.get(), b, s);
+        for (int pass = 0; pass < 2; ++pass) {
+            ts_tn<double>(n, Qr.get(), q, q, Wr.get(), b, b, C.get(), q, nullptr, 0, 1.0, bs, s);
+            ts_nn<double>(n, Qr.get(), q, q, C.get(), q, b, Wr.get(), b, nullptr, 0, -1.0, 1.0, s);
+        }
+        blk_extract(n, b, Wr.get(), b, W, s);
+        LAP_HIP(hipStreamSynchronize(s));
+        projected = true;
+    }
+    // [Q | kept columns] for the column-by-column pass
+    const int qb = projected ? 0 : q;
+    LAP_REQUIRE(qb + b <= kMaxBasis - 1, LAP_EUNSUPPORTED, "q + b must not exceed 63 for one column");
+    DevBuf<double> Bq((size_t)n * (qb + b));
+    if (qb > 0) LAP_HIP(hipMemcpyAsync(Bq.get(), Q, sizeof(double) * n * qb, hipMemcpyDeviceToDevice, s));
     int rank = 0;
     JDStatus h;
     for (int c = 0; c < b; ++c) {
-        jd_orth<double>(n, Bt.get(), q + rank, W + (size_t)c * n, v.get(), rs, st.get(), s);
-        jd_scale_copy(n, v.get(), Bt.get() + (size_t)(q + rank) * n, st.get(), s);
+        jd_orth<double>(n, Bq.get(), qb + rank, W + (size_t)c * n, v.get(), rs, st.get(), s);
+        jd_scale_copy(n, v.get(), Bq.get() + (size_t)(qb + rank) * n, st.get(), s);
         LAP_HIP(hipMemcpyAsync(&h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
         LAP_HIP(hipStreamSynchronize(s));
-        if (!h.degenerate) ++rank;
+        const bool dropped = h.degenerate || (projected && !(h.orth_n1 > 1e-12 * norm0[c]));
+        if (!dropped) ++rank;
     }
     if (rank > 0)
-        LAP_HIP(hipMemcpyAsync(W, Bt.get() + (size_t)q * n, sizeof(double) * n * rank, hipMemcpyDeviceToDevice, s));
+        LAP_HIP(hipMemcpyAsync(W, Bq.get() + (size_t)qb * n, sizeof(double) * n * rank, hipMemcpyDeviceToDevice, s));
     if (rank < b)
         LAP_HIP(hipMemsetAsync(W + (size_t)rank * n, 0, sizeof(double) * n * (b - rank), s));
     LAP_HIP(hipStreamSynchronize(s));
@@ -44,7 +80,9 @@ lap_status orth_block(int n, int q, const double *Q, int b, double *W, int *rank
 
 using lapeig::Failure;
 
-#define LAP_GUARD_BEGIN try {
+#define LAP_GUARD_BEGIN \
+    lapeig::set_error("");  \
+    try {
 #define LAP_GUARD_END                                                       \
     }                                                                       \
     catch (const Failure &f) {                                              \

@@ -9,7 +9,7 @@
 #include <functional>
 #include <numeric>
 
-#include "jd_kernels.h"
+#include "block_kernels.h"
 
 namespace lapeig {
 
@@ -142,7 +142,12 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     if (nx < k) src = next_start();
 
     while (nx < k) {
-        if (it >= kmax) { status = LAP_ENOCONV; break; }
+        if (it >= kmax) {
+            status = LAP_ENOCONV;
+            set_error("outer-iteration limit " + std::to_string(kmax) + " reached with " + std::to_string(nx) +
+                      " of " + std::to_string(k) + " pairs certified");
+            break;
+        }
         ++it;
         // step 2: orthogonalize against [X | V]; step 3: normalize, w = G v
         if (src_is_t) jd_orth<T>(n, B.get(), nx + m, t.get(), v.get(), rs, st.get(), s);
@@ -284,7 +289,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
 
 lap_status jd_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
                     int evecs_on_device, double *res, lap_eigs_info *info) {
-    LAP_REQUIRE(o.block == 1, LAP_EUNSUPPORTED, "block > 1 is not supported by this solver");
+    if (o.block > 1) return jd_block_solve(P, k, tol, o, evals, evecs, evecs_on_device, res, info);
     if (o.precision == LAP_PREC_MIXED)
         return jd_run<float>(P, k, tol, o, evals, evecs, evecs_on_device, res, info);
     return jd_run<double>(P, k, tol, o, evals, evecs, evecs_on_device, res, info);

@@ -1,0 +1,331 @@
+// Block Jacobi-Davidson: Algorithm 2 with b corrections per outer iteration.
+//
+// Each outer iteration solves the correction equations of the b smallest
+// unconverged Ritz pairs together (one block PCG over an n x b SpMM, shared
+// projector Q = [X, U]), orthonormalizes the b corrections against [X V] and
+// among themselves, and expands V, W = GV and H = V'W by b columns at once.
+// Deflation, restart and certification are those of Algorithm 2 (eq.
+// JDsismorethanone; m_min/m_max of Section 3.2), applied to the leading Ritz
+// pair.  Basis storage is row-major: [X | V] is n x (k + m_max), W n x m_max.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <functional>
+#include <map>
+#include <numeric>
+
+#include "block_kernels.h"
+
+namespace lapeig {
+
+namespace {
+
+bool converged_b(double rnorm, double theta, double tol) {
+    const double scale = theta < 1.0 ? theta : 1.0;
+    return rnorm <= tol * scale;
+}
+
+struct OwnStreamB {
+    hipStream_t s = nullptr;
+    OwnStreamB() { LAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+    ~OwnStreamB() { if (s) (void)hipStreamDestroy(s); }
+};
+
+template <typename Tp>
+struct PinnedB {
+    Tp *h = nullptr;
+    PinnedB() { LAP_HIP(hipHostMalloc((void **)&h, sizeof(Tp), hipHostMallocDefault)); }
+    ~PinnedB() { if (h) (void)hipHostFree(h); }
+};
+
+// graphs of the block PCG keyed by (q, b)
+struct GraphCache {
+    std::map<std::pair<int, int>, hipGraphExec_t> exec;
+    ~GraphCache() {
+        for (auto &e : exec)
+            if (e.second) (void)hipGraphExecDestroy(e.second);
+    }
+    hipGraphExec_t get(int q, int b, hipStream_t s, const std::function<void()> &enqueue) {
+        auto key = std::make_pair(q, b);
+        auto it = exec.find(key);
+        if (it != exec.end()) return it->second;
+        hipGraph_t g = nullptr;
+        LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue();
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        LAP_HIP(hipStreamEndCapture(s, &g));
+        hipGraphExec_t e = nullptr;
+        hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        LAP_HIP(err);
+        exec[key] = e;
+        return e;
+    }
+};
+
+template <typename T>
+lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                   int evecs_on_device, double *res_out, lap_eigs_info *info) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int n = P->n;
+    const int b = o.block, mmax = o.m_max, mmin = o.m_min;
+    LAP_REQUIRE(b >= 2 && b <= kMaxBlock, LAP_EUNSUPPORTED, "block size must be 2..32");
+    LAP_REQUIRE(mmin >= b && mmin + b <= mmax, LAP_EINVAL, "block solver needs m_min >= b and m_min + b <= m_max");
+    LAP_REQUIRE(mmax <= 96, LAP_EUNSUPPORTED, "m_max above 96");
+    LAP_REQUIRE(k + mmax <= 128, LAP_EUNSUPPORTED, "k + m_max above 128");
+    const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
+    LAP_HIP(hipStreamSynchronize(P->stream));
+    OwnStreamB own;
+    hipStream_t s = own.s;
+    const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
+    GraphCache graphs;
+
+    const int ldb = k + mmax, ldh = mmax, ldq = k + b;
+    const int nz = std::min(P->ncomp, k);
+    DevBuf<double> XV((size_t)n * ldb), W((size_t)n * mmax), H((size_t)mmax * mmax), theta(mmax),
+        Y((size_t)mmax * mmax), Vn((size_t)n * b), Cc((size_t)ldb * b), S((size_t)b * b), Sth(b), Sz((size_t)b * b),
+        M((size_t)b * b), U((size_t)n * b), GU((size_t)n * b), R((size_t)n * b), u0(n), gu(n), isz(std::max(nz, 1));
+    DevBuf<T> Q((size_t)n * ldq), Tt((size_t)n * b);
+    DevBuf<BlockStatus> bst(1);
+    DevBuf<JDStatus> jst(1);
+    PinnedB<BlockStatus> hb;
+    PinnedB<JDStatus> hj;
+    PinnedB<BPcgState<T>> hp;
+    ReduceScratch rs;
+    rs.ensure(4 * device_cu_count(), 64);
+    BlockScratch bs;
+    bs.ensure();
+    BPcgWork<T> pw;
+    pw.ensure(n, b, ldq);
+    ts_prepare<double>();
+    ts_prepare<T>();
+
+    std::vector<double> lam, resid;
+    {
+        std::vector<double> inv(std::max(nz, 1));
+        for (int c = 0; c < nz; ++c) inv[c] = 1.0 / std::sqrt((double)P->comp_size[c]);
+        LAP_HIP(hipMemcpyAsync(isz.get(), inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, s));
+        if (nz > 0) blk_zero_space<T>(n, nz, P->d_comp.get(), isz.get(), XV.get(), ldb, Q.get(), ldq, s);
+        for (int c = 0; c < nz; ++c) { lam.push_back(0.0); resid.push_back(0.0); }
+    }
+    int nx = nz, m = 0, it = 0;
+    long long mvp = 0, inner = 0, colbase = 0;
+    lap_status status = LAP_OK;
+
+    // the first block: the caller's start vectors (up to b), then random columns
+    int src_cols = 0;     // columns waiting in Vn (double) or Tt (T)
+    bool src_is_t = false;
+    auto random_block = [&]() {
+        blk_random(n, b, o.seed, colbase, P->d_iperm.get(), Vn.get(), b, s);
+        colbase += b;
+        src_cols = b;
+        src_is_t = false;
+    };
+    if (o.init && o.init_cols > 0) {
+        // the caller's start vectors (column-major, caller order) first, then random columns
+        const int c0 = std::min(o.init_cols, b);
+        DevBuf<double> tmp((size_t)n * c0);
+        LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * c0, hipMemcpyHostToDevice, s));
+        blk_random(n, b, o.seed, colbase, P->d_iperm.get(), Vn.get(), b, s);
+        colbase += b;
+        blk_cm_to_rm(n, c0, tmp.get(), P->d_perm.get(), Vn.get(), b, s);
+        LAP_HIP(hipStreamSynchronize(s));
+        src_cols = b;
+        src_is_t = false;
+    } else if (nx < k) {
+        random_block();
+    }
+    bool pcg_pending = false;
+    int pcg_cols = 0;
+
+    auto account_pcg = [&]() {
+        if (!pcg_pending) return;
+        for (int c = 0; c < pcg_cols; ++c) {
+            const int its = hp.h->brk[c] ? hp.h->brk[c] : hp.h->its[c];
+            inner += its;
+            mvp += its;
+        }
+        pcg_pending = false;
+    };
+
+    // SVQB of Vn's `cur` columns; result into dest (ld); returns the kept count
+    auto svqb = [&](int cur, double rel, double abs_thr, double *dest, int lddest) -> int {
+        ts_tn<double>(n, Vn.get(), b, cur, Vn.get(), b, cur, S.get(), b, nullptr, 0, 1.0, bs, s);
+        jd_rr(cur, S.get(), b, Sth.get(), Sz.get(), b, nullptr, s);
+        blk_svqb(cur, Sth.get(), Sz.get(), b, rel, abs_thr, M.get(), b, bst.get(), s);
+        LAP_HIP(hipMemcpyAsync(hb.h, bst.get(), sizeof(BlockStatus), hipMemcpyDeviceToHost, s));
+        if (pcg_pending) LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+        account_pcg();
+        const int kept = hb.h->kept;
+        if (kept > 0) ts_nn<double>(n, Vn.get(), b, cur, M.get(), b, kept, dest, lddest, nullptr, 0, 1.0, 0.0, s);
+        return kept;
+    };
+
+    while (nx < k) {
+        if (it >= kmax) {
+            status = LAP_ENOCONV;
+            set_error("outer-iteration limit " + std::to_string(kmax) + " reached with " + std::to_string(nx) +
+                      " of " + std::to_string(k) + " pairs certified");
+            break;
+        }
+        ++it;
+        if (src_is_t) blk_to_f64<T>(n, src_cols, Tt.get(), src_cols, Vn.get(), b, s);
+        // orthonormalize the new block: SVQB (scale), then twice
+        // [classical Gram-Schmidt against [X V]; SVQB]
+        int cur = svqb(src_cols, 1e-20, 0.0, Vn.get(), b);
+        for (int pass = 0; pass < 2 && cur > 0; ++pass) {
+            const int nb = nx + m;
+            if (nb > 0) {
+                ts_tn<double>(n, XV.get(), ldb, nb, Vn.get(), b, cur, Cc.get(), ldb, nullptr, 0, 1.0, bs, s);
+                ts_nn<double>(n, XV.get(), ldb, nb, Cc.get(), ldb, cur, Vn.get(), b, nullptr, 0, -1.0, 1.0, s);
+            }
+            double *dest = pass == 1 ? XV.get() + nx + m : Vn.get();
+            const int ld = pass == 1 ? ldb : b;
+            cur = svqb(cur, 1e-20, 1e-20, dest, ld);
+        }
+        if (cur == 0) {  // the corrections lay in span[X V]
+            random_block();
+            continue;
+        }
+        const int add = std::min(cur, mmax - m);
+        double *Vb = XV.get() + nx;
+        // W(:, m:m+add) = G V(:, m:m+add);  H border
+        spmm<double>(*P, add, Vb + m, ldb, W.get() + m, mmax, nullptr, s);
+        mvp += add;
+        ts_tn<double>(n, Vb, ldb, m + add, W.get() + m, mmax, add, H.get() + (size_t)m * ldh, ldh, H.get() + m, ldh,
+                      1.0, bs, s);
+        m += add;
+
+        bool need_pcg = true;
+        int bu = 0;
+        for (;;) {
+            jd_rr(m, H.get(), ldh, theta.get(), Y.get(), mmax, nullptr, s);
+            Vb = XV.get() + nx;
+            bu = std::min(std::min(b, m), k - nx);
+            ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, bu, U.get(), b, nullptr, 0, 1.0, 0.0, s);
+            ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, bu, GU.get(), b, nullptr, 0, 1.0, 0.0, s);
+            blk_resid<T>(n, bu, U.get(), GU.get(), b, theta.get(), R.get(), Q.get(), ldq, nx, u0.get(), rs, bst.get(),
+                         s);
+            LAP_HIP(hipMemcpyAsync(hb.h, bst.get(), sizeof(BlockStatus), hipMemcpyDeviceToHost, s));
+            if (pcg_pending)
+                LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
+            LAP_HIP(hipStreamSynchronize(s));
+            account_pcg();
+            const double th = hb.h->theta[0], rn = hb.h->rnorm[0];
+            if (!std::isfinite(th) || !std::isfinite(rn))
+                throw Failure{LAP_EDEVICE, "non-finite Ritz value or residual"};
+            if (!converged_b(rn, th, tol)) break;
+            jd_certify(*P, u0.get(), gu.get(), rs, jst.get(), s);
+            ++mvp;
+            LAP_HIP(hipMemcpyAsync(hj.h, jst.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
+            LAP_HIP(hipStreamSynchronize(s));
+            const double ct = hj.h->cert_theta, cr = hj.h->cert_rnorm;
+            if (!converged_b(cr, ct, tol)) break;
+            // lock: V <- V Y (the first column, u, joins X); W <- W Y(:, 2:m)
+            ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, m, Vb, ldb, nullptr, 0, 1.0, 0.0, s);
+            if (m > 1)
+                ts_nn<double>(n, W.get(), mmax, m, Y.get() + mmax, mmax, m - 1, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
+            jd_hdiag(H.get(), ldh, m - 1, theta.get(), 1, s);
+            lam.push_back(ct);
+            resid.push_back(cr);
+            ++nx;
+            --m;
+            if (nx >= k) { need_pcg = false; break; }
+            if (m == 0) {
+                need_pcg = false;
+                random_block();
+                break;
+            }
+        }
+        if (nx >= k) break;
+        if (!need_pcg) continue;
+        // restart before the basis would outgrow m_max
+        if (m + b > mmax) {
+            const int keep = std::max(mmin, bu);
+            Vb = XV.get() + nx;
+            ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, keep, Vb, ldb, nullptr, 0, 1.0, 0.0, s);
+            ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, keep, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
+            jd_hdiag(H.get(), ldh, keep, theta.get(), 0, s);
+            m = keep;
+        }
+        // block PCG on the bu correction equations, Q = [X U]
+        {
+            const int q = nx + bu;
+            auto enqueue = [&]() {
+                bpcg_enqueue<T>(*P, bu, theta.get(), Q.get(), ldq, q, R.get(), b, Tt.get(), pw, rs, bs, o.itmax,
+                                o.rtol_pcg, s);
+            };
+            if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, bu, s, enqueue), s));
+            else enqueue();
+        }
+        pcg_pending = true;
+        pcg_cols = bu;
+        src_is_t = true;
+        src_cols = bu;
+    }
+    if (pcg_pending) {
+        LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+        account_pcg();
+    }
+
+    // ---- output (as the single-vector solver)
+    const int nconv = std::min(nx, k);
+    std::vector<int> order(nconv);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return lam[a] < lam[c]; });
+    std::vector<double> Xh((size_t)n * std::max(nconv, 1));
+    if (nconv > 0) {
+        DevBuf<double> Xc((size_t)n * nconv);
+        blk_extract(n, nconv, XV.get(), ldb, Xc.get(), s);
+        LAP_HIP(hipMemcpyAsync(Xh.data(), Xc.get(), sizeof(double) * n * nconv, hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<double> out((size_t)n * nconv);
+    for (int j = 0; j < nconv; ++j) {
+        const double *x = Xh.data() + (size_t)order[j] * n;
+        double *y = out.data() + (size_t)j * n;
+        for (int i = 0; i < n; ++i) y[i] = x[P->perm[i]];
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::fabs(y[i]) > std::fabs(y[best])) best = i;
+        if (y[best] < 0.0)
+            for (int i = 0; i < n; ++i) y[i] = -y[i];
+        evals[j] = lam[order[j]];
+        if (res_out) res_out[j] = resid[order[j]];
+    }
+    if (evecs && nconv > 0) {
+        if (evecs_on_device)
+            LAP_HIP(hipMemcpyAsync(evecs, out.data(), sizeof(double) * n * nconv, hipMemcpyHostToDevice, s));
+        else
+            std::copy(out.begin(), out.end(), evecs);
+    }
+    LAP_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->nconv = nconv;
+        info->ncomp = P->ncomp;
+        info->outer = it;
+        info->inner = (int)inner;
+        info->mvp = mvp;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return status;
+}
+
+}  // namespace
+
+lap_status jd_block_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                          int evecs_on_device, double *res, lap_eigs_info *info) {
+    if (o.precision == LAP_PREC_MIXED)
+        return jdb_run<float>(P, k, tol, o, evals, evecs, evecs_on_device, res, info);
+    return jdb_run<double>(P, k, tol, o, evals, evecs, evecs_on_device, res, info);
+}
+
+}  // namespace lapeig

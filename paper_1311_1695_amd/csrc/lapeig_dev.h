@@ -126,8 +126,30 @@ __device__ bool grid_reduce(const T (&acc)[NV], int nv, T *partial, unsigned *co
 // and calls f(i, x_i, y_i, q_i) on exactly one lane per row.  Rows are
 // visited workgroup-per-row (huge), wavefront-per-row (long), then
 // lane-per-row inside 64-row slices; the grid strides over the units.
+// Every loop keeps four independent index->gather chains in flight, and the
+// summation order is fixed, so results are reproducible bit for bit.
 // f must not synchronize.
 // ---------------------------------------------------------------------------
+template <typename T, bool WEIGHTED, bool QF>
+__device__ __forceinline__ void edge_terms(const int *__restrict__ col, const T *__restrict__ wt,
+                                           const T *__restrict__ x, T xi, int e, int e1, int stride,
+                                           T &acc, T &aq) {
+    for (; e + 3 * stride < e1; e += 4 * stride) {
+        const int j0 = col[e], j1 = col[e + stride], j2 = col[e + 2 * stride], j3 = col[e + 3 * stride];
+        T w0 = T(1), w1 = T(1), w2 = T(1), w3 = T(1);
+        if (WEIGHTED) { w0 = wt[e]; w1 = wt[e + stride]; w2 = wt[e + 2 * stride]; w3 = wt[e + 3 * stride]; }
+        const T d0 = xi - x[j0], d1 = xi - x[j1], d2 = xi - x[j2], d3 = xi - x[j3];
+        acc += w0 * d0; acc += w1 * d1; acc += w2 * d2; acc += w3 * d3;
+        if (QF) { aq += w0 * d0 * d0; aq += w1 * d1 * d1; aq += w2 * d2 * d2; aq += w3 * d3 * d3; }
+    }
+    for (; e < e1; e += stride) {
+        const T d = xi - x[col[e]];
+        const T w = WEIGHTED ? wt[e] : T(1);
+        acc += w * d;
+        if (QF) aq += w * d * d;
+    }
+}
+
 template <typename T, bool WEIGHTED, bool QF, class F>
 __device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w,
                                              const T *__restrict__ x, F &&f) {
@@ -136,13 +158,8 @@ __device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w
     for (int r = blockIdx.x; r < g.n_huge; r += gridDim.x) {
         const T xi = x[r];
         T acc = T(0), aq = T(0);
-        const int e1 = g.rowptr[r + 1];
-        for (int e = g.rowptr[r] + threadIdx.x; e < e1; e += blockDim.x) {
-            const T d = xi - x[g.col[e]];
-            const T wt = WEIGHTED ? w.csr[e] : T(1);
-            acc += wt * d;
-            if (QF) aq += wt * d * d;
-        }
+        edge_terms<T, WEIGHTED, QF>(g.col, w.csr, x, xi, g.rowptr[r] + threadIdx.x, g.rowptr[r + 1], blockDim.x,
+                                    acc, aq);
         acc = block_sum(acc);
         if (QF) aq = block_sum(aq);
         if (threadIdx.x == 0) f(r, xi, acc, aq);
@@ -154,13 +171,7 @@ __device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w
             const int r = g.n_huge + u;
             const T xi = x[r];
             T acc = T(0), aq = T(0);
-            const int e1 = g.rowptr[r + 1];
-            for (int e = g.rowptr[r] + lane; e < e1; e += kWave) {
-                const T d = xi - x[g.col[e]];
-                const T wt = WEIGHTED ? w.csr[e] : T(1);
-                acc += wt * d;
-                if (QF) aq += wt * d * d;
-            }
+            edge_terms<T, WEIGHTED, QF>(g.col, w.csr, x, xi, g.rowptr[r] + lane, g.rowptr[r + 1], kWave, acc, aq);
             acc = wave_sum(acc);
             if (QF) aq = wave_sum(aq);
             if (lane == 0) f(r, xi, acc, aq);
@@ -169,17 +180,10 @@ __device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w
             const int r = g.n_long + s * kWave + lane;
             if (r < g.n) {
                 const int off = g.sell_off[s];
-                const int width = (g.sell_off[s + 1] - off) >> 6;
+                const int end = g.sell_off[s + 1];
                 const T xi = x[r];
                 T acc = T(0), aq = T(0);
-                const int *cp = g.sell_col + off + lane;
-#pragma unroll 4
-                for (int t = 0; t < width; ++t) {
-                    const T d = xi - x[cp[t * kWave]];
-                    const T wt = WEIGHTED ? w.sell[off + t * kWave + lane] : T(1);
-                    acc += wt * d;
-                    if (QF) aq += wt * d * d;
-                }
+                edge_terms<T, WEIGHTED, QF>(g.sell_col, w.sell, x, xi, off + lane, end, kWave, acc, aq);
                 f(r, xi, acc, aq);
             }
         }

@@ -155,8 +155,8 @@ namespace lapeig {
 
 // ------------------------------------------------------------- plan.cpp
 // Validate (host), renumber, classify rows, build slices, upload.
-void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_threshold = 64,
-                int huge_threshold = 4096);
+void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_threshold = 32,
+                int huge_threshold = 512);
 
 // ------------------------------------------------------------- spmv.hip
 // y = (G - sigma I) x, b = 1, plan order.
@@ -165,6 +165,8 @@ void spmv(const lap_plan &P, const T *x, T *y, double sigma, hipStream_t s);
 // Y = G X - X diag(shift) for n x b row-major blocks, plan order.
 template <typename T>
 void spmm(const lap_plan &P, int b, const T *X, T *Y, const double *shift_dev, hipStream_t s);
+template <typename T>
+void spmm(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, hipStream_t s);
 
 // Reduction scratch: per-block partial sums and a completion counter.
 struct ReduceScratch {

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Graph g, Weights<T> w, const T 
 // one column group.
 template <typename T, bool W, int BL>
 __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
-                                                 const T *__restrict__ X, T *__restrict__ Y,
+                                                 const T *__restrict__ X, int ldx, T *__restrict__ Y, int ldy,
                                                  const double *__restrict__ shift) {
     constexpr int RPW = kWave / BL;  // rows per wavefront in the slice part
     const int lane = lane_id();
@@ -30,11 +30,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
     for (int r = blockIdx.x * kWavesPerBlock + wave_id(); r < nrow_wave;
          r += gridDim.x * kWavesPerBlock) {
         T acc = T(0);
-        T xi = c < b ? X[(size_t)r * b + c] : T(0);
+        T xi = c < b ? X[(size_t)r * ldx + c] : T(0);
         const int e1 = g.rowptr[r + 1];
         for (int e = g.rowptr[r] + sub; e < e1; e += RPW) {
             if (c < b) {
-                const T d = xi - X[(size_t)g.col[e] * b + c];
+                const T d = xi - X[(size_t)g.col[e] * ldx + c];
                 acc += (W ? w.csr[e] : T(1)) * d;
             }
         }
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
         for (int o = BL; o < kWave; o <<= 1) acc += __shfl_xor(acc, o, kWave);
         if (sub == 0 && c < b) {
             const T s = shift ? T(shift[c]) : T(0);
-            Y[(size_t)r * b + c] = acc - s * xi;
+            Y[(size_t)r * ldy + c] = acc - s * xi;
         }
     }
     // slice rows: each slice of 64 rows is handled by 64 / RPW passes
@@ -57,16 +57,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
         if (r < g.n && c < b) {
             const int off = g.sell_off[s];
             const int width = (g.sell_off[s + 1] - off) >> 6;
-            const T xi = X[(size_t)r * b + c];
+            const T xi = X[(size_t)r * ldx + c];
             T acc = T(0);
 #pragma unroll 4
             for (int t = 0; t < width; ++t) {
                 const int at = off + t * kWave + l;
-                const T d = xi - X[(size_t)g.sell_col[at] * b + c];
+                const T d = xi - X[(size_t)g.sell_col[at] * ldx + c];
                 acc += (W ? w.sell[at] : T(1)) * d;
             }
             const T sh = shift ? T(shift[c]) : T(0);
-            Y[(size_t)r * b + c] = acc - sh * xi;
+            Y[(size_t)r * ldy + c] = acc - sh * xi;
         }
     }
 }
@@ -97,7 +97,8 @@ void spmv(const lap_plan &P, const T *x, T *y, double sigma, hipStream_t s) {
 }
 
 template <typename T, int BL>
-static void spmm_launch(const lap_plan &P, int b, const T *X, T *Y, const double *shift, hipStream_t s) {
+static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
+                        hipStream_t s) {
     const Graph &g = P.g;
     long long units = (long long)g.nslices * BL;
     if (g.n_long > units) units = g.n_long;
@@ -106,22 +107,27 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, T *Y, const double
     if (grid > (1 << 20)) grid = 1 << 20;
     if (P.weighted)
         hipLaunchKernelGGL((k_spmm<T, true, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
-                           Y, shift);
+                           ldx, Y, ldy, shift);
     else
         hipLaunchKernelGGL((k_spmm<T, false, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
-                           Y, shift);
+                           ldx, Y, ldy, shift);
     LAP_HIP(hipGetLastError());
 }
 
 template <typename T>
+void spmm(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, hipStream_t s) {
+    if (b <= 1) spmm_launch<T, 1>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    else if (b <= 2) spmm_launch<T, 2>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    else if (b <= 4) spmm_launch<T, 4>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    else if (b <= 8) spmm_launch<T, 8>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    else if (b <= 16) spmm_launch<T, 16>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    else if (b <= 32) spmm_launch<T, 32>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    else spmm_launch<T, 64>(P, b, X, ldx, Y, ldy, shift_dev, s);
+}
+
+template <typename T>
 void spmm(const lap_plan &P, int b, const T *X, T *Y, const double *shift_dev, hipStream_t s) {
-    if (b <= 1) spmm_launch<T, 1>(P, b, X, Y, shift_dev, s);
-    else if (b <= 2) spmm_launch<T, 2>(P, b, X, Y, shift_dev, s);
-    else if (b <= 4) spmm_launch<T, 4>(P, b, X, Y, shift_dev, s);
-    else if (b <= 8) spmm_launch<T, 8>(P, b, X, Y, shift_dev, s);
-    else if (b <= 16) spmm_launch<T, 16>(P, b, X, Y, shift_dev, s);
-    else if (b <= 32) spmm_launch<T, 32>(P, b, X, Y, shift_dev, s);
-    else spmm_launch<T, 64>(P, b, X, Y, shift_dev, s);
+    spmm<T>(P, b, X, b, Y, b, shift_dev, s);
 }
 
 template <typename T>
@@ -137,6 +143,8 @@ template void spmv<float>(const lap_plan &, const float *, float *, double, hipS
 template void spmv<double>(const lap_plan &, const double *, double *, double, hipStream_t);
 template void spmm<float>(const lap_plan &, int, const float *, float *, const double *, hipStream_t);
 template void spmm<double>(const lap_plan &, int, const double *, double *, const double *, hipStream_t);
+template void spmm<float>(const lap_plan &, int, const float *, int, float *, int, const double *, hipStream_t);
+template void spmm<double>(const lap_plan &, int, const double *, int, double *, int, const double *, hipStream_t);
 template void permute_rows<float>(const int *, int, int, const float *, float *, hipStream_t);
 template void permute_rows<double>(const int *, int, int, const double *, double *, hipStream_t);
 

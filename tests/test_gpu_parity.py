@@ -357,3 +357,50 @@ def test_eigs_graph_replay_matches_eager_launches(monkeypatch):
     c = lap.lap_eigs(plan, 8, 1e-8, precision="mixed")
     assert np.array_equal(a.evals, b.evals) and np.array_equal(a.evecs, b.evecs)
     assert np.array_equal(a.evals, c.evals) and a.mvp == b.mvp == c.mvp
+
+
+# ---------------------------------------------------------------------------
+# Block Jacobi-Davidson (b corrections per outer iteration, MFMA products)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_eigs_block_pa5k_vs_dense(precision):
+    L = graph("pa5k")
+    plan = lap.Plan(L)
+    r = lap.lap_eigs(plan, 10, 1e-8, precision=precision, block=4, m_min=8, m_max=24, kmax=400)
+    assert r.nconv == 10
+    _certified(L, r, 1e-8)
+    w, V = dense_ref("pa5k")
+    check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
+
+
+@pytest.mark.parametrize("b", [3, 8])
+def test_eigs_block_cl30k_vs_oracle(b):
+    L = graph("cl30k")
+    plan = lap.Plan(L)
+    r = lap.lap_eigs(plan, 10, 1e-8, precision="mixed", block=b, m_min=max(b, 6), m_max=max(b, 6) + 2 * b + 4,
+                     kmax=400)
+    assert r.nconv == 10
+    _certified(L, r, 1e-8)
+    w, V = oracle_ref("cl30k", 14)
+    check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
+
+
+def test_eigs_block_zero_space_and_weighted():
+    G = graph("mixed_union")
+    r = lap.lap_eigs_csr(G, 7, 1e-10, block=3, m_min=6, m_max=15, kmax=400)
+    assert r.ncomp == 4 and np.all(r.evals[:4] == 0.0)
+    w, V = dense_ref("mixed_union")
+    check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
+    L = graph("cl30k_w")
+    r = lap.lap_eigs_csr(L, 6, 1e-8, block=4, m_min=8, m_max=20, kmax=400)
+    _certified(L, r, 1e-8)
+    w2, V2 = oracle_ref("cl30k_w", 12)
+    check_against_reference(r.evals, r.evecs, w2, V2, val_rtol=1e-8, angle_tol=1e-6)
+
+
+def test_eigs_block_rejects_bad_sizes():
+    plan = lap.Plan(graph("pa5k"))
+    with pytest.raises(lap.LapError) as e:
+        lap.lap_eigs(plan, 10, 1e-8, block=8, m_min=5, m_max=10)
+    assert e.value.code == lap.LAP_EINVAL
