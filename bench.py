@@ -106,6 +106,47 @@ def cpu_baseline(L, k, tol, budget_s=12.0):
     return statistics.median(times), len(times), res
 
 
+def certify(L, r, tol):
+    """Largest relative residual ||Gx - lx|| / min(l, 1) over the non-zero pairs,
+    recomputed on the host in FP64."""
+    import numpy as np
+    G = L.to_scipy()
+    res = np.linalg.norm(G @ r.evecs - r.evecs * r.evals, axis=0)
+    pos = r.evals > 0
+    return float(np.max(res[pos] / np.minimum(r.evals[pos], 1.0))) if pos.any() else 0.0
+
+
+def extra_configs(lap, torch, gg, np, reps=3):
+    """The other workloads: plain FP64 JD on the preferential-attachment
+    graph (n = 5000, k = 10) and block JD (b = 20) on the Chung-Lu
+    exponent-2.1 graph (n = 330,000, k = 20), mixed and FP64."""
+    out = []
+    runs = [
+        ("pa5k", 10, 1e-8, [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed"))]),
+        ("cl330k", 20, 1e-8, [("mixed_block20", dict(precision="mixed", block=20, m_min=20, m_max=60)),
+                              ("fp64_block20", dict(precision="fp64", block=20, m_min=20, m_max=60)),
+                              ("mixed_single", dict(precision="mixed", m_min=5, m_max=10))]),
+    ]
+    for name, k, tol, variants in runs:
+        L = gg.workload(name, SEED)
+        plan = lap.Plan(L)
+        entry = {"workload": name, "n": L.n, "nnz": L.nnz, "k": k, "tol": tol, "runs": {}}
+        for label, kw in variants:
+            r = lap.lap_eigs(plan, k, tol, seed=1, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = lap.lap_eigs(plan, k, tol, seed=1, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            entry["runs"][label] = {"s": round(dt, 5), "mvp": r.mvp, "outer": r.outer, "inner": r.inner,
+                                    "nconv": r.nconv, "max_rel_residual": certify(L, r, tol),
+                                    "lambda2": float(r.evals[1]), "lambda_k": float(r.evals[-1])}
+        plan.close()
+        out.append(entry)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +155,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time the SpMV on larger graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--spmv-only", action="store_true", help="only the product kernel loop (for profiling)")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the other workloads (pa5k FP64; cl330k block JD)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build",
@@ -213,6 +256,8 @@ def main():
                           "GB/s": round(ab / tb / 1e9, 1), "frac": round(ab / tb / 1e9 / HBM_PEAK_GBS, 4)})
             pb.close()
         out["spmv_sweep"] = sweep
+    if args.extra:
+        out["configs"] = extra_configs(lap, torch, gg, np)
     if not args.no_cpu:
         t_cpu, reps, cres = cpu_baseline(L, K_PAIRS, TOL)
         out["cpu_baseline"] = {"value": round(t_cpu, 4), "unit": "s", "cores": 1, "kind": "oracle",

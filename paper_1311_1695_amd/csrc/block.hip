@@ -349,13 +349,6 @@ __global__ void k_random_block(int n, int b, unsigned long long seed, long long 
 // projector Q (row-major, q columns, type T).  Per-column state; a column
 // stops on its own (tolerance or breakdown) and is masked afterwards.
 
-template <typename T>
-__device__ __forceinline__ T qrow_dot(const T *__restrict__ qi, const T *__restrict__ C, int q, int c) {
-    T s = T(0);
-    for (int j = 0; j < q; ++j) s += qi[j] * C[j + (size_t)c * q];
-    return s;
-}
-
 // init 1: Res = -R (convert), T = 0; ||r_c||
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bpcg_init1(int n, int b, const double *__restrict__ R, int ldr,
@@ -455,15 +448,13 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_pap(int n, int b, const T *__re
     }
 }
 
-// update: X += alpha P;  Res -= alpha (S - Q C2);  Y = D^{-1} Res;
+// update: X += alpha P;  Res -= alpha Z  (Z = (I - QQ')S);  Y = D^{-1} Res;
 // ||Res_c||, rho'_c;  beta, stop test
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bpcg_update(int n, int b, T *__restrict__ X, T *__restrict__ Res,
-                                                        const T *__restrict__ P, const T *__restrict__ S,
-                                                        T *__restrict__ Y, const T *__restrict__ dinv,
-                                                        const T *__restrict__ Q, int ldq, int q,
-                                                        const T *__restrict__ C2, T *partial, unsigned *counter,
-                                                        BPcgState<T> *st, int it, T rtol) {
+                                                        const T *__restrict__ P, const T *__restrict__ Z,
+                                                        T *__restrict__ Y, const T *__restrict__ dinv, T *partial,
+                                                        unsigned *counter, BPcgState<T> *st, int it, T rtol) {
     if (st->nactive == 0) return;
     __shared__ T al[32];
     __shared__ int act[32], cp[32];
@@ -477,7 +468,6 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_update(int n, int b, T *__restr
 #pragma unroll
     for (int j = 0; j < 64; ++j) acc[j] = T(0);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const T *qi = Q + (size_t)i * ldq;
         const T d = dinv[i];
 #pragma unroll
         for (int c = 0; c < 32; ++c) {
@@ -486,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_update(int n, int b, T *__restr
                 if (cp[c]) X[at] = P[at];  // no step taken before the breakdown: M(-r)
                 if (act[c]) {
                     X[at] += al[c] * P[at];
-                    const T r = Res[at] - al[c] * (S[at] - qrow_dot(qi, C2, q, c));
+                    const T r = Res[at] - al[c] * Z[at];
                     Res[at] = r;
                     const T y = d * r;
                     Y[at] = y;
@@ -514,18 +504,22 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_update(int n, int b, T *__restr
     }
 }
 
-// P = (Y - Q C1) + beta P  (active columns; init: beta = 0)
+// P = Z + beta P  (Z = (I - QQ')Y; active columns; init: P = Z)
 template <typename T, bool INIT>
-__global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__restrict__ Y, T *__restrict__ P,
-                                                   const T *__restrict__ Q, int ldq, int q, const T *__restrict__ C1,
+__global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__restrict__ Z, T *__restrict__ P,
                                                    const BPcgState<T> *st) {
     if (st->nactive == 0) return;
+    __shared__ T be[32];
+    __shared__ int act[32];
+    for (int c = threadIdx.x; c < b; c += blockDim.x) {
+        be[c] = st->beta[c];
+        act[c] = st->active[c];
+    }
+    __syncthreads();
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < (size_t)n * b; t += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = t / b;
         const int c = (int)(t % b);
-        if (!st->active[c]) continue;
-        const T z = Y[t] - qrow_dot(Q + i * ldq, C1, q, c);
-        P[t] = INIT ? z : z + st->beta[c] * P[t];
+        if (!act[c]) continue;
+        P[t] = INIT ? Z[t] : Z[t] + be[c] * P[t];
     }
 }
 
@@ -647,6 +641,8 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
     const T *dinv = P.dinv<T>();
     T *C = w.C.get();  // q x b column-major coefficients
     hipLaunchKernelGGL((k_bpcg_init1<T>), dim3(gv), dim3(kBlock), 0, s, n, b, R, ldr, w.res.get(), X, part, cnt, st);
+    T *Z = w.z.get();
+    const int gp = bgrid((size_t)n * b);
     // Res <- (I - QQ')Res
     if (q > 0) {
         ts_tn<T>(n, Q, ldq, q, w.res.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
@@ -654,19 +650,35 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
     }
     hipLaunchKernelGGL((k_bpcg_init2<T>), dim3(gv), dim3(kBlock), 0, s, n, b, w.res.get(), w.y.get(), dinv, part, cnt,
                        st);
-    if (q > 0) ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
-    hipLaunchKernelGGL((k_bpcg_p<T, true>), dim3(bgrid((size_t)n * b)), dim3(kBlock), 0, s, n, b, w.y.get(), w.p.get(),
-                       Q, ldq, q, C, st);
+    // P = (I - QQ') Y
+    const T *Zy = w.y.get();
+    if (q > 0) {
+        ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
+        ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.y.get(), b, T(-1), T(0), s);
+        Zy = Z;
+    }
+    hipLaunchKernelGGL((k_bpcg_p<T, true>), dim3(gp), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
     for (int it = 1; it <= itmax; ++it) {
+        // S = G P - P diag(theta);  Z = (I - QQ') S
         spmm<T>(P, b, w.p.get(), b, w.s.get(), b, theta_dev, s);
-        if (q > 0) ts_tn<T>(n, Q, ldq, q, w.s.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
+        const T *Zs = w.s.get();
+        if (q > 0) {
+            ts_tn<T>(n, Q, ldq, q, w.s.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
+            ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.s.get(), b, T(-1), T(0), s);
+            Zs = Z;
+        }
         hipLaunchKernelGGL((k_bpcg_pap<T>), dim3(gv), dim3(kBlock), 0, s, n, b, w.p.get(), w.s.get(), part, cnt, st, it);
-        hipLaunchKernelGGL((k_bpcg_update<T>), dim3(gv), dim3(kBlock), 0, s, n, b, X, w.res.get(), w.p.get(), w.s.get(),
-                           w.y.get(), dinv, Q, ldq, q, C, part, cnt, st, it, (T)rtol);
+        hipLaunchKernelGGL((k_bpcg_update<T>), dim3(gv), dim3(kBlock), 0, s, n, b, X, w.res.get(), w.p.get(), Zs,
+                           w.y.get(), dinv, part, cnt, st, it, (T)rtol);
         if (it == itmax) break;
-        if (q > 0) ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
-        hipLaunchKernelGGL((k_bpcg_p<T, false>), dim3(bgrid((size_t)n * b)), dim3(kBlock), 0, s, n, b, w.y.get(),
-                           w.p.get(), Q, ldq, q, C, st);
+        // P = (I - QQ') Y + beta P
+        Zy = w.y.get();
+        if (q > 0) {
+            ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
+            ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.y.get(), b, T(-1), T(0), s);
+            Zy = Z;
+        }
+        hipLaunchKernelGGL((k_bpcg_p<T, false>), dim3(gp), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
     }
     hipLaunchKernelGGL((k_bpcg_count<T>), dim3(1), dim3(64), 0, s, b, st);
     LAP_HIP(hipGetLastError());

@@ -33,11 +33,12 @@ struct BPcgState {
 
 template <typename T>
 struct BPcgWork {
-    DevBuf<T> res, p, s, y, C;
+    DevBuf<T> res, p, s, y, z, C;
     DevBuf<BPcgState<T>> st;
     void ensure(int n, int b, int qmax) {
         if (res.get()) return;
         res.alloc((size_t)n * b); p.alloc((size_t)n * b); s.alloc((size_t)n * b); y.alloc((size_t)n * b);
+        z.alloc((size_t)n * b);
         C.alloc((size_t)(qmax + 1) * b);
         st.alloc(1);
     }

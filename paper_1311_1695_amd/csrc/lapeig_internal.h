@@ -89,10 +89,15 @@ struct DevBuf {
 };
 
 // ------------------------------------------------------------ the graph
+constexpr int kChunk = 64;   // edges per chunk of a long row in the block product
+
 struct Graph {
     int n = 0;
     int n_huge = 0, n_long = 0;   // row-class boundaries (plan order)
     int nslices = 0;              // 64-row slices covering [n_long, n)
+    int nchunks = 0;              // kChunk-edge chunks of the rows [0, n_long)
+    const int *chunk_row = nullptr;  // row of each chunk
+    const int *chunk_off = nullptr;  // first chunk of each long row (n_long + 1)
     const int *rowptr = nullptr;  // CSR of A, plan order, n + 1
     const int *col = nullptr;
     const int *sell_off = nullptr;  // nslices + 1 offsets into sell_col
@@ -124,13 +129,14 @@ struct lap_plan {
     int max_degree = 0;
 
     lapeig::DevBuf<int> d_perm, d_iperm, d_comp;
-    lapeig::DevBuf<int> d_rowptr, d_col, d_sell_off, d_sell_col;
+    lapeig::DevBuf<int> d_rowptr, d_col, d_sell_off, d_sell_col, d_chunk_row, d_chunk_off;
     lapeig::DevBuf<float> d_w32, d_sellw32, d_dinv32;
     lapeig::DevBuf<double> d_w64, d_sellw64, d_dinv64;
     lapeig::Graph g;
     // scratch of the building-block entry points
     lapeig::DevBuf<double> d_shift;
     lapeig::DevBuf<char> tmp_x, tmp_y;
+    lapeig::DevBuf<char> chunk_part;  // per-chunk partial sums of the block product
 
     template <typename T>
     lapeig::Weights<T> weights() const;

@@ -157,6 +157,15 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
         }
     }
 
+    // long rows in chunks of kChunk edges (the block product splits them)
+    std::vector<int> coff(n_long + 1, 0), crow;
+    for (int r = 0; r < n_long; ++r) {
+        const int d = prow[r + 1] - prow[r];
+        const int nc = (d + kChunk - 1) / kChunk;
+        coff[r + 1] = coff[r] + nc;
+        for (int c = 0; c < nc; ++c) crow.push_back(r);
+    }
+
     // connected components (plan order), breadth-first
     std::vector<int> comp(n, -1), queue(n);
     int ncomp = 0;
@@ -205,6 +214,8 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
     upload(P->d_col, pcol);
     upload(P->d_sell_off, soff);
     upload(P->d_sell_col, scol);
+    upload(P->d_chunk_off, coff);
+    upload(P->d_chunk_row, crow);
     upload(P->d_dinv64, dinv);
     std::vector<float> dinv32(dinv.begin(), dinv.end());
     upload(P->d_dinv32, dinv32);
@@ -223,6 +234,11 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
     P->g.col = P->d_col.get();
     P->g.sell_off = P->d_sell_off.get();
     P->g.sell_col = P->d_sell_col.get();
+    P->g.nchunks = (int)crow.size();
+    // partial sums of chunked rows for block products of up to 64 double columns
+    P->chunk_part.alloc(std::max<size_t>(crow.size(), 1) * 64 * sizeof(double));
+    P->g.chunk_row = P->d_chunk_row.get();
+    P->g.chunk_off = P->d_chunk_off.get();
 }
 
 int device_cu_count() {

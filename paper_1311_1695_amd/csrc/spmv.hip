@@ -12,62 +12,107 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Graph g, Weights<T> w, const T 
     for_each_row<T, W, false>(g, w, x, [&](int i, T xi, T yi, T) { y[i] = yi - sigma * xi; });
 }
 
-// Block product, n x b row-major.  One lane per (row, column) for slice rows:
-// a wavefront handles 64 / BL rows with BL lanes each (BL >= b columns, a power
-// of two), so a neighbour gather reads b contiguous values.  Long and huge
-// rows: a wavefront (or workgroup) per row, each lane striding the row for
-// one column group.
+// Block product, n x b row-major (leading dimensions ldx, ldy).  A lane owns
+// one column c < BL of one row slot; a gather of neighbour j reads the b
+// contiguous values X[j, 0..b).
+//   long rows (degree > the long threshold): split into kChunk-edge chunks,
+//     one wavefront per chunk with 64 / BL edge slots; a row of one chunk is
+//     written directly, longer rows leave per-chunk partial sums that
+//     k_spmm_combine adds in chunk order (deterministic);
+//   slice rows: 64 / BL rows per wavefront pass, one lane per (row, column).
 template <typename T, bool W, int BL>
 __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
                                                  const T *__restrict__ X, int ldx, T *__restrict__ Y, int ldy,
-                                                 const double *__restrict__ shift) {
-    constexpr int RPW = kWave / BL;  // rows per wavefront in the slice part
+                                                 const double *__restrict__ shift, T *__restrict__ part) {
+    constexpr int RPW = kWave / BL;  // row (or edge) slots per wavefront
     const int lane = lane_id();
-    const int c = lane % BL;         // column of this lane
-    const int sub = lane / BL;       // row slot within the wavefront
-    // long and huge rows: wavefront per row, lanes (sub) stride edges, c columns
-    const int nrow_wave = g.n_long;
-    for (int r = blockIdx.x * kWavesPerBlock + wave_id(); r < nrow_wave;
-         r += gridDim.x * kWavesPerBlock) {
+    const int c = lane % BL;
+    const int sub = lane / BL;
+    const int gw = blockIdx.x * kWavesPerBlock + wave_id();
+    const int nw = gridDim.x * kWavesPerBlock;
+    for (int u = gw; u < g.nchunks; u += nw) {
+        const int r = g.chunk_row[u];
+        const int first = g.chunk_off[r];
+        const int nch = g.chunk_off[r + 1] - first;
+        const int e0 = g.rowptr[r] + (u - first) * kChunk;
+        const int e1 = min(e0 + kChunk, g.rowptr[r + 1]);
         T acc = T(0);
-        T xi = c < b ? X[(size_t)r * ldx + c] : T(0);
-        const int e1 = g.rowptr[r + 1];
-        for (int e = g.rowptr[r] + sub; e < e1; e += RPW) {
-            if (c < b) {
-                const T d = xi - X[(size_t)g.col[e] * ldx + c];
-                acc += (W ? w.csr[e] : T(1)) * d;
+        const T xi = c < b ? X[(size_t)r * ldx + c] : T(0);
+        if (c < b) {
+            int e = e0 + sub;
+            for (; e + 3 * RPW < e1; e += 4 * RPW) {
+                const int j0 = g.col[e], j1 = g.col[e + RPW], j2 = g.col[e + 2 * RPW], j3 = g.col[e + 3 * RPW];
+                const T d0 = xi - X[(size_t)j0 * ldx + c], d1 = xi - X[(size_t)j1 * ldx + c];
+                const T d2 = xi - X[(size_t)j2 * ldx + c], d3 = xi - X[(size_t)j3 * ldx + c];
+                if (W) {
+                    acc += w.csr[e] * d0; acc += w.csr[e + RPW] * d1;
+                    acc += w.csr[e + 2 * RPW] * d2; acc += w.csr[e + 3 * RPW] * d3;
+                } else {
+                    acc += d0; acc += d1; acc += d2; acc += d3;
+                }
             }
+            for (; e < e1; e += RPW) acc += (W ? w.csr[e] : T(1)) * (xi - X[(size_t)g.col[e] * ldx + c]);
         }
-        // reduce over the RPW row slots holding the same column
 #pragma unroll
         for (int o = BL; o < kWave; o <<= 1) acc += __shfl_xor(acc, o, kWave);
         if (sub == 0 && c < b) {
-            const T s = shift ? T(shift[c]) : T(0);
-            Y[(size_t)r * ldy + c] = acc - s * xi;
+            if (nch == 1) {
+                const T sh = shift ? T(shift[c]) : T(0);
+                Y[(size_t)r * ldy + c] = acc - sh * xi;
+            } else {
+                part[(size_t)u * b + c] = acc;
+            }
         }
     }
-    // slice rows: each slice of 64 rows is handled by 64 / RPW passes
-    const int nslices = g.nslices;
-    const int units = nslices * BL;  // (slice, group of RPW rows)
-    for (int u = blockIdx.x * kWavesPerBlock + wave_id(); u < units; u += gridDim.x * kWavesPerBlock) {
+    const int units = g.nslices * BL;  // (slice, group of RPW rows)
+    for (int u = gw; u < units; u += nw) {
         const int s = u / BL;
         const int grp = u % BL;
-        const int l = grp * RPW + sub;  // lane of the slice this row occupies
+        const int l = grp * RPW + sub;
         const int r = g.n_long + s * kWave + l;
         if (r < g.n && c < b) {
             const int off = g.sell_off[s];
             const int width = (g.sell_off[s + 1] - off) >> 6;
             const T xi = X[(size_t)r * ldx + c];
             T acc = T(0);
-#pragma unroll 4
-            for (int t = 0; t < width; ++t) {
+            int t = 0;
+            for (; t + 3 < width; t += 4) {
+                const int a0 = off + t * kWave + l;
+                const int j0 = g.sell_col[a0], j1 = g.sell_col[a0 + kWave], j2 = g.sell_col[a0 + 2 * kWave],
+                          j3 = g.sell_col[a0 + 3 * kWave];
+                const T d0 = xi - X[(size_t)j0 * ldx + c], d1 = xi - X[(size_t)j1 * ldx + c];
+                const T d2 = xi - X[(size_t)j2 * ldx + c], d3 = xi - X[(size_t)j3 * ldx + c];
+                if (W) {
+                    acc += w.sell[a0] * d0; acc += w.sell[a0 + kWave] * d1;
+                    acc += w.sell[a0 + 2 * kWave] * d2; acc += w.sell[a0 + 3 * kWave] * d3;
+                } else {
+                    acc += d0; acc += d1; acc += d2; acc += d3;
+                }
+            }
+            for (; t < width; ++t) {
                 const int at = off + t * kWave + l;
-                const T d = xi - X[(size_t)g.sell_col[at] * ldx + c];
-                acc += (W ? w.sell[at] : T(1)) * d;
+                acc += (W ? w.sell[at] : T(1)) * (xi - X[(size_t)g.sell_col[at] * ldx + c]);
             }
             const T sh = shift ? T(shift[c]) : T(0);
             Y[(size_t)r * ldy + c] = acc - sh * xi;
         }
+    }
+}
+
+// rows split into several chunks: Y = sum of the chunk partials (in chunk
+// order) - shift * x
+template <typename T>
+__global__ void k_spmm_combine(Graph g, int b, const T *__restrict__ X, int ldx, T *__restrict__ Y, int ldy,
+                               const double *__restrict__ shift, const T *__restrict__ part) {
+    const size_t total = (size_t)g.n_long * b;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(t / b), c = (int)(t % b);
+        const int first = g.chunk_off[r], last = g.chunk_off[r + 1];
+        if (last - first < 2) continue;
+        T acc = T(0);
+        for (int u = first; u < last; ++u) acc += part[(size_t)u * b + c];
+        const T sh = shift ? T(shift[c]) : T(0);
+        Y[(size_t)r * ldy + c] = acc - sh * X[(size_t)r * ldx + c];
     }
 }
 
@@ -101,16 +146,28 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
                         hipStream_t s) {
     const Graph &g = P.g;
     long long units = (long long)g.nslices * BL;
-    if (g.n_long > units) units = g.n_long;
+    if (g.nchunks > units) units = g.nchunks;
     int grid = (int)((units + kWavesPerBlock - 1) / kWavesPerBlock);
     if (grid < 1) grid = 1;
     if (grid > (1 << 20)) grid = 1 << 20;
+    T *part = nullptr;
+    if (g.nchunks > 0) {
+        const size_t bytes = (size_t)g.nchunks * b * sizeof(T);
+        lap_plan &mp = const_cast<lap_plan &>(P);
+        LAP_REQUIRE(mp.chunk_part.n >= bytes, LAP_EDEVICE, "block-product scratch not reserved");
+        part = reinterpret_cast<T *>(mp.chunk_part.get());
+    }
     if (P.weighted)
-        hipLaunchKernelGGL((k_spmm<T, true, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
-                           ldx, Y, ldy, shift);
+        hipLaunchKernelGGL((k_spmm<T, true, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx, Y,
+                           ldy, shift, part);
     else
-        hipLaunchKernelGGL((k_spmm<T, false, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
-                           ldx, Y, ldy, shift);
+        hipLaunchKernelGGL((k_spmm<T, false, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx, Y,
+                           ldy, shift, part);
+    if (g.n_long > 0) {
+        const size_t tot = (size_t)g.n_long * b;
+        int cg = (int)std::min<size_t>((tot + kBlock - 1) / kBlock, 4096);
+        hipLaunchKernelGGL((k_spmm_combine<T>), dim3(cg), dim3(kBlock), 0, s, g, b, X, ldx, Y, ldy, shift, part);
+    }
     LAP_HIP(hipGetLastError());
 }
 
