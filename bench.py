@@ -144,6 +144,22 @@ def extra_configs(lap, torch, gg, np, reps=3):
                                     "lambda2": float(r.evals[1]), "lambda_k": float(r.evals[-1])}
         plan.close()
         out.append(entry)
+    # a batch of 256 uneven preferential-attachment graphs, 5 pairs each, one launch
+    graphs = gg.pa_batch(256, SEED)
+    b = lap.lap_batch_create(graphs)
+    entry = {"workload": "pa_batch256", "graphs": len(graphs), "sum_n": sum(g.n for g in graphs),
+             "sum_nnz": sum(g.nnz for g in graphs), "k": 5, "tol": 1e-8, "runs": {}}
+    for label, prec in (("mixed", "mixed"), ("fp64", "fp64")):
+        lap.lap_batch_eigs(b, 5, 1e-8, precision=prec)
+        t0 = time.perf_counter()
+        res = lap.lap_batch_eigs(b, 5, 1e-8, precision=prec)
+        dt = time.perf_counter() - t0
+        worst = max(certify(L, r, 1e-8) for L, r in zip(graphs[:16], res[:16]))
+        entry["runs"][label] = {"s": round(dt, 4), "mvp_total": int(sum(r.mvp for r in res)),
+                                "nconv_min": int(min(r.nconv for r in res)),
+                                "max_rel_residual_first16": worst}
+    b.close()
+    out.append(entry)
     return out
 
 

@@ -171,6 +171,32 @@ lap_status lap_pcg(lap_plan *plan, lap_dtype dtype, int b, const double *theta,
                    const double *Q, int q, const double *R, double *T, int itmax,
                    double rtol, int *iters_out, int flags, void *stream);
 
+/* Many independent graphs at once (the batched form of Algorithm 2): one
+ * persistent launch, captured in a hipGraph, in which each 512-thread
+ * workgroup runs the whole single-vector solver for one graph with all its
+ * reductions in LDS, taking graphs largest first from a device queue.
+ * Each graph is validated as in lap_plan_create and must be connected
+ * (LAP_EUNSUPPORTED otherwise); 1 <= k <= 8, m_max <= 16, block = 1.
+ * lap_batch_create validates, renumbers and uploads the graphs (host
+ * arrays); the handle owns the device copies.  lap_batch_eigs solves all
+ * graphs for the k smallest pairs each:
+ *   evals: host, nb x k (graph g's values at g*k, ascending);
+ *   evecs: host or NULL, graph g's n_g x k column-major block at offset
+ *          k * (n_0 + ... + n_{g-1}), in the caller's vertex order;
+ *   res:   host or NULL, nb x k certified residual norms;
+ *   infos: host or NULL, nb entries.
+ * Pairs a graph did not certify within kmax are NaN (evals, res) and zero
+ * vectors; the call then returns LAP_ENOCONV.  Synchronizes before it
+ * returns. */
+typedef struct lap_batch lap_batch;
+lap_status lap_batch_create(const lap_csr *Ls, int nb, lap_batch **out);
+void lap_batch_destroy(lap_batch *batch);
+int32_t lap_batch_total_n(const lap_batch *batch);
+lap_status lap_batch_eigs(lap_batch *batch, int k, double tol, const lap_eigs_opts *opts, double *evals,
+                          double *evecs, double *res, lap_eigs_info *infos, void *stream);
+lap_status lap_eigs_batch(const lap_csr *Ls, int nb, int k, double tol, const lap_eigs_opts *opts,
+                          double *evals, double *evecs, double *res, lap_eigs_info *infos, void *stream);
+
 const char *lap_status_string(lap_status s);
 const char *lap_last_error(void);
 

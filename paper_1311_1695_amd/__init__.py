@@ -25,8 +25,9 @@ import os
 
 import numpy as np
 
-__all__ = ["LapError", "Plan", "EigResult", "lap_plan_create", "lap_eigs", "lap_eigs_csr", "lap_spmv",
-           "lap_orth", "lap_pcg", "library_path", "load_library", "LAP_PREC_FP64", "LAP_PREC_MIXED"]
+__all__ = ["LapError", "Plan", "Batch", "EigResult", "lap_plan_create", "lap_eigs", "lap_eigs_csr", "lap_spmv",
+           "lap_orth", "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "library_path",
+           "load_library", "LAP_PREC_FP64", "LAP_PREC_MIXED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblapeig.so")
@@ -38,8 +39,9 @@ LAP_PREC_FP64, LAP_PREC_MIXED = 0, 1
 LAP_ORDER_PLAN = 1
 
 EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
-            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg", "lap_status_string",
-            "lap_last_error"]
+            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg", "lap_batch_create",
+            "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
+            "lap_status_string", "lap_last_error"]
 
 
 class LapError(RuntimeError):
@@ -94,11 +96,20 @@ def load_library():
     lib.lap_orth.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, ip, vp]
     lib.lap_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, f64p, vp, ctypes.c_int, vp, vp, ctypes.c_int,
                             ctypes.c_double, ip, ctypes.c_int, vp]
+    lib.lap_batch_create.argtypes = [P(_Csr), ctypes.c_int, P(vp)]
+    lib.lap_batch_destroy.argtypes = [vp]
+    lib.lap_batch_destroy.restype = None
+    lib.lap_batch_total_n.argtypes = [vp]
+    lib.lap_batch_total_n.restype = ctypes.c_int32
+    lib.lap_batch_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info), vp]
+    lib.lap_eigs_batch.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p,
+                                   f64p, P(_Info), vp]
     lib.lap_status_string.argtypes = [ctypes.c_int]
     lib.lap_status_string.restype = ctypes.c_char_p
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
-    for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg"]:
+    for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg",
+                 "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -283,3 +294,71 @@ def lap_pcg(plan: Plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_o
                        its.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), LAP_ORDER_PLAN if plan_order else 0,
                        _stream_handle(stream)))
     return its
+
+
+class Batch:
+    """Many connected graphs resident on the device for lap_batch_eigs."""
+
+    def __init__(self, graphs):
+        lib = load_library()
+        self._keep = []
+        arr = (_Csr * len(graphs))()
+        for g, L in enumerate(graphs):
+            st, keep = _csr_struct(L)
+            arr[g] = st
+            self._keep.append(keep)
+        self._arr = arr
+        self.ns = [int(L.n) for L in graphs]
+        h = ctypes.c_void_p()
+        _check(lib.lap_batch_create(arr, len(graphs), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().lap_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lap_batch_create(graphs) -> Batch:
+    return Batch(graphs)
+
+
+def lap_batch_eigs(batch: Batch, k: int, tol: float, *, allow_noconv=False, stream=None, **kw):
+    """The k smallest pairs of every graph of the batch; returns a list of
+    EigResult (evecs as numpy n x k arrays in each graph's vertex order)."""
+    lib = load_library()
+    o, keep = _opts(**kw)
+    nb = len(batch.ns)
+    ev = np.zeros(nb * k)
+    res = np.zeros(nb * k)
+    X = np.zeros(k * sum(batch.ns))
+    infos = (_Info * nb)()
+    code = lib.lap_batch_eigs(batch._h, int(k), float(tol), ctypes.byref(o),
+                              ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), infos, _stream_handle(stream))
+    if code != LAP_OK and not (allow_noconv and code == LAP_ENOCONV):
+        _check(code)
+    out, off = [], 0
+    for g, n in enumerate(batch.ns):
+        inf = infos[g]
+        nc = inf.nconv
+        blk = X[off:off + n * k].reshape(k, n).T
+        out.append(EigResult(ev[g * k:g * k + nc].copy(), blk[:, :nc].copy(), res[g * k:g * k + nc].copy(), nc,
+                             inf.ncomp, inf.outer, inf.inner, int(inf.mvp), inf.seconds, code))
+        off += n * k
+    return out
+
+
+def lap_eigs_batch(graphs, k, tol, **kw):
+    b = Batch(graphs)
+    try:
+        return lap_batch_eigs(b, k, tol, **kw)
+    finally:
+        b.close()

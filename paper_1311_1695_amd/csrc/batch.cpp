@@ -1,0 +1,279 @@
+// Host side of the batched solver: validation, per-graph degree
+// renumbering, packing (largest job first), one graph-captured persistent
+// launch, and unpacking into the caller's vertex order.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "batch_kernels.h"
+
+struct lap_batch {
+    int nb = 0;
+    bool weighted = false;
+    std::vector<int> n;                        // vertices per graph
+    std::vector<std::vector<int>> perm;        // caller -> plan index, per graph
+    std::vector<long long> rp_off, ci_off;
+    std::vector<int> nlong;
+    lapeig::DevBuf<int> rowptr, col;
+    lapeig::DevBuf<float> w32;
+    lapeig::DevBuf<double> w64;
+    long long total_n = 0, total_nnz = 0;
+};
+
+namespace lapeig {
+
+namespace {
+
+constexpr int kBatchLong = 32;  // rows above this degree get a wavefront each
+
+void pack(lap_batch *B, const lap_csr *Ls, int nb) {
+    for (int g = 0; g < nb; ++g) {
+        try {
+            validate_laplacian(&Ls[g]);
+        } catch (const Failure &f) {
+            throw Failure{f.code, "graph " + std::to_string(g) + ": " + f.msg};
+        }
+    }
+    std::vector<int> rp_all, ci_all;
+    std::vector<double> w_all;
+    B->nb = nb;
+    for (int g = 0; g < nb; ++g) {
+        const lap_csr &L = Ls[g];
+        for (int i = 0; i < L.n; ++i)
+            for (int e = L.rowptr[i]; e < L.rowptr[i + 1]; ++e)
+                if (L.col[e] != i && L.val[e] != -1.0) B->weighted = true;
+    }
+    for (int g = 0; g < nb; ++g) {
+        const lap_csr &L = Ls[g];
+        const int n = L.n;
+        std::vector<int> deg(n, 0);
+        for (int i = 0; i < n; ++i)
+            for (int e = L.rowptr[i]; e < L.rowptr[i + 1]; ++e)
+                if (L.col[e] != i) ++deg[i];
+        std::vector<int> iperm(n);
+        std::iota(iperm.begin(), iperm.end(), 0);
+        std::stable_sort(iperm.begin(), iperm.end(), [&](int a, int b) { return deg[a] > deg[b]; });
+        std::vector<int> perm(n);
+        for (int p = 0; p < n; ++p) perm[iperm[p]] = p;
+        // connectivity: the batched solver deflates the single zero pair e/sqrt(n)
+        {
+            std::vector<char> seen(n, 0);
+            std::vector<int> q(n);
+            int head = 0, tail = 0;
+            q[tail++] = 0;
+            seen[0] = 1;
+            while (head < tail) {
+                const int i = q[head++];
+                for (int e = L.rowptr[i]; e < L.rowptr[i + 1]; ++e)
+                    if (!seen[L.col[e]]) { seen[L.col[e]] = 1; q[tail++] = L.col[e]; }
+            }
+            LAP_REQUIRE(tail == n, LAP_EUNSUPPORTED,
+                        "graph " + std::to_string(g) + " is not connected (the batched solver needs connected graphs)");
+        }
+        B->rp_off.push_back((long long)rp_all.size());
+        B->ci_off.push_back((long long)ci_all.size());
+        int acc = 0;
+        std::vector<std::pair<int, double>> tmp;
+        rp_all.push_back(0);
+        for (int p = 0; p < n; ++p) {
+            const int i = iperm[p];
+            tmp.clear();
+            for (int e = L.rowptr[i]; e < L.rowptr[i + 1]; ++e)
+                if (L.col[e] != i) tmp.emplace_back(perm[L.col[e]], -L.val[e]);
+            std::sort(tmp.begin(), tmp.end());
+            for (auto &t : tmp) {
+                ci_all.push_back(t.first);
+                w_all.push_back(t.second);
+            }
+            acc += (int)tmp.size();
+            rp_all.push_back(acc);
+        }
+        int nl = 0;
+        while (nl < n && deg[iperm[nl]] > kBatchLong) ++nl;
+        B->n.push_back(n);
+        B->nlong.push_back(nl);
+        B->perm.push_back(std::move(perm));
+        B->total_n += n;
+        B->total_nnz += acc;
+    }
+    B->rowptr.alloc(rp_all.size());
+    B->col.alloc(std::max<size_t>(ci_all.size(), 1));
+    LAP_HIP(hipMemcpy(B->rowptr.get(), rp_all.data(), sizeof(int) * rp_all.size(), hipMemcpyHostToDevice));
+    if (!ci_all.empty())
+        LAP_HIP(hipMemcpy(B->col.get(), ci_all.data(), sizeof(int) * ci_all.size(), hipMemcpyHostToDevice));
+    if (B->weighted) {
+        std::vector<float> wf(w_all.begin(), w_all.end());
+        B->w64.alloc(std::max<size_t>(w_all.size(), 1));
+        B->w32.alloc(std::max<size_t>(w_all.size(), 1));
+        LAP_HIP(hipMemcpy(B->w64.get(), w_all.data(), sizeof(double) * w_all.size(), hipMemcpyHostToDevice));
+        LAP_HIP(hipMemcpy(B->w32.get(), wf.data(), sizeof(float) * wf.size(), hipMemcpyHostToDevice));
+    }
+}
+
+}  // namespace
+
+lap_status batch_create(const lap_csr *Ls, int nb, lap_batch **out) {
+    LAP_REQUIRE(Ls && nb >= 1 && out, LAP_EINVAL, "need graphs, nb >= 1 and an output handle");
+    lap_batch *B = new lap_batch();
+    try {
+        pack(B, Ls, nb);
+    } catch (...) {
+        delete B;
+        throw;
+    }
+    *out = B;
+    return LAP_OK;
+}
+
+void batch_destroy(lap_batch *B) { delete B; }
+int batch_total_n(const lap_batch *B) { return B ? (int)B->total_n : 0; }
+
+lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                       double *res, lap_eigs_info *infos, hipStream_t user) {
+    const auto t0 = std::chrono::steady_clock::now();
+    LAP_REQUIRE(k >= 1 && k <= kBatchMaxK, LAP_EUNSUPPORTED, "the batched solver supports 1 <= k <= 8");
+    LAP_REQUIRE(o.m_max <= kBatchMaxM && o.m_min >= 1 && o.m_min < o.m_max, LAP_EUNSUPPORTED,
+                "the batched solver supports m_max <= 16");
+    LAP_REQUIRE(o.block == 1, LAP_EUNSUPPORTED, "the batched solver corrects one pair per outer iteration");
+    const int nb = B->nb;
+    for (int g = 0; g < nb; ++g)
+        LAP_REQUIRE(k < B->n[g], LAP_EINVAL, "graph " + std::to_string(g) + " has n <= k");
+    const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
+    // descriptors and workspace offsets
+    std::vector<BGraph> gd(nb);
+    long long w64 = 0, w32 = 0, ov = 0;
+    for (int g = 0; g < nb; ++g) {
+        const long long n = B->n[g];
+        BGraph &d = gd[g];
+        d.n = (int)n;
+        d.nlong = B->nlong[g];
+        d.k = k;
+        d.pad = 0;
+        d.rp = B->rp_off[g];
+        d.ci = B->ci_off[g];
+        d.w64 = w64;
+        d.w32 = w32;
+        d.out_vec = ov;
+        d.out_val = (long long)g * k;
+        w64 += n * (k + 2LL * o.m_max + 4);
+        w32 += n * (k + 5LL);
+        ov += n * k;
+    }
+    // largest job first
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    {
+        std::vector<long long> nnz(nb);
+        for (int g = 0; g < nb; ++g) nnz[g] = (g + 1 < nb ? B->ci_off[g + 1] : B->total_nnz) - B->ci_off[g];
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nnz[a] > nnz[c]; });
+    }
+    DevBuf<BGraph> dg(nb);
+    DevBuf<int> dord(nb);
+    DevBuf<unsigned> dq(1);
+    DevBuf<double> ws64(w64), ws32(w32), outv(ov), outl((size_t)nb * k), outr((size_t)nb * k);
+    DevBuf<BResult> dres(nb);
+    hipStream_t s = nullptr;
+    LAP_HIP(hipStreamSynchronize(user));
+    LAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct SG {
+        hipStream_t s;
+        hipGraphExec_t e = nullptr;
+        ~SG() {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } guard{s};
+    LAP_HIP(hipMemcpyAsync(dg.get(), gd.data(), sizeof(BGraph) * nb, hipMemcpyHostToDevice, s));
+    LAP_HIP(hipMemcpyAsync(dord.get(), order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    LAP_HIP(hipMemsetAsync(outl.get(), 0, sizeof(double) * nb * k, s));
+    LAP_HIP(hipMemsetAsync(outr.get(), 0, sizeof(double) * nb * k, s));
+    BatchArgs a{};
+    a.ngraphs = nb;
+    a.graphs = dg.get();
+    a.order = dord.get();
+    a.queue = dq.get();
+    a.rowptr = B->rowptr.get();
+    a.col = B->col.get();
+    a.w32 = B->weighted ? B->w32.get() : nullptr;
+    a.w64 = B->weighted ? B->w64.get() : nullptr;
+    a.ws64 = ws64.get();
+    a.ws32 = ws32.get();
+    a.out_vec = outv.get();
+    a.out_val = outl.get();
+    a.out_res = outr.get();
+    a.results = dres.get();
+    a.m_min = o.m_min;
+    a.m_max = o.m_max;
+    a.itmax = o.itmax;
+    a.kmax = kmax;
+    a.tol = tol;
+    a.rtol_pcg = o.rtol_pcg;
+    a.seed = o.seed;
+    const int grid = std::min(nb, device_cu_count());
+    // one persistent launch, captured in a graph (queue reset + solver)
+    hipGraph_t graph = nullptr;
+    LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        batch_launch(a, o.precision == LAP_PREC_MIXED, B->weighted, grid, s);
+    } catch (...) {
+        (void)hipStreamEndCapture(s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    LAP_HIP(hipStreamEndCapture(s, &graph));
+    hipError_t err = hipGraphInstantiate(&guard.e, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    LAP_HIP(err);
+    LAP_HIP(hipGraphLaunch(guard.e, s));
+    // results
+    std::vector<BResult> hres(nb);
+    std::vector<double> hv(ov), hl((size_t)nb * k), hr((size_t)nb * k);
+    LAP_HIP(hipMemcpyAsync(hres.data(), dres.get(), sizeof(BResult) * nb, hipMemcpyDeviceToHost, s));
+    LAP_HIP(hipMemcpyAsync(hl.data(), outl.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
+    LAP_HIP(hipMemcpyAsync(hr.data(), outr.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
+    if (evecs) LAP_HIP(hipMemcpyAsync(hv.data(), outv.get(), sizeof(double) * ov, hipMemcpyDeviceToHost, s));
+    LAP_HIP(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    lap_status status = LAP_OK;
+    for (int g = 0; g < nb; ++g) {
+        const int n = B->n[g];
+        const int nc = std::min(hres[g].nconv, k);
+        if (nc < k) status = LAP_ENOCONV;
+        for (int j = 0; j < k; ++j) {
+            evals[(size_t)g * k + j] = j < nc ? hl[(size_t)g * k + j] : NAN;
+            if (res) res[(size_t)g * k + j] = j < nc ? hr[(size_t)g * k + j] : NAN;
+        }
+        if (evecs) {
+            const double *src = hv.data() + gd[g].out_vec;
+            double *dst = evecs + gd[g].out_vec;
+            const std::vector<int> &pm = B->perm[g];
+            for (int j = 0; j < k; ++j) {
+                double *y = dst + (size_t)j * n;
+                if (j >= nc) {
+                    for (int i = 0; i < n; ++i) y[i] = 0.0;
+                    continue;
+                }
+                const double *x = src + (size_t)j * n;
+                for (int i = 0; i < n; ++i) y[i] = x[pm[i]];
+                int best = 0;
+                for (int i = 1; i < n; ++i)
+                    if (std::fabs(y[i]) > std::fabs(y[best])) best = i;
+                if (y[best] < 0.0)
+                    for (int i = 0; i < n; ++i) y[i] = -y[i];
+            }
+        }
+        if (infos) {
+            infos[g].nconv = nc;
+            infos[g].ncomp = 1;
+            infos[g].outer = hres[g].outer;
+            infos[g].inner = hres[g].inner;
+            infos[g].mvp = hres[g].mvp;
+            infos[g].seconds = secs;
+        }
+    }
+    if (status == LAP_ENOCONV) set_error("some graphs reached the outer-iteration limit (see infos[g].nconv)");
+    return status;
+}
+
+}  // namespace lapeig

@@ -271,4 +271,40 @@ lap_status lap_pcg(lap_plan *p, lap_dtype dt, int b, const double *theta, const 
     LAP_GUARD_END
 }
 
+lap_status lap_batch_create(const lap_csr *Ls, int nb, lap_batch **out) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(out != nullptr, LAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    return lapeig::batch_create(Ls, nb, out);
+    LAP_GUARD_END
+}
+
+void lap_batch_destroy(lap_batch *b) { lapeig::batch_destroy(b); }
+
+int32_t lap_batch_total_n(const lap_batch *b) { return lapeig::batch_total_n(b); }
+
+lap_status lap_batch_eigs(lap_batch *b, int k, double tol, const lap_eigs_opts *opts, double *evals, double *evecs,
+                          double *res, lap_eigs_info *infos, void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(b != nullptr, LAP_EINVAL, "batch is NULL");
+    LAP_REQUIRE(tol > 0.0 && std::isfinite(tol), LAP_EINVAL, "tol must be > 0");
+    LAP_REQUIRE(evals != nullptr, LAP_EINVAL, "evals is NULL");
+    lap_eigs_opts o;
+    if (opts) o = *opts;
+    else lap_eigs_default_opts(&o);
+    check_opts(o, 0);
+    return lapeig::batch_solve(b, k, tol, o, evals, evecs, res, infos, (hipStream_t)stream);
+    LAP_GUARD_END
+}
+
+lap_status lap_eigs_batch(const lap_csr *Ls, int nb, int k, double tol, const lap_eigs_opts *opts, double *evals,
+                          double *evecs, double *res, lap_eigs_info *infos, void *stream) {
+    lap_batch *b = nullptr;
+    lap_status s = lap_batch_create(Ls, nb, &b);
+    if (s != LAP_OK) return s;
+    s = lap_batch_eigs(b, k, tol, opts, evals, evecs, res, infos, stream);
+    lap_batch_destroy(b);
+    return s;
+}
+
 }  // extern "C"

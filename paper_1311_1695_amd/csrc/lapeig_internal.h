@@ -160,6 +160,7 @@ inline const double *lap_plan::dinv<double>() const { return d_dinv64.get(); }
 namespace lapeig {
 
 // ------------------------------------------------------------- plan.cpp
+void validate_laplacian(const lap_csr *L);  // throws Failure (no HIP calls)
 // Validate (host), renumber, classify rows, build slices, upload.
 void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_threshold = 32,
                 int huge_threshold = 512);
@@ -199,5 +200,11 @@ lap_status pcg_entry(lap_plan *P, lap_dtype dt, int b, const double *theta_host,
                      int flags, hipStream_t s);
 
 int device_cu_count();
+
+lap_status batch_create(const lap_csr *Ls, int nb, lap_batch **out);
+void batch_destroy(lap_batch *B);
+int batch_total_n(const lap_batch *B);
+lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                       double *res, lap_eigs_info *infos, hipStream_t user);
 
 }  // namespace lapeig

@@ -14,10 +14,12 @@ std::string row_msg(const char *what, long long row) {
     return std::string(what) + " (row " + std::to_string(row) + ")";
 }
 
+}  // namespace
+
 // Section 2: G = D - A with A the weighted adjacency of a simple undirected
 // graph with positive weights and D the generalized degrees.  Everything is
 // checked before the first HIP call.
-void validate(const lap_csr *L) {
+void validate_laplacian(const lap_csr *L) {
     LAP_REQUIRE(L != nullptr, LAP_EINVAL, "lap_csr is NULL");
     LAP_REQUIRE(L->n >= 1, LAP_EINVAL, "n must be >= 1");
     LAP_REQUIRE(L->nnz >= 0, LAP_EINVAL, "nnz must be >= 0");
@@ -66,6 +68,8 @@ void validate(const lap_csr *L) {
     }
 }
 
+namespace {
+
 template <typename T>
 void upload(DevBuf<T> &dst, const std::vector<T> &src) {
     dst.alloc(src.size());
@@ -77,7 +81,7 @@ void upload(DevBuf<T> &dst, const std::vector<T> &src) {
 
 void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_threshold,
                 int huge_threshold) {
-    validate(L);
+    validate_laplacian(L);
     const int n = L->n;
     const int32_t *rp = L->rowptr, *cl = L->col;
     const double *v = L->val;

@@ -404,3 +404,57 @@ def test_eigs_block_rejects_bad_sizes():
     with pytest.raises(lap.LapError) as e:
         lap.lap_eigs(plan, 10, 1e-8, block=8, m_min=5, m_max=10)
     assert e.value.code == lap.LAP_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent solver (one launch, one workgroup per graph)
+# ---------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=None)
+def small_batch():
+    graphs = gg.pa_batch(6, 77, n_lo=400, n_hi=2500)
+    u, v = gg.chung_lu_edges(3000, 2.2, 4.0, 91)
+    n, u, v, _ = gg.largest_component(3000, u, v)
+    graphs.append(gg.laplacian_from_edges(n, u, v, name="cl_small"))
+    graphs.append(gg.path_graph(150))
+    return graphs
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_matches_dense_per_graph(precision):
+    graphs = small_batch()
+    out = lap.lap_eigs_batch(graphs, 5, 1e-8, precision=precision)
+    for L, r in zip(graphs, out):
+        assert r.nconv == 5, L.name
+        _certified(L, r, 1e-8)
+        w, V = np.linalg.eigh(L.dense())
+        check_against_reference(r.evals, r.evecs, w[:40], V[:, :40], val_rtol=1e-8, angle_tol=1e-6)
+    # the single-graph solver agrees
+    r1 = lap.lap_eigs_csr(graphs[0], 5, 1e-8)
+    assert np.allclose(r1.evals, out[0].evals, rtol=1e-8)
+
+
+def test_batch_weighted_and_reuse():
+    u, v = gg.chung_lu_edges(2000, 2.2, 4.0, 5)
+    wts = gg.integer_weights(u.shape[0], 6)
+    n, u, v, wts = gg.largest_component(2000, u, v, wts)
+    Lw = gg.laplacian_from_edges(n, u, v, wts)
+    graphs = [Lw, gg.workload("pa5k", 3)]
+    b = lap.lap_batch_create(graphs)
+    a1 = lap.lap_batch_eigs(b, 4, 1e-8)
+    a2 = lap.lap_batch_eigs(b, 4, 1e-8)
+    for L, r, r2 in zip(graphs, a1, a2):
+        _certified(L, r, 1e-8)
+        assert np.array_equal(r.evals, r2.evals)
+        w = np.linalg.eigvalsh(L.dense())[:4]
+        assert np.allclose(r.evals, w, rtol=1e-8, atol=1e-13)
+
+
+def test_batch_rejects_disconnected_and_large_k():
+    G = gg.disjoint_union(gg.path_graph(10), gg.cycle_graph(8))
+    with pytest.raises(lap.LapError) as e:
+        lap.lap_eigs_batch([gg.path_graph(20), G], 3, 1e-8)
+    assert e.value.code == lap.LAP_EUNSUPPORTED
+    with pytest.raises(lap.LapError) as e:
+        lap.lap_eigs_batch([gg.path_graph(50)], 9, 1e-8)
+    assert e.value.code == lap.LAP_EUNSUPPORTED
