@@ -125,6 +125,13 @@ __global__ __launch_bounds__(kBlock) void k_hborder(int n, const double *__restr
     }
 }
 
+// Makes the payload written to *hm visible to the host, then the sequence
+// number the host waits for (host-coherent memory; one thread calls it).
+__device__ __forceinline__ void publish(HostMirror *hm, unsigned seq) {
+    __threadfence_system();
+    __hip_atomic_store(&hm->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ---------------------------------------------------------------------------
 // All eigenpairs of the small symmetric H (step 5) in one workgroup:
 // cyclic Jacobi in the round-robin (tournament) ordering, so the m/2
@@ -143,7 +150,6 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     double *A = lds;              // me x me, row-major
     double *Z = A + me * me;      // me x me, row-major accumulator of rotations
     __shared__ double cs[kRRMax / 2], sn[kRRMax / 2];
-    __shared__ int pp[kRRMax / 2], qq[kRRMax / 2];
     __shared__ int any_rot;
     __shared__ double fro2;
     const int tid = threadIdx.x;
@@ -153,66 +159,94 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
         Z[t] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (tid == 0) {
+    {
+        __shared__ double wsum[kWavesPerBlock];
         double f = 0.0;
-        for (int t = 0; t < me * me; ++t) f += A[t] * A[t];
-        fro2 = f;
+        for (int t = tid; t < me * me; t += blockDim.x) f += A[t] * A[t];
+        f = wave_sum(f);
+        if (lane_id() == 0) wsum[wave_id()] = f;
+        __syncthreads();
+        if (tid == 0) {
+            double g = 0.0;
+            for (int w = 0; w < (int)blockDim.x / kWave; ++w) g += wsum[w];
+            fro2 = g;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const double tol = 2.220446049250313e-16 * sqrt(fro2) / (double)me;
     const int half = me / 2;
+    // pair k of a round: players k and me-1-k of the tournament table, whose
+    // position 0 stays fixed while the others rotate by one each round
+    auto pair_of = [&](int k, int round, int &p, int &q) {
+        const int a = k == 0 ? 0 : 1 + (k - 1 + round) % (me - 1);
+        const int kb = me - 1 - k;
+        const int b = kb == 0 ? 0 : 1 + (kb - 1 + round) % (me - 1);
+        p = a < b ? a : b;
+        q = a < b ? b : a;
+    };
     int sweeps = 0;
     for (; sweeps < 60 && me > 1; ++sweeps) {
         if (tid == 0) any_rot = 0;
         __syncthreads();
         for (int round = 0; round < me - 1; ++round) {
-            // tournament pairing: position 0 fixed, the others rotate
+            // phase 1: the rotation of every pair (symmetric Schur 2x2)
             if (tid < half) {
-                auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
-                int a = player(tid), b = player(me - 1 - tid);
-                int p = a < b ? a : b, q = a < b ? b : a;
-                double c = 1.0, s = 0.0;
+                int p, q;
+                pair_of(tid, round, p, q);
+                double c = 1.0, sv = 0.0;
                 const double apq = A[p * me + q];
                 if (fabs(apq) > tol) {
                     const double tau = (A[q * me + q] - A[p * me + p]) / (2.0 * apq);
                     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
+                    sv = t * c;
                     any_rot = 1;
                 }
-                pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+                cs[tid] = c;
+                sn[tid] = sv;
             }
             __syncthreads();
-            // rows: A <- J' A
-            for (int t = tid; t < half * me; t += blockDim.x) {
-                const int k = t / me, j = t % me;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    const double ap = A[p * me + j], aq = A[q * me + j];
-                    A[p * me + j] = c * ap - s * aq;
-                    A[q * me + j] = s * ap + c * aq;
+            // phase 2: A <- J'AJ by 2x2 blocks (pairs k <= l; block (l, k) is
+            // the mirror), Z <- ZJ by (row, pair); all operands are read
+            // before anything is written, and no two threads share an entry
+            for (int e = tid; e < half * half; e += blockDim.x) {
+                const int k = e / half, l = e % half;
+                if (k > l) continue;
+                const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+                if (sk == 0.0 && sl == 0.0) continue;
+                int pk, qk, pl, ql;
+                pair_of(k, round, pk, qk);
+                pair_of(l, round, pl, ql);
+                const double b00 = A[pk * me + pl], b01 = A[pk * me + ql];
+                const double b10 = A[qk * me + pl], b11 = A[qk * me + ql];
+                if (k == l) {
+                    // diagonal block: the pair's own rotation annihilates b01
+                    const double t = ck != 0.0 ? sk / ck : 0.0;
+                    A[pk * me + pk] = b00 - t * b01;
+                    A[qk * me + qk] = b11 + t * b01;
+                    A[pk * me + qk] = 0.0;
+                    A[qk * me + pk] = 0.0;
+                } else {
+                    // rows by pair k, then columns by pair l
+                    const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+                    const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+                    const double n00 = cl * r00 - sl * r01, n01 = sl * r00 + cl * r01;
+                    const double n10 = cl * r10 - sl * r11, n11 = sl * r10 + cl * r11;
+                    A[pk * me + pl] = n00; A[pl * me + pk] = n00;
+                    A[pk * me + ql] = n01; A[ql * me + pk] = n01;
+                    A[qk * me + pl] = n10; A[pl * me + qk] = n10;
+                    A[qk * me + ql] = n11; A[ql * me + qk] = n11;
                 }
             }
-            __syncthreads();
-            // columns: A <- A J, Z <- Z J
-            for (int t = tid; t < half * me; t += blockDim.x) {
-                const int k = t / me, i = t % me;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    const double ap = A[i * me + p], aq = A[i * me + q];
-                    A[i * me + p] = c * ap - s * aq;
-                    A[i * me + q] = s * ap + c * aq;
-                    const double zp = Z[i * me + p], zq = Z[i * me + q];
-                    Z[i * me + p] = c * zp - s * zq;
-                    Z[i * me + q] = s * zp + c * zq;
-                }
-            }
-            __syncthreads();
-            if (tid < half && sn[tid] != 0.0) {
-                A[pp[tid] * me + qq[tid]] = 0.0;
-                A[qq[tid] * me + pp[tid]] = 0.0;
+            for (int e = tid; e < me * half; e += blockDim.x) {
+                const int i = e / half, k = e % half;
+                const double ck = cs[k], sk = sn[k];
+                if (sk == 0.0) continue;
+                int p, q;
+                pair_of(k, round, p, q);
+                const double zp = Z[i * me + p], zq = Z[i * me + q];
+                Z[i * me + p] = ck * zp - sk * zq;
+                Z[i * me + q] = sk * zp + ck * zq;
             }
             __syncthreads();
         }
@@ -242,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_ritz(int n, const double *__restrict
                                                  const double *__restrict__ Y, const double *__restrict__ theta,
                                                  double *__restrict__ u, double *__restrict__ r,
                                                  T *__restrict__ Q, int ldq, int qcol, double *partial,
-                                                 unsigned *counter, JDStatus *st) {
+                                                 unsigned *counter, JDStatus *st, HostMirror *hm, unsigned seq) {
     __shared__ double y[kRRMax];
     for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = Y[j];
     __syncthreads();
@@ -264,9 +298,18 @@ __global__ __launch_bounds__(kBlock) void k_ritz(int n, const double *__restrict
     __shared__ double out[2];
     if (grid_reduce<double, 2>(acc, 2, partial, counter, out)) {
         if (threadIdx.x == 0) {
+            const double un = sqrt(out[1]);
+            const double rn = sqrt(out[0]) / un;
             st->theta = th;
-            st->unorm = sqrt(out[1]);
-            st->rnorm = sqrt(out[0]) / st->unorm;
+            st->unorm = un;
+            st->rnorm = rn;
+            if (hm) {
+                hm->theta = th;
+                hm->unorm = un;
+                hm->rnorm = rn;
+                hm->degenerate = st->degenerate;
+                publish(hm, seq);
+            }
         }
     }
 }
@@ -295,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_cert1(Graph g, Weights<double> w, co
 // Certificate, part 2: ||G u - theta u|| / ||u||.
 __global__ __launch_bounds__(kBlock) void k_cert2(int n, const double *__restrict__ u,
                                                   const double *__restrict__ gu, double *partial,
-                                                  unsigned *counter, JDStatus *st) {
+                                                  unsigned *counter, JDStatus *st, HostMirror *hm, unsigned seq) {
     const double th = st->cert_theta;
     double acc[1] = {0.0};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -304,7 +347,15 @@ __global__ __launch_bounds__(kBlock) void k_cert2(int n, const double *__restric
     }
     __shared__ double out[1];
     if (grid_reduce<double, 1>(acc, 1, partial, counter, out)) {
-        if (threadIdx.x == 0) st->cert_rnorm = sqrt(out[0] / st->cert_unorm2);
+        if (threadIdx.x == 0) {
+            const double cr = sqrt(out[0] / st->cert_unorm2);
+            st->cert_rnorm = cr;
+            if (hm) {
+                hm->cert_theta = th;
+                hm->cert_rnorm = cr;
+                publish(hm, seq);
+            }
+        }
     }
 }
 
@@ -468,25 +519,30 @@ void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, J
                                     2 * kRRMax * kRRMax * (int)sizeof(double)));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(kBlock), lds, s, m, H, ldh, theta, Y, ldy, st);
+    // up to 32 columns a single wavefront does it: every barrier of the
+    // round-by-round rotations is then nearly free
+    const int threads = me <= 32 ? kWave : kBlock;
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, st);
     LAP_HIP(hipGetLastError());
 }
 
 template <typename T>
 void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
-             double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s) {
+             double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s, HostMirror *hm,
+             unsigned seq) {
     const int grid = vec_grid(n);
     rs.ensure(grid, 2);
     hipLaunchKernelGGL((k_ritz<T>), dim3(grid), dim3(kBlock), 0, s, n, V, W, m, Y, theta, u, r, Q, ldq, qcol,
-                       rs.partial.get(), rs.counter.get(), st);
+                       rs.partial.get(), rs.counter.get(), st, hm, seq);
     LAP_HIP(hipGetLastError());
 }
 template void jd_ritz<float>(int, const double *, const double *, int, const double *, const double *, double *,
-                             double *, float *, int, int, ReduceScratch &, JDStatus *, hipStream_t);
+                             double *, float *, int, int, ReduceScratch &, JDStatus *, hipStream_t, HostMirror *, unsigned);
 template void jd_ritz<double>(int, const double *, const double *, int, const double *, const double *, double *,
-                              double *, double *, int, int, ReduceScratch &, JDStatus *, hipStream_t);
+                              double *, double *, int, int, ReduceScratch &, JDStatus *, hipStream_t, HostMirror *, unsigned);
 
-void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &rs, JDStatus *st, hipStream_t s) {
+void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &rs, JDStatus *st, hipStream_t s,
+                HostMirror *hm, unsigned seq) {
     const int grid = row_grid(P.g, 4 * device_cu_count());
     rs.ensure(std::max(grid, vec_grid(P.n)), 2);
     if (P.weighted)
@@ -496,7 +552,7 @@ void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &r
         hipLaunchKernelGGL((k_cert1<false>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), u, gu,
                            rs.partial.get(), rs.counter.get(), st);
     hipLaunchKernelGGL(k_cert2, dim3(vec_grid(P.n)), dim3(kBlock), 0, s, P.n, u, gu, rs.partial.get(),
-                       rs.counter.get(), st);
+                       rs.counter.get(), st, hm, seq);
     LAP_HIP(hipGetLastError());
 }
 

@@ -6,7 +6,8 @@
 //   k_ts_tn  C = A'B   (A n x ka, B n x kb, row-major): each wavefront
 //            accumulates 16x16 tiles over its 4-row chunks, the four
 //            wavefronts are summed in LDS, each workgroup writes one partial
-//            tile set, and k_ts_reduce adds the partials in workgroup order.
+//            tile set, and k_ts_reduce adds the partials (one wavefront per
+//            output element, in a fixed order).
 //   k_ts_nn  Out = alpha A C + (addend | beta Out)  (C ka x kb column-major,
 //            staged in LDS): each wavefront owns 16-row blocks, so Out may
 //            overlap A (in-place rotation of a basis).
@@ -92,17 +93,30 @@ __global__ __launch_bounds__(kBlock) void k_ts_tn(int n, const T *__restrict__ A
     for (int t = threadIdx.x; t < PI * PJ; t += blockDim.x) out[t] = red[t];
 }
 
-// out[i + j ldc] = alpha * sum_g part_g[i][j]  (and mirror[j + i ldm] when given)
+// out[i + j ldc] = alpha * sum_g part_g[i][j]  (and mirror[j + i ldm] when given).
+// One wavefront per output element: lane l adds partials l, l + 64, ... in
+// order, then a fixed butterfly sums the lanes (deterministic for a given G).
 template <typename T>
-__global__ void k_ts_reduce(int G, const T *__restrict__ part, int pj, int ps, int ka, int kb, T *out, int ldc,
-                            T *mirror, int ldm, int mirror_rows, T alpha) {
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ka * kb; idx += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(kBlock) void k_ts_reduce(int G, const T *__restrict__ part, int pj, int ps, int ka,
+                                                      int kb, T *out, int ldc, T *mirror, int ldm, int mirror_rows,
+                                                      T alpha) {
+    const int lane = lane_id();
+    for (int idx = blockIdx.x * kWavesPerBlock + wave_id(); idx < ka * kb; idx += gridDim.x * kWavesPerBlock) {
         const int i = idx / kb, j = idx % kb;
+        const T *src = part + i * pj + j;
         T s = T(0);
-        for (int g = 0; g < G; ++g) s += part[(size_t)g * ps + i * pj + j];
-        s *= alpha;
-        out[i + (size_t)j * ldc] = s;
-        if (mirror && i < mirror_rows) mirror[j + (size_t)i * ldm] = s;
+        int g = lane;
+        for (; g + 3 * kWave < G; g += 4 * kWave) {
+            const T a0 = src[(size_t)g * ps], a1 = src[(size_t)(g + kWave) * ps];
+            const T a2 = src[(size_t)(g + 2 * kWave) * ps], a3 = src[(size_t)(g + 3 * kWave) * ps];
+            s += a0; s += a1; s += a2; s += a3;
+        }
+        for (; g < G; g += kWave) s += src[(size_t)g * ps];
+        s = wave_sum(s) * alpha;
+        if (lane == 0) {
+            out[i + (size_t)j * ldc] = s;
+            if (mirror && i < mirror_rows) mirror[j + (size_t)i * ldm] = s;
+        }
     }
 }
 
@@ -168,8 +182,9 @@ void ts_tn_launch(int n, const T *A, int lda, int ka, const T *B, int ldb, int k
     const int tot = ka * kb;
     // rows of C at or past ka - kb pair with the new square block, which the
     // direct write already holds in full: mirror only the rows above it
-    hipLaunchKernelGGL((k_ts_reduce<T>), dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0, s, G, part, TJ * 16, PS,
-                       ka, kb, out, ldc, mirror, ldm, ka - kb, alpha);
+    const int rgrid = std::min((tot + kWavesPerBlock - 1) / kWavesPerBlock, 4 * device_cu_count());
+    hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rgrid), dim3(kBlock), 0, s, G, part, TJ * 16, PS, ka, kb, out, ldc,
+                       mirror, ldm, ka - kb, alpha);
     LAP_HIP(hipGetLastError());
 }
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <functional>
 #include <numeric>
 
@@ -63,10 +64,65 @@ struct OwnStream {
     ~OwnStream() { if (s) (void)hipStreamDestroy(s); }
 };
 
-struct PinnedStatus {
-    JDStatus *h = nullptr;
-    PinnedStatus() { LAP_HIP(hipHostMalloc((void **)&h, sizeof(JDStatus), hipHostMallocDefault)); }
-    ~PinnedStatus() { if (h) (void)hipHostFree(h); }
+// Host-coherent pinned status the kernels publish into (see HostMirror).
+struct PinnedMirror {
+    HostMirror *h = nullptr;
+    PinnedMirror() {
+        LAP_HIP(hipHostMalloc((void **)&h, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
+        std::memset(h, 0, sizeof(HostMirror));
+    }
+    ~PinnedMirror() { if (h) (void)hipHostFree(h); }
+    PinnedMirror(const PinnedMirror &) = delete;
+    PinnedMirror &operator=(const PinnedMirror &) = delete;
+};
+
+// Waits until the kernels have published sequence number `seq`.  Spins on
+// the pinned word; if the stream drains without it, that is an error.
+void wait_published(const HostMirror *hm, unsigned seq, hipStream_t s) {
+    for (unsigned spin = 1;; ++spin) {
+        if (__atomic_load_n(&hm->seq, __ATOMIC_ACQUIRE) == seq) return;
+        if ((spin & 255) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(&hm->seq, __ATOMIC_ACQUIRE) == seq) return;
+                throw Failure{LAP_EDEVICE, "solver status was not published"};
+            }
+            if (e != hipErrorNotReady) LAP_HIP(e);
+        }
+    }
+}
+
+// Work areas of the single-vector solver, kept in the plan between solves
+// of the same shape (n, k, m_max) and inner-solve settings.
+template <typename T>
+struct JdWork : SolverCache {
+    int n, k, mmax, itmax;
+    double rtol;
+    DevBuf<double> B, W, H, theta, Y, v, u, r, gu, vrand, isz;
+    DevBuf<T> Q, t;
+    DevBuf<JDStatus> st;
+    PinnedMirror hm;
+    ReduceScratch rs;
+    PcgWork<T> pw;
+    PcgGraphs<T> graphs;
+    JdWork(int n_, int k_, int mmax_, int itmax_, double rtol_)
+        : n(n_), k(k_), mmax(mmax_), itmax(itmax_), rtol(rtol_) {
+        B.alloc((size_t)n * (k + mmax));
+        W.alloc((size_t)n * mmax);
+        H.alloc((size_t)mmax * mmax);
+        theta.alloc(mmax);
+        Y.alloc((size_t)mmax * mmax);
+        v.alloc(n); u.alloc(n); r.alloc(n); gu.alloc(n); vrand.alloc(n);
+        isz.alloc(std::max(k, 1));
+        Q.alloc((size_t)n * k);
+        t.alloc(n);
+        st.alloc(1);
+        rs.ensure(std::max(4 * device_cu_count(), 1), 64);
+        pw.ensure(n, k);
+    }
+    bool fits(int n_, int k_, int mmax_, int itmax_, double rtol_) const {
+        return n == n_ && k == k_ && mmax == mmax_ && itmax == itmax_ && rtol == rtol_;
+    }
 };
 
 template <typename T>
@@ -80,7 +136,6 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     OwnStream own;
     hipStream_t s = own.s;
     const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
-    PcgGraphs<T> graphs;
     const int mmax = o.m_max, mmin = o.m_min;
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
     LAP_REQUIRE(k + mmax <= kMaxBasis, LAP_EUNSUPPORTED,
@@ -88,16 +143,23 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     const int nz = std::min(P->ncomp, k);
     const int ldq = k;
 
-    DevBuf<double> B((size_t)n * (k + mmax)), W((size_t)n * mmax), H((size_t)mmax * mmax), theta(mmax),
-        Y((size_t)mmax * mmax), v(n), u(n), r(n), gu(n), vrand(n), isz(std::max(nz, 1));
-    DevBuf<T> Q((size_t)n * ldq), t(n);
-    DevBuf<JDStatus> st(1);
-    PinnedStatus hst;
-    ReduceScratch rs;
-    rs.ensure(std::max(4 * device_cu_count(), 1), 64);
-    PcgWork<T> pw;
-    pw.ensure(n);
+    auto *cache = dynamic_cast<JdWork<T> *>(P->jd_cache.get());
+    if (!cache || !cache->fits(n, k, mmax, o.itmax, o.rtol_pcg)) {
+        P->jd_cache.reset();
+        P->jd_cache.reset(cache = new JdWork<T>(n, k, mmax, o.itmax, o.rtol_pcg));
+    }
+    JdWork<T> &wk = *cache;
+    DevBuf<double> &B = wk.B, &W = wk.W, &H = wk.H, &theta = wk.theta, &Y = wk.Y, &v = wk.v, &u = wk.u, &r = wk.r,
+                   &gu = wk.gu, &vrand = wk.vrand, &isz = wk.isz;
+    DevBuf<T> &Q = wk.Q, &t = wk.t;
+    DevBuf<JDStatus> &st = wk.st;
+    HostMirror *hm = wk.hm.h;
+    unsigned seq = hm->seq;
+    ReduceScratch &rs = wk.rs;
+    PcgWork<T> &pw = wk.pw;
+    PcgGraphs<T> &graphs = wk.graphs;
     LAP_HIP(hipMemsetAsync(H.get(), 0, sizeof(double) * mmax * mmax, s));
+    LAP_HIP(hipMemsetAsync(pw.st.get(), 0, sizeof(PcgState<T>), s));
 
     std::vector<double> lam, resid;
     lam.reserve(k);
@@ -138,7 +200,6 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
 
     bool src_is_t = false;
     const double *src = nullptr;
-    bool pcg_pending = false;
     if (nx < k) src = next_start();
 
     while (nx < k) {
@@ -164,18 +225,10 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
             // step 5: eigenpairs of H; step 6: Ritz vector and residual
             jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s);
             Vb = B.get() + (size_t)nx * n;
-            jd_ritz<T>(n, Vb, W.get(), m, Y.get(), theta.get(), u.get(), r.get(), Q.get(), ldq, nx, rs, st.get(), s);
-            LAP_HIP(hipMemcpyAsync(hst.h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
-            PcgState<T> pstate;
-            if (pcg_pending) LAP_HIP(hipMemcpyAsync(&pstate, pw.st.get(), sizeof(pstate), hipMemcpyDeviceToHost, s));
-            LAP_HIP(hipStreamSynchronize(s));
-            if (pcg_pending) {
-                const int its = pstate.breakdown ? pstate.breakdown : pstate.iters;
-                inner += its;
-                mvp += its;
-                pcg_pending = false;
-            }
-            if (first && hst.h->degenerate) {
+            jd_ritz<T>(n, Vb, W.get(), m, Y.get(), theta.get(), u.get(), r.get(), Q.get(), ldq, nx, rs, st.get(), s,
+                       hm, ++seq);
+            wait_published(hm, seq, s);
+            if (first && hm->degenerate) {
                 // the new direction lay in span[X V]: drop it, take a fresh start vector
                 --m;
                 need_pcg = false;
@@ -184,16 +237,15 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
                 break;
             }
             first = false;
-            const double th = hst.h->theta, rn = hst.h->rnorm;
+            const double th = hm->theta, rn = hm->rnorm;
             if (!std::isfinite(th) || !std::isfinite(rn))
                 throw Failure{LAP_EDEVICE, "non-finite Ritz value or residual"};
             // step 7: exit test, certified with a fresh product and eq. (1)
             if (!converged(rn, th, tol)) break;
-            jd_certify(*P, u.get(), gu.get(), rs, st.get(), s);
+            jd_certify(*P, u.get(), gu.get(), rs, st.get(), s, hm, ++seq);
             ++mvp;
-            LAP_HIP(hipMemcpyAsync(hst.h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
-            LAP_HIP(hipStreamSynchronize(s));
-            const double ct = hst.h->cert_theta, cr = hst.h->cert_rnorm;
+            wait_published(hm, seq, s);
+            const double ct = hm->cert_theta, cr = hm->cert_rnorm;
             if (!converged(cr, ct, tol)) break;
             // lock u = V y_1 as x_{nx}; keep V y_2.. as the new basis, H = diag
             jd_rotate(n, m, Y.get(), mmax, Vb, Vb, 0, m, nullptr, W.get(), W.get(), 1, m - 1, s);
@@ -228,21 +280,20 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         {
             const int q = nx + 1;
             auto enqueue = [&]() {
-                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, rs, o.itmax, o.rtol_pcg, s);
+                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, o.itmax, o.rtol_pcg, s);
             };
             if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, s, enqueue), s));
             else enqueue();
         }
-        pcg_pending = true;
         src_is_t = true;
     }
-    if (pcg_pending) {
+    {
+        // inner products of all correction equations of this solve
         PcgState<T> pstate;
         LAP_HIP(hipMemcpyAsync(&pstate, pw.st.get(), sizeof(pstate), hipMemcpyDeviceToHost, s));
         LAP_HIP(hipStreamSynchronize(s));
-        const int its = pstate.breakdown ? pstate.breakdown : pstate.iters;
-        inner += its;
-        mvp += its;
+        inner = pstate.total;
+        mvp += pstate.total;
     }
 
     // ---- output: ascending order, caller's vertex order, canonical signs

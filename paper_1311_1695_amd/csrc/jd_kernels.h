@@ -19,12 +19,30 @@ struct JDStatus {
     int degenerate, rr_sweeps;
 };
 
+// PCG scalars that outlive one launch.  Launch number sq of a solve is a
+// no-op once stop_seq is nonzero and <= sq; a launch that decides to stop
+// writes stop_seq = sq + 1, which no other workgroup of the same launch
+// treats as a stop, so the flag never races with its readers.
+// The few status values the host decides on, published by the kernel that
+// finishes them into host-coherent pinned memory: payload first, then a
+// system-scope fence, then the sequence number the host waits for.
+struct HostMirror {
+    double theta, unorm, rnorm, cert_theta, cert_rnorm;
+    int degenerate, pad;
+    unsigned seq, pad2;
+};
+
 template <typename T>
 struct PcgState {
-    T c0[64], c1[64], c2[64];
-    T rho, alpha, beta, r0, rn, pAp;
-    int stop, iters, breakdown, pad;
+    T rho[2];   // rho = res' M res of the last two iterations, by parity
+    T r0;       // norm of the right-hand side
+    int stop_seq, iters, breakdown;
+    int total;  // products of all solves since the host last cleared it
 };
+
+// Workgroups of one PCG launch (bounded so that folding the partial sums
+// of the previous launch stays cheap in every workgroup).
+inline int pcg_max_groups() { return 2 * device_cu_count(); }
 
 template <typename S>
 void jd_orth(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
@@ -36,8 +54,10 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
 void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s);
 template <typename T>
 void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
-             double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s);
-void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &rs, JDStatus *st, hipStream_t s);
+             double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s,
+             HostMirror *hm = nullptr, unsigned seq = 0);
+void jd_certify(const lap_plan &P, const double *u, double *gu, ReduceScratch &rs, JDStatus *st, hipStream_t s,
+                HostMirror *hm = nullptr, unsigned seq = 0);
 void jd_rotate(int n, int m, const double *Y, int ldy, const double *vin, double *vout, int vc0, int vnc,
                const double *vscale0, const double *win, double *wout, int wc0, int wnc, hipStream_t s);
 void jd_hdiag(double *H, int ldh, int cnt, const double *theta, int off, hipStream_t s);
@@ -52,11 +72,16 @@ void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipS
 template <typename T>
 struct PcgWork {
     DevBuf<T> res, p, s, y;
+    DevBuf<T> gq;    // G Q, row-major like Q
+    DevBuf<T> part;  // two areas of per-workgroup partial sums (ping-pong)
     DevBuf<PcgState<T>> st;
-    void ensure(int n) {
-        if (res.n >= (size_t)n && st.get()) return;
-        res.alloc(n); p.alloc(n); s.alloc(n); y.alloc(n);
-        st.alloc(1);
+    void ensure(int n, int ldq) {
+        if (res.n < (size_t)n || !st.get()) {
+            res.alloc(n); p.alloc(n); s.alloc(n); y.alloc(n);
+            part.alloc(2 * (size_t)pcg_max_groups() * 64);
+            st.alloc(1);
+        }
+        if (gq.n < (size_t)n * ldq) gq.alloc((size_t)n * ldq);
     }
 };
 
@@ -65,6 +90,6 @@ struct PcgWork {
 // -r (r double, plan order).  Enqueues everything; nothing is read back.
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, ReduceScratch &rs, int itmax, double rtol, hipStream_t s);
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s);
 
 }  // namespace lapeig

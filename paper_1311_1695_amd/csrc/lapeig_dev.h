@@ -119,11 +119,72 @@ __device__ bool grid_reduce(const T (&acc)[NV], int nv, T *partial, unsigned *co
     return true;
 }
 
+// Deferred cross-workgroup sums.  A producer launch leaves one row of nv
+// partial sums per workgroup (plain stores); the launch after it, which the
+// kernel boundary makes them visible to, folds them in every workgroup in
+// the same fixed order, so all workgroups obtain bit-identical totals with
+// no atomics and no cache maintenance inside either kernel.
+constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : v <= 2 ? 2 : v <= 4 ? 4 : v <= 8 ? 8 : v <= 16 ? 16 : v <= 32 ? 32 : 64; }
+
+template <typename T, int NV>
+__device__ __forceinline__ void write_partials(const T (&acc)[NV], int nv, T *__restrict__ part) {
+    static_assert(NV <= kWave, "at most 64 values per reduction");
+    __shared__ T red[kWavesPerBlock][NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        if (j < nv) {
+            T s = wave_sum(acc[j]);
+            if (lane_id() == 0) red[wave_id()][j] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        T s = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += red[w][threadIdx.x];
+        part[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+    }
+}
+
+// out[0..nv) = sum over the nb partial rows of part (row stride NV).  Thread
+// (g, j) adds rows g, g + G, g + 2G, ... of value j in row order; the G group
+// sums are then added in group order; out[nv..NV) is set to zero.
+// Synchronizes the workgroup.
+template <typename T, int NV>
+__device__ __forceinline__ void fold_partials(const T *__restrict__ part, int nb, int nv, T *out) {
+    constexpr int NVP = pow2_at_least(NV);
+    constexpr int GROUPS = kBlock / NVP;
+    __shared__ T fin[GROUPS][NVP];
+    const int j = threadIdx.x % NVP, g = threadIdx.x / NVP;
+    T s = T(0);
+    if (j < nv) {
+        int b = g;
+        for (; b + 7 * GROUPS < nb; b += 8 * GROUPS) {
+            T a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = part[(size_t)(b + u * GROUPS) * NV + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += a[u];
+        }
+        for (; b < nb; b += GROUPS) s += part[(size_t)b * NV + j];
+    }
+    fin[g][j] = s;
+    __syncthreads();
+    if (threadIdx.x < NV) {  // values nv .. NV-1 come out as zeros
+        T t = fin[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < GROUPS; ++q) t += fin[q][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Row engine.  For every row i of the grid's share it computes
 //   y_i = sum_{j in N(i)} w_ij (x_i - x_j)        ( = (G x)_i )
 //   q_i = sum_{j in N(i)} w_ij (x_i - x_j)^2      (only when QF; sum_i q_i = 2 x'Gx, eq. (1))
-// and calls f(i, x_i, y_i, q_i) on exactly one lane per row.  Rows are
+// and calls f(i, x_i, y_i, q_i) on exactly one lane per row (for_each_row_pre
+// also passes f what pre(i) loaded for the row before its gathers began).  Rows are
 // visited workgroup-per-row (huge), wavefront-per-row (long), then
 // lane-per-row inside 64-row slices; the grid strides over the units.
 // Every loop keeps four independent index->gather chains in flight, and the
@@ -150,44 +211,54 @@ __device__ __forceinline__ void edge_terms(const int *__restrict__ col, const T 
     }
 }
 
-template <typename T, bool WEIGHTED, bool QF, class F>
-__device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w,
-                                             const T *__restrict__ x, F &&f) {
+template <typename T, bool WEIGHTED, bool QF, class Pre, class F>
+__device__ __forceinline__ void for_each_row_pre(const Graph &g, const Weights<T> &w,
+                                                 const T *__restrict__ x, Pre &&pre, F &&f) {
     const int lane = lane_id();
     // huge rows: the whole workgroup strides over the row
     for (int r = blockIdx.x; r < g.n_huge; r += gridDim.x) {
+        const auto pd = pre(r);
         const T xi = x[r];
         T acc = T(0), aq = T(0);
         edge_terms<T, WEIGHTED, QF>(g.col, w.csr, x, xi, g.rowptr[r] + threadIdx.x, g.rowptr[r + 1], blockDim.x,
                                     acc, aq);
         acc = block_sum(acc);
         if (QF) aq = block_sum(aq);
-        if (threadIdx.x == 0) f(r, xi, acc, aq);
+        if (threadIdx.x == 0) f(r, xi, acc, aq, pd);
     }
     const int nlong = g.n_long - g.n_huge;
     const int units = nlong + g.nslices;
     for (int u = blockIdx.x * kWavesPerBlock + wave_id(); u < units; u += gridDim.x * kWavesPerBlock) {
         if (u < nlong) {
             const int r = g.n_huge + u;
+            const auto pd = pre(r);
             const T xi = x[r];
             T acc = T(0), aq = T(0);
             edge_terms<T, WEIGHTED, QF>(g.col, w.csr, x, xi, g.rowptr[r] + lane, g.rowptr[r + 1], kWave, acc, aq);
             acc = wave_sum(acc);
             if (QF) aq = wave_sum(aq);
-            if (lane == 0) f(r, xi, acc, aq);
+            if (lane == 0) f(r, xi, acc, aq, pd);
         } else {
             const int s = u - nlong;
             const int r = g.n_long + s * kWave + lane;
             if (r < g.n) {
+                // operands of f are requested before the gathers start
+                const auto pd = pre(r);
                 const int off = g.sell_off[s];
                 const int end = g.sell_off[s + 1];
                 const T xi = x[r];
                 T acc = T(0), aq = T(0);
                 edge_terms<T, WEIGHTED, QF>(g.sell_col, w.sell, x, xi, off + lane, end, kWave, acc, aq);
-                f(r, xi, acc, aq);
+                f(r, xi, acc, aq, pd);
             }
         }
     }
+}
+
+template <typename T, bool WEIGHTED, bool QF, class F>
+__device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w, const T *__restrict__ x, F &&f) {
+    for_each_row_pre<T, WEIGHTED, QF>(
+        g, w, x, [](int) { return 0; }, [&](int i, T xi, T yi, T qi, int) { f(i, xi, yi, qi); });
 }
 
 // Grid size for a row-engine launch: enough wavefronts to cover the units,

@@ -22,6 +22,7 @@
 
 #include <cstdint>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/lapeig.h"
@@ -113,6 +114,14 @@ struct Weights {
 }  // namespace lapeig
 
 // The opaque plan of the C ABI.
+namespace lapeig {
+// Work areas a solver keeps in its plan between calls (device buffers and
+// captured launch graphs), so repeated solves on one plan allocate nothing.
+struct SolverCache {
+    virtual ~SolverCache() = default;
+};
+}  // namespace lapeig
+
 struct lap_plan {
     int n = 0;
     long long nnz_a = 0;     // off-diagonal entries (2 per edge)
@@ -137,6 +146,7 @@ struct lap_plan {
     lapeig::DevBuf<double> d_shift;
     lapeig::DevBuf<char> tmp_x, tmp_y;
     lapeig::DevBuf<char> chunk_part;  // per-chunk partial sums of the block product
+    std::unique_ptr<lapeig::SolverCache> jd_cache;  // single-vector solver work areas
 
     template <typename T>
     lapeig::Weights<T> weights() const;
