@@ -11,35 +11,13 @@
 //   k_ts_nn  Out = alpha A C + (addend | beta Out)  (C ka x kb column-major,
 //            staged in LDS): each wavefront owns 16-row blocks, so Out may
 //            overlap A (in-place rotation of a basis).
-// MFMA operand layout (wave64, 16x16x4): lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16]; accumulator element r of lane l is D[row][l % 16]
-// with row = 4 (l / 16) + r for the FP32 instruction and row = l / 16 + 4 r
-// for the FP64 one (both checked on the device).
+// (MFMA operand and accumulator layouts: see Mfma in lapeig_dev.h.)
 #include "lapeig_dev.h"
 #include "block_kernels.h"
 
 namespace lapeig {
 
 namespace {
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct Mfma<float> {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
 
 template <typename T, int TI, int TJ>
 __global__ __launch_bounds__(kBlock) void k_ts_tn(int n, const T *__restrict__ A, int lda, int ka,

@@ -2,6 +2,8 @@
 // host driver (jd.cpp) and the C ABI.
 #pragma once
 
+#include <algorithm>
+
 #include "lapeig_internal.h"
 
 namespace lapeig {
@@ -32,10 +34,14 @@ struct HostMirror {
     unsigned seq, pad2;
 };
 
+constexpr int kPipeQ = 14;  // widest projector of the one-launch-per-iteration PCG
+
 template <typename T>
 struct PcgState {
     T rho[2];   // rho = res' M res of the last two iterations, by parity
     T r0;       // norm of the right-hand side
+    // pipelined form: gamma, alpha and Q's of the last two iterations
+    T gam[2], alp[2], cs[2][16];
     int stop_seq, iters, breakdown;
     int total;  // products of all solves since the host last cleared it
 };
@@ -74,14 +80,22 @@ struct PcgWork {
     DevBuf<T> res, p, s, y;
     DevBuf<T> gq;    // G Q, row-major like Q
     DevBuf<T> part;  // two areas of per-workgroup partial sums (ping-pong)
+    // pipelined form: u = M res, w ~ A u, wh = D^{-1} w (two buffers), q, z;
+    // qq = [Q | D^{-1}Q] and gqq = G qq (row-major, 2q columns); K = Q'D^{-1}Q
+    DevBuf<T> u, w, wh, qv, z, qq, gqq, kmat, kpart;
     DevBuf<PcgState<T>> st;
     void ensure(int n, int ldq) {
         if (res.n < (size_t)n || !st.get()) {
             res.alloc(n); p.alloc(n); s.alloc(n); y.alloc(n);
+            u.alloc(n); w.alloc(n); wh.alloc(2 * (size_t)n); qv.alloc(n); z.alloc(n);
             part.alloc(2 * (size_t)pcg_max_groups() * 64);
+            kmat.alloc(256);
+            kpart.alloc((size_t)pcg_max_groups() * 256);
             st.alloc(1);
         }
         if (gq.n < (size_t)n * ldq) gq.alloc((size_t)n * ldq);
+        const size_t wq = 2 * (size_t)std::min(ldq, kPipeQ);
+        if (qq.n < (size_t)n * wq) { qq.alloc((size_t)n * wq); gqq.alloc((size_t)n * wq); }
     }
 };
 

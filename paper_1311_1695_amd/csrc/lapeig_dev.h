@@ -119,6 +119,30 @@ __device__ bool grid_reduce(const T (&acc)[NV], int nv, T *partial, unsigned *co
     return true;
 }
 
+// Matrix-core 16x16x4 multiply-accumulate, wave64.  Operand layout: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element r of
+// lane l is D[row(l, r)][l % 16] with row = 4 (l / 16) + r for the FP32
+// instruction and row = l / 16 + 4 r for the FP64 one (both checked on the
+// device).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
 // Deferred cross-workgroup sums.  A producer launch leaves one row of nv
 // partial sums per workgroup (plain stores); the launch after it, which the
 // kernel boundary makes them visible to, folds them in every workgroup in
@@ -126,17 +150,48 @@ __device__ bool grid_reduce(const T (&acc)[NV], int nv, T *partial, unsigned *co
 // no atomics and no cache maintenance inside either kernel.
 constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : v <= 2 ? 2 : v <= 4 ? 4 : v <= 8 ? 8 : v <= 16 ? 16 : v <= 32 ? 32 : 64; }
 
-template <typename T, int NV>
-__device__ __forceinline__ void write_partials(const T (&acc)[NV], int nv, T *__restrict__ part) {
-    static_assert(NV <= kWave, "at most 64 values per reduction");
-    __shared__ T red[kWavesPerBlock][NV];
+// Reduce-scatter of NV per-lane values over the wavefront (NV a power of
+// two): each butterfly step trades half of the remaining values with the
+// partner lane, so NV values cost NV - 1 + log2(64 / NV) shuffles instead of
+// 6 NV.  Afterwards v[0] holds the wavefront total of value idx, where idx
+// collects the halving bits of the lane; lanes that agree on them hold the
+// same total, and every total is added in one fixed order.
+template <typename T, int NV, int CNT, int M>
+__device__ __forceinline__ void rs_step(T (&v)[NV], int lane, int &idx) {
+    if constexpr (M >= 1) {
+        if constexpr (CNT > 1) {
+            constexpr int half = CNT / 2;
+            const bool up = (lane & M) != 0;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        if (j < nv) {
-            T s = wave_sum(acc[j]);
-            if (lane_id() == 0) red[wave_id()][j] = s;
+            for (int i = 0; i < half; ++i) {
+                const T keep = up ? v[half + i] : v[i];
+                const T give = up ? v[i] : v[half + i];
+                v[i] = keep + __shfl_xor(give, M, kWave);
+            }
+            if (up) idx += half;
+            rs_step<T, NV, half, M / 2>(v, lane, idx);
+        } else {
+            v[0] += __shfl_xor(v[0], M, kWave);
+            rs_step<T, NV, 1, M / 2>(v, lane, idx);
         }
     }
+}
+
+template <typename T, int NV>
+__device__ __forceinline__ int wave_reduce_scatter(T (&v)[NV]) {
+    static_assert((NV & (NV - 1)) == 0 && NV >= 1 && NV <= kWave, "NV must be a power of two <= 64");
+    int idx = 0;
+    rs_step<T, NV, NV, kWave / 2>(v, lane_id(), idx);
+    return idx;
+}
+
+// Leaves this workgroup's nv sums of acc (destroyed) in part[blockIdx.x][.].
+template <typename T, int NV>
+__device__ __forceinline__ void write_partials(T (&acc)[NV], int nv, T *__restrict__ part) {
+    static_assert(NV <= kWave, "at most 64 values per reduction");
+    __shared__ T red[kWavesPerBlock][NV];
+    const int idx = wave_reduce_scatter<T, NV>(acc);
+    if ((lane_id() & (kWave / NV - 1)) == 0 && idx < nv) red[wave_id()][idx] = acc[0];
     __syncthreads();
     if (threadIdx.x < nv) {
         T s = red[0][threadIdx.x];
@@ -147,26 +202,28 @@ __device__ __forceinline__ void write_partials(const T (&acc)[NV], int nv, T *__
 }
 
 // out[0..nv) = sum over the nb partial rows of part (row stride NV).  Thread
-// (g, j) adds rows g, g + G, g + 2G, ... of value j in row order; the G group
-// sums are then added in group order; out[nv..NV) is set to zero.
-// Synchronizes the workgroup.
+// (g, j) adds rows g, g + G, g + 2G, ... of value j in row order, with up to
+// 32 loads in flight (8 for 64 double values); the G group sums are then added in group order;
+// out[nv..NV) is set to zero.  Synchronizes the workgroup.
 template <typename T, int NV>
 __device__ __forceinline__ void fold_partials(const T *__restrict__ part, int nb, int nv, T *out) {
     constexpr int NVP = pow2_at_least(NV);
     constexpr int GROUPS = kBlock / NVP;
+    constexpr int U = (sizeof(T) == 8 && NV >= 64) ? 8 : 32;  // registers of the widest case
     __shared__ T fin[GROUPS][NVP];
     const int j = threadIdx.x % NVP, g = threadIdx.x / NVP;
     T s = T(0);
     if (j < nv) {
-        int b = g;
-        for (; b + 7 * GROUPS < nb; b += 8 * GROUPS) {
-            T a[8];
+        for (int b0 = g; b0 < nb; b0 += U * GROUPS) {
+            T a[U];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = part[(size_t)(b + u * GROUPS) * NV + j];
+            for (int u = 0; u < U; ++u) {
+                const int b = b0 + u * GROUPS;
+                a[u] = b < nb ? part[(size_t)b * NV + j] : T(0);
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += a[u];
+            for (int u = 0; u < U; ++u) s += a[u];
         }
-        for (; b < nb; b += GROUPS) s += part[(size_t)b * NV + j];
     }
     fin[g][j] = s;
     __syncthreads();

@@ -18,6 +18,8 @@
 //       res -= alpha (s - Q c2);  y = D^{-1} res;    partials res'res, res'y, Q'y
 // A device flag turns the remaining launches into no-ops once the iteration
 // stops, so the whole solve is enqueued without host round trips.
+#include <cstdlib>
+
 #include "lapeig_dev.h"
 #include "jd_kernels.h"
 
@@ -136,25 +138,35 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ps(Graph g, Weights<T> w, const 
     T acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = T(0);
+    // narrow projectors: the rows of Q and GQ are requested before the
+    // gathers; wide ones (too many registers) load them after
+    constexpr bool PREF = NV <= 16;
+    constexpr int NQP = PREF ? NQ : 1;
     auto pre = [&](int i) {
-        PsRow<T, NQ> d;
+        PsRow<T, NQP> d;
         d.p = INIT ? T(0) : p[i];
         d.s = INIT ? T(0) : s[i];
-        const T *qi = Q + (size_t)i * ldq;
-        const T *gi = GQ + (size_t)i * ldq;
+        if (PREF) {
+            const T *qi = Q + (size_t)i * ldq;
+            const T *gi = GQ + (size_t)i * ldq;
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-            d.qv[j] = j < q ? qi[j] : T(0);
-            d.gq[j] = j < q ? gi[j] : T(0);
+            for (int j = 0; j < NQP; ++j) {
+                d.qv[j] = j < q ? qi[j] : T(0);
+                d.gq[j] = j < q ? gi[j] : T(0);
+            }
         }
         return d;
     };
-    for_each_row_pre<T, Wt, false>(g, w, y, pre, [&](int i, T yi, T gyi, T, const PsRow<T, NQ> &d) {
+    for_each_row_pre<T, Wt, false>(g, w, y, pre, [&](int i, T yi, T gyi, T, const PsRow<T, NQP> &d) {
+        const T *qi = Q + (size_t)i * ldq;
+        const T *gi = GQ + (size_t)i * ldq;
+        auto qval = [&](int j) { return PREF ? d.qv[j < NQP ? j : 0] : (j < q ? qi[j] : T(0)); };
+        auto gval = [&](int j) { return PREF ? d.gq[j < NQP ? j : 0] : (j < q ? gi[j] : T(0)); };
         T qc = T(0), gc = T(0);
 #pragma unroll
         for (int j = 0; j < NQ; ++j) {
-            qc += d.qv[j] * tot[OFF + j];
-            gc += d.gq[j] * tot[OFF + j];
+            qc += qval(j) * tot[OFF + j];
+            gc += gval(j) * tot[OFF + j];
         }
         T pi = yi - qc;
         T si = ((gyi - th * yi) - gc) + th * qc;
@@ -167,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ps(Graph g, Weights<T> w, const 
         acc[0] += pi * si;
 #pragma unroll
         for (int j = 0; j < NV - 1; ++j)
-            if (j < NQ) acc[1 + j] += d.qv[j] * si;
+            if (j < NQ) acc[1 + j] += qval(j) * si;
     });
     write_partials<T, NV>(acc, q + 1, part_out);
 }
@@ -188,16 +200,20 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
                                                        const T *__restrict__ part_in, int nb_in,
                                                        T *__restrict__ part_out, PcgState<T> *st, int sq, int it) {
     constexpr int NQ = NV - 2;
+    constexpr bool PREF = NV <= 16;  // wide projectors: Q rows are loaded where used
+    constexpr int NQP = PREF ? NQ : 1;
     auto load = [&](int i) {
-        UpRow<T, NQ> d;
+        UpRow<T, NQP> d;
         d.t = t[i];
         d.p = p[i];
         d.res = res[i];
         d.s = s[i];
         d.dinv = dinv[i];
-        const T *qi = Q + (size_t)i * ldq;
+        if (PREF) {
+            const T *qi = Q + (size_t)i * ldq;
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) d.qv[j] = j < q ? qi[j] : T(0);
+            for (int j = 0; j < NQP; ++j) d.qv[j] = j < q ? qi[j] : T(0);
+        }
         return d;
     };
     // the first row's operands and the scalars are requested before the fold
@@ -205,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
     const int stride = gridDim.x * blockDim.x;
     const int stop_v = st->stop_seq;
     const T rho = st->rho[(it - 1) & 1];
-    UpRow<T, NQ> d0;
+    UpRow<T, NQP> d0;
     if (i0 < n) d0 = load(i0);
     __shared__ T tot[NV];
     fold_partials<T, NV>(part_in, nb_in, q + 1, tot);
@@ -231,10 +247,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = T(0);
     for (int i = i0; i < n; i += stride) {
-        const UpRow<T, NQ> d = i == i0 ? d0 : load(i);
+        const UpRow<T, NQP> d = i == i0 ? d0 : load(i);
+        const T *qi = Q + (size_t)i * ldq;
+        auto qval = [&](int j) { return PREF ? d.qv[j < NQP ? j : 0] : (j < q ? qi[j] : T(0)); };
         T proj = T(0);
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) proj += d.qv[j] * tot[1 + j];
+        for (int j = 0; j < NQ; ++j) proj += qval(j) * tot[1 + j];
         t[i] = d.t + alpha * d.p;
         const T ri = d.res - alpha * (d.s - proj);
         res[i] = ri;
@@ -243,9 +261,339 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
         acc[0] += ri * ri;
         acc[1] += ri * yi;
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) acc[2 + j] += d.qv[j] * yi;
+        for (int j = 0; j < NQ; ++j) acc[2 + j] += qval(j) * yi;
     }
     write_partials<T, NV>(acc, q + 2, part_out);
+}
+
+// ===========================================================================
+// Pipelined form: one launch per iteration (projectors of up to kPipeQ
+// columns).  The recurrences of Ghysels and Vanroose's pipelined CG carry
+// A u and the preconditioned products along, so each launch needs only the
+// inner products of the launch before it:
+//   u = M res,  w = A u,  m = M w,  n = A m,  s = A p,  q = M s,  z = A q
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+//   z = n + beta z,  q = m + beta q,  s = w + beta s,  p = u + beta p
+//   t += alpha p,  res -= alpha s,  u -= alpha q,  w -= alpha z
+// with gamma = res'u and delta = w'u.  The projections stay exact: w, s and
+// z are kept without their Q components (w~ = (G - theta I) u etc.), whose
+// coefficients follow from folded inner products: Q'w~ directly, Q's~ by
+// its own recurrence, and m = M w = D^{-1}(w~ - Q c_w) - Q c_m with
+// c_w = Q'w~, c_m = Q'D^{-1}w~ - K c_w, K = Q'D^{-1}Q.  The product
+// n~ = (G - theta I) m gathers only wh = D^{-1} w~ and corrects with the
+// rows of G Q and G D^{-1} Q, formed once per solve.
+constexpr int kPP = 16;  // init1 / init2 partials: q + 1 values
+constexpr int kPN = 32;  // init3 / iteration partials, fixed layout:
+// [0] res'u  [1] w~'u  [2] res'res  [3 + j] Q'w~  [17 + j] Q'wh
+constexpr int kCW = 3, kCD = 3 + kPipeQ, kPNV = 3 + 2 * kPipeQ;
+
+// init1: res = -r, t = 0, qq rows [Q_i | dinv_i Q_i]; partials r'r, -Q'r;
+// and this workgroup's share of K = Q'D^{-1}Q on the matrix cores (each
+// wavefront accumulates 4-row chunks into one 16x16 tile).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__restrict__ r, T *__restrict__ res,
+                                                     T *__restrict__ t, const T *__restrict__ Q, int ldq, int q,
+                                                     const T *__restrict__ dinv, T *__restrict__ qq,
+                                                     T *__restrict__ part_out, T *__restrict__ kpart,
+                                                     PcgState<T> *st) {
+    if (leader()) {
+        st->stop_seq = 0;
+        st->iters = 0;
+        st->breakdown = 0;
+    }
+    const int q2 = 2 * q;
+    T acc[kPP];
+#pragma unroll
+    for (int j = 0; j < kPP; ++j) acc[j] = T(0);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const T ri = (T)r[i];
+        const T di = dinv[i];
+        res[i] = -ri;
+        t[i] = T(0);
+        acc[0] += ri * ri;
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j)
+            if (j < q) {
+                const T qij = Q[(size_t)i * ldq + j];
+                acc[1 + j] -= qij * ri;
+                qq[(size_t)i * q2 + j] = qij;
+                qq[(size_t)i * q2 + q + j] = di * qij;
+            }
+    }
+    write_partials<T, kPP>(acc, q + 1, part_out);
+
+    using V4 = typename Mfma<T>::v4;
+    V4 kc = V4{T(0), T(0), T(0), T(0)};
+    const int lane = lane_id(), mi = lane & 15, kk = lane >> 4;
+    const int step = gridDim.x * kWavesPerBlock * 4;
+    for (int k0 = (blockIdx.x * kWavesPerBlock + wave_id()) * 4; k0 < n; k0 += step) {
+        const int row = k0 + kk;
+        T a = T(0), b = T(0);
+        if (row < n && mi < q) {
+            a = Q[(size_t)row * ldq + mi];
+            b = dinv[row] * a;
+        }
+        kc = Mfma<T>::mac(a, b, kc);
+    }
+    __shared__ T ks[256];
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+        if (wave_id() == w)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int at = Mfma<T>::row(lane, e) * 16 + mi;
+                ks[at] = (w == 0 ? T(0) : ks[at]) + kc[e];
+            }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) kpart[(size_t)blockIdx.x * 256 + e] = ks[e];
+}
+
+// init2: K = sum of the Gram tiles (one wavefront per entry); r0 = ||r||,
+// c0 = -Q'r, stop if r = 0; res -= Q c0; yh = D^{-1} res;  partials res'yh, Q'yh
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res, T *__restrict__ yh,
+                                                     const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
+                                                     int q, const T *__restrict__ part_in, int nb_in,
+                                                     T *__restrict__ part_out, const T *__restrict__ kpart, int nk,
+                                                     T *__restrict__ kmat, PcgState<T> *st) {
+    __shared__ T tot[kPP];
+    fold_partials<T, kPP>(part_in, nb_in, q + 1, tot);
+    {
+        const int lane = lane_id();
+        for (int e = blockIdx.x * kWavesPerBlock + wave_id(); e < 256; e += gridDim.x * kWavesPerBlock) {
+            T sum = T(0);
+            for (int b = lane; b < nk; b += kWave) sum += kpart[(size_t)b * 256 + e];
+            sum = wave_sum(sum);
+            if (lane == 0) kmat[e] = sum;
+        }
+    }
+    const T r0 = sqrt(tot[0]);
+    if (leader()) {
+        st->r0 = r0;
+        if (!(r0 > T(0))) st->stop_seq = 2;
+    }
+    if (!(r0 > T(0))) return;
+    T acc[kPP];
+#pragma unroll
+    for (int j = 0; j < kPP; ++j) acc[j] = T(0);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const T *qi = Q + (size_t)i * ldq;
+        T qv[kPipeQ];
+        T proj = T(0);
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            qv[j] = j < q ? qi[j] : T(0);
+            proj += qv[j] * tot[1 + j];
+        }
+        const T ri = res[i] - proj;
+        res[i] = ri;
+        const T yi = dinv[i] * ri;
+        yh[i] = yi;
+        acc[0] += ri * yi;
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) acc[1 + j] += qv[j] * yi;
+    }
+    write_partials<T, kPP>(acc, q + 1, part_out);
+}
+
+// init3: c_y = Q'yh;  u = yh - Q c_y;  w~ = (G - theta I) u, gathered as
+// (G - theta I) yh - GQ c_y + theta Q c_y;  wh = D^{-1} w~;  iteration partials
+template <typename T>
+struct P3Row {
+    T q[kPipeQ], gq[kPipeQ];
+    T dinv, res;
+};
+
+template <typename T, bool Wt>
+__global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, const double *__restrict__ theta,
+                                                     const T *__restrict__ Q, int ldq, const T *__restrict__ gqq,
+                                                     int q, const T *__restrict__ dinv, const T *__restrict__ res,
+                                                     const T *__restrict__ yh, T *__restrict__ u, T *__restrict__ wv,
+                                                     T *__restrict__ wh, const T *__restrict__ part_in, int nb_in,
+                                                     T *__restrict__ part_out, const PcgState<T> *st, int sq) {
+    const int stop_v = st->stop_seq;
+    const T th = (T)theta[0];
+    __shared__ T tot[kPP];
+    fold_partials<T, kPP>(part_in, nb_in, q + 1, tot);
+    if (stop_v != 0 && stop_v <= sq) return;
+    const int q2 = 2 * q;
+    T acc[kPN];
+#pragma unroll
+    for (int j = 0; j < kPN; ++j) acc[j] = T(0);
+    auto pre = [&](int i) {
+        P3Row<T> d;
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            d.q[j] = j < q ? Q[(size_t)i * ldq + j] : T(0);
+            d.gq[j] = j < q ? gqq[(size_t)i * q2 + j] : T(0);
+        }
+        d.dinv = dinv[i];
+        d.res = res[i];
+        return d;
+    };
+    for_each_row_pre<T, Wt, false>(g, w, yh, pre, [&](int i, T yi, T gyi, T, const P3Row<T> &d) {
+        T qc = T(0), gc = T(0);
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            qc += d.q[j] * tot[1 + j];
+            gc += d.gq[j] * tot[1 + j];
+        }
+        const T ui = yi - qc;
+        const T wi = ((gyi - th * yi) - gc) + th * qc;
+        const T hi = d.dinv * wi;
+        u[i] = ui;
+        wv[i] = wi;
+        wh[i] = hi;
+        acc[0] += d.res * ui;
+        acc[1] += wi * ui;
+        acc[2] += d.res * d.res;
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            acc[kCW + j] += d.q[j] * wi;
+            acc[kCD + j] += d.q[j] * hi;
+        }
+    });
+    write_partials<T, kPN>(acc, kPNV, part_out);
+}
+
+// Iteration i (launch 3 + i): fold gamma, delta, ||res||^2, c_w, c_dw;
+// stop test (i > 0); beta, alpha or breakdown; then the row updates above.
+template <typename T>
+struct PIRow {
+    T q[kPipeQ], gq[kPipeQ], gdq[kPipeQ];
+    T dinv, t, res, u, w, p, s, qv, z;
+};
+
+template <typename T, bool Wt>
+__global__ __launch_bounds__(kBlock) void k_pp_iter(
+    Graph g, Weights<T> w, const double *__restrict__ theta, const T *__restrict__ Q, int ldq,
+    const T *__restrict__ gqq, int q, const T *__restrict__ kmat, const T *__restrict__ dinv, T *__restrict__ t,
+    T *__restrict__ res, T *__restrict__ u, T *__restrict__ wv, const T *__restrict__ wh_in,
+    T *__restrict__ wh_out, T *__restrict__ p, T *__restrict__ s, T *__restrict__ qv, T *__restrict__ z,
+    const T *__restrict__ part_in, int nb_in, T *__restrict__ part_out, PcgState<T> *st, int sq, int it, T rtol) {
+    // scalars and the small operands first, so that their latency overlaps the fold
+    const int stop_v = st->stop_seq;
+    const T th = (T)theta[0];
+    const T r0 = st->r0;
+    const T gam_prev = st->gam[(it + 1) & 1], alp_prev = st->alp[(it + 1) & 1];
+    const int tj = threadIdx.x;
+    T krow[kPipeQ];
+    T cs_prev = T(0);
+    if (tj < q) {
+#pragma unroll
+        for (int a = 0; a < kPipeQ; ++a) krow[a] = a < q ? kmat[tj * 16 + a] : T(0);
+        if (it > 0) cs_prev = st->cs[(it + 1) & 1][tj];
+    }
+    __shared__ T tot[kPN];
+    __shared__ T coef[3][kPipeQ];  // c_w, c_s, c_m
+    fold_partials<T, kPN>(part_in, nb_in, kPNV, tot);
+    if (stop_v != 0 && stop_v <= sq) return;
+    const T gam = tot[0], dlt = tot[1], rr = tot[2];
+    if (it > 0 && sqrt(rr) <= rtol * r0) {
+        if (leader()) st->stop_seq = sq + 1;
+        return;
+    }
+    const T beta = it > 0 ? gam / gam_prev : T(0);
+    const T den = it > 0 ? dlt - beta * gam / alp_prev : dlt;  // p'A p
+    if (!(den > T(0))) {  // the projected operator is indefinite along p
+        if (leader()) {
+            st->stop_seq = sq + 1;
+            st->breakdown = it + 1;
+            st->total += 1;  // the product of the failed step counts
+        }
+        // no step was taken before the breakdown: return M(-r), which u holds
+        if (it == 0)
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += gridDim.x * blockDim.x) t[i] = u[i];
+        return;
+    }
+    const T alpha = gam / den;
+    if (tj < kPipeQ) {
+        T cw = T(0), cs = T(0), cm = T(0);
+        if (tj < q) {
+            cw = tot[kCW + tj];
+            cs = cw + beta * cs_prev;
+            T kc = T(0);
+#pragma unroll
+            for (int a = 0; a < kPipeQ; ++a) kc += krow[a] * tot[kCW + a];
+            cm = tot[kCD + tj] - kc;
+            if (blockIdx.x == 0) st->cs[it & 1][tj] = cs;
+        }
+        coef[0][tj] = cw;
+        coef[1][tj] = cs;
+        coef[2][tj] = cm;
+    }
+    if (leader()) {
+        st->gam[it & 1] = gam;
+        st->alp[it & 1] = alpha;
+        st->iters = it + 1;
+        st->total += 1;
+    }
+    __syncthreads();
+    const int q2 = 2 * q;
+    const bool first = it == 0;
+    T acc[kPN];
+#pragma unroll
+    for (int j = 0; j < kPN; ++j) acc[j] = T(0);
+    auto pre = [&](int i) {
+        PIRow<T> d;
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            d.q[j] = j < q ? Q[(size_t)i * ldq + j] : T(0);
+            d.gq[j] = j < q ? gqq[(size_t)i * q2 + j] : T(0);
+            d.gdq[j] = j < q ? gqq[(size_t)i * q2 + q + j] : T(0);
+        }
+        d.dinv = dinv[i];
+        d.t = t[i];
+        d.res = res[i];
+        d.u = u[i];
+        d.w = wv[i];
+        d.p = first ? T(0) : p[i];
+        d.s = first ? T(0) : s[i];
+        d.qv = first ? T(0) : qv[i];
+        d.z = first ? T(0) : z[i];
+        return d;
+    };
+    for_each_row_pre<T, Wt, false>(g, w, wh_in, pre, [&](int i, T hi, T ghi, T, const PIRow<T> &d) {
+        T qcw = T(0), qcs = T(0), qcm = T(0), gcw = T(0), gcm = T(0);
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            qcw += d.q[j] * coef[0][j];
+            qcs += d.q[j] * coef[1][j];
+            qcm += d.q[j] * coef[2][j];
+            gcw += d.gdq[j] * coef[0][j];
+            gcm += d.gq[j] * coef[2][j];
+        }
+        const T dqcw = d.dinv * qcw;
+        const T mi = (hi - dqcw) - qcm;                                         // m = M w
+        const T ni = ((ghi - th * hi) - (gcw - th * dqcw)) - (gcm - th * qcm);  // (G - theta I) m
+        const T zi = first ? ni : ni + beta * d.z;
+        const T qi = first ? mi : mi + beta * d.qv;
+        const T si = first ? d.w : d.w + beta * d.s;
+        const T pi = first ? d.u : d.u + beta * d.p;
+        const T tn = d.t + alpha * pi;
+        const T rn = d.res - alpha * (si - qcs);
+        const T un = d.u - alpha * qi;
+        const T wn = d.w - alpha * zi;
+        const T hn = d.dinv * wn;
+        t[i] = tn;
+        res[i] = rn;
+        u[i] = un;
+        wv[i] = wn;
+        wh_out[i] = hn;
+        p[i] = pi;
+        s[i] = si;
+        qv[i] = qi;
+        z[i] = zi;
+        acc[0] += rn * un;
+        acc[1] += wn * un;
+        acc[2] += rn * rn;
+#pragma unroll
+        for (int j = 0; j < kPipeQ; ++j) {
+            acc[kCW + j] += d.q[j] * wn;
+            acc[kCD + j] += d.q[j] * hn;
+        }
+    });
+    write_partials<T, kPN>(acc, kPNV, part_out);
 }
 
 inline int vgrid(int n) {
@@ -295,6 +643,55 @@ void enqueue_nv(const lap_plan &P, const double *theta, const T *Q, int ldq, int
     LAP_HIP(hipGetLastError());
 }
 
+template <typename T>
+void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
+                       PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
+    const int n = P.n;
+    const int gv = vgrid(n);
+    const int gr = row_grid(P.g, pcg_max_groups());
+    const int q2 = 2 * q;
+    LAP_REQUIRE(w.qq.n >= (size_t)n * q2 && w.kpart.n >= (size_t)gv * 256, LAP_EDEVICE,
+                "PCG work area too small for the projector");
+    T *pa = w.part.get();
+    T *pb = pa + (size_t)pcg_max_groups() * 64;
+    PcgState<T> *st = w.st.get();
+    const T *dinv = P.dinv<T>();
+    const T tol = (T)rtol;
+    T *wh0 = w.wh.get(), *wh1 = wh0 + n;
+    hipLaunchKernelGGL((k_pp_init1<T>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q, dinv,
+                       w.qq.get(), pa, w.kpart.get(), st);
+    if (q > 0) spmm<T>(P, q2, w.qq.get(), q2, w.gqq.get(), q2, nullptr, s);
+    hipLaunchKernelGGL((k_pp_init2<T>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq, q, pa, gv,
+                       pb, w.kpart.get(), gv, w.kmat.get(), st);
+    if (P.weighted)
+        hipLaunchKernelGGL((k_pp_init3<T, true>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
+                           w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
+    else
+        hipLaunchKernelGGL((k_pp_init3<T, false>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
+                           w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
+    for (int it = 0; it < itmax; ++it) {
+        T *pin = (it & 1) ? pb : pa;
+        T *pout = (it & 1) ? pa : pb;
+        const T *hin = (it & 1) ? wh1 : wh0;
+        T *hout = (it & 1) ? wh0 : wh1;
+        if (P.weighted)
+            hipLaunchKernelGGL((k_pp_iter<T, true>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
+                               w.gqq.get(), q, w.kmat.get(), dinv, t, w.res.get(), w.u.get(), w.w.get(), hin, hout,
+                               w.p.get(), w.s.get(), w.qv.get(), w.z.get(), pin, gr, pout, st, 3 + it, it, tol);
+        else
+            hipLaunchKernelGGL((k_pp_iter<T, false>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q,
+                               ldq, w.gqq.get(), q, w.kmat.get(), dinv, t, w.res.get(), w.u.get(), w.w.get(), hin,
+                               hout, w.p.get(), w.s.get(), w.qv.get(), w.z.get(), pin, gr, pout, st, 3 + it, it, tol);
+    }
+    LAP_HIP(hipGetLastError());
+}
+
+// The one-launch form unless the projector is too wide for it (or the
+// two-launch form is asked for, which the tests use to cover both).
+inline bool use_pipelined(int q) {
+    return q <= kPipeQ && std::getenv("LAPEIG_PCG_TWO_LAUNCH") == nullptr;
+}
+
 // ---- conversions used by the C ABI entry point
 template <typename T>
 __global__ void k_pack_q(int n, int q, const double *__restrict__ Qc, const int *__restrict__ map, T *__restrict__ Qr,
@@ -335,7 +732,9 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
     for (int c = 0; c < b; ++c) {
         LAP_HIP(hipMemcpyAsync(th.get(), theta_host + c, sizeof(double), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_gather_col, dim3(gv), dim3(kBlock), 0, s, n, R + (size_t)c * n, map, r.get());
-        if (q <= 14)
+        if (use_pipelined(q))
+            enqueue_pipelined<T>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
+        else if (q <= 14)
             enqueue_nv<T, 16>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
         else
             enqueue_nv<T, 64>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
@@ -355,7 +754,9 @@ template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
                  PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
     LAP_REQUIRE(q >= 0 && q <= kMaxQ, LAP_EUNSUPPORTED, "projector wider than 62 columns");
-    if (q <= 14)
+    if (use_pipelined(q))
+        enqueue_pipelined<T>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
+    else if (q <= 14)
         enqueue_nv<T, 16>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
     else
         enqueue_nv<T, 64>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);

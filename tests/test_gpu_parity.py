@@ -167,8 +167,16 @@ def _pcg_case(name, q, seed):
     return L, Q, theta, r
 
 
-@pytest.mark.parametrize("name,q", [("pa5k", 2), ("cl30k", 11), ("cl30k_w", 5), ("star9000", 3)])
-def test_pcg_fp64_matches_oracle_elementwise(name, q):
+# q <= 14 runs the one-launch-per-iteration (pipelined) form, q = 16 and the
+# environment switch run the two-launch form: both must reproduce the oracle.
+@pytest.mark.parametrize("name,q,form", [("pa5k", 2, "pipelined"), ("cl30k", 11, "pipelined"),
+                                         ("cl30k_w", 5, "pipelined"), ("star9000", 3, "pipelined"),
+                                         ("pa5k", 1, "pipelined"), ("cl30k", 14, "pipelined"),
+                                         ("cl30k", 11, "two_launch"), ("cl30k_w", 5, "two_launch"),
+                                         ("cl30k", 16, "two_launch")])
+def test_pcg_fp64_matches_oracle_elementwise(name, q, form, monkeypatch):
+    if form == "two_launch":
+        monkeypatch.setenv("LAPEIG_PCG_TWO_LAUNCH", "1")
     L, Q, theta, r = _pcg_case(name, q, 7)
     plan = lap.Plan(L)
     t_ref, mvp_ref, br_ref = oracle.pcg_correction(L, theta, Q, r, precond=oracle.PREC_JACOBI, itmax=20, rtol=1e-2)
