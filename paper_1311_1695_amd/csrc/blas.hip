@@ -144,19 +144,40 @@ constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
 
 __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restrict__ Hin, int ldh,
                                                    double *__restrict__ theta, double *__restrict__ Y,
-                                                   int ldy, JDStatus *st) {
+                                                   int ldy, int warm, JDStatus *st) {
     extern __shared__ double lds[];
     const int me = (m + 1) & ~1;  // even size; index m is a dummy when m is odd
     double *A = lds;              // me x me, row-major
     double *Z = A + me * me;      // me x me, row-major accumulator of rotations
     __shared__ double cs[kRRMax / 2], sn[kRRMax / 2];
+    __shared__ int pp[kRRMax / 2], qq[kRRMax / 2];
     __shared__ int any_rot;
     __shared__ double fro2;
     const int tid = threadIdx.x;
-    for (int t = tid; t < me * me; t += blockDim.x) {
-        const int i = t / me, j = t % me;
-        A[t] = (i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0;
-        Z[t] = (i == j) ? 1.0 : 0.0;
+    if (warm && m >= 2) {
+        // H = [H1 h; h' eta] with H1 = Yp diag(theta) Yp' from the previous
+        // call (theta and Y still hold it): start from the arrowhead
+        // [diag(theta) Yp'h; h'Yp eta] and accumulate onto Z = diag(Yp, 1)
+        const int mp = m - 1;
+        for (int t = tid; t < me * me; t += blockDim.x) {
+            const int i = t / me, j = t % me;
+            Z[t] = (i < mp && j < mp) ? Y[(size_t)j * ldy + i] : (i == j ? 1.0 : 0.0);
+            A[t] = (i == j && i < mp) ? theta[i] : 0.0;
+        }
+        __syncthreads();
+        for (int i = tid; i < mp; i += blockDim.x) {
+            double b = 0.0;
+            for (int r = 0; r < mp; ++r) b += Z[r * me + i] * Hin[(size_t)mp * ldh + r];
+            A[i * me + mp] = b;
+            A[mp * me + i] = b;
+        }
+        if (tid == 0) A[mp * me + mp] = Hin[(size_t)mp * ldh + mp];
+    } else {
+        for (int t = tid; t < me * me; t += blockDim.x) {
+            const int i = t / me, j = t % me;
+            A[t] = (i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0;
+            Z[t] = (i == j) ? 1.0 : 0.0;
+        }
     }
     __syncthreads();
     {
@@ -175,78 +196,58 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     }
     const double tol = 2.220446049250313e-16 * sqrt(fro2) / (double)me;
     const int half = me / 2;
-    // pair k of a round: players k and me-1-k of the tournament table, whose
-    // position 0 stays fixed while the others rotate by one each round
-    auto pair_of = [&](int k, int round, int &p, int &q) {
-        const int a = k == 0 ? 0 : 1 + (k - 1 + round) % (me - 1);
-        const int kb = me - 1 - k;
-        const int b = kb == 0 ? 0 : 1 + (kb - 1 + round) % (me - 1);
-        p = a < b ? a : b;
-        q = a < b ? b : a;
-    };
     int sweeps = 0;
     for (; sweeps < 60 && me > 1; ++sweeps) {
         if (tid == 0) any_rot = 0;
         __syncthreads();
         for (int round = 0; round < me - 1; ++round) {
-            // phase 1: the rotation of every pair (symmetric Schur 2x2)
+            // tournament pairing: position 0 fixed, the others rotate
             if (tid < half) {
-                int p, q;
-                pair_of(tid, round, p, q);
-                double c = 1.0, sv = 0.0;
+                auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
+                int a = player(tid), b = player(me - 1 - tid);
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
                 const double apq = A[p * me + q];
                 if (fabs(apq) > tol) {
                     const double tau = (A[q * me + q] - A[p * me + p]) / (2.0 * apq);
                     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
-                    sv = t * c;
+                    s = t * c;
                     any_rot = 1;
                 }
-                cs[tid] = c;
-                sn[tid] = sv;
+                pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
             }
             __syncthreads();
-            // phase 2: A <- J'AJ by 2x2 blocks (pairs k <= l; block (l, k) is
-            // the mirror), Z <- ZJ by (row, pair); all operands are read
-            // before anything is written, and no two threads share an entry
-            for (int e = tid; e < half * half; e += blockDim.x) {
-                const int k = e / half, l = e % half;
-                if (k > l) continue;
-                const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
-                if (sk == 0.0 && sl == 0.0) continue;
-                int pk, qk, pl, ql;
-                pair_of(k, round, pk, qk);
-                pair_of(l, round, pl, ql);
-                const double b00 = A[pk * me + pl], b01 = A[pk * me + ql];
-                const double b10 = A[qk * me + pl], b11 = A[qk * me + ql];
-                if (k == l) {
-                    // diagonal block: the pair's own rotation annihilates b01
-                    const double t = ck != 0.0 ? sk / ck : 0.0;
-                    A[pk * me + pk] = b00 - t * b01;
-                    A[qk * me + qk] = b11 + t * b01;
-                    A[pk * me + qk] = 0.0;
-                    A[qk * me + pk] = 0.0;
-                } else {
-                    // rows by pair k, then columns by pair l
-                    const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
-                    const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
-                    const double n00 = cl * r00 - sl * r01, n01 = sl * r00 + cl * r01;
-                    const double n10 = cl * r10 - sl * r11, n11 = sl * r10 + cl * r11;
-                    A[pk * me + pl] = n00; A[pl * me + pk] = n00;
-                    A[pk * me + ql] = n01; A[ql * me + pk] = n01;
-                    A[qk * me + pl] = n10; A[pl * me + qk] = n10;
-                    A[qk * me + ql] = n11; A[ql * me + qk] = n11;
+            // rows: A <- J' A
+            for (int t = tid; t < half * me; t += blockDim.x) {
+                const int k = t / me, j = t % me;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                if (s != 0.0) {
+                    const double ap = A[p * me + j], aq = A[q * me + j];
+                    A[p * me + j] = c * ap - s * aq;
+                    A[q * me + j] = s * ap + c * aq;
                 }
             }
-            for (int e = tid; e < me * half; e += blockDim.x) {
-                const int i = e / half, k = e % half;
-                const double ck = cs[k], sk = sn[k];
-                if (sk == 0.0) continue;
-                int p, q;
-                pair_of(k, round, p, q);
-                const double zp = Z[i * me + p], zq = Z[i * me + q];
-                Z[i * me + p] = ck * zp - sk * zq;
-                Z[i * me + q] = sk * zp + ck * zq;
+            __syncthreads();
+            // columns: A <- A J, Z <- Z J
+            for (int t = tid; t < half * me; t += blockDim.x) {
+                const int k = t / me, i = t % me;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                if (s != 0.0) {
+                    const double ap = A[i * me + p], aq = A[i * me + q];
+                    A[i * me + p] = c * ap - s * aq;
+                    A[i * me + q] = s * ap + c * aq;
+                    const double zp = Z[i * me + p], zq = Z[i * me + q];
+                    Z[i * me + p] = c * zp - s * zq;
+                    Z[i * me + q] = s * zp + c * zq;
+                }
+            }
+            __syncthreads();
+            if (tid < half && sn[tid] != 0.0) {
+                A[pp[tid] * me + qq[tid]] = 0.0;
+                A[qq[tid] * me + pp[tid]] = 0.0;
             }
             __syncthreads();
         }
@@ -509,7 +510,8 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
     LAP_HIP(hipGetLastError());
 }
 
-void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s) {
+void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
+           bool warm) {
     LAP_REQUIRE(m >= 1 && m <= kRRMax, LAP_EUNSUPPORTED, "projected matrix larger than 96");
     const int me = (m + 1) & ~1;
     const size_t lds = 2 * (size_t)me * me * sizeof(double);
@@ -522,7 +524,7 @@ void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, J
     // up to 32 columns a single wavefront does it: every barrier of the
     // round-by-round rotations is then nearly free
     const int threads = me <= 32 ? kWave : kBlock;
-    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, st);
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, warm ? 1 : 0, st);
     LAP_HIP(hipGetLastError());
 }
 

@@ -173,6 +173,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         for (int c = 0; c < nz; ++c) { lam.push_back(0.0); resid.push_back(0.0); }
     }
     int nx = nz, m = 0, it = 0;
+    int y_rows = 0;  // order of the block of H that theta and Y diagonalize
     long long mvp = 0, inner = 0;
     long long start_col = 0;
     lap_status status = LAP_OK;
@@ -223,7 +224,9 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         bool first = true;
         for (;;) {
             // step 5: eigenpairs of H; step 6: Ritz vector and residual
-            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s);
+            // warm start when theta and Y still diagonalize the leading block
+            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s, y_rows == m - 1);
+            y_rows = m;
             Vb = B.get() + (size_t)nx * n;
             jd_ritz<T>(n, Vb, W.get(), m, Y.get(), theta.get(), u.get(), r.get(), Q.get(), ldq, nx, rs, st.get(), s,
                        hm, ++seq);
@@ -254,6 +257,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
             ++nx;
             --m;
             jd_hdiag(H.get(), mmax, m, theta.get(), 1, s);
+            y_rows = 0;
             if (nx >= k) { need_pcg = false; break; }
             if (m == 0) {
                 need_pcg = false;
@@ -275,6 +279,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
             jd_rotate(n, m, Y.get(), mmax, Vb, Vb, 0, mmin, nullptr, W.get(), W.get(), 0, mmin, s);
             jd_hdiag(H.get(), mmax, mmin, theta.get(), 0, s);
             m = mmin;
+            y_rows = 0;
         }
         // step 8: correction equation with Q = [X u]
         {
