@@ -40,9 +40,18 @@ def spmv_bytes(n: int, nnz_a: int, elem: int = 4) -> int:
     return 4 * (n + 1) + 4 * nnz_a + 2 * elem * n
 
 
-def kernel_sources_sha() -> str:
+def pcg_iter_bytes(n: int, nnz_a: int, q: int, elem: int = 4) -> int:
+    """Algorithmic bytes of one iteration launch of the projected PCG
+    (k_pp_iter, unweighted): the CSR structure, one compulsory read of the
+    gathered vector wh, nine n-vectors read (dinv, t, res, u, w, p, s, q, z)
+    and nine written (t, res, u, w, wh, p, s, q, z), and the rows of Q, GQ
+    and G D^-1 Q (3q values per row)."""
+    return 4 * (n + 1) + 4 * nnz_a + elem * n * (1 + 9 + 9) + 3 * q * elem * n
+
+
+def kernel_sources_sha(files=("pcg.hip", "lapeig_dev.h", "lapeig_internal.h")) -> str:
     h = hashlib.sha256()
-    for f in ("spmv.hip", "lapeig_dev.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1311_1695_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -81,8 +90,48 @@ def time_spmv(lap, torch, plan, n, reps=200, dtype=None):
     return best  # seconds per launch
 
 
+PCG_Q = 10  # projector width of the roofline measurement: k = 10 pairs, as in the solve's last steps
+
+
+def time_pcg_iteration(lap, torch, np, plan, n, q=PCG_Q, reps=5):
+    """Average time of one iteration launch of the projected PCG in FP32:
+    lap_pcg with rtol = 1e-30 runs exactly itmax iteration launches, so the
+    difference of a 40- and a 10-iteration call, timed with HIP events on
+    the stream lap_pcg launches on, divided by 30, is one launch (its
+    dispatch gap included).  (Beyond about 50 iterations the FP32
+    recurrences of this system lose positivity and stop early.)  Q = [1/sqrt(n), q-1 random orthonormal
+    columns], theta = 0: the projected operator is positive definite, so no
+    breakdown ends the iteration early."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, q))
+    X[:, 0] = 1.0
+    Q = np.linalg.qr(X)[0]
+    r = rng.standard_normal(n)
+    r -= Q @ (Q.T @ r)
+    Qt = torch.tensor(Q.T.copy(), device="cuda")
+    Rt = torch.tensor(r[None, :].copy(), device="cuda")
+    Tt = torch.zeros_like(Rt)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run(its):
+        best = None
+        for _ in range(reps):
+            e0.record(s)
+            got = lap.lap_pcg(plan, 0.0, Qt, Rt, Tt, itmax=its, rtol=1e-30, dtype="f32", stream=s)
+            e1.record(s)
+            e1.synchronize()
+            assert int(got[0]) == its, "the timing run stopped early"
+            t = e0.elapsed_time(e1) * 1e-3
+            best = t if best is None else min(best, t)
+        return best
+
+    run(40)
+    return (run(40) - run(10)) / 30.0
+
+
 def traffic_from_profile(sha: str, nbytes_alg: int):
-    path = os.path.join(ROOT, "profiles", "spmv_f32_cl30k_pmc.json")
+    path = os.path.join(ROOT, "profiles", "pp_iter_f32_cl30k_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -171,6 +220,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time the SpMV on larger graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--spmv-only", action="store_true", help="only the product kernel loop (for profiling)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the PCG iteration timing and a copy of known size (for profiling)")
     ap.add_argument("--extra", action="store_true",
                     help="also time the other workloads (pa5k FP64; cl330k block JD)")
     args = ap.parse_args()
@@ -192,7 +243,18 @@ def main():
     nnz_a = L.nnz - L.n
     plan = lap.Plan(L)
 
-    # ---- the product kernel: live timing for the roofline
+    # ---- the dominant kernel, one PCG iteration launch: live timing for the roofline
+    t_pcg = time_pcg_iteration(lap, torch, np, plan, L.n)
+    alg_pcg = pcg_iter_bytes(L.n, nnz_a, PCG_Q)
+    if args.roofline_only:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"pcg_iter_s": t_pcg, "alg_bytes": alg_pcg, "copy_bytes_each_way": a.numel() * 4}))
+        return
+    # ---- the plain product kernel, for the SpMV bandwidth of the metric
     t_spmv = time_spmv(lap, torch, plan, L.n, reps=2000 if args.spmv_only else 500)
     alg = spmv_bytes(L.n, nnz_a, 4)
     if args.spmv_only:
@@ -255,12 +317,16 @@ def main():
                     "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3)},
     }
     sha = kernel_sources_sha()
-    achieved = alg / t_spmv / 1e9
-    out["roofline"] = {"kernel": "k_spmv<float> (unweighted Laplacian product, b=1)", "bound": "hbm",
+    achieved = alg_pcg / t_pcg / 1e9
+    out["roofline"] = {"kernel": f"k_pp_iter<float> (one projected PCG iteration, q={PCG_Q})", "bound": "hbm",
                        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_from_profile(sha, alg),
-                       "alg_bytes_per_launch": alg, "avg_launch_us": round(t_spmv * 1e6, 3),
+                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_from_profile(sha, alg_pcg),
+                       "alg_bytes_per_launch": alg_pcg, "avg_launch_us": round(t_pcg * 1e6, 3),
                        "kernel_sources_sha": sha}
+    a_spmv = alg / t_spmv / 1e9
+    out["spmv"] = {"kernel": "k_spmv<float> (unweighted Laplacian product, b=1)", "GB/s": round(a_spmv, 2),
+                   "frac": round(a_spmv / HBM_PEAK_GBS, 5), "alg_bytes_per_launch": alg,
+                   "avg_launch_us": round(t_spmv * 1e6, 3)}
     if args.sweep:
         sweep = []
         for name, builder in [("cl1m_tc", lambda: gg.workload("cl1m_tc", SEED))]:

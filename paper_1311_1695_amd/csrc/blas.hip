@@ -453,6 +453,44 @@ inline int vec_grid(int n) {
     return g < 1 ? 1 : (g > cap ? cap : g);
 }
 
+// Output of the eigenvectors: column j = column order[j] of X (plan order,
+// element (i, c) at X[i sr + c sc]) in the caller's vertex order, with the
+// sign that makes its largest-magnitude entry positive (ties: the lowest
+// caller index).  One workgroup per column; the arg-max is reduced in a
+// fixed order.
+__global__ __launch_bounds__(kBlock) void k_finalize(int n, const double *__restrict__ X, long long sr, long long sc,
+                                                     const int *__restrict__ order, const int *__restrict__ perm,
+                                                     double *__restrict__ out) {
+    const int j = blockIdx.x;
+    const long long c = order[j];
+    double bv = -1.0;
+    int bi = n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = fabs(X[(long long)perm[i] * sr + c * sc]);
+        if (v > bv) { bv = v; bi = i; }  // i increases: the first maximum stays
+    }
+    __shared__ double sv[kBlock];
+    __shared__ int si[kBlock];
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const double ov = sv[threadIdx.x + h];
+            const int oi = si[threadIdx.x + h];
+            if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int best = si[0];
+    const double sign = (best < n && X[(long long)perm[best] * sr + c * sc] < 0.0) ? -1.0 : 1.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        out[(size_t)j * n + i] = sign * X[(long long)perm[i] * sr + c * sc];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -597,6 +635,13 @@ void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipS
 void jd_random(int n, uint64_t seed, long long colidx, const int *iperm, double *v, hipStream_t s) {
     hipLaunchKernelGGL(k_random, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, (unsigned long long)seed, colidx,
                        iperm, v);
+    LAP_HIP(hipGetLastError());
+}
+
+void jd_finalize(int n, int nconv, const double *X, long long sr, long long sc, const int *order_dev,
+                 const int *perm_dev, double *out_dev, hipStream_t s) {
+    if (nconv <= 0) return;
+    hipLaunchKernelGGL(k_finalize, dim3(nconv), dim3(kBlock), 0, s, n, X, sr, sc, order_dev, perm_dev, out_dev);
     LAP_HIP(hipGetLastError());
 }
 

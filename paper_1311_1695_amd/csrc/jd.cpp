@@ -64,6 +64,37 @@ struct OwnStream {
     ~OwnStream() { if (s) (void)hipStreamDestroy(s); }
 };
 
+}  // namespace
+
+void emit_pairs(const lap_plan &P, int nconv, const double *X, long long sr, long long sc,
+                const std::vector<double> &lam, const std::vector<double> &resid, double *evals, double *evecs,
+                int evecs_on_device, double *res_out, DevBuf<double> &scratch, hipStream_t s) {
+    const int n = P.n;
+    std::vector<int> order(nconv);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    for (int j = 0; j < nconv; ++j) {
+        evals[j] = lam[order[j]];
+        if (res_out) res_out[j] = resid[order[j]];
+    }
+    if (evecs && nconv > 0) {
+        DevBuf<int> dorder(nconv);
+        LAP_HIP(hipMemcpyAsync(dorder.get(), order.data(), sizeof(int) * nconv, hipMemcpyHostToDevice, s));
+        double *dst = evecs;
+        if (!evecs_on_device) {
+            if (scratch.n < (size_t)n * nconv) scratch.alloc((size_t)n * nconv);
+            dst = scratch.get();
+        }
+        jd_finalize(n, nconv, X, sr, sc, dorder.get(), P.d_perm.get(), dst, s);
+        if (!evecs_on_device)
+            LAP_HIP(hipMemcpyAsync(evecs, dst, sizeof(double) * n * nconv, hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+    }
+    LAP_HIP(hipStreamSynchronize(s));
+}
+
+namespace {
+
 // Host-coherent pinned status the kernels publish into (see HostMirror).
 struct PinnedMirror {
     HostMirror *h = nullptr;
@@ -105,6 +136,8 @@ struct JdWork : SolverCache {
     ReduceScratch rs;
     PcgWork<T> pw;
     PcgGraphs<T> graphs;
+    DevBuf<double> outbuf;  // eigenvectors on their way to host memory
+    OwnStream own;          // the solver's stream
     JdWork(int n_, int k_, int mmax_, int itmax_, double rtol_)
         : n(n_), k(k_), mmax(mmax_), itmax(itmax_), rtol(rtol_) {
         B.alloc((size_t)n * (k + mmax));
@@ -133,8 +166,6 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     // work on a stream of our own (capturable even when the caller uses the
     // default stream), ordered after the caller's pending work
     LAP_HIP(hipStreamSynchronize(P->stream));
-    OwnStream own;
-    hipStream_t s = own.s;
     const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
     const int mmax = o.m_max, mmin = o.m_min;
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
@@ -149,6 +180,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         P->jd_cache.reset(cache = new JdWork<T>(n, k, mmax, o.itmax, o.rtol_pcg));
     }
     JdWork<T> &wk = *cache;
+    hipStream_t s = wk.own.s;
     DevBuf<double> &B = wk.B, &W = wk.W, &H = wk.H, &theta = wk.theta, &Y = wk.Y, &v = wk.v, &u = wk.u, &r = wk.r,
                    &gu = wk.gu, &vrand = wk.vrand, &isz = wk.isz;
     DevBuf<T> &Q = wk.Q, &t = wk.t;
@@ -303,33 +335,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
 
     // ---- output: ascending order, caller's vertex order, canonical signs
     const int nconv = std::min(nx, k);
-    std::vector<int> order(nconv);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] < lam[b]; });
-    std::vector<double> Xh((size_t)n * nconv);
-    if (nconv > 0)
-        LAP_HIP(hipMemcpyAsync(Xh.data(), B.get(), sizeof(double) * n * nconv, hipMemcpyDeviceToHost, s));
-    LAP_HIP(hipStreamSynchronize(s));
-    std::vector<double> out((size_t)n * nconv);
-    for (int j = 0; j < nconv; ++j) {
-        const double *x = Xh.data() + (size_t)order[j] * n;
-        double *y = out.data() + (size_t)j * n;
-        for (int i = 0; i < n; ++i) y[i] = x[P->perm[i]];
-        int best = 0;
-        for (int i = 1; i < n; ++i)
-            if (std::fabs(y[i]) > std::fabs(y[best])) best = i;
-        if (y[best] < 0.0)
-            for (int i = 0; i < n; ++i) y[i] = -y[i];
-        evals[j] = lam[order[j]];
-        if (res_out) res_out[j] = resid[order[j]];
-    }
-    if (evecs && nconv > 0) {
-        if (evecs_on_device)
-            LAP_HIP(hipMemcpyAsync(evecs, out.data(), sizeof(double) * n * nconv, hipMemcpyHostToDevice, s));
-        else
-            std::copy(out.begin(), out.end(), evecs);
-    }
-    LAP_HIP(hipStreamSynchronize(s));
+    emit_pairs(*P, nconv, B.get(), 1, n, lam, resid, evals, evecs, evecs_on_device, res_out, wk.outbuf, s);
     if (info) {
         info->nconv = nconv;
         info->ncomp = P->ncomp;

@@ -278,36 +278,8 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
 
     // ---- output (as the single-vector solver)
     const int nconv = std::min(nx, k);
-    std::vector<int> order(nconv);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return lam[a] < lam[c]; });
-    std::vector<double> Xh((size_t)n * std::max(nconv, 1));
-    if (nconv > 0) {
-        DevBuf<double> Xc((size_t)n * nconv);
-        blk_extract(n, nconv, XV.get(), ldb, Xc.get(), s);
-        LAP_HIP(hipMemcpyAsync(Xh.data(), Xc.get(), sizeof(double) * n * nconv, hipMemcpyDeviceToHost, s));
-        LAP_HIP(hipStreamSynchronize(s));
-    }
-    std::vector<double> out((size_t)n * nconv);
-    for (int j = 0; j < nconv; ++j) {
-        const double *x = Xh.data() + (size_t)order[j] * n;
-        double *y = out.data() + (size_t)j * n;
-        for (int i = 0; i < n; ++i) y[i] = x[P->perm[i]];
-        int best = 0;
-        for (int i = 1; i < n; ++i)
-            if (std::fabs(y[i]) > std::fabs(y[best])) best = i;
-        if (y[best] < 0.0)
-            for (int i = 0; i < n; ++i) y[i] = -y[i];
-        evals[j] = lam[order[j]];
-        if (res_out) res_out[j] = resid[order[j]];
-    }
-    if (evecs && nconv > 0) {
-        if (evecs_on_device)
-            LAP_HIP(hipMemcpyAsync(evecs, out.data(), sizeof(double) * n * nconv, hipMemcpyHostToDevice, s));
-        else
-            std::copy(out.begin(), out.end(), evecs);
-    }
-    LAP_HIP(hipStreamSynchronize(s));
+    DevBuf<double> outbuf;
+    emit_pairs(*P, nconv, XV.get(), ldb, 1, lam, resid, evals, evecs, evecs_on_device, res_out, outbuf, s);
     if (info) {
         info->nconv = nconv;
         info->ncomp = P->ncomp;

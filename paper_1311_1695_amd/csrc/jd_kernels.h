@@ -78,6 +78,19 @@ void jd_random(int n, uint64_t seed, long long colidx, const int *iperm, double 
 // out = v * inv_norm (the normalization left by jd_orth)
 void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipStream_t s);
 
+// Eigenvector output: out (n x nconv column-major, caller order, device) =
+// columns order[j] of X (plan order, element (i, c) at X[i sr + c sc]),
+// each with its largest-magnitude entry made positive (ties: lowest index).
+void jd_finalize(int n, int nconv, const double *X, long long sr, long long sc, const int *order_dev,
+                 const int *perm_dev, double *out_dev, hipStream_t s);
+
+// Writes the nconv locked pairs (values lam, residuals resid, vectors the
+// columns of X as for jd_finalize) in ascending order to the caller's
+// buffers (evecs on the device or in host memory), then synchronizes s.
+void emit_pairs(const lap_plan &P, int nconv, const double *X, long long sr, long long sc,
+                const std::vector<double> &lam, const std::vector<double> &resid, double *evals, double *evecs,
+                int evecs_on_device, double *res_out, DevBuf<double> &scratch, hipStream_t s);
+
 // PCG work vectors (plan order, type T).
 template <typename T>
 struct PcgWork {
