@@ -107,6 +107,39 @@ void lap_eigs_default_opts(lap_eigs_opts *opts);
 lap_status lap_plan_create(const lap_csr *L, void *stream, lap_plan **out);
 void lap_plan_destroy(lap_plan *plan);
 
+/* Row classes of the Laplacian product (an engineering choice; the paper
+ * fixes no data layout).  Rows, in decreasing degree, of degree above
+ * huge_threshold are evaluated by a workgroup each, above long_threshold by
+ * a wavefront each, the rest in 64-row column-major slices; a plan starts
+ * with long = 32, huge = 512.  Results do not depend on the layout except
+ * through the order of floating-point additions within a row.
+ *   lap_plan_set_layout: rebuild the layout for the given thresholds
+ *     (1 <= long_threshold <= huge_threshold, else LAP_EINVAL).  Blocks
+ *     until the device is idle; work areas that solves cached in the plan
+ *     are released.
+ *   lap_plan_layout: the current thresholds (host out-parameters).
+ *   lap_plan_autotune: time the product (FP32 or FP64, b columns, b in
+ *     [1, 64]) for a grid of thresholds and keep the fastest layout.
+ *     cache_path (or NULL): a JSON file of earlier choices keyed by device,
+ *     b, precision, n, nnz and a log2 histogram of the row degrees; a
+ *     matching entry is applied without timing, a new choice is added (the
+ *     file is rewritten through a temporary and a rename).  info (or NULL)
+ *     receives the choice and the time per product of the chosen and of the
+ *     initial layout.  Takes from milliseconds to a few seconds. */
+typedef struct {
+    int32_t long_threshold;
+    int32_t huge_threshold;
+    double best_us;        /* microseconds per product, chosen layout */
+    double default_us;     /* microseconds per product at long 32, huge 512 (0 from cache) */
+    int32_t candidates;    /* layouts timed (0 when taken from the cache) */
+    int32_t from_cache;    /* 1 when the choice came from cache_path */
+} lap_tune_info;
+
+lap_status lap_plan_set_layout(lap_plan *plan, int32_t long_threshold, int32_t huge_threshold);
+lap_status lap_plan_layout(const lap_plan *plan, int32_t *long_threshold, int32_t *huge_threshold);
+lap_status lap_plan_autotune(lap_plan *plan, lap_dtype dtype, int32_t b, const char *cache_path,
+                             lap_tune_info *info);
+
 /* Size of the plan's matrix and its vertex renumbering: perm[i] is the
  * solver's internal index of the caller's vertex i (host array of n). */
 int32_t lap_plan_n(const lap_plan *plan);

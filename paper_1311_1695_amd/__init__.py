@@ -39,6 +39,7 @@ LAP_PREC_FP64, LAP_PREC_MIXED = 0, 1
 LAP_ORDER_PLAN = 1
 
 EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
+            "lap_plan_set_layout", "lap_plan_layout", "lap_plan_autotune",
             "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
@@ -48,6 +49,12 @@ class LapError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} [{code}]")
         self.code = code
+
+
+class _TuneInfo(ctypes.Structure):
+    _fields_ = [("long_threshold", ctypes.c_int32), ("huge_threshold", ctypes.c_int32),
+                ("best_us", ctypes.c_double), ("default_us", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
 class _Csr(ctypes.Structure):
@@ -90,6 +97,9 @@ def load_library():
     lib.lap_plan_n.argtypes = [vp]
     lib.lap_plan_n.restype = ctypes.c_int32
     lib.lap_plan_perm.argtypes = [vp, i32p]
+    lib.lap_plan_set_layout.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    lib.lap_plan_layout.argtypes = [vp, i32p, i32p]
+    lib.lap_plan_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p, P(_TuneInfo)]
     lib.lap_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p, P(_Info)]
     lib.lap_eigs_csr.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info)]
     lib.lap_spmv.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
@@ -157,6 +167,26 @@ class Plan:
         _check(load_library().lap_plan_perm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
 
+    def layout(self):
+        """(long_threshold, huge_threshold) of the product's row classes."""
+        lt, ht = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().lap_plan_layout(self._h, ctypes.byref(lt), ctypes.byref(ht)))
+        return int(lt.value), int(ht.value)
+
+    def set_layout(self, long_threshold, huge_threshold):
+        _check(load_library().lap_plan_set_layout(self._h, int(long_threshold), int(huge_threshold)))
+
+    def autotune(self, dtype="f32", b=1, cache_path=None) -> dict:
+        """Time the product for a grid of row-class thresholds, keep the
+        fastest; see lap_plan_autotune."""
+        info = _TuneInfo()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(load_library().lap_plan_autotune(self._h, {"f32": LAP_F32, "f64": LAP_F64}[dtype], int(b), path,
+                                                ctypes.byref(info)))
+        return {"long_threshold": info.long_threshold, "huge_threshold": info.huge_threshold,
+                "best_us": info.best_us, "default_us": info.default_us, "candidates": info.candidates,
+                "from_cache": bool(info.from_cache)}
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             load_library().lap_plan_destroy(self._h)
@@ -171,6 +201,18 @@ class Plan:
 
 def lap_plan_create(L, stream=None) -> Plan:
     return Plan(L, stream)
+
+
+def lap_plan_set_layout(plan: Plan, long_threshold, huge_threshold):
+    plan.set_layout(long_threshold, huge_threshold)
+
+
+def lap_plan_layout(plan: Plan):
+    return plan.layout()
+
+
+def lap_plan_autotune(plan: Plan, dtype="f32", b=1, cache_path=None) -> dict:
+    return plan.autotune(dtype, b, cache_path)
 
 
 @dataclasses.dataclass

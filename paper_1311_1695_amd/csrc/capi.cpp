@@ -157,6 +157,35 @@ lap_status lap_plan_perm(const lap_plan *p, int32_t *perm) {
     LAP_GUARD_END
 }
 
+lap_status lap_plan_set_layout(lap_plan *p, int32_t long_threshold, int32_t huge_threshold) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(long_threshold >= 1 && huge_threshold >= long_threshold, LAP_EINVAL,
+                "row-class thresholds must satisfy 1 <= long <= huge");
+    lapeig::build_layout(p, long_threshold, huge_threshold);
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_plan_layout(const lap_plan *p, int32_t *long_threshold, int32_t *huge_threshold) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p && long_threshold && huge_threshold, LAP_EINVAL, "plan or output pointer is NULL");
+    *long_threshold = p->long_threshold;
+    *huge_threshold = p->huge_threshold;
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_plan_autotune(lap_plan *p, lap_dtype dtype, int32_t b, const char *cache_path, lap_tune_info *info) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(dtype == LAP_F32 || dtype == LAP_F64, LAP_EINVAL, "dtype must be LAP_F32 or LAP_F64");
+    LAP_REQUIRE(b >= 1 && b <= 64, LAP_EINVAL, "block width must be in [1, 64]");
+    lapeig::autotune(p, dtype, b, cache_path, info);
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
 static void check_opts(const lap_eigs_opts &o, int n) {
     LAP_REQUIRE(o.m_min >= 1 && o.m_max > o.m_min, LAP_EINVAL, "need 1 <= m_min < m_max");
     LAP_REQUIRE(o.itmax >= 1, LAP_EINVAL, "itmax must be >= 1");

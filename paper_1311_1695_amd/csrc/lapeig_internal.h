@@ -147,6 +147,9 @@ struct lap_plan {
     lapeig::DevBuf<char> tmp_x, tmp_y;
     lapeig::DevBuf<char> chunk_part;  // per-chunk partial sums of the block product
     std::unique_ptr<lapeig::SolverCache> jd_cache;  // single-vector solver work areas
+    // plan-order CSR of A on the host (rebuilding the row classes needs it)
+    std::vector<int> h_rowptr, h_col;
+    std::vector<double> h_w;
 
     template <typename T>
     lapeig::Weights<T> weights() const;
@@ -174,6 +177,11 @@ void validate_laplacian(const lap_csr *L);  // throws Failure (no HIP calls)
 // Validate (host), renumber, classify rows, build slices, upload.
 void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_threshold = 32,
                 int huge_threshold = 512);
+// Rebuild the row classes of an existing plan for other thresholds.
+void build_layout(lap_plan *plan, int long_threshold, int huge_threshold);
+
+// ------------------------------------------------------------- tune.cpp
+void autotune(lap_plan *plan, lap_dtype dt, int b, const char *cache_path, lap_tune_info *info);
 
 // ------------------------------------------------------------- spmv.hip
 // y = (G - sigma I) x, b = 1, plan order.

@@ -128,48 +128,6 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
             }
         }
     }
-    int n_long = 0, n_huge = 0;
-    while (n_long < n && deg[iperm[n_long]] > long_threshold) ++n_long;
-    while (n_huge < n && deg[iperm[n_huge]] > huge_threshold) ++n_huge;
-
-    // 64-row column-major slices for rows [n_long, n)
-    int nslices = (n - n_long + kWave - 1) / kWave;
-    std::vector<int> soff(nslices + 1, 0);
-    for (int s = 0; s < nslices; ++s) {
-        int r0 = n_long + s * kWave;
-        int width = deg[iperm[r0]];  // rows sorted by decreasing degree
-        soff[s + 1] = soff[s] + width * kWave;
-    }
-    std::vector<int> scol(soff[nslices]);
-    std::vector<double> sw(weighted ? soff[nslices] : 0);
-    for (int s = 0; s < nslices; ++s) {
-        int r0 = n_long + s * kWave;
-        int width = (soff[s + 1] - soff[s]) / kWave;
-        for (int l = 0; l < kWave; ++l) {
-            int r = r0 + l;
-            int d = r < n ? prow[r + 1] - prow[r] : 0;
-            for (int t = 0; t < width; ++t) {
-                size_t at = (size_t)soff[s] + (size_t)t * kWave + l;
-                if (t < d) {
-                    scol[at] = pcol[prow[r] + t];
-                    if (weighted) sw[at] = pw[prow[r] + t];
-                } else {  // padding: the row itself contributes w (x_r - x_r) = 0
-                    scol[at] = r < n ? r : n - 1;
-                    if (weighted) sw[at] = 0.0;
-                }
-            }
-        }
-    }
-
-    // long rows in chunks of kChunk edges (the block product splits them)
-    std::vector<int> coff(n_long + 1, 0), crow;
-    for (int r = 0; r < n_long; ++r) {
-        const int d = prow[r + 1] - prow[r];
-        const int nc = (d + kChunk - 1) / kChunk;
-        coff[r + 1] = coff[r] + nc;
-        for (int c = 0; c < nc; ++c) crow.push_back(r);
-    }
-
     // connected components (plan order), breadth-first
     std::vector<int> comp(n, -1), queue(n);
     int ncomp = 0;
@@ -203,8 +161,6 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
     P->nnz_a = nnz_a;
     P->weighted = weighted;
     P->stream = stream;
-    P->long_threshold = long_threshold;
-    P->huge_threshold = huge_threshold;
     P->max_degree = n ? deg[iperm[0]] : 0;
     P->perm = perm;
     P->iperm = iperm;
@@ -216,33 +172,95 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
     upload(P->d_comp, comp);
     upload(P->d_rowptr, prow);
     upload(P->d_col, pcol);
-    upload(P->d_sell_off, soff);
-    upload(P->d_sell_col, scol);
-    upload(P->d_chunk_off, coff);
-    upload(P->d_chunk_row, crow);
     upload(P->d_dinv64, dinv);
     std::vector<float> dinv32(dinv.begin(), dinv.end());
     upload(P->d_dinv32, dinv32);
     if (weighted) {
         upload(P->d_w64, pw);
-        upload(P->d_sellw64, sw);
-        std::vector<float> pw32(pw.begin(), pw.end()), sw32(sw.begin(), sw.end());
+        std::vector<float> pw32(pw.begin(), pw.end());
         upload(P->d_w32, pw32);
-        upload(P->d_sellw32, sw32);
     }
     P->g.n = n;
+    P->g.rowptr = P->d_rowptr.get();
+    P->g.col = P->d_col.get();
+    // the plan-order CSR stays on the host, so the row-class layout can be rebuilt
+    P->h_rowptr = std::move(prow);
+    P->h_col = std::move(pcol);
+    P->h_w = std::move(pw);
+    build_layout(P, long_threshold, huge_threshold);
+}
+
+// Row classes for the given thresholds (rows are in decreasing degree, so
+// each class is a prefix): the 64-row column-major slices of the short rows
+// and the kChunk-edge chunks of the long ones, uploaded to the device.
+// Solver work areas captured with the old layout are dropped.
+void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
+    LAP_REQUIRE(long_threshold >= 1 && huge_threshold >= long_threshold, LAP_EINVAL,
+                "row-class thresholds must satisfy 1 <= long <= huge");
+    const int n = P->n;
+    const bool weighted = P->weighted;
+    const std::vector<int> &prow = P->h_rowptr, &pcol = P->h_col;
+    const std::vector<double> &pw = P->h_w;
+    auto deg = [&](int r) { return prow[r + 1] - prow[r]; };
+    int n_long = 0, n_huge = 0;
+    while (n_long < n && deg(n_long) > long_threshold) ++n_long;
+    while (n_huge < n && deg(n_huge) > huge_threshold) ++n_huge;
+
+    // 64-row column-major slices for rows [n_long, n)
+    const int nslices = (n - n_long + kWave - 1) / kWave;
+    std::vector<int> soff(nslices + 1, 0);
+    for (int s = 0; s < nslices; ++s) soff[s + 1] = soff[s] + deg(n_long + s * kWave) * kWave;
+    std::vector<int> scol(soff[nslices]);
+    std::vector<double> sw(weighted ? soff[nslices] : 0);
+    for (int s = 0; s < nslices; ++s) {
+        const int r0 = n_long + s * kWave;
+        const int width = (soff[s + 1] - soff[s]) / kWave;
+        for (int l = 0; l < kWave; ++l) {
+            const int r = r0 + l;
+            const int d = r < n ? deg(r) : 0;
+            for (int t = 0; t < width; ++t) {
+                const size_t at = (size_t)soff[s] + (size_t)t * kWave + l;
+                if (t < d) {
+                    scol[at] = pcol[prow[r] + t];
+                    if (weighted) sw[at] = pw[prow[r] + t];
+                } else {  // padding: the row itself contributes w (x_r - x_r) = 0
+                    scol[at] = r < n ? r : n - 1;
+                    if (weighted) sw[at] = 0.0;
+                }
+            }
+        }
+    }
+    // long rows in chunks of kChunk edges (the block product splits them)
+    std::vector<int> coff(n_long + 1, 0), crow;
+    for (int r = 0; r < n_long; ++r) {
+        const int nc = (deg(r) + kChunk - 1) / kChunk;
+        coff[r + 1] = coff[r] + nc;
+        for (int c = 0; c < nc; ++c) crow.push_back(r);
+    }
+
+    P->jd_cache.reset();
+    LAP_HIP(hipDeviceSynchronize());  // no launch may still read the old layout
+    upload(P->d_sell_off, soff);
+    upload(P->d_sell_col, scol);
+    upload(P->d_chunk_off, coff);
+    upload(P->d_chunk_row, crow);
+    if (weighted) {
+        upload(P->d_sellw64, sw);
+        std::vector<float> sw32(sw.begin(), sw.end());
+        upload(P->d_sellw32, sw32);
+    }
+    P->long_threshold = long_threshold;
+    P->huge_threshold = huge_threshold;
     P->g.n_huge = n_huge;
     P->g.n_long = n_long;
     P->g.nslices = nslices;
-    P->g.rowptr = P->d_rowptr.get();
-    P->g.col = P->d_col.get();
     P->g.sell_off = P->d_sell_off.get();
     P->g.sell_col = P->d_sell_col.get();
     P->g.nchunks = (int)crow.size();
-    // partial sums of chunked rows for block products of up to 64 double columns
-    P->chunk_part.alloc(std::max<size_t>(crow.size(), 1) * 64 * sizeof(double));
     P->g.chunk_row = P->d_chunk_row.get();
     P->g.chunk_off = P->d_chunk_off.get();
+    // partial sums of chunked rows for block products of up to 64 double columns
+    P->chunk_part.alloc(std::max<size_t>(crow.size(), 1) * 64 * sizeof(double));
 }
 
 int device_cu_count() {
