@@ -118,27 +118,33 @@ void lap_plan_destroy(lap_plan *plan);
  *     until the device is idle; work areas that solves cached in the plan
  *     are released.
  *   lap_plan_layout: the current thresholds (host out-parameters).
- *   lap_plan_autotune: time the product (FP32 or FP64, b columns, b in
- *     [1, 64]) for a grid of thresholds and keep the fastest layout.
+ *   lap_plan_autotune: time a kernel for a grid of thresholds and keep the
+ *     fastest layout.  target LAP_TUNE_PRODUCT: the product itself (FP32 or
+ *     FP64, b columns, b in [1, 64]), as lap_spmv uses it; LAP_TUNE_PCG: one
+ *     iteration launch of the projected PCG that lap_eigs runs per
+ *     correction equation (b = 1; FP32 for LAP_PREC_MIXED, FP64 for
+ *     LAP_PREC_FP64), whose per-row work favours other thresholds.
  *     cache_path (or NULL): a JSON file of earlier choices keyed by device,
- *     b, precision, n, nnz and a log2 histogram of the row degrees; a
+ *     target, b, precision, n, nnz and a log2 histogram of row degrees; a
  *     matching entry is applied without timing, a new choice is added (the
  *     file is rewritten through a temporary and a rename).  info (or NULL)
  *     receives the choice and the time per product of the chosen and of the
  *     initial layout.  Takes from milliseconds to a few seconds. */
+typedef enum { LAP_TUNE_PRODUCT = 0, LAP_TUNE_PCG = 1 } lap_tune_target;
+
 typedef struct {
     int32_t long_threshold;
     int32_t huge_threshold;
-    double best_us;        /* microseconds per product, chosen layout */
-    double default_us;     /* microseconds per product at long 32, huge 512 (0 from cache) */
+    double best_us;        /* microseconds per timed launch, chosen layout */
+    double default_us;     /* the same at long 32, huge 512 (0 when from the cache) */
     int32_t candidates;    /* layouts timed (0 when taken from the cache) */
     int32_t from_cache;    /* 1 when the choice came from cache_path */
 } lap_tune_info;
 
 lap_status lap_plan_set_layout(lap_plan *plan, int32_t long_threshold, int32_t huge_threshold);
 lap_status lap_plan_layout(const lap_plan *plan, int32_t *long_threshold, int32_t *huge_threshold);
-lap_status lap_plan_autotune(lap_plan *plan, lap_dtype dtype, int32_t b, const char *cache_path,
-                             lap_tune_info *info);
+lap_status lap_plan_autotune(lap_plan *plan, lap_tune_target target, lap_dtype dtype, int32_t b,
+                             const char *cache_path, lap_tune_info *info);
 
 /* Size of the plan's matrix and its vertex renumbering: perm[i] is the
  * solver's internal index of the caller's vertex i (host array of n). */

@@ -99,7 +99,7 @@ def load_library():
     lib.lap_plan_perm.argtypes = [vp, i32p]
     lib.lap_plan_set_layout.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.lap_plan_layout.argtypes = [vp, i32p, i32p]
-    lib.lap_plan_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p, P(_TuneInfo)]
+    lib.lap_plan_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p, P(_TuneInfo)]
     lib.lap_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p, P(_Info)]
     lib.lap_eigs_csr.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info)]
     lib.lap_spmv.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
@@ -176,12 +176,14 @@ class Plan:
     def set_layout(self, long_threshold, huge_threshold):
         _check(load_library().lap_plan_set_layout(self._h, int(long_threshold), int(huge_threshold)))
 
-    def autotune(self, dtype="f32", b=1, cache_path=None) -> dict:
-        """Time the product for a grid of row-class thresholds, keep the
-        fastest; see lap_plan_autotune."""
+    def autotune(self, dtype="f32", b=1, cache_path=None, target="product") -> dict:
+        """Time a kernel ("product": the Laplacian product; "pcg": one
+        projected-PCG iteration of lap_eigs) for a grid of row-class
+        thresholds, keep the fastest; see lap_plan_autotune."""
         info = _TuneInfo()
         path = None if cache_path is None else os.fsencode(cache_path)
-        _check(load_library().lap_plan_autotune(self._h, {"f32": LAP_F32, "f64": LAP_F64}[dtype], int(b), path,
+        _check(load_library().lap_plan_autotune(self._h, {"product": 0, "pcg": 1}[target],
+                                                {"f32": LAP_F32, "f64": LAP_F64}[dtype], int(b), path,
                                                 ctypes.byref(info)))
         return {"long_threshold": info.long_threshold, "huge_threshold": info.huge_threshold,
                 "best_us": info.best_us, "default_us": info.default_us, "candidates": info.candidates,
@@ -211,8 +213,8 @@ def lap_plan_layout(plan: Plan):
     return plan.layout()
 
 
-def lap_plan_autotune(plan: Plan, dtype="f32", b=1, cache_path=None) -> dict:
-    return plan.autotune(dtype, b, cache_path)
+def lap_plan_autotune(plan: Plan, dtype="f32", b=1, cache_path=None, target="product") -> dict:
+    return plan.autotune(dtype, b, cache_path, target)
 
 
 @dataclasses.dataclass

@@ -176,12 +176,15 @@ lap_status lap_plan_layout(const lap_plan *p, int32_t *long_threshold, int32_t *
     LAP_GUARD_END
 }
 
-lap_status lap_plan_autotune(lap_plan *p, lap_dtype dtype, int32_t b, const char *cache_path, lap_tune_info *info) {
+lap_status lap_plan_autotune(lap_plan *p, lap_tune_target target, lap_dtype dtype, int32_t b, const char *cache_path,
+                             lap_tune_info *info) {
     LAP_GUARD_BEGIN
     LAP_REQUIRE(p, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(target == LAP_TUNE_PRODUCT || target == LAP_TUNE_PCG, LAP_EINVAL, "unknown tuning target");
     LAP_REQUIRE(dtype == LAP_F32 || dtype == LAP_F64, LAP_EINVAL, "dtype must be LAP_F32 or LAP_F64");
     LAP_REQUIRE(b >= 1 && b <= 64, LAP_EINVAL, "block width must be in [1, 64]");
-    lapeig::autotune(p, dtype, b, cache_path, info);
+    LAP_REQUIRE(target == LAP_TUNE_PRODUCT || b == 1, LAP_EINVAL, "the PCG target takes b = 1");
+    lapeig::autotune(p, dtype, b, (int)target, cache_path, info);
     return LAP_OK;
     LAP_GUARD_END
 }

@@ -181,7 +181,7 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_t
 void build_layout(lap_plan *plan, int long_threshold, int huge_threshold);
 
 // ------------------------------------------------------------- tune.cpp
-void autotune(lap_plan *plan, lap_dtype dt, int b, const char *cache_path, lap_tune_info *info);
+void autotune(lap_plan *plan, lap_dtype dt, int b, int target, const char *cache_path, lap_tune_info *info);
 
 // ------------------------------------------------------------- spmv.hip
 // y = (G - sigma I) x, b = 1, plan order.

@@ -15,7 +15,7 @@
 #include <sstream>
 #include <utility>
 
-#include "lapeig_internal.h"
+#include "jd_kernels.h"
 
 namespace lapeig {
 
@@ -91,6 +91,78 @@ double time_product(lap_plan *P, lap_dtype dt, int b, int reps) {
     return best;
 }
 
+// Seconds per iteration launch of the projected PCG (the single-vector
+// solver's inner loop) on the current layout: Q = the first q unit vectors,
+// theta = 0 (the projected operator is then positive definite), rtol so
+// small that no iteration stops; graphs of 6 and 16 iterations are replayed
+// and their difference divided by 10.
+template <typename T>
+double time_pcg(lap_plan *P, int q) {
+    const int n = P->n;
+    PcgWork<T> w;
+    w.ensure(n, q);
+    DevBuf<T> Q((size_t)n * q), t(n);
+    DevBuf<double> r(n), theta(1);
+    LAP_HIP(hipMemset(Q.get(), 0, sizeof(T) * n * q));
+    LAP_HIP(hipMemset(theta.get(), 0, sizeof(double)));
+    const T one = T(1);
+    for (int j = 0; j < q; ++j)
+        LAP_HIP(hipMemcpy(Q.get() + (size_t)j * q + j, &one, sizeof(T), hipMemcpyHostToDevice));
+    {
+        std::vector<double> h(n);
+        unsigned long long x = 0x9e3779b97f4a7c15ull;
+        for (int i = 0; i < n; ++i) {
+            x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+            h[i] = i < q ? 0.0 : (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        LAP_HIP(hipMemcpy(r.get(), h.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    }
+    hipStream_t s = nullptr;
+    LAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    double per[2] = {0.0, 0.0};
+    const int its[2] = {6, 16};
+    try {
+        EventPair ev;
+        for (int v = 0; v < 2; ++v) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            pcg_enqueue<T>(*P, theta.get(), Q.get(), q, q, r.get(), t.get(), w, its[v], 1e-30, s);  // warm
+            LAP_HIP(hipStreamSynchronize(s));
+            LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                pcg_enqueue<T>(*P, theta.get(), Q.get(), q, q, r.get(), t.get(), w, its[v], 1e-30, s);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            LAP_HIP(hipStreamEndCapture(s, &g));
+            hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            LAP_HIP(e);
+            double best = 1e300;
+            for (int rep = 0; rep < 4; ++rep) {
+                LAP_HIP(hipEventRecord(ev.a, s));
+                LAP_HIP(hipGraphLaunch(ge, s));
+                LAP_HIP(hipEventRecord(ev.b, s));
+                LAP_HIP(hipEventSynchronize(ev.b));
+                float ms = 0.f;
+                LAP_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                best = std::min(best, 1e-3 * ms);
+            }
+            (void)hipGraphExecDestroy(ge);
+            per[v] = best;
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    LAP_HIP(hipStreamSynchronize(s));
+    LAP_HIP(hipStreamDestroy(s));
+    return std::max(per[1] - per[0], 0.0) / (its[1] - its[0]);
+}
+
 // Rows of the long and huge classes for a pair of thresholds.
 std::pair<int, int> classes(const lap_plan *P, int lt, int ht) {
     int nl = 0, nh = 0;
@@ -100,7 +172,7 @@ std::pair<int, int> classes(const lap_plan *P, int lt, int ht) {
     return {nl, nh};
 }
 
-std::string cache_key(const lap_plan *P, lap_dtype dt, int b) {
+std::string cache_key(const lap_plan *P, lap_dtype dt, int b, int target) {
     hipDeviceProp_t prop;
     std::string arch = "gpu";
     if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
@@ -113,7 +185,7 @@ std::string cache_key(const lap_plan *P, lap_dtype dt, int b) {
         ++hist[bin];
     }
     std::ostringstream k;
-    k << arch << "|b" << b << "|" << (dt == LAP_F32 ? "f32" : "f64") << "|w" << (P->weighted ? 1 : 0) << "|n"
+    k << arch << (target == LAP_TUNE_PCG ? "|pcg" : "|product") << "|b" << b << "|" << (dt == LAP_F32 ? "f32" : "f64") << "|w" << (P->weighted ? 1 : 0) << "|n"
       << P->n << "|nnz" << P->nnz_a << "|h";
     for (int i = 0; i < 32; ++i)
         if (hist[i]) k << i << ":" << hist[i] << ",";
@@ -167,11 +239,14 @@ void write_cache(const char *path, const std::vector<Entry> &entries) {
 
 }  // namespace
 
-void autotune(lap_plan *P, lap_dtype dt, int b, const char *cache_path, lap_tune_info *info) {
+void autotune(lap_plan *P, lap_dtype dt, int b, int target, const char *cache_path, lap_tune_info *info) {
     LAP_REQUIRE(dt == LAP_F32 || dt == LAP_F64, LAP_EINVAL, "dtype must be LAP_F32 or LAP_F64");
+    LAP_REQUIRE(target == LAP_TUNE_PRODUCT || target == LAP_TUNE_PCG, LAP_EINVAL, "unknown tuning target");
     LAP_REQUIRE(b >= 1 && b <= 64, LAP_EINVAL, "block width must be in [1, 64]");
+    LAP_REQUIRE(target != LAP_TUNE_PCG || b == 1, LAP_EINVAL, "the PCG target takes b = 1");
+    LAP_REQUIRE(target != LAP_TUNE_PCG || P->n > 16, LAP_EINVAL, "the PCG target needs n > 16");
     const int def_lt = 32, def_ht = 512;
-    const std::string key = cache_key(P, dt, b);
+    const std::string key = cache_key(P, dt, b, target);
     lap_tune_info out{};
     if (cache_path) {
         for (const Entry &e : read_cache(cache_path)) {
@@ -187,7 +262,7 @@ void autotune(lap_plan *P, lap_dtype dt, int b, const char *cache_path, lap_tune
     }
     const int reps = P->n >= 200000 ? 20 : 100;
     // candidate thresholds; pairs that classify the rows alike are timed once
-    const int longs[] = {8, 16, 32, 64, 128};
+    const int longs[] = {2, 4, 8, 16, 32, 64, 128};
     const int huges[] = {128, 256, 512, 1024, 2048, 8192};
     std::vector<std::pair<int, int>> cand, seen;
     cand.push_back({def_lt, def_ht});
@@ -204,7 +279,9 @@ void autotune(lap_plan *P, lap_dtype dt, int b, const char *cache_path, lap_tune
     std::pair<int, int> best_c = cand[0];
     for (size_t i = 0; i < cand.size(); ++i) {
         build_layout(P, cand[i].first, cand[i].second);
-        const double t = time_product(P, dt, b, reps);
+        const double t = target == LAP_TUNE_PCG
+                             ? (dt == LAP_F32 ? time_pcg<float>(P, 8) : time_pcg<double>(P, 8))
+                             : time_product(P, dt, b, reps);
         if (i == 0) def_t = t;
         if (t < best) {
             best = t;

@@ -86,7 +86,7 @@ def test_autotune_chooses_a_timed_layout_and_caches_it(tmp_path):
     assert len(doc["entries"]) == 1
     e = doc["entries"][0]
     assert (e["long"], e["huge"]) == (info["long_threshold"], info["huge_threshold"])
-    assert "|b1|f32|" in e["key"]
+    assert "|product|b1|f32|" in e["key"]
     # a second plan of the same graph takes the cached choice without timing
     plan2 = lap.Plan(L)
     info2 = plan2.autotune("f32", 1, str(cache))
@@ -110,3 +110,22 @@ def test_eigs_after_retuning_match_the_dense_reference():
             r = lap.lap_eigs(plan, k, 1e-8, precision=prec)
             assert r.nconv == k
             assert np.all(np.abs(r.evals - ref) <= 1e-8 * np.maximum(ref, 1e-3)), (lt, ht, prec, r.evals - ref)
+
+
+@pytest.mark.parametrize("dtype,prec", [("f32", "mixed"), ("f64", "fp64")])
+def test_pcg_target_tunes_for_the_inner_solve(dtype, prec, tmp_path):
+    L = graph("pa5k")
+    plan = lap.Plan(L)
+    cache = tmp_path / "t.json"
+    info = plan.autotune(dtype, 1, str(cache), target="pcg")
+    assert not info["from_cache"] and info["candidates"] >= 2
+    assert 0 < info["best_us"] <= info["default_us"] * (1 + 1e-12)
+    assert plan.layout() == (info["long_threshold"], info["huge_threshold"])
+    assert "|pcg|b1|" + dtype + "|" in json.loads(cache.read_text())["entries"][0]["key"]
+    with pytest.raises(lap.LapError):
+        plan.autotune(dtype, 4, None, target="pcg")
+    k = 6
+    ref = np.linalg.eigvalsh(L.dense())[:k]
+    r = lap.lap_eigs(plan, k, 1e-8, precision=prec)
+    assert r.nconv == k
+    assert np.all(np.abs(r.evals - ref) <= 1e-8 * np.maximum(ref, 1e-3))
