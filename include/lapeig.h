@@ -82,9 +82,12 @@ typedef struct {
     int precision;       /* lap_precision */
     int block;           /* corrections per outer iteration: 1 is Algorithm 2 */
     uint64_t seed;       /* SplitMix64 stream for start vectors */
-    const double *init;  /* optional start block, host, n x init_cols column-major,
-                            caller's vertex order; NULL for a seeded random start */
+    const double *init;  /* optional start block, n x init_cols column-major, caller's
+                            vertex order; NULL for a seeded random start.  The solver
+                            orthogonalizes it, so any columns will do; the answer is
+                            certified either way and only the iteration count changes */
     int init_cols;
+    int init_on_device;  /* 0: init is host memory; 1: device memory */
 } lap_eigs_opts;
 
 typedef struct {
@@ -235,6 +238,53 @@ lap_status lap_batch_eigs(lap_batch *batch, int k, double tol, const lap_eigs_op
                           double *evecs, double *res, lap_eigs_info *infos, void *stream);
 lap_status lap_eigs_batch(const lap_csr *Ls, int nb, int k, double tol, const lap_eigs_opts *opts,
                           double *evals, double *evecs, double *res, lap_eigs_info *infos, void *stream);
+
+/* Learned start block (an engineering addition: the paper starts from a
+ * single unit vector, Algorithm 2).  A small message-passing network over
+ * the plan's graph proposes out_cols start vectors; lap_eigs takes them as
+ * opts.init, and its FP64 certificate decides the answer as always.
+ *   features of vertex i: 1, log(1 + d_i), the mean of log(1 + d_j) over
+ *     its neighbours (weighted), and random_channels values sqrt(3) u with
+ *     u the SplitMix64 uniform variate in [-1, 1) of counter
+ *     i * random_channels + c under feature_seed (i the caller's index);
+ *   layers hidden layers h' = ReLU([h | D^{-1}A h] W + b), width hidden;
+ *   output Y = [h | D^{-1}A h] W_o + b_o (out_cols columns), minus its
+ *     column means (the component of the zero eigenvector; connected
+ *     graphs).
+ * Parameters are FP32, one flat vector: per layer W (column-major,
+ * 2 F_in x F_out) then b, output layer last; lap_mpnn_create draws W
+ * Glorot-uniform from SplitMix64 under cfg->seed, b = 0.
+ * Training minimizes loss = 1 - trace(S^{-1} C C')/kx, S = Yh'Yh,
+ * C = Yh'X, for orthonormal eigenvectors X (n x kx, orthogonal to the
+ * constant vector): the mean squared cosine of the principal angles
+ * between span X and span Yh, complemented.  Limits: 1 <= hidden <= 32,
+ * 0 <= layers <= 8, 0 <= random_channels <= 16, 1 <= out_cols,
+ * out_cols + kx <= 32; loss and training need a connected graph.
+ *   lap_mpnn_infer: V0 (device, n x out_cols column-major, caller order).
+ *   lap_mpnn_loss_grad: X device (n x kx column-major, caller order);
+ *     loss (host double); grad (host, num_params floats) or NULL.
+ *   lap_mpnn_train_step: the same, then one Adam step (beta 0.9 / 0.999,
+ *     eps 1e-8) with learning rate lr.
+ * All three run on stream and synchronize it before returning. */
+typedef struct {
+    int32_t layers;
+    int32_t hidden;
+    int32_t random_channels;
+    int32_t out_cols;
+    uint64_t seed;
+} lap_mpnn_config;
+typedef struct lap_mpnn lap_mpnn;
+
+lap_status lap_mpnn_create(const lap_mpnn_config *cfg, lap_mpnn **out);
+void lap_mpnn_destroy(lap_mpnn *net);
+int64_t lap_mpnn_num_params(const lap_mpnn *net);
+lap_status lap_mpnn_get_params(const lap_mpnn *net, float *params);
+lap_status lap_mpnn_set_params(lap_mpnn *net, const float *params); /* also resets Adam */
+lap_status lap_mpnn_infer(lap_mpnn *net, lap_plan *plan, uint64_t feature_seed, double *V0, void *stream);
+lap_status lap_mpnn_loss_grad(lap_mpnn *net, lap_plan *plan, uint64_t feature_seed, const double *X, int kx,
+                              double *loss, float *grad, void *stream);
+lap_status lap_mpnn_train_step(lap_mpnn *net, lap_plan *plan, uint64_t feature_seed, const double *X, int kx,
+                               float lr, double *loss, void *stream);
 
 const char *lap_status_string(lap_status s);
 const char *lap_last_error(void);

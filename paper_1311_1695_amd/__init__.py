@@ -40,6 +40,8 @@ LAP_ORDER_PLAN = 1
 
 EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
             "lap_plan_set_layout", "lap_plan_layout", "lap_plan_autotune",
+            "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
+            "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
             "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
@@ -66,7 +68,12 @@ class _Opts(ctypes.Structure):
     _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("itmax", ctypes.c_int),
                 ("rtol_pcg", ctypes.c_double), ("kmax", ctypes.c_int), ("precision", ctypes.c_int),
                 ("block", ctypes.c_int), ("seed", ctypes.c_uint64), ("init", ctypes.POINTER(ctypes.c_double)),
-                ("init_cols", ctypes.c_int)]
+                ("init_cols", ctypes.c_int), ("init_on_device", ctypes.c_int)]
+
+
+class _MpnnConfig(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int32), ("hidden", ctypes.c_int32), ("random_channels", ctypes.c_int32),
+                ("out_cols", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class _Info(ctypes.Structure):
@@ -114,6 +121,17 @@ def load_library():
     lib.lap_batch_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info), vp]
     lib.lap_eigs_batch.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p,
                                    f64p, P(_Info), vp]
+    lib.lap_mpnn_create.argtypes = [P(_MpnnConfig), P(vp)]
+    lib.lap_mpnn_destroy.argtypes = [vp]
+    lib.lap_mpnn_destroy.restype = None
+    lib.lap_mpnn_num_params.argtypes = [vp]
+    lib.lap_mpnn_num_params.restype = ctypes.c_int64
+    f32p = P(ctypes.c_float)
+    lib.lap_mpnn_get_params.argtypes = [vp, f32p]
+    lib.lap_mpnn_set_params.argtypes = [vp, f32p]
+    lib.lap_mpnn_infer.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
+    lib.lap_mpnn_loss_grad.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int, f64p, f32p, vp]
+    lib.lap_mpnn_train_step.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int, ctypes.c_float, f64p, vp]
     lib.lap_status_string.argtypes = [ctypes.c_int]
     lib.lap_status_string.restype = ctypes.c_char_p
     lib.lap_last_error.argtypes = []
@@ -239,7 +257,13 @@ def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0,
     o.precision = {"mixed": LAP_PREC_MIXED, "fp64": LAP_PREC_FP64}[precision] if isinstance(precision, str) else int(precision)
     o.block, o.seed = block, seed
     keep = None
-    if init is not None:
+    if init is not None and hasattr(init, "data_ptr"):
+        # a torch tensor on the device, (p, n) row-major = n x p column-major
+        keep = init
+        o.init = ctypes.cast(ctypes.c_void_p(init.data_ptr()), ctypes.POINTER(ctypes.c_double))
+        o.init_cols = int(init.shape[0]) if init.dim() == 2 else 1
+        o.init_on_device = 1
+    elif init is not None:
         keep = np.asfortranarray(np.asarray(init, dtype=np.float64))
         if keep.ndim == 1:
             keep = keep[:, None]
@@ -251,7 +275,8 @@ def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0,
 def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noconv=False, **kw) -> EigResult:
     """The k smallest eigenpairs (k counts the zero eigenvalues).  Keyword
     options: precision ('mixed' | 'fp64'), m_min, m_max, itmax, rtol_pcg,
-    kmax, block, seed, init (n x p start block)."""
+    kmax, block, seed, init (n x p numpy start block, or a (p, n) float64
+    device tensor such as Mpnn.infer returns)."""
     lib = load_library()
     o, keep = _opts(**kw)
     n = plan.n
@@ -406,3 +431,70 @@ def lap_eigs_batch(graphs, k, tol, **kw):
         return lap_batch_eigs(b, k, tol, **kw)
     finally:
         b.close()
+
+
+class Mpnn:
+    """The warm-start network of lap_mpnn_* on the current device (all of its
+    arithmetic in the library's kernels).  X and the inferred start block
+    are float64 device tensors of shape (columns, n), i.e. n x columns
+    column-major, in the caller's vertex order."""
+
+    def __init__(self, layers=2, hidden=32, random_channels=4, out_cols=9, seed=1):
+        lib = load_library()
+        self.cfg = _MpnnConfig(int(layers), int(hidden), int(random_channels), int(out_cols), int(seed))
+        h = ctypes.c_void_p()
+        _check(lib.lap_mpnn_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+        self.num_params = int(lib.lap_mpnn_num_params(h))
+
+    @property
+    def out_cols(self) -> int:
+        return int(self.cfg.out_cols)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(load_library().lap_mpnn_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        assert a.size == self.num_params
+        _check(load_library().lap_mpnn_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def infer(self, plan: Plan, feature_seed=1, stream=None):
+        import torch
+        V = torch.empty((self.out_cols, plan.n), dtype=torch.float64, device="cuda")
+        _check(load_library().lap_mpnn_infer(self._h, plan._h, int(feature_seed), ctypes.c_void_p(V.data_ptr()),
+                                             _stream_handle(stream)))
+        return V
+
+    def loss_grad(self, plan: Plan, X, feature_seed=1, stream=None, want_grad=True):
+        loss = ctypes.c_double()
+        g = np.empty(self.num_params, dtype=np.float32) if want_grad else None
+        _check(load_library().lap_mpnn_loss_grad(
+            self._h, plan._h, int(feature_seed), ctypes.c_void_p(X.data_ptr()), int(X.shape[0]),
+            ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None,
+            _stream_handle(stream)))
+        return loss.value, g
+
+    def train_step(self, plan: Plan, X, lr=1e-2, feature_seed=1, stream=None) -> float:
+        loss = ctypes.c_double()
+        _check(load_library().lap_mpnn_train_step(self._h, plan._h, int(feature_seed), ctypes.c_void_p(X.data_ptr()),
+                                                  int(X.shape[0]), float(lr), ctypes.byref(loss),
+                                                  _stream_handle(stream)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().lap_mpnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lap_mpnn_create(**cfg) -> Mpnn:
+    return Mpnn(**cfg)

@@ -1,10 +1,12 @@
 // extern "C" entry points of lapeig.h: argument validation (on the host,
 // before any HIP call), error codes and messages, order conversions.
 #include <cmath>
+#include <memory>
 #include <new>
 #include <vector>
 
 #include "block_kernels.h"
+#include "mpnn_internal.h"
 
 namespace lapeig {
 
@@ -112,6 +114,101 @@ void lap_eigs_default_opts(lap_eigs_opts *o) {
     o->seed = 1;
     o->init = nullptr;
     o->init_cols = 0;
+    o->init_on_device = 0;
+}
+
+lap_status lap_mpnn_create(const lap_mpnn_config *cfg, lap_mpnn **out) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(cfg && out, LAP_EINVAL, "config or output pointer is NULL");
+    *out = nullptr;
+    std::unique_ptr<lap_mpnn> m(new lap_mpnn);
+    lapeig::mpnn_init(m.get(), *cfg);
+    *out = m.release();
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+void lap_mpnn_destroy(lap_mpnn *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    delete m;
+}
+
+int64_t lap_mpnn_num_params(const lap_mpnn *m) { return m ? (int64_t)m->nparams : 0; }
+
+lap_status lap_mpnn_get_params(const lap_mpnn *m, float *params) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(m && params, LAP_EINVAL, "network or params is NULL");
+    LAP_HIP(hipSetDevice(m->device));
+    LAP_HIP(hipMemcpy(params, m->params.get(), sizeof(float) * m->nparams, hipMemcpyDeviceToHost));
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_mpnn_set_params(lap_mpnn *m, const float *params) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(m && params, LAP_EINVAL, "network or params is NULL");
+    for (long long t = 0; t < m->nparams; ++t)
+        LAP_REQUIRE(std::isfinite(params[t]), LAP_EINVAL, "params hold non-finite values");
+    LAP_HIP(hipSetDevice(m->device));
+    LAP_HIP(hipMemcpy(m->params.get(), params, sizeof(float) * m->nparams, hipMemcpyHostToDevice));
+    LAP_HIP(hipMemset(m->adam_m.get(), 0, sizeof(float) * m->nparams));
+    LAP_HIP(hipMemset(m->adam_v.get(), 0, sizeof(float) * m->nparams));
+    m->step = 0;
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+static void check_net(const lap_mpnn *m, const lap_plan *p) {
+    LAP_REQUIRE(m && p, LAP_EINVAL, "network or plan is NULL");
+    LAP_REQUIRE(m->device == p->device, LAP_EINVAL, "network and plan live on different devices");
+}
+
+lap_status lap_mpnn_infer(lap_mpnn *m, lap_plan *p, uint64_t feature_seed, double *V0, void *stream) {
+    LAP_GUARD_BEGIN
+    check_net(m, p);
+    LAP_REQUIRE(V0, LAP_EINVAL, "V0 is NULL");
+    LAP_HIP(hipSetDevice(p->device));
+    hipStream_t s = (hipStream_t)stream;
+    lapeig::mpnn_forward(m, *p, feature_seed, s);
+    lapeig::mpnn_output(m, *p, V0, s);
+    LAP_HIP(hipStreamSynchronize(s));
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_mpnn_loss_grad(lap_mpnn *m, lap_plan *p, uint64_t feature_seed, const double *X, int kx, double *loss,
+                              float *grad, void *stream) {
+    LAP_GUARD_BEGIN
+    check_net(m, p);
+    LAP_REQUIRE(X && loss, LAP_EINVAL, "X or loss is NULL");
+    LAP_REQUIRE(kx >= 1 && m->cfg.out_cols + kx <= lapeig::kMpnnMaxCols, LAP_EINVAL,
+                "need 1 <= kx and out_cols + kx <= 32");
+    LAP_HIP(hipSetDevice(p->device));
+    hipStream_t s = (hipStream_t)stream;
+    *loss = lapeig::mpnn_loss_grad(m, *p, feature_seed, X, kx, s);
+    if (grad)
+        LAP_HIP(hipMemcpy(grad, m->grad.get(), sizeof(float) * m->nparams, hipMemcpyDeviceToHost));
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_mpnn_train_step(lap_mpnn *m, lap_plan *p, uint64_t feature_seed, const double *X, int kx, float lr,
+                               double *loss, void *stream) {
+    LAP_GUARD_BEGIN
+    check_net(m, p);
+    LAP_REQUIRE(X, LAP_EINVAL, "X is NULL");
+    LAP_REQUIRE(kx >= 1 && m->cfg.out_cols + kx <= lapeig::kMpnnMaxCols, LAP_EINVAL,
+                "need 1 <= kx and out_cols + kx <= 32");
+    LAP_REQUIRE(std::isfinite(lr) && lr > 0.f, LAP_EINVAL, "lr must be > 0");
+    LAP_HIP(hipSetDevice(p->device));
+    hipStream_t s = (hipStream_t)stream;
+    const double l = lapeig::mpnn_loss_grad(m, *p, feature_seed, X, kx, s);
+    lapeig::mpnn_adam(m, lr, s);
+    LAP_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = l;
+    return LAP_OK;
+    LAP_GUARD_END
 }
 
 const char *lap_status_string(lap_status s) {
@@ -197,7 +294,8 @@ static void check_opts(const lap_eigs_opts &o, int n) {
     LAP_REQUIRE(o.block >= 1, LAP_EINVAL, "block must be >= 1");
     LAP_REQUIRE(o.init_cols >= 0 && (o.init_cols == 0 || o.init != nullptr), LAP_EINVAL,
                 "init_cols > 0 needs an init block");
-    if (o.init)
+    LAP_REQUIRE(o.init_on_device == 0 || o.init_on_device == 1, LAP_EINVAL, "init_on_device must be 0 or 1");
+    if (o.init && !o.init_on_device)  // a device block is checked by the solver's non-finite guards
         for (long long t = 0; t < (long long)n * o.init_cols; ++t)
             LAP_REQUIRE(std::isfinite(o.init[t]), LAP_EINVAL, "init block holds non-finite values");
 }

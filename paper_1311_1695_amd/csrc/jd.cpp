@@ -216,7 +216,8 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     if (o.init && o.init_cols > 0) {
         init_dev.alloc((size_t)n * o.init_cols);
         DevBuf<double> tmp((size_t)n * o.init_cols);
-        LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * o.init_cols, hipMemcpyHostToDevice, s));
+        LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * o.init_cols,
+                                o.init_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         for (int c = 0; c < o.init_cols; ++c)
             permute_rows<double>(P->d_perm.get(), n, 1, tmp.get() + (size_t)c * n, init_dev.get() + (size_t)c * n, s);
         LAP_HIP(hipStreamSynchronize(s));

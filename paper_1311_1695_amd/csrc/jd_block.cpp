@@ -131,7 +131,8 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         // the caller's start vectors (column-major, caller order) first, then random columns
         const int c0 = std::min(o.init_cols, b);
         DevBuf<double> tmp((size_t)n * c0);
-        LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * c0, hipMemcpyHostToDevice, s));
+        LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * c0,
+                                o.init_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         blk_random(n, b, o.seed, colbase, P->d_iperm.get(), Vn.get(), b, s);
         colbase += b;
         blk_cm_to_rm(n, c0, tmp.get(), P->d_perm.get(), Vn.get(), b, s);

@@ -32,7 +32,7 @@ __all__ = [
     "pa_edges", "chung_lu_edges", "triadic_closure", "integer_weights",
     "path_graph", "cycle_graph", "star_graph", "complete_graph",
     "complete_bipartite_graph", "hypercube_graph", "grid_graph",
-    "disjoint_union", "workload", "WORKLOADS", "pa_batch",
+    "disjoint_union", "workload", "WORKLOADS", "pa_batch", "collaboration",
 ]
 
 
@@ -320,6 +320,13 @@ def _cl_lcc(n, gamma, dbar, seed, name, w_max=None, triadic=None, weighted=False
     w = integer_weights(u.shape[0], seed + 104729) if weighted else None
     n2, u, v, w = largest_component(n, u, v, w)
     return laplacian_from_edges(n2, u, v, w, name=name)
+
+
+def collaboration(n: int, seed: int, weighted: bool = False) -> LaplacianCSR:
+    """The collaboration-like family of the warm-start workload (Chung-Lu
+    exponent 2.3, mean degree 7, triadic closure 0.3, largest component) at
+    any size: the graphs the warm-start network is trained on."""
+    return _cl_lcc(n, 2.3, 7.0, seed, f"collab{n}", triadic=0.3, weighted=weighted)
 
 
 WORKLOADS = {
