@@ -212,6 +212,60 @@ def extra_configs(lap, torch, gg, np, reps=3):
     return out
 
 
+def warm_start_config(lap, torch, gg, np, reps=2):
+    """The collaboration-like graph (Chung-Lu exponent 2.3, n = 1.1M, mean
+    degree 7, triadic closure 0.3, largest component), k = 10 at 1e-8: JD
+    started from the learned network's block vs from the seeded random
+    vector (mixed precision), and plain FP64 JD from the random vector.
+    The network (2 layers, width 32, 4 random channels, 9 columns) is
+    trained first, on the GPU, on six graphs of the same family with
+    n <= 20k whose eigenvectors lap_eigs computes (tol 1e-6)."""
+    t0 = time.perf_counter()
+    train = [gg.collaboration(n, s) for n, s in [(8000, 101), (12000, 102), (16000, 103), (20000, 104),
+                                                 (10000, 105), (14000, 106)]]
+    plans = [lap.Plan(L) for L in train]
+    targets = [lap.lap_eigs(p, 10, 1e-6, evecs_on_device=True).evecs[1:].contiguous() for p in plans]
+    net = lap.Mpnn(layers=2, hidden=32, random_channels=4, out_cols=9, seed=7)
+    losses = []
+    for s in range(400):
+        g = s % len(plans)
+        losses.append(net.train_step(plans[g], targets[g], lr=3e-3, feature_seed=1 + (s // len(plans)) % 4))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+    L = gg.workload("cl1m_tc", SEED)
+    plan = lap.Plan(L)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    V0 = net.infer(plan, feature_seed=1)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t1
+    entry = {"workload": "cl1m_tc", "n": L.n, "nnz": L.nnz, "k": 10, "tol": 1e-8,
+             "network": {"layers": 2, "hidden": 32, "random_channels": 4, "out_cols": 9,
+                         "params": net.num_params, "train_steps": 400, "train_s": round(t_train, 3),
+                         "loss_first": round(float(np.mean(losses[:6])), 4),
+                         "loss_last": round(float(np.mean(losses[-6:])), 4),
+                         "infer_ms": round(t_infer * 1e3, 3)},
+             "runs": {}}
+    variants = [("mixed_warm", dict(precision="mixed", init=V0)), ("mixed_random", dict(precision="mixed")),
+                ("fp64_random", dict(precision="fp64"))]
+    for label, kw in variants:
+        best, r = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = lap.lap_eigs(plan, 10, 1e-8, seed=1, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        entry["runs"][label] = {"s": round(best, 5), "mvp": r.mvp, "outer": r.outer, "inner": r.inner,
+                                "nconv": r.nconv, "max_rel_residual": certify(L, r, 1e-8)}
+    entry["runs"]["mixed_warm"]["s_with_inference"] = round(entry["runs"]["mixed_warm"]["s"] + t_infer, 5)
+    plan.close()
+    return entry
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,7 +277,9 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the PCG iteration timing and a copy of known size (for profiling)")
     ap.add_argument("--extra", action="store_true",
-                    help="also time the other workloads (pa5k FP64; cl330k block JD)")
+                    help="also time the other workloads (pa5k FP64; cl330k block JD; batch)")
+    ap.add_argument("--warmstart", action="store_true",
+                    help="also time the learned warm start on the 1.1M-vertex collaboration graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build",
@@ -340,6 +396,8 @@ def main():
         out["spmv_sweep"] = sweep
     if args.extra:
         out["configs"] = extra_configs(lap, torch, gg, np)
+    if args.warmstart:
+        out["warm_start"] = warm_start_config(lap, torch, gg, np)
     if not args.no_cpu:
         t_cpu, reps, cres = cpu_baseline(L, K_PAIRS, TOL)
         out["cpu_baseline"] = {"value": round(t_cpu, 4), "unit": "s", "cores": 1, "kind": "oracle",
