@@ -120,3 +120,44 @@ def test_entry_points_reject_null_arguments():
     assert lib.lap_pcg(None, lap.LAP_F32, 1, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0,
                        None, None, 20, 1e-2, None, 0, None) == lap.LAP_EINVAL
     assert lib.lap_last_error()
+
+
+def test_layout_and_tuning_entry_points_reject_null_plans():
+    lib = lap.load_library()
+    lt, ht = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.lap_plan_set_layout(None, 32, 512) == -1
+    assert lib.lap_plan_layout(None, ctypes.byref(lt), ctypes.byref(ht)) == -1
+    info = lap._TuneInfo()
+    assert lib.lap_plan_autotune(None, 0, 0, 1, None, ctypes.byref(info)) == -1
+
+
+@pytest.mark.parametrize("cfg", [dict(hidden=0), dict(hidden=33), dict(layers=-1), dict(layers=9),
+                                 dict(random_channels=17), dict(out_cols=0), dict(out_cols=32)])
+def test_network_config_is_validated_before_the_device(cfg):
+    base = dict(layers=2, hidden=32, random_channels=4, out_cols=9, seed=1)
+    base.update(cfg)
+    lib = lap.load_library()
+    c = lap._MpnnConfig(base["layers"], base["hidden"], base["random_channels"], base["out_cols"], base["seed"])
+    h = ctypes.c_void_p()
+    assert lib.lap_mpnn_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_network_entry_points_reject_null_handles():
+    lib = lap.load_library()
+    loss = ctypes.c_double()
+    assert lib.lap_mpnn_create(None, None) == -1
+    assert lib.lap_mpnn_num_params(None) == 0
+    assert lib.lap_mpnn_get_params(None, None) == -1
+    assert lib.lap_mpnn_set_params(None, None) == -1
+    assert lib.lap_mpnn_infer(None, None, 1, None, None) == -1
+    assert lib.lap_mpnn_loss_grad(None, None, 1, None, 4, ctypes.byref(loss), None, None) == -1
+    assert lib.lap_mpnn_train_step(None, None, 1, None, 4, 1e-3, ctypes.byref(loss), None) == -1
+    lib.lap_mpnn_destroy(None)
+
+
+def test_eigs_options_default_to_a_host_start_block():
+    lib = lap.load_library()
+    o = lap._Opts()
+    lib.lap_eigs_default_opts(ctypes.byref(o))
+    assert o.init_on_device == 0 and o.init_cols == 0 and not o.init
