@@ -274,41 +274,79 @@ __global__ void k_svqb(int b, const double *__restrict__ lam, const double *__re
     }
 }
 
-// R = GU - U diag(theta);  ||R_c||^2, ||U_c||^2;  U also into Q (type T,
-// columns qoff..) and column 0 of U into u0 (for the certificate).
+template <typename T, int NQ>
+__device__ __forceinline__ void col_partials(const T (&acc)[NQ], int b, T *__restrict__ part) {
+    __shared__ T red[NQ][kBlock];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) red[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    if ((int)threadIdx.x < b) {
+        const int base = (int)(((size_t)blockIdx.x * blockDim.x) % (size_t)b);
+        const int t0 = ((int)threadIdx.x - base + b) % b;  // first thread of this column
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            T s = T(0);
+            for (int t = t0; t < kBlock; t += b) s += red[j][t];
+            part[(size_t)blockIdx.x * 64 + 32 * j + threadIdx.x] = s;
+        }
+    }
+}
+
+// totals[v] = sum over the nb partial rows of value v (v < nv; row stride 64)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bfold(const T *__restrict__ part, int nb, int nv, T *__restrict__ totals) {
+    const int lane = lane_id();
+    for (int v = blockIdx.x * kWavesPerBlock + wave_id(); v < nv; v += gridDim.x * kWavesPerBlock) {
+        T s = T(0);
+        int g = lane;
+        for (; g + 3 * kWave < nb; g += 4 * kWave) {
+            const T a0 = part[(size_t)g * 64 + v], a1 = part[(size_t)(g + kWave) * 64 + v];
+            const T a2 = part[(size_t)(g + 2 * kWave) * 64 + v], a3 = part[(size_t)(g + 3 * kWave) * 64 + v];
+            s += a0; s += a1; s += a2; s += a3;
+        }
+        for (; g < nb; g += kWave) s += part[(size_t)g * 64 + v];
+        s = wave_sum(s);
+        if (lane == 0) totals[v] = s;
+    }
+}
+
+// R = GU - U diag(theta);  U also into Q (type T, columns qoff..) and
+// column 0 of U into u0 (for the certificate).  Column grid over the n x ldu
+// blocks (columns c >= bu are skipped); partials ||R_c||^2, ||U_c||^2.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_block_resid(int n, int bu, const double *__restrict__ U,
                                                         const double *__restrict__ GU, int ldu,
                                                         const double *__restrict__ theta, double *__restrict__ R,
                                                         T *__restrict__ Q, int ldq, int qoff, double *__restrict__ u0,
-                                                        double *partial, unsigned *counter, BlockStatus *st) {
-    __shared__ double th[32];
-    for (int c = threadIdx.x; c < bu; c += blockDim.x) th[c] = theta[c];
-    __syncthreads();
-    double acc[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) acc[j] = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int c = 0; c < 32; ++c) {
-            if (c < bu) {
-                const double uv = U[(size_t)i * ldu + c];
-                const double rv = GU[(size_t)i * ldu + c] - th[c] * uv;
-                R[(size_t)i * ldu + c] = rv;
-                Q[(size_t)i * ldq + qoff + c] = (T)uv;
-                acc[c] += rv * rv;
-                acc[32 + c] += uv * uv;
-            }
+                                                        double *__restrict__ part) {
+    const size_t tot = (size_t)n * ldu, stride = (size_t)gridDim.x * blockDim.x;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t % ldu);
+    double acc[2] = {0.0, 0.0};
+    if (c < bu) {
+        const double th = theta[c];
+        for (; t < tot; t += stride) {
+            const size_t i = t / ldu;
+            const double uv = U[t];
+            const double rv = GU[t] - th * uv;
+            R[t] = rv;
+            Q[i * ldq + qoff + c] = (T)uv;
+            if (c == 0) u0[i] = uv;
+            acc[0] += rv * rv;
+            acc[1] += uv * uv;
         }
-        u0[i] = U[(size_t)i * ldu];
     }
-    __shared__ double out[64];
-    if (grid_reduce<double, 64>(acc, 64, partial, counter, out)) {
-        for (int c = threadIdx.x; c < bu; c += blockDim.x) {
-            st->unorm[c] = sqrt(out[32 + c]);
-            st->rnorm[c] = sqrt(out[c]) / st->unorm[c];
-            st->theta[c] = th[c];
-        }
+    col_partials<double, 2>(acc, ldu, part);
+}
+
+// Ritz residual norms of the block from the folded sums
+__global__ void k_block_resid_status(int bu, const double *__restrict__ theta, const double *__restrict__ tot,
+                                     BlockStatus *st) {
+    for (int c = threadIdx.x; c < bu; c += blockDim.x) {
+        const double un = sqrt(tot[32 + c]);
+        st->unorm[c] = un;
+        st->rnorm[c] = sqrt(tot[c]) / un;
+        st->theta[c] = theta[c];
     }
 }
 
@@ -341,189 +379,157 @@ __global__ void k_random_block(int n, int b, unsigned long long seed, long long 
 // Columns c < b solve (I-QQ')(G - theta_c I)(I-QQ') t_c = -r_c with a shared
 // projector Q (row-major, q columns, type T).  Per-column state; a column
 // stops on its own (tolerance or breakdown) and is masked afterwards.
+//
+// The elementwise launches run on a "column grid": its stride (workgroups x
+// 256) is a multiple of b, so every thread keeps one column of the row-major
+// n x b blocks for its whole loop, loads are coalesced, and each thread
+// accumulates one value per quantity.  Workgroups leave per-column partial
+// sums (row stride 64: quantity j of column c at 32 j + c), which k_bfold
+// adds (one wavefront per value, fixed order) into a totals slot of the
+// state read by the next launch.
 
-// init 1: Res = -R (convert), T = 0; ||r_c||
+__device__ __forceinline__ bool leader0() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// any column still iterating (flags of slot a)
+template <typename T>
+__device__ __forceinline__ bool any_active(const BPcgState<T> *st, int a, int b) {
+    int any = 0;
+    for (int c = 0; c < b; ++c) any |= st->act[a][c];
+    return any != 0;
+}
+
+// init 1: Res = -R (converted), X = 0;  partials ||r_c||^2
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bpcg_init1(int n, int b, const double *__restrict__ R, int ldr,
-                                                       T *__restrict__ Res, T *__restrict__ X, T *partial,
-                                                       unsigned *counter, BPcgState<T> *st) {
-    T acc[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = T(0);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-            if (c < b) {
-                const T r = (T)R[(size_t)i * ldr + c];
-                Res[(size_t)i * b + c] = -r;
-                X[(size_t)i * b + c] = T(0);
-                acc[c] += r * r;
-            }
+                                                       T *__restrict__ Res, T *__restrict__ X, T *__restrict__ part) {
+    const size_t tot = (size_t)n * b, stride = (size_t)gridDim.x * blockDim.x;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t % b);
+    T acc[1] = {T(0)};
+    for (; t < tot; t += stride) {
+        const size_t i = t / b;
+        const T r = (T)R[i * ldr + c];
+        Res[t] = -r;
+        X[t] = T(0);
+        acc[0] += r * r;
     }
-    __shared__ T out[32];
-    if (grid_reduce<T, 32>(acc, b, partial, counter, out)) {
-        for (int c = threadIdx.x; c < b; c += blockDim.x) {
-            st->r0[c] = sqrt(out[c]);
-            st->active[c] = st->r0[c] > T(0);
-            st->its[c] = 0;
-            st->brk[c] = 0;
-            st->copy_p[c] = 0;
-        }
-        if (threadIdx.x == 0) {
-            int a = 0;
-            for (int c = 0; c < b; ++c) a += st->r0[c] > T(0);
-            st->nactive = a;
-        }
-    }
+    col_partials<T, 1>(acc, b, part);
 }
 
-// Y = D^{-1} Res;  rho_c = Res_c' Y_c   (init)
+// init 2 (after Res <- (I - QQ')Res): r0_c and the flags; Y = D^{-1} Res;
+// partials rho_c = Res_c'Y_c
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bpcg_init2(int n, int b, const T *__restrict__ Res, T *__restrict__ Y,
-                                                       const T *__restrict__ dinv, T *partial, unsigned *counter,
+                                                       const T *__restrict__ dinv, T *__restrict__ part,
                                                        BPcgState<T> *st) {
-    if (st->nactive == 0) return;
-    T acc[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = T(0);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const T d = dinv[i];
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-            if (c < b) {
-                const T r = Res[(size_t)i * b + c];
-                const T y = d * r;
-                Y[(size_t)i * b + c] = y;
-                acc[c] += r * y;
-            }
+    if (blockIdx.x == 0 && (int)threadIdx.x < b) {
+        const int c = threadIdx.x;
+        const T r0 = sqrt(st->tot_a[c]);
+        st->r0[c] = r0;
+        st->act[0][c] = r0 > T(0);
+        st->its[c] = 0;
+        st->brk[c] = 0;
     }
-    __shared__ T out[32];
-    if (grid_reduce<T, 32>(acc, b, partial, counter, out)) {
-        for (int c = threadIdx.x; c < b; c += blockDim.x) {
-            st->rho[c] = out[c];
-            st->beta[c] = T(0);
-        }
+    const size_t tot = (size_t)n * b, stride = (size_t)gridDim.x * blockDim.x;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    T acc[1] = {T(0)};
+    for (; t < tot; t += stride) {
+        const T r = Res[t];
+        const T y = dinv[t / b] * r;
+        Y[t] = y;
+        acc[0] += r * y;
     }
+    col_partials<T, 1>(acc, b, part);
 }
 
-// pAp_c = P_c' S_c;  alpha_c or breakdown
+// p0: rho_c from the folded sums; P = Z  (Z = (I - QQ')Y)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bpcg_p0(int n, int b, const T *__restrict__ Z, T *__restrict__ P,
+                                                    BPcgState<T> *st) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < b) st->rho[0][threadIdx.x] = st->tot_b[threadIdx.x];
+    const size_t tot = (size_t)n * b;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x)
+        P[t] = Z[t];
+}
+
+// pap: partials P_c'S_c  (= P_c'(I-QQ')S_c, P orthogonal to Q)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bpcg_pap(int n, int b, const T *__restrict__ P, const T *__restrict__ S,
-                                                     T *partial, unsigned *counter, BPcgState<T> *st, int it) {
-    if (st->nactive == 0) return;
-    T acc[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = T(0);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-            if (c < b) acc[c] += P[(size_t)i * b + c] * S[(size_t)i * b + c];
-    }
-    __shared__ T out[32];
-    if (grid_reduce<T, 32>(acc, b, partial, counter, out)) {
-        if (threadIdx.x == 0) {
-            int a = 0;
-            for (int c = 0; c < b; ++c) {
-                st->copy_p[c] = 0;
-                if (!st->active[c]) continue;
-                const T pap = out[c];
-                if (!(pap > T(0))) {  // indefinite along p: stop this column
-                    st->active[c] = 0;
-                    st->brk[c] = it;
-                    st->copy_p[c] = (it == 1);
-                } else {
-                    st->alpha[c] = st->rho[c] / pap;
-                    ++a;
-                }
-            }
-            st->nactive_step = a;
-        }
-    }
+                                                     T *__restrict__ part, const BPcgState<T> *st) {
+    if (!any_active(st, 0, b)) return;
+    const size_t tot = (size_t)n * b, stride = (size_t)gridDim.x * blockDim.x;
+    T acc[1] = {T(0)};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) acc[0] += P[t] * S[t];
+    col_partials<T, 1>(acc, b, part);
 }
 
-// update: X += alpha P;  Res -= alpha Z  (Z = (I - QQ')S);  Y = D^{-1} Res;
-// ||Res_c||, rho'_c;  beta, stop test
+// update (iteration it): alpha_c = rho_c / pAp_c or breakdown; X += alpha P;
+// Res -= alpha Z (Z = (I-QQ')S); Y = D^{-1} Res; partials Res'Res, Res'Y.
+// Reads flags of slot 0, writes slot 1.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bpcg_update(int n, int b, T *__restrict__ X, T *__restrict__ Res,
                                                         const T *__restrict__ P, const T *__restrict__ Z,
-                                                        T *__restrict__ Y, const T *__restrict__ dinv, T *partial,
-                                                        unsigned *counter, BPcgState<T> *st, int it, T rtol) {
-    if (st->nactive == 0) return;
-    __shared__ T al[32];
-    __shared__ int act[32], cp[32];
-    for (int c = threadIdx.x; c < b; c += blockDim.x) {
-        act[c] = st->active[c];
-        al[c] = st->alpha[c];
-        cp[c] = st->copy_p[c];
+                                                        T *__restrict__ Y, const T *__restrict__ dinv,
+                                                        T *__restrict__ part, BPcgState<T> *st, int it) {
+    if (!any_active(st, 0, b)) {
+        if (blockIdx.x == 0 && (int)threadIdx.x < b) st->act[1][threadIdx.x] = 0;
+        return;
     }
-    __syncthreads();
-    T acc[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) acc[j] = T(0);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const T d = dinv[i];
-#pragma unroll
-        for (int c = 0; c < 32; ++c) {
-            if (c < b) {
-                const size_t at = (size_t)i * b + c;
-                if (cp[c]) X[at] = P[at];  // no step taken before the breakdown: M(-r)
-                if (act[c]) {
-                    X[at] += al[c] * P[at];
-                    const T r = Res[at] - al[c] * Z[at];
-                    Res[at] = r;
-                    const T y = d * r;
-                    Y[at] = y;
-                    acc[c] += r * r;
-                    acc[32 + c] += r * y;
-                }
-            }
+    const size_t tot = (size_t)n * b, stride = (size_t)gridDim.x * blockDim.x;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t % b);
+    const int act = st->act[0][c];
+    const T pap = st->tot_a[c];
+    const bool brk = act && !(pap > T(0));  // the projected operator is indefinite along p
+    const bool step = act && !brk;
+    const T alpha = step ? st->rho[(it + 1) & 1][c] / pap : T(0);
+    if (blockIdx.x == 0 && (int)threadIdx.x < b) {
+        // threads 0..b-1 of workgroup 0 own columns 0..b-1
+        st->act[1][c] = step;
+        if (brk) st->brk[c] = it;
+        if (step) st->its[c] = it;
+    }
+    T acc[2] = {T(0), T(0)};
+    if (step) {
+        for (; t < tot; t += stride) {
+            X[t] += alpha * P[t];
+            const T r = Res[t] - alpha * Z[t];
+            Res[t] = r;
+            const T y = dinv[t / b] * r;
+            Y[t] = y;
+            acc[0] += r * r;
+            acc[1] += r * y;
         }
+    } else if (brk && it == 1) {
+        for (; t < tot; t += stride) X[t] = P[t];  // no step was taken before the breakdown: M(-r)
     }
-    __shared__ T out[64];
-    if (grid_reduce<T, 64>(acc, 64, partial, counter, out)) {
-        if (threadIdx.x == 0) {
-            int a = 0;
-            for (int c = 0; c < b; ++c) {
-                if (!act[c]) continue;
-                st->its[c] = it;
-                st->rn[c] = sqrt(out[c]);
-                st->beta[c] = out[32 + c] / st->rho[c];
-                st->rho[c] = out[32 + c];
-                if (st->rn[c] <= rtol * st->r0[c]) st->active[c] = 0;
-                else ++a;
-            }
-            st->nactive = a;
-        }
-    }
+    col_partials<T, 2>(acc, b, part);
 }
 
-// P = Z + beta P  (Z = (I - QQ')Y; active columns; init: P = Z)
-template <typename T, bool INIT>
-__global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__restrict__ Z, T *__restrict__ P,
-                                                   const BPcgState<T> *st) {
-    if (st->nactive == 0) return;
-    __shared__ T be[32];
-    __shared__ int act[32];
-    for (int c = threadIdx.x; c < b; c += blockDim.x) {
-        be[c] = st->beta[c];
-        act[c] = st->active[c];
-    }
-    __syncthreads();
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < (size_t)n * b; t += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(t % b);
-        if (!act[c]) continue;
-        P[t] = INIT ? Z[t] : Z[t] + be[c] * P[t];
-    }
-}
-
-// nactive from the per-column flags, for the stopping of the whole block
+// p (iteration it): ||Res_c|| <= rtol r0_c stops column c; else
+// beta = rho'/rho, P = Z + beta P (Z = (I-QQ')Y).  Reads flags of slot 1,
+// writes slot 0.
 template <typename T>
-__global__ void k_bpcg_count(int b, BPcgState<T> *st) {
-    if (threadIdx.x == 0) {
-        int a = 0;
-        for (int c = 0; c < b; ++c) a += st->active[c];
-        st->nactive = a;
+__global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__restrict__ Z, T *__restrict__ P,
+                                                   BPcgState<T> *st, int it, T rtol) {
+    if (!any_active(st, 1, b)) {
+        if (blockIdx.x == 0 && (int)threadIdx.x < b) st->act[0][threadIdx.x] = 0;
+        return;
     }
+    const size_t tot = (size_t)n * b, stride = (size_t)gridDim.x * blockDim.x;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t % b);
+    const int act = st->act[1][c];
+    const T rn = sqrt(st->tot_b[c]);
+    const T rho_new = st->tot_b[32 + c];
+    const bool go = act && !(rn <= rtol * st->r0[c]);
+    const T beta = go ? rho_new / st->rho[(it + 1) & 1][c] : T(0);
+    if (blockIdx.x == 0 && (int)threadIdx.x < b) {
+        st->act[0][c] = go;
+        if (go) st->rho[it & 1][c] = rho_new;
+    }
+    if (!go) return;
+    for (; t < tot; t += stride) P[t] = Z[t] + beta * P[t];
 }
 
 // zero eigenvectors (normalized component indicators) into [X | V] and Q
@@ -564,6 +570,15 @@ inline int bgrid(size_t work) {
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// Grid of a column kernel: stride (workgroups x 256) a multiple of b.
+inline int cgrid(size_t n, int b) {
+    int g = bgrid(n * (size_t)b);
+    int a = b, c = kBlock;
+    while (c) { const int r = a % c; a = c; c = r; }  // gcd(b, 256)
+    const int m = b / a;
+    return ((g + m - 1) / m) * m;
+}
+
 }  // namespace
 
 void blk_svqb(int b, const double *lam, const double *Z, int ldz, double rel, double abs_thr, double *M, int ldm,
@@ -575,11 +590,15 @@ void blk_svqb(int b, const double *lam, const double *Z, int ldz, double rel, do
 template <typename T>
 void blk_resid(int n, int bu, const double *U, const double *GU, int ldu, const double *theta, double *R, T *Q,
                int ldq, int qoff, double *u0, ReduceScratch &rs, BlockStatus *st, hipStream_t s) {
-    LAP_REQUIRE(bu <= 32, LAP_EUNSUPPORTED, "block wider than 32");
-    const int grid = bgrid(n);
-    rs.ensure(grid, 64);
+    LAP_REQUIRE(bu <= 32 && ldu <= 32 && bu <= ldu, LAP_EUNSUPPORTED, "block wider than 32");
+    const int grid = cgrid(n, ldu);
+    rs.ensure(grid + 1, 64);
+    double *part = rs.partial.get();
+    double *tot = part + (size_t)grid * 64;  // one more row for the totals
     hipLaunchKernelGGL((k_block_resid<T>), dim3(grid), dim3(kBlock), 0, s, n, bu, U, GU, ldu, theta, R, Q, ldq, qoff,
-                       u0, rs.partial.get(), rs.counter.get(), st);
+                       u0, part);
+    hipLaunchKernelGGL((k_bfold<double>), dim3(16), dim3(kBlock), 0, s, part, grid, 64, tot);
+    hipLaunchKernelGGL(k_block_resid_status, dim3(1), dim3(64), 0, s, bu, theta, tot, st);
     LAP_HIP(hipGetLastError());
 }
 template void blk_resid<float>(int, int, const double *, const double *, int, const double *, double *, float *, int,
@@ -622,27 +641,29 @@ void blk_random(int n, int b, uint64_t seed, long long colbase, const int *iperm
 
 template <typename T>
 void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q, int ldq, int q, const double *R,
-                  int ldr, T *X, BPcgWork<T> &w, ReduceScratch &rs, BlockScratch &bs, int itmax, double rtol,
-                  hipStream_t s) {
-    LAP_REQUIRE(b >= 1 && b <= 32, LAP_EUNSUPPORTED, "block wider than 32");
+                  int ldr, T *X, BPcgWork<T> &w, BlockScratch &bs, int itmax, double rtol, hipStream_t s) {
+    LAP_REQUIRE(b >= 1 && b <= kMaxBlock, LAP_EUNSUPPORTED, "block wider than 32");
     const int n = P.n;
-    const int gv = bgrid(n);
-    rs.ensure(gv, 64);
-    T *part = reinterpret_cast<T *>(rs.partial.get());
-    unsigned *cnt = rs.counter.get();
+    const int gc = cgrid(n, b);
+    LAP_REQUIRE(w.part.n >= (size_t)gc * 64, LAP_EDEVICE, "block PCG work area too small");
+    T *part = w.part.get();
     BPcgState<T> *st = w.st.get();
     const T *dinv = P.dinv<T>();
     T *C = w.C.get();  // q x b column-major coefficients
-    hipLaunchKernelGGL((k_bpcg_init1<T>), dim3(gv), dim3(kBlock), 0, s, n, b, R, ldr, w.res.get(), X, part, cnt, st);
     T *Z = w.z.get();
-    const int gp = bgrid((size_t)n * b);
+    auto fold = [&](int nv, T *totals) {
+        const int fg = std::min((nv + kWavesPerBlock - 1) / kWavesPerBlock, 16);
+        hipLaunchKernelGGL((k_bfold<T>), dim3(fg), dim3(kBlock), 0, s, part, gc, nv, totals);
+    };
+    hipLaunchKernelGGL((k_bpcg_init1<T>), dim3(gc), dim3(kBlock), 0, s, n, b, R, ldr, w.res.get(), X, part);
+    fold(b, st->tot_a);
     // Res <- (I - QQ')Res
     if (q > 0) {
         ts_tn<T>(n, Q, ldq, q, w.res.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
         ts_nn<T>(n, Q, ldq, q, C, q, b, w.res.get(), b, nullptr, 0, T(-1), T(1), s);
     }
-    hipLaunchKernelGGL((k_bpcg_init2<T>), dim3(gv), dim3(kBlock), 0, s, n, b, w.res.get(), w.y.get(), dinv, part, cnt,
-                       st);
+    hipLaunchKernelGGL((k_bpcg_init2<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.res.get(), w.y.get(), dinv, part, st);
+    fold(b, st->tot_b);
     // P = (I - QQ') Y
     const T *Zy = w.y.get();
     if (q > 0) {
@@ -650,7 +671,7 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.y.get(), b, T(-1), T(0), s);
         Zy = Z;
     }
-    hipLaunchKernelGGL((k_bpcg_p<T, true>), dim3(gp), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
+    hipLaunchKernelGGL((k_bpcg_p0<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
     for (int it = 1; it <= itmax; ++it) {
         // S = G P - P diag(theta);  Z = (I - QQ') S
         spmm<T>(P, b, w.p.get(), b, w.s.get(), b, theta_dev, s);
@@ -660,26 +681,26 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
             ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.s.get(), b, T(-1), T(0), s);
             Zs = Z;
         }
-        hipLaunchKernelGGL((k_bpcg_pap<T>), dim3(gv), dim3(kBlock), 0, s, n, b, w.p.get(), w.s.get(), part, cnt, st, it);
-        hipLaunchKernelGGL((k_bpcg_update<T>), dim3(gv), dim3(kBlock), 0, s, n, b, X, w.res.get(), w.p.get(), Zs,
-                           w.y.get(), dinv, part, cnt, st, it, (T)rtol);
+        hipLaunchKernelGGL((k_bpcg_pap<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.p.get(), w.s.get(), part, st);
+        fold(b, st->tot_a);
+        hipLaunchKernelGGL((k_bpcg_update<T>), dim3(gc), dim3(kBlock), 0, s, n, b, X, w.res.get(), w.p.get(), Zs,
+                           w.y.get(), dinv, part, st, it);
         if (it == itmax) break;
+        fold(32 + b, st->tot_b);
         // P = (I - QQ') Y + beta P
-        Zy = w.y.get();
+        const T *Zy2 = w.y.get();
         if (q > 0) {
             ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
             ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.y.get(), b, T(-1), T(0), s);
-            Zy = Z;
+            Zy2 = Z;
         }
-        hipLaunchKernelGGL((k_bpcg_p<T, false>), dim3(gp), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
+        hipLaunchKernelGGL((k_bpcg_p<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy2, w.p.get(), st, it, (T)rtol);
     }
-    hipLaunchKernelGGL((k_bpcg_count<T>), dim3(1), dim3(64), 0, s, b, st);
     LAP_HIP(hipGetLastError());
 }
 template void bpcg_enqueue<float>(const lap_plan &, int, const double *, const float *, int, int, const double *, int,
-                                  float *, BPcgWork<float> &, ReduceScratch &, BlockScratch &, int, double, hipStream_t);
+                                  float *, BPcgWork<float> &, BlockScratch &, int, double, hipStream_t);
 template void bpcg_enqueue<double>(const lap_plan &, int, const double *, const double *, int, int, const double *,
-                                   int, double *, BPcgWork<double> &, ReduceScratch &, BlockScratch &, int, double,
-                                   hipStream_t);
+                                   int, double *, BPcgWork<double> &, BlockScratch &, int, double, hipStream_t);
 
 }  // namespace lapeig

@@ -24,22 +24,28 @@ struct BlockStatus {
     int kept;
 };
 
+// Block PCG state.  A launch never reads what workgroups of the same
+// launch write: the per-column flags and rho alternate between two slots,
+// and the folded sums of consecutive reductions between tot_a and tot_b.
 template <typename T>
 struct BPcgState {
-    T rho[kMaxBlock], alpha[kMaxBlock], beta[kMaxBlock], r0[kMaxBlock], rn[kMaxBlock];
-    int active[kMaxBlock], its[kMaxBlock], brk[kMaxBlock], copy_p[kMaxBlock];
-    int nactive, nactive_step;
+    T tot_a[64], tot_b[64];  // column sums of the last reductions (value c, or 32 + c)
+    T r0[kMaxBlock];
+    T rho[2][kMaxBlock];
+    int act[2][kMaxBlock];   // column still iterating
+    int its[kMaxBlock], brk[kMaxBlock];
 };
 
 template <typename T>
 struct BPcgWork {
-    DevBuf<T> res, p, s, y, z, C;
+    DevBuf<T> res, p, s, y, z, C, part;
     DevBuf<BPcgState<T>> st;
     void ensure(int n, int b, int qmax) {
         if (res.get()) return;
         res.alloc((size_t)n * b); p.alloc((size_t)n * b); s.alloc((size_t)n * b); y.alloc((size_t)n * b);
         z.alloc((size_t)n * b);
         C.alloc((size_t)(qmax + 1) * b);
+        part.alloc((size_t)(4 * device_cu_count() + kMaxBlock) * 64);
         st.alloc(1);
     }
 };
@@ -77,8 +83,7 @@ void blk_random(int n, int b, uint64_t seed, long long colbase, const int *iperm
                 hipStream_t s);
 template <typename T>
 void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q, int ldq, int q, const double *R,
-                  int ldr, T *X, BPcgWork<T> &w, ReduceScratch &rs, BlockScratch &bs, int itmax, double rtol,
-                  hipStream_t s);
+                  int ldr, T *X, BPcgWork<T> &w, BlockScratch &bs, int itmax, double rtol, hipStream_t s);
 
 lap_status jd_block_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
                           int evecs_on_device, double *res, lap_eigs_info *info);

@@ -69,6 +69,42 @@ struct GraphCache {
     }
 };
 
+// Work areas of the block solver, kept in the plan between solves of the
+// same shape (n, k, b, m_max) and inner-solve settings.
+template <typename T>
+struct JdbWork : SolverCache {
+    int n, k, b, mmax, itmax;
+    double rtol;
+    DevBuf<double> XV, W, H, theta, Y, Vn, Cc, S, Sth, Sz, M, U, GU, R, u0, gu, isz, outbuf;
+    DevBuf<T> Q, Tt;
+    DevBuf<BlockStatus> bst;
+    DevBuf<JDStatus> jst;
+    PinnedB<BlockStatus> hb;
+    PinnedB<JDStatus> hj;
+    PinnedB<BPcgState<T>> hp;
+    ReduceScratch rs;
+    BlockScratch bs;
+    BPcgWork<T> pw;
+    GraphCache graphs;
+    OwnStreamB own;
+    JdbWork(int n_, int k_, int b_, int mmax_, int itmax_, double rtol_)
+        : n(n_), k(k_), b(b_), mmax(mmax_), itmax(itmax_), rtol(rtol_) {
+        const int ldb = k + mmax, ldq = k + b;
+        XV.alloc((size_t)n * ldb); W.alloc((size_t)n * mmax); H.alloc((size_t)mmax * mmax); theta.alloc(mmax);
+        Y.alloc((size_t)mmax * mmax); Vn.alloc((size_t)n * b); Cc.alloc((size_t)ldb * b); S.alloc((size_t)b * b);
+        Sth.alloc(b); Sz.alloc((size_t)b * b); M.alloc((size_t)b * b); U.alloc((size_t)n * b);
+        GU.alloc((size_t)n * b); R.alloc((size_t)n * b); u0.alloc(n); gu.alloc(n); isz.alloc(std::max(k, 1));
+        Q.alloc((size_t)n * ldq); Tt.alloc((size_t)n * b);
+        bst.alloc(1); jst.alloc(1);
+        rs.ensure(4 * device_cu_count(), 64);
+        bs.ensure();
+        pw.ensure(n, b, ldq);
+    }
+    bool fits(int n_, int k_, int b_, int mmax_, int itmax_, double rtol_) const {
+        return n == n_ && k == k_ && b == b_ && mmax == mmax_ && itmax == itmax_ && rtol == rtol_;
+    }
+};
+
 template <typename T>
 lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
                    int evecs_on_device, double *res_out, lap_eigs_info *info) {
@@ -81,30 +117,32 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
     LAP_REQUIRE(k + mmax <= 128, LAP_EUNSUPPORTED, "k + m_max above 128");
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
     LAP_HIP(hipStreamSynchronize(P->stream));
-    OwnStreamB own;
-    hipStream_t s = own.s;
     const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
-    GraphCache graphs;
+    ts_prepare<double>();
+    ts_prepare<T>();
+    auto *cache = dynamic_cast<JdbWork<T> *>(P->jdb_cache.get());
+    if (!cache || !cache->fits(n, k, b, mmax, o.itmax, o.rtol_pcg)) {
+        P->jdb_cache.reset();
+        P->jdb_cache.reset(cache = new JdbWork<T>(n, k, b, mmax, o.itmax, o.rtol_pcg));
+    }
+    JdbWork<T> &wk = *cache;
+    hipStream_t s = wk.own.s;
+    GraphCache &graphs = wk.graphs;
 
     const int ldb = k + mmax, ldh = mmax, ldq = k + b;
     const int nz = std::min(P->ncomp, k);
-    DevBuf<double> XV((size_t)n * ldb), W((size_t)n * mmax), H((size_t)mmax * mmax), theta(mmax),
-        Y((size_t)mmax * mmax), Vn((size_t)n * b), Cc((size_t)ldb * b), S((size_t)b * b), Sth(b), Sz((size_t)b * b),
-        M((size_t)b * b), U((size_t)n * b), GU((size_t)n * b), R((size_t)n * b), u0(n), gu(n), isz(std::max(nz, 1));
-    DevBuf<T> Q((size_t)n * ldq), Tt((size_t)n * b);
-    DevBuf<BlockStatus> bst(1);
-    DevBuf<JDStatus> jst(1);
-    PinnedB<BlockStatus> hb;
-    PinnedB<JDStatus> hj;
-    PinnedB<BPcgState<T>> hp;
-    ReduceScratch rs;
-    rs.ensure(4 * device_cu_count(), 64);
-    BlockScratch bs;
-    bs.ensure();
-    BPcgWork<T> pw;
-    pw.ensure(n, b, ldq);
-    ts_prepare<double>();
-    ts_prepare<T>();
+    DevBuf<double> &XV = wk.XV, &W = wk.W, &H = wk.H, &theta = wk.theta, &Y = wk.Y, &Vn = wk.Vn, &Cc = wk.Cc,
+                   &S = wk.S, &Sth = wk.Sth, &Sz = wk.Sz, &M = wk.M, &U = wk.U, &GU = wk.GU, &R = wk.R, &u0 = wk.u0,
+                   &gu = wk.gu, &isz = wk.isz;
+    DevBuf<T> &Q = wk.Q, &Tt = wk.Tt;
+    DevBuf<BlockStatus> &bst = wk.bst;
+    DevBuf<JDStatus> &jst = wk.jst;
+    PinnedB<BlockStatus> &hb = wk.hb;
+    PinnedB<JDStatus> &hj = wk.hj;
+    PinnedB<BPcgState<T>> &hp = wk.hp;
+    ReduceScratch &rs = wk.rs;
+    BlockScratch &bs = wk.bs;
+    BPcgWork<T> &pw = wk.pw;
 
     std::vector<double> lam, resid;
     {
@@ -260,7 +298,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         {
             const int q = nx + bu;
             auto enqueue = [&]() {
-                bpcg_enqueue<T>(*P, bu, theta.get(), Q.get(), ldq, q, R.get(), b, Tt.get(), pw, rs, bs, o.itmax,
+                bpcg_enqueue<T>(*P, bu, theta.get(), Q.get(), ldq, q, R.get(), b, Tt.get(), pw, bs, o.itmax,
                                 o.rtol_pcg, s);
             };
             if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, bu, s, enqueue), s));
@@ -279,8 +317,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
 
     // ---- output (as the single-vector solver)
     const int nconv = std::min(nx, k);
-    DevBuf<double> outbuf;
-    emit_pairs(*P, nconv, XV.get(), ldb, 1, lam, resid, evals, evecs, evecs_on_device, res_out, outbuf, s);
+    emit_pairs(*P, nconv, XV.get(), ldb, 1, lam, resid, evals, evecs, evecs_on_device, res_out, wk.outbuf, s);
     if (info) {
         info->nconv = nconv;
         info->ncomp = P->ncomp;

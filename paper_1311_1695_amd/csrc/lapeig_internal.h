@@ -146,7 +146,8 @@ struct lap_plan {
     lapeig::DevBuf<double> d_shift;
     lapeig::DevBuf<char> tmp_x, tmp_y;
     lapeig::DevBuf<char> chunk_part;  // per-chunk partial sums of the block product
-    std::unique_ptr<lapeig::SolverCache> jd_cache;  // single-vector solver work areas
+    std::unique_ptr<lapeig::SolverCache> jd_cache;   // single-vector solver work areas
+    std::unique_ptr<lapeig::SolverCache> jdb_cache;  // block solver work areas
     // plan-order CSR of A on the host (rebuilding the row classes needs it)
     std::vector<int> h_rowptr, h_col;
     std::vector<double> h_w;

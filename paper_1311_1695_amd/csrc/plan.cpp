@@ -239,6 +239,7 @@ void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
     }
 
     P->jd_cache.reset();
+    P->jdb_cache.reset();
     LAP_HIP(hipDeviceSynchronize());  // no launch may still read the old layout
     upload(P->d_sell_off, soff);
     upload(P->d_sell_col, scol);
