@@ -144,7 +144,7 @@ constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
 
 __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restrict__ Hin, int ldh,
                                                    double *__restrict__ theta, double *__restrict__ Y,
-                                                   int ldy, int warm, JDStatus *st) {
+                                                   int ldy, int mprev, JDStatus *st) {
     extern __shared__ double lds[];
     const int me = (m + 1) & ~1;  // even size; index m is a dummy when m is odd
     double *A = lds;              // me x me, row-major
@@ -154,24 +154,24 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     __shared__ int any_rot;
     __shared__ double fro2;
     const int tid = threadIdx.x;
-    if (warm && m >= 2) {
-        // H = [H1 h; h' eta] with H1 = Yp diag(theta) Yp' from the previous
-        // call (theta and Y still hold it): start from the arrowhead
-        // [diag(theta) Yp'h; h'Yp eta] and accumulate onto Z = diag(Yp, 1)
-        const int mp = m - 1;
+    if (mprev >= 1 && mprev < m) {
+        // H = [H1 H12; H12' H22] with H1 = Yp diag(theta) Yp' from the previous
+        // call (theta and Y still hold it): start from
+        // [diag(theta) Yp'H12; H12'Yp H22] and accumulate onto Z = diag(Yp, I)
+        const int mp = mprev;
         for (int t = tid; t < me * me; t += blockDim.x) {
             const int i = t / me, j = t % me;
             Z[t] = (i < mp && j < mp) ? Y[(size_t)j * ldy + i] : (i == j ? 1.0 : 0.0);
-            A[t] = (i == j && i < mp) ? theta[i] : 0.0;
+            A[t] = (i == j && i < mp) ? theta[i] : ((i >= mp && j >= mp && i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0);
         }
         __syncthreads();
-        for (int i = tid; i < mp; i += blockDim.x) {
-            double b = 0.0;
-            for (int r = 0; r < mp; ++r) b += Z[r * me + i] * Hin[(size_t)mp * ldh + r];
-            A[i * me + mp] = b;
-            A[mp * me + i] = b;
+        for (int t = tid; t < mp * (m - mp); t += blockDim.x) {
+            const int i = t % mp, c = mp + t / mp;
+            double v = 0.0;
+            for (int r = 0; r < mp; ++r) v += Z[r * me + i] * Hin[(size_t)c * ldh + r];
+            A[i * me + c] = v;
+            A[c * me + i] = v;
         }
-        if (tid == 0) A[mp * me + mp] = Hin[(size_t)mp * ldh + mp];
     } else {
         for (int t = tid; t < me * me; t += blockDim.x) {
             const int i = t / me, j = t % me;
@@ -549,7 +549,7 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
 }
 
 void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
-           bool warm) {
+           int mprev) {
     LAP_REQUIRE(m >= 1 && m <= kRRMax, LAP_EUNSUPPORTED, "projected matrix larger than 96");
     const int me = (m + 1) & ~1;
     const size_t lds = 2 * (size_t)me * me * sizeof(double);
@@ -562,7 +562,7 @@ void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, J
     // up to 32 columns a single wavefront does it: every barrier of the
     // round-by-round rotations is then nearly free
     const int threads = me <= 32 ? kWave : kBlock;
-    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, warm ? 1 : 0, st);
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, mprev, st);
     LAP_HIP(hipGetLastError());
 }
 

@@ -258,7 +258,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         for (;;) {
             // step 5: eigenpairs of H; step 6: Ritz vector and residual
             // warm start when theta and Y still diagonalize the leading block
-            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s, y_rows == m - 1);
+            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s, y_rows == m - 1 ? y_rows : 0);
             y_rows = m;
             Vb = B.get() + (size_t)nx * n;
             jd_ritz<T>(n, Vb, W.get(), m, Y.get(), theta.get(), u.get(), r.get(), Q.get(), ldq, nx, rs, st.get(), s,

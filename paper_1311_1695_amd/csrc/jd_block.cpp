@@ -153,6 +153,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         for (int c = 0; c < nz; ++c) { lam.push_back(0.0); resid.push_back(0.0); }
     }
     int nx = nz, m = 0, it = 0;
+    int y_rows = 0;  // order of the block of H that theta and Y diagonalize
     long long mvp = 0, inner = 0, colbase = 0;
     lap_status status = LAP_OK;
 
@@ -245,7 +246,9 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         bool need_pcg = true;
         int bu = 0;
         for (;;) {
-            jd_rr(m, H.get(), ldh, theta.get(), Y.get(), mmax, nullptr, s);
+            // warm start when theta and Y still diagonalize the leading block
+            jd_rr(m, H.get(), ldh, theta.get(), Y.get(), mmax, nullptr, s, y_rows < m ? y_rows : 0);
+            y_rows = m;
             Vb = XV.get() + nx;
             bu = std::min(std::min(b, m), k - nx);
             ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, bu, U.get(), b, nullptr, 0, 1.0, 0.0, s);
@@ -272,6 +275,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
             if (m > 1)
                 ts_nn<double>(n, W.get(), mmax, m, Y.get() + mmax, mmax, m - 1, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
             jd_hdiag(H.get(), ldh, m - 1, theta.get(), 1, s);
+            y_rows = 0;
             lam.push_back(ct);
             resid.push_back(cr);
             ++nx;
@@ -293,6 +297,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
             ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, keep, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
             jd_hdiag(H.get(), ldh, keep, theta.get(), 0, s);
             m = keep;
+            y_rows = 0;
         }
         // block PCG on the bu correction equations, Q = [X U]
         {

@@ -58,10 +58,11 @@ void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, c
 void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, int ldh, ReduceScratch &rs,
                 hipStream_t s);
 // Eigenpairs of the m x m H (column-major, ld ldh): theta ascending, Y
-// column-major (ld ldy).  warm: theta and Y still hold the eigenpairs of
-// the leading (m-1) x (m-1) block, which has not changed since.
+// column-major (ld ldy).  mprev in [1, m): theta and Y still hold the
+// eigenpairs of the leading mprev x mprev block, which has not changed
+// since (warm start); 0: none.
 void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
-           bool warm = false);
+           int mprev = 0);
 template <typename T>
 void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
              double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s,
