@@ -242,8 +242,9 @@ __device__ __forceinline__ void fold_partials(const T *__restrict__ part, int nb
 //   q_i = sum_{j in N(i)} w_ij (x_i - x_j)^2      (only when QF; sum_i q_i = 2 x'Gx, eq. (1))
 // and calls f(i, x_i, y_i, q_i) on exactly one lane per row (for_each_row_pre
 // also passes f what pre(i) loaded for the row before its gathers began).  Rows are
-// visited workgroup-per-row (huge), wavefront-per-row (long), then
-// lane-per-row inside 64-row slices; the grid strides over the units.
+// visited workgroup-per-row (huge), wavefront-per-row (long), eight
+// lanes per row (the rows of the wide slices), then lane-per-row inside
+// 64-row slices; the grid strides over the units.
 // Every loop keeps four independent index->gather chains in flight, and the
 // summation order is fixed, so results are reproducible bit for bit.
 // f must not synchronize.
@@ -284,9 +285,27 @@ __device__ __forceinline__ void for_each_row_pre(const Graph &g, const Weights<T
         if (threadIdx.x == 0) f(r, xi, acc, aq, pd);
     }
     const int nlong = g.n_long - g.n_huge;
-    const int units = nlong + g.nslices;
+    const int nmid = g.nslices_mid * (kWave / 8);  // eight rows per unit
+    const int units = nlong + nmid + (g.nslices - g.nslices_mid);
     for (int u = blockIdx.x * kWavesPerBlock + wave_id(); u < units; u += gridDim.x * kWavesPerBlock) {
-        if (u < nlong) {
+        if (u >= nlong && u < nlong + nmid) {
+            // eight lanes per row; the eight partial sums meet in the row's first lane
+            const int r = g.n_long + (u - nlong) * 8 + (lane >> 3);
+            const bool live = r < g.n;
+            const int rr = live ? r : g.n - 1;
+            const auto pd = pre(rr);
+            const T xi = x[rr];
+            T acc = T(0), aq = T(0);
+            if (live)
+                edge_terms<T, WEIGHTED, QF>(g.col, w.csr, x, xi, g.rowptr[r] + (lane & 7), g.rowptr[r + 1], 8, acc,
+                                            aq);
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                acc += __shfl_xor(acc, o, kWave);
+                if (QF) aq += __shfl_xor(aq, o, kWave);
+            }
+            if (live && (lane & 7) == 0) f(r, xi, acc, aq, pd);
+        } else if (u < nlong) {
             const int r = g.n_huge + u;
             const auto pd = pre(r);
             const T xi = x[r];
@@ -296,7 +315,7 @@ __device__ __forceinline__ void for_each_row_pre(const Graph &g, const Weights<T
             if (QF) aq = wave_sum(aq);
             if (lane == 0) f(r, xi, acc, aq, pd);
         } else {
-            const int s = u - nlong;
+            const int s = u - nlong - nmid + g.nslices_mid;
             const int r = g.n_long + s * kWave + lane;
             if (r < g.n) {
                 // operands of f are requested before the gathers start
@@ -321,7 +340,7 @@ __device__ __forceinline__ void for_each_row(const Graph &g, const Weights<T> &w
 // Grid size for a row-engine launch: enough wavefronts to cover the units,
 // capped so that one pass of partial sums stays small.
 inline int row_grid(const Graph &g, int cap) {
-    const int units = (g.n_long - g.n_huge) + g.nslices;
+    const int units = (g.n_long - g.n_huge) + g.nslices_mid * (kWave / 8) + (g.nslices - g.nslices_mid);
     int blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
     blocks = blocks > g.n_huge ? blocks : g.n_huge;
     if (blocks < 1) blocks = 1;

@@ -16,6 +16,12 @@
 //                           n_long + 64 s + l and reads its s-th neighbour at
 //                           sell_col[sell_off[slice] + 64 s + l]; padding
 //                           entries point at the row itself, weight 0.
+// On graphs small enough that the grid holds only a few units per SIMD, the
+// row engine visits the first nslices_mid slices (those wider than kMidWidth
+// slots) through the CSR arrays instead, eight lanes per row and eight rows
+// per wavefront, so that no wavefront gathers much more than 64 kMidWidth
+// entries and the widest slices no longer finish last; the block product
+// reads them as slices.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,11 +97,13 @@ struct DevBuf {
 
 // ------------------------------------------------------------ the graph
 constexpr int kChunk = 64;   // edges per chunk of a long row in the block product
+constexpr int kMidWidth = 8; // slices wider than this are visited eight lanes per row
 
 struct Graph {
     int n = 0;
     int n_huge = 0, n_long = 0;   // row-class boundaries (plan order)
     int nslices = 0;              // 64-row slices covering [n_long, n)
+    int nslices_mid = 0;          // leading slices visited eight lanes per row (row engine)
     int nchunks = 0;              // kChunk-edge chunks of the rows [0, n_long)
     const int *chunk_row = nullptr;  // row of each chunk
     const int *chunk_off = nullptr;  // first chunk of each long row (n_long + 1)

@@ -255,6 +255,13 @@ void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
     P->g.n_huge = n_huge;
     P->g.n_long = n_long;
     P->g.nslices = nslices;
+    // When the grid holds only a few units per SIMD, the widest slices would
+    // finish last; their rows are then visited eight lanes per row.  Larger
+    // graphs stride many units through every wavefront, which evens the load.
+    int mid = 0;
+    if ((long long)(n_long - n_huge) + nslices <= 16LL * device_cu_count())
+        while (mid < nslices && soff[mid + 1] - soff[mid] > kMidWidth * kWave) ++mid;  // widest slices lead
+    P->g.nslices_mid = mid;
     P->g.sell_off = P->d_sell_off.get();
     P->g.sell_col = P->d_sell_col.get();
     P->g.nchunks = (int)crow.size();

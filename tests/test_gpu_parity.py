@@ -39,6 +39,21 @@ def graph(name):
                                  gg.complete_graph(70))
     if name == "tiny":
         return gg.path_graph(2)
+    if name == "mid_partial":
+        # one partial slice, every row of degree 9..32: visited eight lanes
+        # per row, with the unit's last lanes past the final row
+        return gg.disjoint_union(gg.complete_graph(20), gg.complete_graph(15))
+    if name == "mid_er40":
+        # Erdos-Renyi n = 40, p = 0.3: one partial slice visited eight lanes per
+        # row, with a simple spectrum (the complete graphs above are degenerate)
+        rng = np.random.default_rng(40)
+        iu, ju = np.triu_indices(40, 1)
+        keep = rng.random(iu.size) < 0.3
+        return gg.laplacian_from_edges(40, iu[keep], ju[keep], name="er40")
+    if name == "mid_union":
+        # a full wide slice (degrees 32, 19, 11) then a short partial one
+        return gg.disjoint_union(gg.complete_graph(33), gg.complete_graph(12), gg.path_graph(50),
+                                 gg.star_graph(20))
     if name in ("pa5k", "cl30k", "cl30k_w"):
         return gg.workload(name, 1001)
     raise KeyError(name)
@@ -52,7 +67,8 @@ def _plan(name):
 # SpMV / SpMM
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["pa5k", "cl30k", "cl30k_w", "star9000", "mixed_union", "tiny"])
+@pytest.mark.parametrize("name", ["pa5k", "cl30k", "cl30k_w", "star9000", "mixed_union", "tiny", "mid_partial",
+                                  "mid_union", "mid_er40"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_spmv_bitwise_on_integer_vectors(name, dtype):
     L = graph(name)
@@ -314,6 +330,17 @@ def test_eigs_closed_forms_and_zero_space():
     # more components than pairs requested
     r = lap.lap_eigs_csr(G, 3, 1e-10)
     assert r.nconv == 3 and np.all(r.evals == 0.0)
+
+
+@pytest.mark.parametrize("name,k", [("mid_union", 8), ("mid_er40", 6)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_eigs_rows_visited_eight_lanes_per_row_vs_dense(name, k, precision):
+    """Graphs whose widest slices take the eight-lanes-per-row path of the
+    row engine (one with a partial last unit): pairs against dense eigh."""
+    r = lap.lap_eigs_csr(graph(name), k, 1e-10, precision=precision)
+    assert r.nconv == k
+    w, V = dense_ref(name)
+    check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
 
 
 def test_eigs_start_block_and_sign_convention():
