@@ -151,7 +151,6 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     double *Z = A + me * me;      // me x me, row-major accumulator of rotations
     __shared__ double cs[kRRMax / 2], sn[kRRMax / 2];
     __shared__ int pp[kRRMax / 2], qq[kRRMax / 2];
-    __shared__ int any_rot;
     __shared__ double fro2;
     const int tid = threadIdx.x;
     if (mprev >= 1 && mprev < m) {
@@ -198,8 +197,23 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     const int half = me / 2;
     int sweeps = 0;
     for (; sweeps < 60 && me > 1; ++sweeps) {
-        if (tid == 0) any_rot = 0;
-        __syncthreads();
+        // A sweep rotates exactly the pairs with |a_pq| > tol, so when no
+        // off-diagonal entry exceeds tol it would change nothing: stop here
+        // instead of running it.
+        {
+            __shared__ double wmax[kWavesPerBlock];
+            double mx = 0.0;
+            for (int t = tid; t < me * me; t += blockDim.x)
+                if (t / me < t % me) mx = fmax(mx, fabs(A[t]));
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+            if (lane_id() == 0) wmax[wave_id()] = mx;
+            __syncthreads();
+            double g = 0.0;
+            for (int w = 0; w < (int)blockDim.x / kWave; ++w) g = fmax(g, wmax[w]);
+            __syncthreads();
+            if (!(g > tol)) break;
+        }
         for (int round = 0; round < me - 1; ++round) {
             // tournament pairing: position 0 fixed, the others rotate
             if (tid < half) {
@@ -213,7 +227,6 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
                     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
                     s = t * c;
-                    any_rot = 1;
                 }
                 pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
             }
@@ -251,9 +264,6 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
             }
             __syncthreads();
         }
-        const int rotated = any_rot;
-        __syncthreads();
-        if (!rotated) break;
     }
     // rank sort of the m real diagonal entries (the dummy index is excluded)
     for (int i = tid; i < m; i += blockDim.x) {

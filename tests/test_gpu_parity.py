@@ -54,8 +54,17 @@ def graph(name):
         # a full wide slice (degrees 32, 19, 11) then a short partial one
         return gg.disjoint_union(gg.complete_graph(33), gg.complete_graph(12), gg.path_graph(50),
                                  gg.star_graph(20))
-    if name in ("pa5k", "cl30k", "cl30k_w"):
+    if name in ("pa5k", "cl30k", "cl30k_w", "cl330k"):
         return gg.workload(name, 1001)
+    if name == "cl330k_w3":
+        # the 330k-vertex graph with integer weights 1..3 (FP32 sums stay exact)
+        L = graph("cl330k")
+        rp, ci = np.asarray(L.rowptr), np.asarray(L.col)
+        rows = np.repeat(np.arange(L.n), np.diff(rp))
+        up = ci > rows
+        u, v = rows[up], ci[up]
+        wts = np.random.default_rng(3).integers(1, 4, size=u.size).astype(np.float64)
+        return gg.laplacian_from_edges(L.n, u, v, wts, name="cl330k_w3")
     raise KeyError(name)
 
 
@@ -68,13 +77,14 @@ def _plan(name):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("name", ["pa5k", "cl30k", "cl30k_w", "star9000", "mixed_union", "tiny", "mid_partial",
-                                  "mid_union", "mid_er40"])
+                                  "mid_union", "mid_er40", "cl330k", "cl330k_w3"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_spmv_bitwise_on_integer_vectors(name, dtype):
     L = graph(name)
     plan = lap.Plan(L)
     rng = np.random.default_rng(11)
-    # |x| < 2^6 keeps every FP32 partial sum exact (degree and weights small)
+    # |x| < 2^6 keeps every FP32 partial sum exact (the largest weighted
+    # degree times 2^7 stays below 2^24)
     lim = 64 if dtype == "f32" else 1 << 20
     x = rng.integers(-lim, lim, size=L.n).astype(np.float64)
     ref = oracle.spmv(L, x)
