@@ -271,7 +271,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sweep", action="store_true", help="also time the SpMV on larger graphs")
+    ap.add_argument("--spmv-graph", default="cl30k",
+                    help="workload of the --spmv-only leg (cl30k, cl330k, cl1m_tc)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--spmv-only", action="store_true", help="only the product kernel loop (for profiling)")
     ap.add_argument("--roofline-only", action="store_true",
@@ -311,6 +312,10 @@ def main():
         print(json.dumps({"pcg_iter_s": t_pcg, "alg_bytes": alg_pcg, "copy_bytes_each_way": a.numel() * 4}))
         return
     # ---- the plain product kernel, for the SpMV bandwidth of the metric
+    if args.spmv_only and args.spmv_graph != "cl30k":
+        L = gg.workload(args.spmv_graph, SEED)
+        nnz_a = L.nnz - L.n
+        plan = lap.Plan(L)
     t_spmv = time_spmv(lap, torch, plan, L.n, reps=2000 if args.spmv_only else 500)
     alg = spmv_bytes(L.n, nnz_a, 4)
     if args.spmv_only:
@@ -320,7 +325,8 @@ def main():
         for _ in range(20):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"spmv_s": t_spmv, "alg_bytes": alg, "copy_bytes_each_way": a.numel() * 4}))
+        print(json.dumps({"workload": args.spmv_graph, "spmv_s": t_spmv, "alg_bytes": alg,
+                          "copy_bytes_each_way": a.numel() * 4}))
         return
 
     def solve(precision):
@@ -383,17 +389,20 @@ def main():
     out["spmv"] = {"kernel": "k_spmv<float> (unweighted Laplacian product, b=1)", "GB/s": round(a_spmv, 2),
                    "frac": round(a_spmv / HBM_PEAK_GBS, 5), "alg_bytes_per_launch": alg,
                    "avg_launch_us": round(t_spmv * 1e6, 3)}
-    if args.sweep:
-        sweep = []
-        for name, builder in [("cl1m_tc", lambda: gg.workload("cl1m_tc", SEED))]:
-            Lb = builder()
-            pb = lap.Plan(Lb)
-            tb = time_spmv(lap, torch, pb, Lb.n, reps=200)
-            ab = spmv_bytes(Lb.n, Lb.nnz - Lb.n, 4)
-            sweep.append({"workload": name, "n": Lb.n, "nnz": Lb.nnz, "avg_launch_us": round(tb * 1e6, 3),
-                          "GB/s": round(ab / tb / 1e9, 1), "frac": round(ab / tb / 1e9 / HBM_PEAK_GBS, 4)})
-            pb.close()
-        out["spmv_sweep"] = sweep
+    # the same product on the large power-law graphs of the other workloads,
+    # where it moves tens of megabytes per launch instead of under one
+    large = []
+    for name in ("cl330k", "cl1m_tc"):
+        Lb = gg.workload(name, SEED)
+        pb = lap.Plan(Lb)
+        tb = time_spmv(lap, torch, pb, Lb.n, reps=200)
+        ab = spmv_bytes(Lb.n, Lb.nnz - Lb.n, 4)
+        large.append({"workload": name, "n": Lb.n, "nnz": Lb.nnz, "alg_bytes_per_launch": ab,
+                      "avg_launch_us": round(tb * 1e6, 3), "GB/s": round(ab / tb / 1e9, 1),
+                      "frac": round(ab / tb / 1e9 / HBM_PEAK_GBS, 4)})
+        pb.close()
+        del Lb
+    out["spmv"]["large_graphs"] = large
     if args.extra:
         out["configs"] = extra_configs(lap, torch, gg, np)
     if args.warmstart:
