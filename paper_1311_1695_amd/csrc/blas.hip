@@ -132,6 +132,23 @@ __device__ __forceinline__ void publish(HostMirror *hm, unsigned seq) {
     __hip_atomic_store(&hm->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// 1/x and 1/sqrt(x) (x > 0 finite) from the hardware FP64 estimates, each
+// refined by two Newton steps (r <- r(2 - xr), y <- y(3 - xy^2)/2), which
+// square the relative error twice and end within about an ulp.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
 // ---------------------------------------------------------------------------
 // All eigenpairs of the small symmetric H (step 5) in one workgroup:
 // cyclic Jacobi in the round-robin (tournament) ordering, so the m/2
@@ -151,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     double *Z = A + me * me;      // me x me, row-major accumulator of rotations
     __shared__ double cs[kRRMax / 2], sn[kRRMax / 2];
     __shared__ int pp[kRRMax / 2], qq[kRRMax / 2];
+    __shared__ int rotates[2];  // some pair of the round rotates (by round parity)
     __shared__ double fro2;
     const int tid = threadIdx.x;
     if (mprev >= 1 && mprev < m) {
@@ -195,6 +213,12 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     }
     const double tol = 2.220446049250313e-16 * sqrt(fro2) / (double)me;
     const int half = me / 2;
+    // items of the rotation phase, walked with a stride of blockDim.x in
+    // row-major order of (k, l) over half x half and of (i, k) over me x half
+    const int k0 = tid / half, l0 = tid % half;
+    const int dk = (int)blockDim.x / half, dl = (int)blockDim.x % half;
+    const int i0 = tid / half, kz0 = tid % half;
+    const int di = dk, dkz = dl;
     int sweeps = 0;
     for (; sweeps < 60 && me > 1; ++sweeps) {
         // A sweep rotates exactly the pairs with |a_pq| > tol, so when no
@@ -216,51 +240,68 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
         }
         for (int round = 0; round < me - 1; ++round) {
             // tournament pairing: position 0 fixed, the others rotate
-            if (tid < half) {
-                auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
-                int a = player(tid), b = player(me - 1 - tid);
-                int p = a < b ? a : b, q = a < b ? b : a;
-                double c = 1.0, s = 0.0;
-                const double apq = A[p * me + q];
-                if (fabs(apq) > tol) {
-                    const double tau = (A[q * me + q] - A[p * me + p]) / (2.0 * apq);
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
+            if (tid < kWave) {  // the pairs of a round (half <= 48) sit in the first wavefront
+                bool rot = false;
+                if (tid < half) {
+                    auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
+                    int a = player(tid), b = player(me - 1 - tid);
+                    int p = a < b ? a : b, q = a < b ? b : a;
+                    double c = 1.0, s = 0.0;
+                    const double apq = A[p * me + q], app = A[p * me + p], aqq = A[q * me + q];
+                    // (entries below the smallest normal are left alone: the
+                    // hardware reciprocal estimate does not take them)
+                    if (fabs(apq) > fmax(tol, 2.2250738585072014e-308)) {
+                        // tau = (aqq - app) / (2 apq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+                        // c = 1 / sqrt(1 + t^2), s = t c; for |tau| > 1e150, t = 1 / (2 tau)
+                        // to double precision (and tau^2 would overflow)
+                        const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+                        const double at = fabs(tau);
+                        const double w = fma(tau, tau, 1.0);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) *
+                                         (at > 1e150 ? 0.5 * rcp_nr(at) : rcp_nr(at + w * rsq_nr(w)));
+                        c = rsq_nr(fma(t, t, 1.0));
+                        s = t * c;
+                        rot = true;
+                    }
+                    pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
                 }
-                pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+                const bool any = __ballot(rot) != 0;
+                if (tid == 0) rotates[round & 1] = any;
             }
             __syncthreads();
-            // rows: A <- J' A
-            for (int t = tid; t < half * me; t += blockDim.x) {
-                const int k = t / me, j = t % me;
+            if (!rotates[round & 1]) continue;  // nothing to rotate: no update, no second barrier
+            // A <- J'AJ.  The pairs of a round are disjoint, so A falls into
+            // independent 2x2 blocks (pair k rows, pair l columns); each item
+            // applies the row rotation of k and then the column rotation of l
+            // to its block, the same operations in the same order as a rows
+            // pass followed by a columns pass.  Z <- ZJ likewise by (row, pair).
+            for (int k = k0, l = l0; k < half; k += dk, l += dl) {
+                if (l >= half) { l -= half; ++k; if (k >= half) break; }
+                const double sk = sn[k], sl = sn[l], ck = cs[k], cl = cs[l];
+                const int p = pp[k], q = qq[k], r = pp[l], c2 = qq[l];
+                if (sk == 0.0 && sl == 0.0) continue;
+                double apr = A[p * me + r], apc = A[p * me + c2], aqr = A[q * me + r], aqc = A[q * me + c2];
+                if (sk != 0.0) {
+                    const double npr = ck * apr - sk * aqr, nqr = sk * apr + ck * aqr;
+                    const double npc = ck * apc - sk * aqc, nqc = sk * apc + ck * aqc;
+                    apr = npr; aqr = nqr; apc = npc; aqc = nqc;
+                }
+                if (sl != 0.0) {
+                    const double npr = cl * apr - sl * apc, npc = sl * apr + cl * apc;
+                    const double nqr = cl * aqr - sl * aqc, nqc = sl * aqr + cl * aqc;
+                    apr = npr; apc = npc; aqr = nqr; aqc = nqc;
+                }
+                if (k == l) { apc = 0.0; aqr = 0.0; }  // the rotated pair's own entries
+                A[p * me + r] = apr; A[p * me + c2] = apc; A[q * me + r] = aqr; A[q * me + c2] = aqc;
+            }
+            for (int i = i0, k = kz0; i < me; i += di, k += dkz) {
+                if (k >= half) { k -= half; ++i; if (i >= me) break; }
+                const double sk = sn[k], ck = cs[k];
                 const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    const double ap = A[p * me + j], aq = A[q * me + j];
-                    A[p * me + j] = c * ap - s * aq;
-                    A[q * me + j] = s * ap + c * aq;
-                }
-            }
-            __syncthreads();
-            // columns: A <- A J, Z <- Z J
-            for (int t = tid; t < half * me; t += blockDim.x) {
-                const int k = t / me, i = t % me;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    const double ap = A[i * me + p], aq = A[i * me + q];
-                    A[i * me + p] = c * ap - s * aq;
-                    A[i * me + q] = s * ap + c * aq;
-                    const double zp = Z[i * me + p], zq = Z[i * me + q];
-                    Z[i * me + p] = c * zp - s * zq;
-                    Z[i * me + q] = s * zp + c * zq;
-                }
-            }
-            __syncthreads();
-            if (tid < half && sn[tid] != 0.0) {
-                A[pp[tid] * me + qq[tid]] = 0.0;
-                A[qq[tid] * me + pp[tid]] = 0.0;
+                if (sk == 0.0) continue;
+                const double zp = Z[i * me + p], zq = Z[i * me + q];
+                Z[i * me + p] = ck * zp - sk * zq;
+                Z[i * me + q] = sk * zp + ck * zq;
             }
             __syncthreads();
         }

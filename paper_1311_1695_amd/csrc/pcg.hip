@@ -466,11 +466,15 @@ struct PIRow {
 
 template <typename T, bool Wt>
 __global__ __launch_bounds__(kBlock) void k_pp_iter(
-    Graph g, Weights<T> w, const double *__restrict__ theta, const T *__restrict__ Q, int ldq,
-    const T *__restrict__ gqq, int q, const T *__restrict__ kmat, const T *__restrict__ dinv, T *__restrict__ t,
+    // what the fold and the scalar step read first leads the list, so that it
+    // arrives in preloaded SGPRs rather than after a kernel-argument load
+    const T *__restrict__ part_in, PcgState<T> *st, int nb_in, int sq, int it, int q,
+    const T *__restrict__ kmat, const double *__restrict__ theta, T rtol,
+    Graph g, Weights<T> w, const T *__restrict__ Q, int ldq,
+    const T *__restrict__ gqq, const T *__restrict__ dinv, T *__restrict__ t,
     T *__restrict__ res, T *__restrict__ u, T *__restrict__ wv, const T *__restrict__ wh_in,
     T *__restrict__ wh_out, T *__restrict__ p, T *__restrict__ s, T *__restrict__ qv, T *__restrict__ z,
-    const T *__restrict__ part_in, int nb_in, T *__restrict__ part_out, PcgState<T> *st, int sq, int it, T rtol) {
+    T *__restrict__ part_out) {
     // scalars and the small operands first, so that their latency overlaps the fold
     const int stop_v = st->stop_seq;
     const T th = (T)theta[0];
@@ -675,13 +679,15 @@ void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int l
         const T *hin = (it & 1) ? wh1 : wh0;
         T *hout = (it & 1) ? wh0 : wh1;
         if (P.weighted)
-            hipLaunchKernelGGL((k_pp_iter<T, true>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
-                               w.gqq.get(), q, w.kmat.get(), dinv, t, w.res.get(), w.u.get(), w.w.get(), hin, hout,
-                               w.p.get(), w.s.get(), w.qv.get(), w.z.get(), pin, gr, pout, st, 3 + it, it, tol);
+            hipLaunchKernelGGL((k_pp_iter<T, true>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
+                               w.kmat.get(), theta, tol, P.g, P.weights<T>(), Q, ldq, w.gqq.get(), dinv, t,
+                               w.res.get(), w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(),
+                               w.z.get(), pout);
         else
-            hipLaunchKernelGGL((k_pp_iter<T, false>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q,
-                               ldq, w.gqq.get(), q, w.kmat.get(), dinv, t, w.res.get(), w.u.get(), w.w.get(), hin,
-                               hout, w.p.get(), w.s.get(), w.qv.get(), w.z.get(), pin, gr, pout, st, 3 + it, it, tol);
+            hipLaunchKernelGGL((k_pp_iter<T, false>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
+                               w.kmat.get(), theta, tol, P.g, P.weights<T>(), Q, ldq, w.gqq.get(), dinv, t,
+                               w.res.get(), w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(),
+                               w.z.get(), pout);
     }
     LAP_HIP(hipGetLastError());
 }
