@@ -150,6 +150,227 @@ __device__ __forceinline__ double rsq_nr(double x) {
 }
 
 // ---------------------------------------------------------------------------
+// Eigenpairs of an arrowhead matrix A = [diag(d) b; b' c] (m x m, n = m - 1
+// poles), the form the projected matrix takes in every Rayleigh-Ritz step of
+// single-vector JD: in the previous Ritz basis after an expansion, and after
+// a restart or a lock, which leave H diagonal.  Its eigenvalues are the
+// roots of the secular equation g(l) = c - l - sum_i b_i^2 / (d_i - l) = 0,
+// which interlace the poles d_i; one lane finds one root.
+//   1. sort the poles; deflate borders |b_i| <= tol (pair (d_i, e_i)) and
+//      poles closer than tol (a plane rotation moves the border weight onto
+//      one of the two), tol = 8 eps max(|d|, |c|, ||b||);
+//   2. each root in coordinates shifted to its nearer pole o (tau = l - d_o,
+//      differences of poles taken first): iterate on the model
+//      g(x) ~ r(t) + r'(t)(x - t) + b_o^2 / x (the pole o exact, the rest of
+//      g linear), whose zero is the root of a quadratic, inside a bracket
+//      kept by the sign of g (bisection when the model root leaves it); stop
+//      when |g| is at its rounding level;
+//   3. recompute the border from the roots (Gu and Eisenstat),
+//      b_i^2 = -prod_k (d_i - l_k) / prod_{j != i} (d_i - d_j), taken as a
+//      product of bounded ratios, so that the eigenvectors
+//      (b_i / (l_k - d_i) ..., 1) come out orthogonal to working precision;
+//   4. undo the rotations and the sort; Y = Z X.
+// One wavefront, m <= 64.  Returns false, having written nothing, when a
+// root does not converge (the caller then runs Jacobi on the same A).
+__device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *theta, double *Y, int ldy) {
+    constexpr double kEps = 2.220446049250313e-16;
+    __shared__ double d0[kWave], ds[kWave], bs[kWave], kd[kWave], kb[kWave];
+    __shared__ double rc[kWave], rs[kWave], lam[kWave + 1], rt[kWave + 1], bh[kWave];
+    __shared__ int pm[kWave], ip[kWave], kix[kWave], ri[kWave], ro[kWave + 1];
+    __shared__ int nrot_s;
+    const int lane = lane_id();
+    const int n = m - 1;
+    // 1. poles, border, corner; the sort (ties by index)
+    double di = 0.0, bi = 0.0;
+    if (lane < n) {
+        di = A[lane * me + lane];
+        bi = A[lane * me + n];
+        d0[lane] = di;
+    }
+    const double c = A[n * me + n];
+    __syncthreads();
+    if (lane < n) {
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += (d0[j] < di) || (d0[j] == di && j < lane);
+        ds[rank] = di;
+        bs[rank] = bi;
+        pm[rank] = lane;
+        ip[lane] = rank;
+    }
+    double amax = fabs(di), b2 = bi * bi;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        amax = fmax(amax, __shfl_xor(amax, o, kWave));
+        b2 += __shfl_xor(b2, o, kWave);
+    }
+    const double bn = sqrt(b2);
+    const double tol = 8.0 * kEps * fmax(fmax(amax, fabs(c)), bn);
+    __syncthreads();
+    // close poles: rotate (i, i + 1) so that b_i = 0 (sequential, one lane)
+    if (lane == 0) {
+        int nr = 0;
+        for (int i = 0; i + 1 < n; ++i) {
+            const double x = bs[i], y = bs[i + 1];
+            if (fabs(x) > tol && fabs(y) > tol && ds[i + 1] - ds[i] <= tol) {
+                const double r = sqrt(fma(x, x, y * y));
+                rc[nr] = y / r;
+                rs[nr] = x / r;
+                ri[nr] = i;
+                ++nr;
+                bs[i] = 0.0;
+                bs[i + 1] = r;
+            }
+        }
+        nrot_s = nr;
+    }
+    __syncthreads();
+    // compaction of the kept poles
+    const bool keep = lane < n && fabs(bs[lane]) > tol;
+    const unsigned long long kmask = __ballot(keep);
+    const int nk = __popcll(kmask);
+    if (keep) {
+        const int pos = __popcll(kmask & ((1ull << lane) - 1ull));
+        kd[pos] = ds[lane];
+        kb[pos] = bs[lane];
+        kix[pos] = lane;
+    }
+    __syncthreads();
+    // 2. the nk + 1 roots of the secular equation of the kept part
+    bool ok = true;
+    if (lane <= nk) {
+        const int k = lane;
+        int o = -1;
+        double t = c;
+        if (nk > 0) {
+            if (k == 0) {
+                o = 0;
+            } else if (k == nk) {
+                o = nk - 1;
+            } else {
+                const double mid = 0.5 * (kd[k - 1] + kd[k]);
+                double gm = c - mid;
+                for (int j = 0; j < nk; ++j) gm -= kb[j] * kb[j] / (kd[j] - mid);
+                o = gm > 0.0 ? k : k - 1;
+            }
+            const double dor = kd[o];
+            const double c0 = c - dor;
+            const double bo2 = kb[o] * kb[o];
+            const double outer = bn + fabs(c0) + tol;
+            double tlo = k >= 1 ? kd[k - 1] - dor : -outer;
+            double thi = k < nk ? kd[k] - dor : outer;
+            // start: the zero of the model at t = 0, -b_o^2 / r(0)
+            double r0 = c0;
+            for (int j = 0; j < nk; ++j)
+                if (j != o) r0 -= kb[j] * kb[j] / (kd[j] - dor);
+            t = r0 != 0.0 ? -bo2 / r0 : 0.5 * (tlo + thi);
+            if (!(tlo < t && t < thi) || t == 0.0) t = 0.5 * (tlo + thi);
+            ok = false;
+            for (int it = 0; it < 80; ++it) {
+                double R = 0.0, Rd = 0.0, Ab = 0.0;
+                for (int j = 0; j < nk; ++j) {
+                    if (j == o) continue;
+                    const double r = 1.0 / ((kd[j] - dor) - t);
+                    const double sj = kb[j] * kb[j] * r;
+                    R += sj;
+                    Rd += sj * r;
+                    Ab += fabs(sj);
+                }
+                const double rt_ = c0 - t - R, rdt = -1.0 - Rd;
+                const double g = rt_ + bo2 / t;
+                if (fabs(g) <= 8.0 * kEps * (fabs(c0) + fabs(t) + Ab + bo2 / fabs(t))) { ok = true; break; }
+                if (g > 0.0) tlo = t; else thi = t;
+                if (thi - tlo <= 4.0 * kEps * fmax(fabs(tlo), fabs(thi))) { ok = true; break; }
+                const double beta = rdt, alpha = rt_ - t * rdt;
+                const double disc = alpha * alpha - 4.0 * beta * bo2;
+                double tn = 0.5 * (tlo + thi);
+                if (disc >= 0.0) {
+                    const double q = -0.5 * (alpha + copysign(sqrt(disc), alpha));
+                    const double x1 = beta != 0.0 ? q / beta : tn, x2 = q != 0.0 ? bo2 / q : tn;
+                    const bool in1 = tlo < x1 && x1 < thi, in2 = tlo < x2 && x2 < thi;
+                    if (in1 && in2) tn = fabs(x1 - t) <= fabs(x2 - t) ? x1 : x2;
+                    else if (in1) tn = x1;
+                    else if (in2) tn = x2;
+                }
+                if (fabs(tn - t) <= 2.0 * kEps * fabs(t)) { ok = true; break; }
+                t = tn;
+                if (t == 0.0) break;
+            }
+        }
+        ro[k] = o;
+        rt[k] = t;
+        lam[k] = o >= 0 ? kd[o] + t : t;
+    }
+    if (__ballot(!ok) != 0) return false;
+    __syncthreads();
+    // 3. the border from the roots: l_k - d_i = t_k - (d_i - d_{o_k})
+    auto dl = [&](int i, int kk) { return ro[kk] >= 0 ? (kd[i] - kd[ro[kk]]) - rt[kk] : kd[i] - rt[kk]; };
+    if (lane < nk) {
+        const int i = lane;
+        double pr = -dl(i, i) * dl(i, i + 1);
+        for (int j = 0; j < i; ++j) pr *= dl(i, j) / (kd[i] - kd[j]);
+        for (int j = i + 1; j < nk; ++j) pr *= dl(i, j + 1) / (kd[i] - kd[j]);
+        bh[i] = copysign(sqrt(fmax(pr, 0.0)), kb[i]);
+    }
+    __syncthreads();
+    // 4. eigenvectors in the sorted coordinates (rows 0..n-1 the sorted
+    // poles, row n the corner), one column per lane, into A (no longer needed)
+    double *X = A;
+    if (lane < m) {
+        const int p = lane;
+        for (int r = 0; r < m; ++r) X[r * me + p] = 0.0;
+        if (p <= nk) {
+            double nrm = 1.0;
+            for (int j = 0; j < nk; ++j) {
+                const double v = bh[j] / (-dl(j, p));
+                nrm = fma(v, v, nrm);
+            }
+            const double inv = 1.0 / sqrt(nrm);
+            for (int j = 0; j < nk; ++j) X[kix[j] * me + p] = bh[j] / (-dl(j, p)) * inv;
+            X[n * me + p] = inv;
+        } else {
+            // the deflated poles, in sorted order, after the roots
+            int cnt = p - (nk + 1), i = 0;
+            for (; i < n; ++i) {
+                const bool kept = (kmask >> i) & 1ull;
+                if (!kept) {
+                    if (cnt == 0) break;
+                    --cnt;
+                }
+            }
+            X[i * me + p] = 1.0;
+            lam[p] = ds[i];
+        }
+    }
+    __syncthreads();
+    // undo the rotations (last first) on the rows, one column per lane
+    const int nr = nrot_s;
+    if (lane < m) {
+        for (int q = nr - 1; q >= 0; --q) {
+            const int i = ri[q];
+            const double cq = rc[q], sq = rs[q];
+            const double xi = X[i * me + lane], xj = X[(i + 1) * me + lane];
+            X[i * me + lane] = cq * xi + sq * xj;
+            X[(i + 1) * me + lane] = -sq * xi + cq * xj;
+        }
+    }
+    __syncthreads();
+    // ascending order; Y(:, rank) = Z X(orig rows, p): original row k < n is sorted row ip[k]
+    if (lane < m) {
+        const int p = lane;
+        const double lp = lam[p];
+        int rank = 0;
+        for (int q = 0; q < m; ++q) rank += (lam[q] < lp) || (lam[q] == lp && q < p);
+        theta[rank] = lp;
+        for (int r = 0; r < m; ++r) {
+            double y = 0.0;
+            for (int kk = 0; kk < m; ++kk) y += Z[r * me + kk] * X[(kk < n ? ip[kk] : n) * me + p];
+            Y[(size_t)rank * ldy + r] = y;
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // All eigenpairs of the small symmetric H (step 5) in one workgroup:
 // cyclic Jacobi in the round-robin (tournament) ordering, so the m/2
 // rotations of a round act on disjoint index pairs and run in parallel.
@@ -208,6 +429,19 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
             double g = 0.0;
             for (int w = 0; w < (int)blockDim.x / kWave; ++w) g += wsum[w];
             fro2 = g;
+        }
+        __syncthreads();
+    }
+    // arrowhead (the leading m-1 block exactly diagonal): the secular-equation path
+    if (blockDim.x == kWave && m >= 2 && m <= kWave) {
+        bool offd = false;
+        for (int t = tid; t < (m - 1) * (m - 1); t += blockDim.x) {
+            const int i = t / (m - 1), j = t % (m - 1);
+            offd |= i != j && A[i * me + j] != 0.0;
+        }
+        if (__ballot(offd) == 0 && arrow_rr(m, me, A, Z, theta, Y, ldy)) {
+            if (tid == 0 && st) st->rr_sweeps = 0;
+            return;
         }
         __syncthreads();
     }
