@@ -19,12 +19,14 @@ namespace {
 // against the nb = nx + m orthonormal columns of B.
 //   pass 1: v = src (converted to double);     c = B'v,  n0 = ||v||^2
 //   pass 2: v -= B c;                          c = B'v
-//   pass 3: v -= B c;                          n1 = ||v||^2  -> inv_norm
+//   pass 3: v -= B c;                          n1 = ||v||^2
+// Each pass leaves one row of partial sums per workgroup and the next
+// launch folds them (every workgroup the same totals, in one fixed order);
+// the last pass's rows are folded by the launch that scales v (norm_scale).
 // ---------------------------------------------------------------------------
 template <typename S, int NV>
-__global__ __launch_bounds__(kBlock) void k_orth1(int n, const double *__restrict__ B, int nb,
-                                                  const S *__restrict__ src, double *__restrict__ v,
-                                                  double *partial, unsigned *counter, JDStatus *st) {
+__global__ __launch_bounds__(kBlock) void k_orth1(double *__restrict__ part_out, int n, const double *__restrict__ B,
+                                                  int nb, const S *__restrict__ src, double *__restrict__ v) {
     double acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
@@ -36,24 +38,20 @@ __global__ __launch_bounds__(kBlock) void k_orth1(int n, const double *__restric
             if (j < nb) acc[j] += B[(size_t)j * n + i] * vi;
         acc[NV - 1] += vi * vi;
     }
-    __shared__ double out[NV];
     // pack the norm right after the nb coefficients
     double packed[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) packed[j] = j < nb ? acc[j] : (j == nb ? acc[NV - 1] : 0.0);
-    if (grid_reduce<double, NV>(packed, nb + 1, partial, counter, out)) {
-        for (int j = threadIdx.x; j < nb; j += blockDim.x) st->coef[j] = out[j];
-        if (threadIdx.x == 0) st->orth_n0 = sqrt(out[nb]);
-    }
+    write_partials<double, NV>(packed, nb + 1, part_out);
 }
 
 template <int NV>
-__global__ __launch_bounds__(kBlock) void k_orth2(int n, const double *__restrict__ B, int nb,
-                                                  double *__restrict__ v, double *partial,
-                                                  unsigned *counter, JDStatus *st, int last) {
+__global__ __launch_bounds__(kBlock) void k_orth2(const double *__restrict__ part_in, int nb_in,
+                                                  double *__restrict__ part_out, int n, const double *__restrict__ B,
+                                                  int nb, double *__restrict__ v, JDStatus *st, int first, int last) {
     __shared__ double c[NV];
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) c[j] = st->coef[j];
-    __syncthreads();
+    fold_partials<double, NV>(part_in, nb_in, nb + first, c);
+    if (first && blockIdx.x == 0 && threadIdx.x == 0) st->orth_n0 = sqrt(c[nb]);
     double acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
@@ -73,29 +71,40 @@ __global__ __launch_bounds__(kBlock) void k_orth2(int n, const double *__restric
             acc[0] += vi * vi;
         }
     }
-    __shared__ double out[NV];
-    const int nv = last ? 1 : nb;
-    if (grid_reduce<double, NV>(acc, nv, partial, counter, out)) {
-        if (!last) {
-            for (int j = threadIdx.x; j < nb; j += blockDim.x) st->coef[j] = out[j];
-        } else if (threadIdx.x == 0) {
-            const double n1 = sqrt(out[0]);
-            st->orth_n1 = n1;
-            // a direction that lay in span(B) leaves only rounding noise
-            st->degenerate = !(n1 > 1e-12 * st->orth_n0);
-            st->inv_norm = st->degenerate ? 0.0 : 1.0 / n1;
-        }
+    if (!last) {
+        write_partials<double, NV>(acc, nb, part_out);
+    } else {
+        double a1[1] = {acc[0]};
+        write_partials<double, 1>(a1, 1, part_out);
     }
+}
+
+// The norm of the orthogonalized v from the last pass's partial rows:
+// n1 = ||v||, the direction is degenerate (it lay in span(B), rounding noise
+// is left) when n1 <= 1e-12 n0, and the scale is 1/n1 (0 if degenerate).
+// Every workgroup computes the same values; the first records them in st.
+__device__ __forceinline__ double norm_scale(const double *__restrict__ rows, int nrows, JDStatus *st) {
+    __shared__ double t[1];
+    fold_partials<double, 1>(rows, nrows, 1, t);
+    const double n1 = sqrt(t[0]);
+    const bool degenerate = !(n1 > 1e-12 * st->orth_n0);
+    const double sc = degenerate ? 0.0 : 1.0 / n1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->orth_n1 = n1;
+        st->degenerate = degenerate;
+        st->inv_norm = sc;
+    }
+    return sc;
 }
 
 // V[:, m] = v / ||v||,  W[:, m] = G V[:, m]  (one MVP, step 3)
 template <bool Wt>
-__global__ __launch_bounds__(kBlock) void k_spmv_normalize(Graph g, Weights<double> w,
+__global__ __launch_bounds__(kBlock) void k_spmv_normalize(const double *__restrict__ norm_rows, int norm_nrows,
+                                                           JDStatus *st, Graph g, Weights<double> w,
                                                            const double *__restrict__ v,
                                                            double *__restrict__ vcol,
-                                                           double *__restrict__ wcol,
-                                                           const JDStatus *st) {
-    const double s = st->inv_norm;
+                                                           double *__restrict__ wcol) {
+    const double s = norm_scale(norm_rows, norm_nrows, st);
     for_each_row<double, Wt, false>(g, w, v, [&](int i, double xi, double yi, double) {
         vcol[i] = xi * s;
         wcol[i] = yi * s;
@@ -123,6 +132,24 @@ __global__ __launch_bounds__(kBlock) void k_hborder(int n, const double *__restr
             H[(size_t)j * ldh + m] = out[j];
         }
     }
+}
+
+// The same border as partial rows (m + 1 <= NV values per workgroup), which
+// the Rayleigh-Ritz kernel folds.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_hborder_part(double *__restrict__ part_out, int n,
+                                                         const double *__restrict__ V, int m,
+                                                         const double *__restrict__ wcol) {
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double wi = wcol[i];
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j <= m) acc[j] += V[(size_t)j * n + i] * wi;
+    }
+    write_partials<double, NV>(acc, m + 1, part_out);
 }
 
 // Makes the payload written to *hm visible to the host, then the sequence
@@ -249,7 +276,7 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
             } else {
                 const double mid = 0.5 * (kd[k - 1] + kd[k]);
                 double gm = c - mid;
-                for (int j = 0; j < nk; ++j) gm -= kb[j] * kb[j] / (kd[j] - mid);
+                for (int j = 0; j < nk; ++j) gm -= kb[j] * kb[j] * rcp_nr(kd[j] - mid);
                 o = gm > 0.0 ? k : k - 1;
             }
             const double dor = kd[o];
@@ -261,7 +288,7 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
             // start: the zero of the model at t = 0, -b_o^2 / r(0)
             double r0 = c0;
             for (int j = 0; j < nk; ++j)
-                if (j != o) r0 -= kb[j] * kb[j] / (kd[j] - dor);
+                if (j != o) r0 -= kb[j] * kb[j] * rcp_nr(kd[j] - dor);
             t = r0 != 0.0 ? -bo2 / r0 : 0.5 * (tlo + thi);
             if (!(tlo < t && t < thi) || t == 0.0) t = 0.5 * (tlo + thi);
             ok = false;
@@ -269,15 +296,16 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
                 double R = 0.0, Rd = 0.0, Ab = 0.0;
                 for (int j = 0; j < nk; ++j) {
                     if (j == o) continue;
-                    const double r = 1.0 / ((kd[j] - dor) - t);
+                    const double r = rcp_nr((kd[j] - dor) - t);
                     const double sj = kb[j] * kb[j] * r;
                     R += sj;
                     Rd += sj * r;
                     Ab += fabs(sj);
                 }
                 const double rt_ = c0 - t - R, rdt = -1.0 - Rd;
-                const double g = rt_ + bo2 / t;
-                if (fabs(g) <= 8.0 * kEps * (fabs(c0) + fabs(t) + Ab + bo2 / fabs(t))) { ok = true; break; }
+                const double bt = bo2 * rcp_nr(t);
+                const double g = rt_ + bt;
+                if (fabs(g) <= 8.0 * kEps * (fabs(c0) + fabs(t) + Ab + fabs(bt))) { ok = true; break; }
                 if (g > 0.0) tlo = t; else thi = t;
                 if (thi - tlo <= 4.0 * kEps * fmax(fabs(tlo), fabs(thi))) { ok = true; break; }
                 const double beta = rdt, alpha = rt_ - t * rdt;
@@ -285,7 +313,7 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
                 double tn = 0.5 * (tlo + thi);
                 if (disc >= 0.0) {
                     const double q = -0.5 * (alpha + copysign(sqrt(disc), alpha));
-                    const double x1 = beta != 0.0 ? q / beta : tn, x2 = q != 0.0 ? bo2 / q : tn;
+                    const double x1 = beta != 0.0 ? q * rcp_nr(beta) : tn, x2 = q != 0.0 ? bo2 * rcp_nr(q) : tn;
                     const bool in1 = tlo < x1 && x1 < thi, in2 = tlo < x2 && x2 < thi;
                     if (in1 && in2) tn = fabs(x1 - t) <= fabs(x2 - t) ? x1 : x2;
                     else if (in1) tn = x1;
@@ -307,8 +335,8 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
     if (lane < nk) {
         const int i = lane;
         double pr = -dl(i, i) * dl(i, i + 1);
-        for (int j = 0; j < i; ++j) pr *= dl(i, j) / (kd[i] - kd[j]);
-        for (int j = i + 1; j < nk; ++j) pr *= dl(i, j + 1) / (kd[i] - kd[j]);
+        for (int j = 0; j < i; ++j) pr *= dl(i, j) * rcp_nr(kd[i] - kd[j]);
+        for (int j = i + 1; j < nk; ++j) pr *= dl(i, j + 1) * rcp_nr(kd[i] - kd[j]);
         bh[i] = copysign(sqrt(fmax(pr, 0.0)), kb[i]);
     }
     __syncthreads();
@@ -321,11 +349,12 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
         if (p <= nk) {
             double nrm = 1.0;
             for (int j = 0; j < nk; ++j) {
-                const double v = bh[j] / (-dl(j, p));
+                const double v = -bh[j] * rcp_nr(dl(j, p));
+                X[kix[j] * me + p] = v;
                 nrm = fma(v, v, nrm);
             }
-            const double inv = 1.0 / sqrt(nrm);
-            for (int j = 0; j < nk; ++j) X[kix[j] * me + p] = bh[j] / (-dl(j, p)) * inv;
+            const double inv = rsq_nr(nrm);
+            for (int j = 0; j < nk; ++j) X[kix[j] * me + p] *= inv;
             X[n * me + p] = inv;
         } else {
             // the deflated poles, in sorted order, after the roots
@@ -380,9 +409,9 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
 // ---------------------------------------------------------------------------
 constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
 
-__global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restrict__ Hin, int ldh,
-                                                   double *__restrict__ theta, double *__restrict__ Y,
-                                                   int ldy, int mprev, JDStatus *st) {
+__global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, double *__restrict__ theta,
+                                                   double *__restrict__ Y, int ldy, int mprev, JDStatus *st,
+                                                   const double *__restrict__ bpart, int brows, int bld) {
     extern __shared__ double lds[];
     const int me = (m + 1) & ~1;  // even size; index m is a dummy when m is odd
     double *A = lds;              // me x me, row-major
@@ -392,6 +421,32 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, const double *__restri
     __shared__ int rotates[2];  // some pair of the round rotates (by round parity)
     __shared__ double fro2;
     const int tid = threadIdx.x;
+    if (bpart) {
+        // the new last column of H from the border kernel's partial rows
+        // (m <= kDeferBorderMax values, brows <= 4 x 64 rows): lane l adds
+        // rows l, l + 64, ..., then a fixed butterfly; H is written (row and
+        // column) before anything below reads it
+        if (tid < kWave) {
+            double acc[kDeferBorderMax];
+#pragma unroll
+            for (int j = 0; j < kDeferBorderMax; ++j) acc[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kDeferRows / kWave; ++q) {
+                const int r = tid + q * kWave;
+                if (r < brows) {
+#pragma unroll
+                    for (int j = 0; j < kDeferBorderMax; ++j)
+                        if (j < m) acc[j] += bpart[(size_t)r * bld + j];
+                }
+            }
+            const int idx = wave_reduce_scatter<double, kDeferBorderMax>(acc);
+            if ((lane_id() & (kWave / kDeferBorderMax - 1)) == 0 && idx < m) {
+                Hin[(size_t)(m - 1) * ldh + idx] = acc[0];
+                Hin[(size_t)idx * ldh + (m - 1)] = acc[0];
+            }
+        }
+        __syncthreads();
+    }
     if (mprev >= 1 && mprev < m) {
         // H = [H1 H12; H12' H22] with H1 = Yp diag(theta) Yp' from the previous
         // call (theta and Y still hold it): start from
@@ -727,8 +782,10 @@ __global__ void k_random(int n, unsigned long long seed, long long colidx, const
         v[i] = splitmix_unit(seed, (unsigned long long)colidx * (unsigned long long)n + iperm[i]);
 }
 
-__global__ void k_scale_copy(int n, const double *__restrict__ v, double *__restrict__ out, const JDStatus *st) {
-    const double sc = st->inv_norm;
+__global__ __launch_bounds__(kBlock) void k_scale_copy(const double *__restrict__ norm_rows, int norm_nrows,
+                                                       JDStatus *st, int n, const double *__restrict__ v,
+                                                       double *__restrict__ out) {
+    const double sc = norm_scale(norm_rows, norm_nrows, st);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = v[i] * sc;
 }
 
@@ -780,17 +837,24 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int n, const double *__rest
 
 // ------------------------------------------------------------------ launchers
 
+// Grid of the kernels whose sums are deferred: at most kDeferRows
+// workgroups, so that a fold reads at most that many partial rows.
+inline int defer_grid(int n) {
+    const int g = (n + kBlock - 1) / kBlock;
+    return g < 1 ? 1 : (g > kDeferRows ? kDeferRows : g);
+}
+
 template <typename S, int NV>
 static void orth_nv(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
                     hipStream_t s) {
-    const int grid = vec_grid(n);
-    rs.ensure(grid, 64);
-    hipLaunchKernelGGL((k_orth1<S, NV>), dim3(grid), dim3(kBlock), 0, s, n, B, nb, src, v, rs.partial.get(),
-                       rs.counter.get(), st);
-    hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, n, B, nb, v, rs.partial.get(),
-                       rs.counter.get(), st, 0);
-    hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, n, B, nb, v, rs.partial.get(),
-                       rs.counter.get(), st, 1);
+    const int grid = defer_grid(n);
+    rs.ensure_deferred();
+    double *pa = rs.dpart.get(), *pb = pa + (size_t)kDeferRows * 64;
+    hipLaunchKernelGGL((k_orth1<S, NV>), dim3(grid), dim3(kBlock), 0, s, pa, n, B, nb, src, v);
+    hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, pa, grid, pb, n, B, nb, v, st, 1, 0);
+    hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, pb, grid, pa, n, B, nb, v, st, 0, 1);
+    rs.norm_rows = pa;
+    rs.norm_nrows = grid;
     LAP_HIP(hipGetLastError());
 }
 
@@ -805,21 +869,39 @@ void jd_orth(int n, const double *B, int nb, const S *src, double *v, ReduceScra
 template void jd_orth<float>(int, const double *, int, const float *, double *, ReduceScratch &, JDStatus *, hipStream_t);
 template void jd_orth<double>(int, const double *, int, const double *, double *, ReduceScratch &, JDStatus *, hipStream_t);
 
-void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, const JDStatus *st, hipStream_t s) {
+void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, JDStatus *st,
+               const ReduceScratch &rs, hipStream_t s) {
+    LAP_REQUIRE(rs.norm_rows != nullptr, LAP_EDEVICE, "expansion without an orthogonalized vector");
     const int grid = row_grid(P.g, 1 << 20);
     if (P.weighted)
-        hipLaunchKernelGGL((k_spmv_normalize<true>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), v,
-                           vcol, wcol, st);
+        hipLaunchKernelGGL((k_spmv_normalize<true>), dim3(grid), dim3(kBlock), 0, s, rs.norm_rows, rs.norm_nrows,
+                           st, P.g, P.weights<double>(), v, vcol, wcol);
     else
-        hipLaunchKernelGGL((k_spmv_normalize<false>), dim3(grid), dim3(kBlock), 0, s, P.g, P.weights<double>(), v,
-                           vcol, wcol, st);
+        hipLaunchKernelGGL((k_spmv_normalize<false>), dim3(grid), dim3(kBlock), 0, s, rs.norm_rows,
+                           rs.norm_nrows, st, P.g, P.weights<double>(), v, vcol, wcol);
     LAP_HIP(hipGetLastError());
 }
 
 void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, int ldh, ReduceScratch &rs,
                 hipStream_t s) {
-    const int grid = vec_grid(n);
     LAP_REQUIRE(m + 1 <= 64, LAP_EUNSUPPORTED, "search space wider than 64 columns");
+    rs.border_rows = nullptr;
+    if (m + 1 <= kDeferBorderMax) {
+        // partial rows only; the Rayleigh-Ritz launch folds them into H
+        const int grid = defer_grid(n);
+        rs.ensure_deferred();
+        double *pb = rs.dpart.get() + (size_t)kDeferRows * 64;
+        if (m + 1 <= 16)
+            hipLaunchKernelGGL((k_hborder_part<16>), dim3(grid), dim3(kBlock), 0, s, pb, n, V, m, wcol);
+        else
+            hipLaunchKernelGGL((k_hborder_part<32>), dim3(grid), dim3(kBlock), 0, s, pb, n, V, m, wcol);
+        LAP_HIP(hipGetLastError());
+        rs.border_rows = pb;
+        rs.border_nrows = grid;
+        rs.border_ld = m + 1 <= 16 ? 16 : 32;
+        return;
+    }
+    const int grid = vec_grid(n);
     rs.ensure(grid, 64);
     if (m + 1 <= 16)
         hipLaunchKernelGGL((k_hborder<16>), dim3(grid), dim3(kBlock), 0, s, n, V, m, wcol, H, ldh, rs.partial.get(),
@@ -833,8 +915,10 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
     LAP_HIP(hipGetLastError());
 }
 
-void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
-           int mprev) {
+void jd_rr(int m, double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
+           int mprev, const ReduceScratch *border) {
+    const double *bpart = border ? border->border_rows : nullptr;
+    LAP_REQUIRE(!bpart || m <= kDeferBorderMax, LAP_EDEVICE, "border partial rows for too large an H");
     LAP_REQUIRE(m >= 1 && m <= kRRMax, LAP_EUNSUPPORTED, "projected matrix larger than 96");
     const int me = (m + 1) & ~1;
     const size_t lds = 2 * (size_t)me * me * sizeof(double);
@@ -847,7 +931,8 @@ void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, J
     // up to 32 columns a single wavefront does it: every barrier of the
     // round-by-round rotations is then nearly free
     const int threads = me <= 32 ? kWave : kBlock;
-    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, mprev, st);
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, mprev, st, bpart,
+                       bpart ? border->border_nrows : 0, bpart ? border->border_ld : 0);
     LAP_HIP(hipGetLastError());
 }
 
@@ -912,8 +997,10 @@ void jd_zero_space(int n, int nz, const int *comp, const double *inv_sqrt_size, 
 template void jd_zero_space<float>(int, int, const int *, const double *, double *, float *, int, hipStream_t);
 template void jd_zero_space<double>(int, int, const int *, const double *, double *, double *, int, hipStream_t);
 
-void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_copy, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, v, out, st);
+void jd_scale_copy(int n, const double *v, double *out, JDStatus *st, const ReduceScratch &rs, hipStream_t s) {
+    LAP_REQUIRE(rs.norm_rows != nullptr, LAP_EDEVICE, "scaling without an orthogonalized vector");
+    hipLaunchKernelGGL(k_scale_copy, dim3(vec_grid(n)), dim3(kBlock), 0, s, rs.norm_rows, rs.norm_nrows, st, n, v,
+                       out);
     LAP_HIP(hipGetLastError());
 }
 

@@ -63,7 +63,7 @@ lap_status orth_block(int n, int q, const double *Q, int b, double *W, int *rank
     JDStatus h;
     for (int c = 0; c < b; ++c) {
         jd_orth<double>(n, Bq.get(), qb + rank, W + (size_t)c * n, v.get(), rs, st.get(), s);
-        jd_scale_copy(n, v.get(), Bq.get() + (size_t)(qb + rank) * n, st.get(), s);
+        jd_scale_copy(n, v.get(), Bq.get() + (size_t)(qb + rank) * n, st.get(), rs, s);
         LAP_HIP(hipMemcpyAsync(&h, st.get(), sizeof(JDStatus), hipMemcpyDeviceToHost, s));
         LAP_HIP(hipStreamSynchronize(s));
         const bool dropped = h.degenerate || (projected && !(h.orth_n1 > 1e-12 * norm0[c]));

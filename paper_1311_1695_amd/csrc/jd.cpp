@@ -248,7 +248,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         if (src_is_t) jd_orth<T>(n, B.get(), nx + m, t.get(), v.get(), rs, st.get(), s);
         else jd_orth<double>(n, B.get(), nx + m, src, v.get(), rs, st.get(), s);
         double *Vb = B.get() + (size_t)nx * n;
-        jd_expand(*P, v.get(), Vb + (size_t)m * n, W.get() + (size_t)m * n, st.get(), s);
+        jd_expand(*P, v.get(), Vb + (size_t)m * n, W.get() + (size_t)m * n, st.get(), rs, s);
         ++mvp;
         // step 4: border H
         jd_hborder(n, Vb, m, W.get() + (size_t)m * n, H.get(), mmax, rs, s);
@@ -258,7 +258,9 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         for (;;) {
             // step 5: eigenpairs of H; step 6: Ritz vector and residual
             // warm start when theta and Y still diagonalize the leading block
-            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s, y_rows == m - 1 ? y_rows : 0);
+            // (the first pass folds the new border column that jd_hborder left)
+            jd_rr(m, H.get(), mmax, theta.get(), Y.get(), mmax, st.get(), s, y_rows == m - 1 ? y_rows : 0,
+                  first ? &rs : nullptr);
             y_rows = m;
             Vb = B.get() + (size_t)nx * n;
             jd_ritz<T>(n, Vb, W.get(), m, Y.get(), theta.get(), u.get(), r.get(), Q.get(), ldq, nx, rs, st.get(), s,

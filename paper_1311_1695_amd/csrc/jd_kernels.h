@@ -53,16 +53,21 @@ inline int pcg_max_groups() { return 2 * device_cu_count(); }
 template <typename S>
 void jd_orth(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
              hipStream_t s);
-void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, const JDStatus *st,
-               hipStream_t s);
+// V[:, m] = v / ||v|| and W[:, m] = G V[:, m], the norm folded from the
+// partial rows that jd_orth left in rs (which also records it in st)
+void jd_expand(const lap_plan &P, const double *v, double *vcol, double *wcol, JDStatus *st,
+               const ReduceScratch &rs, hipStream_t s);
 void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, int ldh, ReduceScratch &rs,
                 hipStream_t s);
 // Eigenpairs of the m x m H (column-major, ld ldh): theta ascending, Y
 // column-major (ld ldy).  mprev in [1, m): theta and Y still hold the
 // eigenpairs of the leading mprev x mprev block, which has not changed
 // since (warm start); 0: none.
-void jd_rr(int m, const double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
-           int mprev = 0);
+// Eigenpairs of H (m x m).  mprev: theta and Y still diagonalize the leading
+// mprev x mprev block (warm start); border: the partial rows that jd_hborder
+// left for the last column of H, folded (and written to H) first, or null.
+void jd_rr(int m, double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
+           int mprev = 0, const ReduceScratch *border = nullptr);
 template <typename T>
 void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
              double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s,
@@ -77,7 +82,8 @@ void jd_zero_space(int n, int nz, const int *comp, const double *inv_sqrt_size, 
                    hipStream_t s);
 void jd_random(int n, uint64_t seed, long long colidx, const int *iperm, double *v, hipStream_t s);
 // out = v * inv_norm (the normalization left by jd_orth)
-void jd_scale_copy(int n, const double *v, double *out, const JDStatus *st, hipStream_t s);
+// out = v / ||v|| with the norm folded from the partial rows jd_orth left in rs
+void jd_scale_copy(int n, const double *v, double *out, JDStatus *st, const ReduceScratch &rs, hipStream_t s);
 
 // Eigenvector output: out (n x nconv column-major, caller order, device) =
 // columns order[j] of X (plan order, element (i, c) at X[i sr + c sc]),

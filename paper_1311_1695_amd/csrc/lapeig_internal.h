@@ -209,7 +209,19 @@ struct ReduceScratch {
     int max_blocks = 0;
     int max_values = 0;
     void ensure(int blocks, int values);
+    // Deferred sums: two areas of kDeferRows x 64 doubles for per-workgroup
+    // partial rows that the consuming launch folds (no fence, no counter).
+    // After jd_orth: the 1-value rows of ||v||^2; after jd_hborder (m + 1 <=
+    // kDeferBorderMax): the rows of the H border (stride border_ld).
+    DevBuf<double> dpart;
+    const double *norm_rows = nullptr;
+    int norm_nrows = 0;
+    const double *border_rows = nullptr;
+    int border_nrows = 0, border_ld = 0;
+    void ensure_deferred();
 };
+constexpr int kDeferRows = 256;       // grid of the kernels whose sums are deferred
+constexpr int kDeferBorderMax = 32;   // H border values folded by the Rayleigh-Ritz kernel
 
 // Gathers and scatters between caller order and plan order.
 template <typename T>

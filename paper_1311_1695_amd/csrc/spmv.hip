@@ -205,6 +205,10 @@ template void spmm<double>(const lap_plan &, int, const double *, int, double *,
 template void permute_rows<float>(const int *, int, int, const float *, float *, hipStream_t);
 template void permute_rows<double>(const int *, int, int, const double *, double *, hipStream_t);
 
+void ReduceScratch::ensure_deferred() {
+    if (!dpart.get()) dpart.alloc(2 * (size_t)kDeferRows * 64);
+}
+
 void ReduceScratch::ensure(int blocks, int values) {
     if (blocks <= max_blocks && values <= max_values && partial.get()) return;
     max_blocks = std::max(blocks, max_blocks);
