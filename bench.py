@@ -279,6 +279,8 @@ def main():
                     help="only the PCG iteration timing and a copy of known size (for profiling)")
     ap.add_argument("--extra", action="store_true",
                     help="also time the other workloads (pa5k FP64; cl330k block JD; batch)")
+    ap.add_argument("--block-only", action="store_true",
+                    help="only block JD (b = 20, mixed) on the 330k-vertex graph (for profiling)")
     ap.add_argument("--warmstart", action="store_true",
                     help="also time the learned warm start on the 1.1M-vertex collaboration graph")
     args = ap.parse_args()
@@ -295,6 +297,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lap.load_library()
+    if args.block_only:
+        Lb = gg.workload("cl330k", SEED)
+        pb = lap.Plan(Lb)
+        kw = dict(precision="mixed", block=20, m_min=20, m_max=60)
+        lap.lap_eigs(pb, 20, TOL, seed=1, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            rb = lap.lap_eigs(pb, 20, TOL, seed=1, **kw)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "cl330k", "block": 20, "s": (time.perf_counter() - t0) / 2,
+                          "outer": rb.outer, "inner": rb.inner, "mvp": rb.mvp, "nconv": rb.nconv}))
+        return
     L = gg.workload("cl30k", SEED)
     st = L.stats()
     nnz_a = L.nnz - L.n

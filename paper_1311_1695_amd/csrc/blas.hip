@@ -798,19 +798,13 @@ inline int vec_grid(int n) {
 // Output of the eigenvectors: column j = column order[j] of X (plan order,
 // element (i, c) at X[i sr + c sc]) in the caller's vertex order, with the
 // sign that makes its largest-magnitude entry positive (ties: the lowest
-// caller index).  One workgroup per column; the arg-max is reduced in a
-// fixed order.
-__global__ __launch_bounds__(kBlock) void k_finalize(int n, const double *__restrict__ X, long long sr, long long sc,
-                                                     const int *__restrict__ order, const int *__restrict__ perm,
-                                                     double *__restrict__ out) {
-    const int j = blockIdx.x;
-    const long long c = order[j];
-    double bv = -1.0;
-    int bi = n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double v = fabs(X[(long long)perm[i] * sr + c * sc]);
-        if (v > bv) { bv = v; bi = i; }  // i increases: the first maximum stays
-    }
+// caller index).  Two launches over (chunk of rows, column): the first
+// leaves each chunk's (max |x|, its first index), the second folds a
+// column's chunks (max with the lowest index on ties, the same in any order)
+// and writes its rows.
+
+// (value, index) of the workgroup: the largest value, the lowest index on ties
+__device__ __forceinline__ void argmax_block(double &bv, int &bi) {
     __shared__ double sv[kBlock];
     __shared__ int si[kBlock];
     sv[threadIdx.x] = bv;
@@ -827,9 +821,47 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int n, const double *__rest
         }
         __syncthreads();
     }
-    const int best = si[0];
-    const double sign = (best < n && X[(long long)perm[best] * sr + c * sc] < 0.0) ? -1.0 : 1.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    bv = sv[0];
+    bi = si[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_max(int n, int rows_per, const double *__restrict__ X,
+                                                      long long sr, long long sc, const int *__restrict__ order,
+                                                      const int *__restrict__ perm, double *__restrict__ part) {
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const long long c = order[j];
+    const int i0 = ch * rows_per, i1 = min(n, i0 + rows_per);
+    double bv = -1.0;
+    int bi = n;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const double v = fabs(X[(long long)perm[i] * sr + c * sc]);
+        if (v > bv) { bv = v; bi = i; }  // i increases: the first maximum stays
+    }
+    argmax_block(bv, bi);
+    if (threadIdx.x == 0) {
+        part[((size_t)j * gridDim.x + ch) * 2] = bv;
+        part[((size_t)j * gridDim.x + ch) * 2 + 1] = (double)bi;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_write(int n, int rows_per, const double *__restrict__ X,
+                                                        long long sr, long long sc, const int *__restrict__ order,
+                                                        const int *__restrict__ perm,
+                                                        const double *__restrict__ part, double *__restrict__ out) {
+    const int j = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+    const long long c = order[j];
+    double bv = -1.0;
+    int bi = n;
+    for (int q = threadIdx.x; q < nch; q += blockDim.x) {
+        const double v = part[((size_t)j * nch + q) * 2];
+        const int i = (int)part[((size_t)j * nch + q) * 2 + 1];
+        if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+    }
+    argmax_block(bv, bi);
+    const double sign = (bi < n && X[(long long)perm[bi] * sr + c * sc] < 0.0) ? -1.0 : 1.0;
+    const int i0 = ch * rows_per, i1 = min(n, i0 + rows_per);
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x)
         out[(size_t)j * n + i] = sign * X[(long long)perm[i] * sr + c * sc];
 }
 
@@ -1010,10 +1042,21 @@ void jd_random(int n, uint64_t seed, long long colidx, const int *iperm, double 
     LAP_HIP(hipGetLastError());
 }
 
+// Row chunks of the output launches: at least 2048 rows, at most 256 chunks.
+int final_chunks(int n) {
+    int c = (n + 2047) / 2048;
+    return c < 1 ? 1 : (c > 256 ? 256 : c);
+}
+
 void jd_finalize(int n, int nconv, const double *X, long long sr, long long sc, const int *order_dev,
-                 const int *perm_dev, double *out_dev, hipStream_t s) {
+                 const int *perm_dev, double *out_dev, double *part, hipStream_t s) {
     if (nconv <= 0) return;
-    hipLaunchKernelGGL(k_finalize, dim3(nconv), dim3(kBlock), 0, s, n, X, sr, sc, order_dev, perm_dev, out_dev);
+    const int nch = final_chunks(n);
+    const int rows_per = (n + nch - 1) / nch;
+    hipLaunchKernelGGL(k_final_max, dim3(nch, nconv), dim3(kBlock), 0, s, n, rows_per, X, sr, sc, order_dev,
+                       perm_dev, part);
+    hipLaunchKernelGGL(k_final_write, dim3(nch, nconv), dim3(kBlock), 0, s, n, rows_per, X, sr, sc, order_dev,
+                       perm_dev, part, out_dev);
     LAP_HIP(hipGetLastError());
 }
 

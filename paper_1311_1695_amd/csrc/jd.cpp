@@ -79,13 +79,14 @@ void emit_pairs(const lap_plan &P, int nconv, const double *X, long long sr, lon
     }
     if (evecs && nconv > 0) {
         DevBuf<int> dorder(nconv);
+        DevBuf<double> dpart(2 * (size_t)nconv * final_chunks(n));
         LAP_HIP(hipMemcpyAsync(dorder.get(), order.data(), sizeof(int) * nconv, hipMemcpyHostToDevice, s));
         double *dst = evecs;
         if (!evecs_on_device) {
             if (scratch.n < (size_t)n * nconv) scratch.alloc((size_t)n * nconv);
             dst = scratch.get();
         }
-        jd_finalize(n, nconv, X, sr, sc, dorder.get(), P.d_perm.get(), dst, s);
+        jd_finalize(n, nconv, X, sr, sc, dorder.get(), P.d_perm.get(), dst, dpart.get(), s);
         if (!evecs_on_device)
             LAP_HIP(hipMemcpyAsync(evecs, dst, sizeof(double) * n * nconv, hipMemcpyDeviceToHost, s));
         LAP_HIP(hipStreamSynchronize(s));

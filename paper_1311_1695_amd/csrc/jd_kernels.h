@@ -88,8 +88,10 @@ void jd_scale_copy(int n, const double *v, double *out, JDStatus *st, const Redu
 // Eigenvector output: out (n x nconv column-major, caller order, device) =
 // columns order[j] of X (plan order, element (i, c) at X[i sr + c sc]),
 // each with its largest-magnitude entry made positive (ties: lowest index).
+// part: device scratch of 2 nconv final_chunks(n) doubles.
+int final_chunks(int n);
 void jd_finalize(int n, int nconv, const double *X, long long sr, long long sc, const int *order_dev,
-                 const int *perm_dev, double *out_dev, hipStream_t s);
+                 const int *perm_dev, double *out_dev, double *part, hipStream_t s);
 
 // Writes the nconv locked pairs (values lam, residuals resid, vectors the
 // columns of X as for jd_finalize) in ascending order to the caller's

@@ -105,6 +105,7 @@ struct Graph {
     int nslices = 0;              // 64-row slices covering [n_long, n)
     int nslices_mid = 0;          // leading slices visited eight lanes per row (row engine)
     int nchunks = 0;              // kChunk-edge chunks of the rows [0, n_long)
+    int n_multi = 0;              // rows [0, n_multi) have two chunks or more (degree > kChunk)
     const int *chunk_row = nullptr;  // row of each chunk
     const int *chunk_off = nullptr;  // first chunk of each long row (n_long + 1)
     const int *rowptr = nullptr;  // CSR of A, plan order, n + 1

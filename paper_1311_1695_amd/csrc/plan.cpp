@@ -265,6 +265,9 @@ void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
     P->g.sell_off = P->d_sell_off.get();
     P->g.sell_col = P->d_sell_col.get();
     P->g.nchunks = (int)crow.size();
+    int n_multi = 0;  // rows in decreasing degree: the chunked ones lead
+    while (n_multi < n_long && deg(n_multi) > kChunk) ++n_multi;
+    P->g.n_multi = n_multi;
     P->g.chunk_row = P->d_chunk_row.get();
     P->g.chunk_off = P->d_chunk_off.get();
     // partial sums of chunked rows for block products of up to 64 double columns

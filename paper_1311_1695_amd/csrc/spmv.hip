@@ -100,19 +100,46 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
 }
 
 // rows split into several chunks: Y = sum of the chunk partials (in chunk
-// order) - shift * x
+// order) - shift * x.  One wavefront per row of two chunks or more: the
+// row's partials (nch x b, contiguous) pass through LDS in tiles of 64
+// chunks, each tile loaded with all its loads in flight, and lane c < b adds
+// column c of the tile in chunk order.
 template <typename T>
-__global__ void k_spmm_combine(Graph g, int b, const T *__restrict__ X, int ldx, T *__restrict__ Y, int ldy,
-                               const double *__restrict__ shift, const T *__restrict__ part) {
-    const size_t total = (size_t)g.n_long * b;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(t / b), c = (int)(t % b);
-        const int first = g.chunk_off[r], last = g.chunk_off[r + 1];
-        if (last - first < 2) continue;
-        T acc = T(0);
-        for (int u = first; u < last; ++u) acc += part[(size_t)u * b + c];
-        const T sh = shift ? T(shift[c]) : T(0);
-        Y[(size_t)r * ldy + c] = acc - sh * X[(size_t)r * ldx + c];
+__global__ __launch_bounds__(kWave) void k_spmm_combine(Graph g, int b, const T *__restrict__ X, int ldx,
+                                                        T *__restrict__ Y, int ldy,
+                                                        const double *__restrict__ shift,
+                                                        const T *__restrict__ part) {
+    constexpr int kTile = kWave;  // chunks per tile
+    constexpr int kBatch = 16;    // loads in flight per lane
+    __shared__ T tile[kTile * 64];
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int first = g.chunk_off[r], nch = g.chunk_off[r + 1] - first;
+    T acc = T(0);
+    for (int u0 = 0; u0 < nch; u0 += kTile) {
+        const int cnt = (nch - u0 < kTile ? nch - u0 : kTile) * b;
+        const T *src = part + (size_t)(first + u0) * b;
+        for (int e0 = 0; e0 < cnt; e0 += kBatch * kWave) {
+            T v[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int e = e0 + k * kWave + lane;
+                v[k] = e < cnt ? src[e] : T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int e = e0 + k * kWave + lane;
+                if (e < cnt) tile[e] = v[k];
+            }
+        }
+        __syncthreads();
+        if (lane < b)
+            for (int e = lane; e < cnt; e += b) acc += tile[e];
+        __syncthreads();
+    }
+    if (lane < b) {
+        const T sh = shift ? T(shift[lane]) : T(0);
+        Y[(size_t)r * ldy + lane] = acc - sh * X[(size_t)r * ldx + lane];
     }
 }
 
@@ -163,11 +190,9 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
     else
         hipLaunchKernelGGL((k_spmm<T, false, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx, Y,
                            ldy, shift, part);
-    if (g.n_long > 0) {
-        const size_t tot = (size_t)g.n_long * b;
-        int cg = (int)std::min<size_t>((tot + kBlock - 1) / kBlock, 4096);
-        hipLaunchKernelGGL((k_spmm_combine<T>), dim3(cg), dim3(kBlock), 0, s, g, b, X, ldx, Y, ldy, shift, part);
-    }
+    if (g.n_multi > 0)
+        hipLaunchKernelGGL((k_spmm_combine<T>), dim3(g.n_multi), dim3(kWave), 0, s, g, b, X, ldx, Y, ldy, shift,
+                           part);
     LAP_HIP(hipGetLastError());
 }
 
