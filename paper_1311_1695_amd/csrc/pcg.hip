@@ -283,9 +283,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
 // n~ = (G - theta I) m gathers only wh = D^{-1} w~ and corrects with the
 // rows of G Q and G D^{-1} Q, formed once per solve.
 constexpr int kPP = 16;  // init1 / init2 partials: q + 1 values
-constexpr int kPN = 32;  // init3 / iteration partials, fixed layout:
-// [0] res'u  [1] w~'u  [2] res'res  [3 + j] Q'w~  [17 + j] Q'wh
-constexpr int kCW = 3, kCD = 3 + kPipeQ, kPNV = 3 + 2 * kPipeQ;
+// init3 / iteration partials for projectors of up to QM columns (QM = 6 or
+// kPipeQ; narrow projectors fold and reduce half as many values), layout
+// [0] res'u  [1] w~'u  [2] res'res  [3 + j] Q'w~  [3 + QM + j] Q'wh
+template <int QM>
+struct PLay {
+    static constexpr int CW = 3, CD = 3 + QM, NV = 3 + 2 * QM;
+    static constexpr int N = NV <= 16 ? 16 : 32;  // row stride (a power of two)
+};
+constexpr int kNarrowQ = 6;
 
 // init1: res = -r, t = 0, qq rows [Q_i | dinv_i Q_i]; partials r'r, -Q'r;
 // and this workgroup's share of K = Q'D^{-1}Q on the matrix cores (each
@@ -398,13 +404,13 @@ __global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res,
 
 // init3: c_y = Q'yh;  u = yh - Q c_y;  w~ = (G - theta I) u, gathered as
 // (G - theta I) yh - GQ c_y + theta Q c_y;  wh = D^{-1} w~;  iteration partials
-template <typename T>
+template <typename T, int QM>
 struct P3Row {
-    T q[kPipeQ], gq[kPipeQ];
+    T q[QM], gq[QM];
     T dinv, res;
 };
 
-template <typename T, bool Wt>
+template <typename T, bool Wt, int QM>
 __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, const double *__restrict__ theta,
                                                      const T *__restrict__ Q, int ldq, const T *__restrict__ gqq,
                                                      int q, const T *__restrict__ dinv, const T *__restrict__ res,
@@ -417,13 +423,14 @@ __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, cons
     fold_partials<T, kPP>(part_in, nb_in, q + 1, tot);
     if (stop_v != 0 && stop_v <= sq) return;
     const int q2 = 2 * q;
-    T acc[kPN];
+    using L = PLay<QM>;
+    T acc[L::N];
 #pragma unroll
-    for (int j = 0; j < kPN; ++j) acc[j] = T(0);
+    for (int j = 0; j < L::N; ++j) acc[j] = T(0);
     auto pre = [&](int i) {
-        P3Row<T> d;
+        P3Row<T, QM> d;
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j) {
+        for (int j = 0; j < QM; ++j) {
             d.q[j] = j < q ? Q[(size_t)i * ldq + j] : T(0);
             d.gq[j] = j < q ? gqq[(size_t)i * q2 + j] : T(0);
         }
@@ -431,10 +438,10 @@ __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, cons
         d.res = res[i];
         return d;
     };
-    for_each_row_pre<T, Wt, false>(g, w, yh, pre, [&](int i, T yi, T gyi, T, const P3Row<T> &d) {
+    for_each_row_pre<T, Wt, false>(g, w, yh, pre, [&](int i, T yi, T gyi, T, const P3Row<T, QM> &d) {
         T qc = T(0), gc = T(0);
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j) {
+        for (int j = 0; j < QM; ++j) {
             qc += d.q[j] * tot[1 + j];
             gc += d.gq[j] * tot[1 + j];
         }
@@ -448,23 +455,23 @@ __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, cons
         acc[1] += wi * ui;
         acc[2] += d.res * d.res;
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j) {
-            acc[kCW + j] += d.q[j] * wi;
-            acc[kCD + j] += d.q[j] * hi;
+        for (int j = 0; j < QM; ++j) {
+            acc[L::CW + j] += d.q[j] * wi;
+            acc[L::CD + j] += d.q[j] * hi;
         }
     });
-    write_partials<T, kPN>(acc, kPNV, part_out);
+    write_partials<T, L::N>(acc, L::NV, part_out);
 }
 
 // Iteration i (launch 3 + i): fold gamma, delta, ||res||^2, c_w, c_dw;
 // stop test (i > 0); beta, alpha or breakdown; then the row updates above.
-template <typename T>
+template <typename T, int QM>
 struct PIRow {
-    T q[kPipeQ], gq[kPipeQ], gdq[kPipeQ];
+    T q[QM], gq[QM], gdq[QM];
     T dinv, t, res, u, w, p, s, qv, z;
 };
 
-template <typename T, bool Wt>
+template <typename T, bool Wt, int QM>
 __global__ __launch_bounds__(kBlock) void k_pp_iter(
     // what the fold and the scalar step read first leads the list, so that it
     // arrives in preloaded SGPRs rather than after a kernel-argument load
@@ -481,16 +488,17 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
     const T r0 = st->r0;
     const T gam_prev = st->gam[(it + 1) & 1], alp_prev = st->alp[(it + 1) & 1];
     const int tj = threadIdx.x;
-    T krow[kPipeQ];
+    T krow[QM];
     T cs_prev = T(0);
     if (tj < q) {
 #pragma unroll
-        for (int a = 0; a < kPipeQ; ++a) krow[a] = a < q ? kmat[tj * 16 + a] : T(0);
+        for (int a = 0; a < QM; ++a) krow[a] = a < q ? kmat[tj * 16 + a] : T(0);
         if (it > 0) cs_prev = st->cs[(it + 1) & 1][tj];
     }
-    __shared__ T tot[kPN];
-    __shared__ T coef[3][kPipeQ];  // c_w, c_s, c_m
-    fold_partials<T, kPN>(part_in, nb_in, kPNV, tot);
+    using L = PLay<QM>;
+    __shared__ T tot[L::N];
+    __shared__ T coef[3][QM];  // c_w, c_s, c_m
+    fold_partials<T, L::N>(part_in, nb_in, L::NV, tot);
     if (stop_v != 0 && stop_v <= sq) return;
     const T gam = tot[0], dlt = tot[1], rr = tot[2];
     if (it > 0 && sqrt(rr) <= rtol * r0) {
@@ -511,15 +519,15 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
         return;
     }
     const T alpha = gam / den;
-    if (tj < kPipeQ) {
+    if (tj < QM) {
         T cw = T(0), cs = T(0), cm = T(0);
         if (tj < q) {
-            cw = tot[kCW + tj];
+            cw = tot[L::CW + tj];
             cs = cw + beta * cs_prev;
             T kc = T(0);
 #pragma unroll
-            for (int a = 0; a < kPipeQ; ++a) kc += krow[a] * tot[kCW + a];
-            cm = tot[kCD + tj] - kc;
+            for (int a = 0; a < QM; ++a) kc += krow[a] * tot[L::CW + a];
+            cm = tot[L::CD + tj] - kc;
             if (blockIdx.x == 0) st->cs[it & 1][tj] = cs;
         }
         coef[0][tj] = cw;
@@ -535,13 +543,13 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
     __syncthreads();
     const int q2 = 2 * q;
     const bool first = it == 0;
-    T acc[kPN];
+    T acc[L::N];
 #pragma unroll
-    for (int j = 0; j < kPN; ++j) acc[j] = T(0);
+    for (int j = 0; j < L::N; ++j) acc[j] = T(0);
     auto pre = [&](int i) {
-        PIRow<T> d;
+        PIRow<T, QM> d;
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j) {
+        for (int j = 0; j < QM; ++j) {
             d.q[j] = j < q ? Q[(size_t)i * ldq + j] : T(0);
             d.gq[j] = j < q ? gqq[(size_t)i * q2 + j] : T(0);
             d.gdq[j] = j < q ? gqq[(size_t)i * q2 + q + j] : T(0);
@@ -557,10 +565,10 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
         d.z = first ? T(0) : z[i];
         return d;
     };
-    for_each_row_pre<T, Wt, false>(g, w, wh_in, pre, [&](int i, T hi, T ghi, T, const PIRow<T> &d) {
+    for_each_row_pre<T, Wt, false>(g, w, wh_in, pre, [&](int i, T hi, T ghi, T, const PIRow<T, QM> &d) {
         T qcw = T(0), qcs = T(0), qcm = T(0), gcw = T(0), gcm = T(0);
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j) {
+        for (int j = 0; j < QM; ++j) {
             qcw += d.q[j] * coef[0][j];
             qcs += d.q[j] * coef[1][j];
             qcm += d.q[j] * coef[2][j];
@@ -592,12 +600,12 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
         acc[1] += wn * un;
         acc[2] += rn * rn;
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j) {
-            acc[kCW + j] += d.q[j] * wn;
-            acc[kCD + j] += d.q[j] * hn;
+        for (int j = 0; j < QM; ++j) {
+            acc[L::CW + j] += d.q[j] * wn;
+            acc[L::CD + j] += d.q[j] * hn;
         }
     });
-    write_partials<T, kPN>(acc, kPNV, part_out);
+    write_partials<T, L::N>(acc, L::NV, part_out);
 }
 
 inline int vgrid(int n) {
@@ -647,9 +655,9 @@ void enqueue_nv(const lap_plan &P, const double *theta, const T *Q, int ldq, int
     LAP_HIP(hipGetLastError());
 }
 
-template <typename T>
-void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
-                       PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
+template <typename T, int QM>
+void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
+                          PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
     const int n = P.n;
     const int gv = vgrid(n);
     const int gr = row_grid(P.g, pcg_max_groups());
@@ -668,10 +676,10 @@ void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int l
     hipLaunchKernelGGL((k_pp_init2<T>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq, q, pa, gv,
                        pb, w.kpart.get(), gv, w.kmat.get(), st);
     if (P.weighted)
-        hipLaunchKernelGGL((k_pp_init3<T, true>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
+        hipLaunchKernelGGL((k_pp_init3<T, true, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
                            w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
     else
-        hipLaunchKernelGGL((k_pp_init3<T, false>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
+        hipLaunchKernelGGL((k_pp_init3<T, false, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
                            w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
     for (int it = 0; it < itmax; ++it) {
         T *pin = (it & 1) ? pb : pa;
@@ -679,17 +687,25 @@ void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int l
         const T *hin = (it & 1) ? wh1 : wh0;
         T *hout = (it & 1) ? wh0 : wh1;
         if (P.weighted)
-            hipLaunchKernelGGL((k_pp_iter<T, true>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
+            hipLaunchKernelGGL((k_pp_iter<T, true, QM>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
                                w.kmat.get(), theta, tol, P.g, P.weights<T>(), Q, ldq, w.gqq.get(), dinv, t,
                                w.res.get(), w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(),
                                w.z.get(), pout);
         else
-            hipLaunchKernelGGL((k_pp_iter<T, false>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
+            hipLaunchKernelGGL((k_pp_iter<T, false, QM>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
                                w.kmat.get(), theta, tol, P.g, P.weights<T>(), Q, ldq, w.gqq.get(), dinv, t,
                                w.res.get(), w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(),
                                w.z.get(), pout);
     }
     LAP_HIP(hipGetLastError());
+}
+
+// Projectors of up to kNarrowQ columns take the narrow instantiation.
+template <typename T>
+void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
+                       PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
+    if (q <= kNarrowQ) enqueue_pipelined_qm<T, kNarrowQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, s);
+    else enqueue_pipelined_qm<T, kPipeQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, s);
 }
 
 // The one-launch form unless the projector is too wide for it (or the
