@@ -1,8 +1,9 @@
 // Internal declarations of the gfx950 Jacobi-Davidson library.
 //
-// Vertex order.  A plan renumbers the vertices by decreasing degree (ties by
-// the caller's index).  Every device array of a plan, and every kernel, works
-// in that "plan order"; the C ABI converts at its edges.
+// Vertex order.  A plan renumbers the vertices by decreasing degree; inside
+// one degree, vertices that share their first neighbour sit side by side
+// (ties by the caller's index).  Every device array of a plan, and every
+// kernel, works in that "plan order"; the C ABI converts at its edges.
 //
 // Matrix layout (plan order).  Only the adjacency part of G = D - A is
 // stored: the Laplacian product is evaluated in edge-difference form
