@@ -197,6 +197,22 @@ lap_status lap_spmv(lap_plan *plan, lap_dtype dtype, int b, const void *X, void 
 lap_status lap_orth(lap_dtype dtype, int n, int q, const double *Q, int b, double *W,
                     int *rank_out, void *stream);
 
+/* All eigenpairs of a small symmetric matrix: the projected matrix H of
+ * Algorithm 2 step 5 (Rayleigh-Ritz), in one workgroup.  When m <= 32 and
+ * the leading (m-1) x (m-1) block is exactly diagonal (an arrowhead, the
+ * form H has in single-vector JD after an expansion, a restart or a lock),
+ * from the secular equation, one root per lane; otherwise, or if a root
+ * does not converge, by cyclic Jacobi.
+ * H: device, m x m column-major, symmetric (both triangles are read; H is
+ * not modified).  theta: device, m doubles, ascending.  Y: device, m x m
+ * column-major, orthonormal eigenvectors (column j belongs to theta[j]).
+ * The caller owns all three.  sweeps_out: host int or NULL; if given, the
+ * call synchronizes stream and stores -1 when the secular-equation path
+ * solved H, otherwise the number of Jacobi sweeps.  1 <= m <= 96 (else
+ * LAP_EINVAL); non-finite entries of H give unspecified output.
+ * Asynchronous on stream when sweeps_out is NULL. */
+lap_status lap_sym_eig(int m, const double *H, double *theta, double *Y, int *sweeps_out, void *stream);
+
 /* PCG on the projected correction equations (Algorithm 2 step 8):
  *   (I - QQ')(G - theta_c I)(I - QQ') t_c = -r_c,  t_c orthogonal to Q,
  * for each column c < b, with the preconditioner M = (I-QQ')P(I-QQ') and

@@ -12,6 +12,7 @@ Entry points mirror the C ABI names:
   lap_eigs(plan, k, tol, **opts)  -> EigResult
   lap_spmv(plan, X, Y, shift=None, plan_order=False, stream=None)
   lap_orth(Q, W, stream=None)     -> rank
+  lap_sym_eig(H, stream=None)     -> (theta, Y, sweeps)
   lap_pcg(plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_order=False) -> iters
 Column blocks for lap_orth / lap_pcg are torch tensors of shape (b, n): row c
 is column c of the n x b column-major block the C ABI expects.  lap_spmv
@@ -26,7 +27,7 @@ import os
 import numpy as np
 
 __all__ = ["LapError", "Plan", "Batch", "EigResult", "lap_plan_create", "lap_eigs", "lap_eigs_csr", "lap_spmv",
-           "lap_orth", "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "library_path",
+           "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "library_path",
            "load_library", "LAP_PREC_FP64", "LAP_PREC_MIXED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,7 +43,7 @@ EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap
             "lap_plan_set_layout", "lap_plan_layout", "lap_plan_autotune",
             "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
-            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg", "lap_batch_create",
+            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
 
@@ -111,6 +112,7 @@ def load_library():
     lib.lap_eigs_csr.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info)]
     lib.lap_spmv.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
     lib.lap_orth.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, ip, vp]
+    lib.lap_sym_eig.argtypes = [ctypes.c_int, vp, vp, vp, ip, vp]
     lib.lap_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, f64p, vp, ctypes.c_int, vp, vp, ctypes.c_int,
                             ctypes.c_double, ip, ctypes.c_int, vp]
     lib.lap_batch_create.argtypes = [P(_Csr), ctypes.c_int, P(vp)]
@@ -136,8 +138,8 @@ def load_library():
     lib.lap_status_string.restype = ctypes.c_char_p
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
-    for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_pcg",
-                 "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch"]:
+    for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
+                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -346,6 +348,26 @@ def lap_orth(Q, W, stream=None) -> int:
     _check(lib.lap_orth(LAP_F64, n, q, qp, b, ctypes.c_void_p(W.data_ptr()), ctypes.byref(rank),
                         _stream_handle(stream)))
     return rank.value
+
+
+def lap_sym_eig(H, stream=None):
+    """All eigenpairs of a small symmetric matrix (the Rayleigh-Ritz step).
+    H: (m, m) float64 device tensor, symmetric.  Returns (theta, Y, sweeps):
+    theta (m,) ascending and Y (m, m) with column j the eigenvector of
+    theta[j], both float64 device tensors, and -1 when the secular-equation
+    path solved H, else the number of Jacobi sweeps."""
+    lib = load_library()
+    import torch
+    if H.dtype != torch.float64 or H.dim() != 2 or H.shape[0] != H.shape[1] or not H.is_cuda:
+        raise LapError(LAP_EINVAL, "H must be a square float64 device tensor")
+    m = int(H.shape[0])
+    Hc = H.t().contiguous()  # column-major
+    theta = torch.empty(m, dtype=torch.float64, device=H.device)
+    Yc = torch.empty((m, m), dtype=torch.float64, device=H.device)  # row j = column j of Y
+    sw = ctypes.c_int(0)
+    _check(lib.lap_sym_eig(m, ctypes.c_void_p(Hc.data_ptr()), ctypes.c_void_p(theta.data_ptr()),
+                           ctypes.c_void_p(Yc.data_ptr()), ctypes.byref(sw), _stream_handle(stream)))
+    return theta, Yc.t(), sw.value
 
 
 def lap_pcg(plan: Plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_order=False, stream=None):

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
             offd |= i != j && A[i * me + j] != 0.0;
         }
         if (__ballot(offd) == 0 && arrow_rr(m, me, A, Z, theta, Y, ldy)) {
-            if (tid == 0 && st) st->rr_sweeps = 0;
+            if (tid == 0 && st) st->rr_sweeps = -1;  // the secular-equation path
             return;
         }
         __syncthreads();

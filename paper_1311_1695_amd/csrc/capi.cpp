@@ -385,6 +385,25 @@ lap_status lap_orth(lap_dtype dt, int n, int q, const double *Q, int b, double *
     LAP_GUARD_END
 }
 
+lap_status lap_sym_eig(int m, const double *H, double *theta, double *Y, int *sweeps_out, void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(m >= 1 && m <= 96, LAP_EINVAL, "need 1 <= m <= 96");
+    LAP_REQUIRE(H && theta && Y, LAP_EINVAL, "H, theta or Y is NULL");
+    const hipStream_t s = (hipStream_t)stream;
+    lapeig::DevBuf<lapeig::JDStatus> st;
+    if (sweeps_out) st.alloc(1);
+    // H is only read: no border rows are passed, so nothing is written back
+    lapeig::jd_rr(m, const_cast<double *>(H), m, theta, Y, m, sweeps_out ? st.get() : nullptr, s);
+    if (sweeps_out) {
+        lapeig::JDStatus hs;
+        LAP_HIP(hipMemcpyAsync(&hs, st.get(), sizeof(hs), hipMemcpyDeviceToHost, s));
+        LAP_HIP(hipStreamSynchronize(s));
+        *sweeps_out = hs.rr_sweeps;
+    }
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
 lap_status lap_pcg(lap_plan *p, lap_dtype dt, int b, const double *theta, const double *Q, int q, const double *R,
                    double *T, int itmax, double rtol, int *iters_out, int flags, void *stream) {
     LAP_GUARD_BEGIN

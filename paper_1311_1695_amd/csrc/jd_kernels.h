@@ -62,10 +62,10 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
 // Eigenpairs of the m x m H (column-major, ld ldh): theta ascending, Y
 // column-major (ld ldy).  mprev in [1, m): theta and Y still hold the
 // eigenpairs of the leading mprev x mprev block, which has not changed
-// since (warm start); 0: none.
-// Eigenpairs of H (m x m).  mprev: theta and Y still diagonalize the leading
-// mprev x mprev block (warm start); border: the partial rows that jd_hborder
-// left for the last column of H, folded (and written to H) first, or null.
+// since (warm start); 0: none.  border: the partial rows that jd_hborder
+// left for the last column of H, folded (and written to H) first, or null
+// (then H is only read).  st->rr_sweeps: -1 after the secular-equation
+// path, else the Jacobi sweeps.
 void jd_rr(int m, double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
            int mprev = 0, const ReduceScratch *border = nullptr);
 template <typename T>

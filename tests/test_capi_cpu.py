@@ -116,6 +116,9 @@ def test_entry_points_reject_null_arguments():
     assert lib.lap_spmv(None, lap.LAP_F32, 1, None, None, None, 0, None) == lap.LAP_EINVAL
     assert lib.lap_orth(lap.LAP_F32, 10, 0, None, 1, None, None, None) == lap.LAP_EINVAL
     assert lib.lap_orth(lap.LAP_F64, 10, 0, None, 1, None, None, None) == lap.LAP_EINVAL
+    assert lib.lap_sym_eig(4, None, None, None, None, None) == lap.LAP_EINVAL
+    assert lib.lap_sym_eig(0, None, None, None, None, None) == lap.LAP_EINVAL
+    assert lib.lap_sym_eig(97, None, None, None, None, None) == lap.LAP_EINVAL
     th = np.zeros(1)
     assert lib.lap_pcg(None, lap.LAP_F32, 1, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0,
                        None, None, 20, 1e-2, None, 0, None) == lap.LAP_EINVAL
