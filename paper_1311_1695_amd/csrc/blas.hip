@@ -176,6 +176,44 @@ __device__ __forceinline__ double rsq_nr(double x) {
     return y;
 }
 
+// Value of x in lane l of the wavefront (l wave-uniform).
+__device__ __forceinline__ double lane_val(double x, int l) {
+    const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ int lane_val(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+
+constexpr int kArrowMax = 32;  // largest arrowhead of the secular-equation path
+
+// x of lane (lane ^ M), M = 1, 2 or 4, by data-parallel primitives (no LDS
+// round trip): quad permutations for 1 and 2; for 4, the row shifted by four
+// lanes one way or the other, by the lane's bit 2.  All lanes involved must
+// be active.
+template <int M>
+__device__ __forceinline__ double xor_lane(double x) {
+    const long long b = __double_as_longlong(x);
+    int lo = (int)b, hi = (int)(b >> 32);
+    if constexpr (M == 1) {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (M == 2) {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+    } else {
+        static_assert(M == 4, "M must be 1, 2 or 4");
+        const int lo_up = __builtin_amdgcn_update_dpp(0, lo, 0x104, 0xF, 0xF, false);  // row_shl:4
+        const int hi_up = __builtin_amdgcn_update_dpp(0, hi, 0x104, 0xF, 0xF, false);
+        const int lo_dn = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xF, 0xF, false);  // row_shr:4
+        const int hi_dn = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xF, 0xF, false);
+        const bool up = (threadIdx.x & 4) != 0;
+        lo = up ? lo_dn : lo_up;
+        hi = up ? hi_dn : hi_up;
+    }
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // ---------------------------------------------------------------------------
 // Eigenpairs of an arrowhead matrix A = [diag(d) b; b' c] (m x m, n = m - 1
 // poles), the form the projected matrix takes in every Rayleigh-Ritz step of
@@ -197,32 +235,35 @@ __device__ __forceinline__ double rsq_nr(double x) {
 //      product of bounded ratios, so that the eigenvectors
 //      (b_i / (l_k - d_i) ..., 1) come out orthogonal to working precision;
 //   4. undo the rotations and the sort; Y = Z X.
-// One wavefront, m <= 64.  Returns false, having written nothing, when a
+// One wavefront, m <= kArrowMax.  The poles, borders, roots and shifts stay
+// in the registers of the lane that owns them and are read across lanes.
+// zid: Z is the identity.  Returns false, having written nothing, when a
 // root does not converge (the caller then runs Jacobi on the same A).
-__device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *theta, double *Y, int ldy) {
+__device__ bool arrow_rr(int m, int me, double *A, const double *Z, bool zid, double *theta, double *Y, int ldy) {
     constexpr double kEps = 2.220446049250313e-16;
-    __shared__ double d0[kWave], ds[kWave], bs[kWave], kd[kWave], kb[kWave];
-    __shared__ double rc[kWave], rs[kWave], lam[kWave + 1], rt[kWave + 1], bh[kWave];
-    __shared__ int pm[kWave], ip[kWave], kix[kWave], ri[kWave], ro[kWave + 1];
+    __shared__ double ds[kWave], bs[kWave], kdl[kWave], kbl[kWave], rc[kWave], rs[kWave];
+    __shared__ double dors[kWave + 1], rts[kWave + 1], bhs[kWave];
+    __shared__ int pms[kWave], ips[kWave], kixs[kWave], ri[kWave];
     __shared__ int nrot_s;
     const int lane = lane_id();
     const int n = m - 1;
-    // 1. poles, border, corner; the sort (ties by index)
+    // 1. poles, border, corner; the rank of each pole (ties by index)
     double di = 0.0, bi = 0.0;
     if (lane < n) {
         di = A[lane * me + lane];
         bi = A[lane * me + n];
-        d0[lane] = di;
     }
     const double c = A[n * me + n];
-    __syncthreads();
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+        const double dj = lane_val(di, j);
+        rank += (dj < di) || (dj == di && j < lane);
+    }
     if (lane < n) {
-        int rank = 0;
-        for (int j = 0; j < n; ++j) rank += (d0[j] < di) || (d0[j] == di && j < lane);
         ds[rank] = di;
         bs[rank] = bi;
-        pm[rank] = lane;
-        ip[lane] = rank;
+        pms[rank] = lane;
+        ips[lane] = rank;
     }
     double amax = fabs(di), b2 = bi * bi;
 #pragma unroll
@@ -233,167 +274,223 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
     const double bn = sqrt(b2);
     const double tol = 8.0 * kEps * fmax(fmax(amax, fabs(c)), bn);
     __syncthreads();
-    // close poles: rotate (i, i + 1) so that b_i = 0 (sequential, one lane)
-    if (lane == 0) {
-        int nr = 0;
-        for (int i = 0; i + 1 < n; ++i) {
-            const double x = bs[i], y = bs[i + 1];
-            if (fabs(x) > tol && fabs(y) > tol && ds[i + 1] - ds[i] <= tol) {
-                const double r = sqrt(fma(x, x, y * y));
-                rc[nr] = y / r;
-                rs[nr] = x / r;
-                ri[nr] = i;
-                ++nr;
-                bs[i] = 0.0;
-                bs[i + 1] = r;
+    // lane s holds the s-th smallest pole and its border
+    const double dsl = lane < n ? ds[lane] : 0.0;
+    double bsl = lane < n ? bs[lane] : 0.0;
+    // close poles: rotate (i, i + 1) so that b_i = 0, in order of i.  Values
+    // change only after a rotation, so if no pair qualifies as it stands the
+    // ordered pass would do nothing: test all pairs at once first.
+    const double dnext = __shfl_down(dsl, 1, kWave), bnext = __shfl_down(bsl, 1, kWave);
+    const bool close = lane + 1 < n && fabs(bsl) > tol && fabs(bnext) > tol && dnext - dsl <= tol;
+    int nr = 0;
+    if (__ballot(close) != 0) {
+        if (lane == 0) {
+            int cnt = 0;
+            for (int i = 0; i + 1 < n; ++i) {
+                const double x = bs[i], y = bs[i + 1];
+                if (fabs(x) > tol && fabs(y) > tol && ds[i + 1] - ds[i] <= tol) {
+                    const double r = sqrt(fma(x, x, y * y));
+                    rc[cnt] = y / r;
+                    rs[cnt] = x / r;
+                    ri[cnt] = i;
+                    ++cnt;
+                    bs[i] = 0.0;
+                    bs[i + 1] = r;
+                }
             }
+            nrot_s = cnt;
         }
-        nrot_s = nr;
+        __syncthreads();
+        nr = nrot_s;
+        bsl = lane < n ? bs[lane] : 0.0;
     }
-    __syncthreads();
-    // compaction of the kept poles
-    const bool keep = lane < n && fabs(bs[lane]) > tol;
+    // the kept poles (|b| > tol), compacted: lane j < nk holds the j-th
+    const bool keep = lane < n && fabs(bsl) > tol;
     const unsigned long long kmask = __ballot(keep);
     const int nk = __popcll(kmask);
     if (keep) {
         const int pos = __popcll(kmask & ((1ull << lane) - 1ull));
-        kd[pos] = ds[lane];
-        kb[pos] = bs[lane];
-        kix[pos] = lane;
+        kdl[pos] = dsl;
+        kbl[pos] = bsl;
+        kixs[pos] = lane;
     }
     __syncthreads();
-    // 2. the nk + 1 roots of the secular equation of the kept part
+    const double kd = lane < nk ? kdl[lane] : 0.0, kb = lane < nk ? kbl[lane] : 0.0;
+    // 2. the nk + 1 roots of the secular equation of the kept part, in
+    // coordinates shifted to the nearer pole o.  Root g is found by the G
+    // lanes of group g (G = 8, 4 or 2 as nk + 1 <= 8, 16 or 32); lane `sub` of
+    // a group takes the poles j = sub, sub + G, ... and the group adds its
+    // sums by a butterfly, so all G lanes hold the same totals and take the
+    // same steps.
+    const int nroot = nk + 1;
+    const int lg = nroot <= 8 ? 3 : (nroot <= 16 ? 2 : 1);
+    const int G = 1 << lg;
+    const int g = lane >> lg, sub = lane & (G - 1);
+    auto group_sum = [&](double v) {
+        v += xor_lane<1>(v);
+        if (G >= 4) v += xor_lane<2>(v);
+        if (G >= 8) v += xor_lane<4>(v);
+        return v;
+    };
     bool ok = true;
-    if (lane <= nk) {
-        const int k = lane;
-        int o = -1;
-        double t = c;
-        if (nk > 0) {
-            if (k == 0) {
-                o = 0;
-            } else if (k == nk) {
-                o = nk - 1;
-            } else {
-                const double mid = 0.5 * (kd[k - 1] + kd[k]);
-                double gm = c - mid;
-                for (int j = 0; j < nk; ++j) gm -= kb[j] * kb[j] * rcp_nr(kd[j] - mid);
-                o = gm > 0.0 ? k : k - 1;
-            }
-            const double dor = kd[o];
-            const double c0 = c - dor;
-            const double bo2 = kb[o] * kb[o];
-            const double outer = bn + fabs(c0) + tol;
-            double tlo = k >= 1 ? kd[k - 1] - dor : -outer;
-            double thi = k < nk ? kd[k] - dor : outer;
-            // start: the zero of the model at t = 0, -b_o^2 / r(0)
-            double r0 = c0;
-            for (int j = 0; j < nk; ++j)
-                if (j != o) r0 -= kb[j] * kb[j] * rcp_nr(kd[j] - dor);
-            t = r0 != 0.0 ? -bo2 / r0 : 0.5 * (tlo + thi);
-            if (!(tlo < t && t < thi) || t == 0.0) t = 0.5 * (tlo + thi);
-            ok = false;
-            for (int it = 0; it < 80; ++it) {
-                double R = 0.0, Rd = 0.0, Ab = 0.0;
-                for (int j = 0; j < nk; ++j) {
-                    if (j == o) continue;
-                    const double r = rcp_nr((kd[j] - dor) - t);
-                    const double sj = kb[j] * kb[j] * r;
-                    R += sj;
-                    Rd += sj * r;
-                    Ab += fabs(sj);
-                }
-                const double rt_ = c0 - t - R, rdt = -1.0 - Rd;
-                const double bt = bo2 * rcp_nr(t);
-                const double g = rt_ + bt;
-                if (fabs(g) <= 8.0 * kEps * (fabs(c0) + fabs(t) + Ab + fabs(bt))) { ok = true; break; }
-                if (g > 0.0) tlo = t; else thi = t;
-                if (thi - tlo <= 4.0 * kEps * fmax(fabs(tlo), fabs(thi))) { ok = true; break; }
-                const double beta = rdt, alpha = rt_ - t * rdt;
-                const double disc = alpha * alpha - 4.0 * beta * bo2;
-                double tn = 0.5 * (tlo + thi);
-                if (disc >= 0.0) {
-                    const double q = -0.5 * (alpha + copysign(sqrt(disc), alpha));
-                    const double x1 = beta != 0.0 ? q * rcp_nr(beta) : tn, x2 = q != 0.0 ? bo2 * rcp_nr(q) : tn;
-                    const bool in1 = tlo < x1 && x1 < thi, in2 = tlo < x2 && x2 < thi;
-                    if (in1 && in2) tn = fabs(x1 - t) <= fabs(x2 - t) ? x1 : x2;
-                    else if (in1) tn = x1;
-                    else if (in2) tn = x2;
-                }
-                if (fabs(tn - t) <= 2.0 * kEps * fabs(t)) { ok = true; break; }
-                t = tn;
-                if (t == 0.0) break;
-            }
+    int og = -1;
+    double tg = c, dorg = 0.0;
+    if (nk > 0 && g <= nk) {
+        const double kdg = g < nk ? kdl[g] : 0.0, kdgm = g >= 1 ? kdl[g - 1] : 0.0;
+        if (g == 0) {
+            og = 0;
+        } else if (g == nk) {
+            og = nk - 1;
+        } else {
+            const double mid = 0.5 * (kdgm + kdg);
+            double s = 0.0;
+            for (int j = sub; j < nk; j += G) s += kbl[j] * kbl[j] * rcp_nr(kdl[j] - mid);
+            const double gm = (c - mid) - group_sum(s);
+            og = gm > 0.0 ? g : g - 1;
         }
-        ro[k] = o;
-        rt[k] = t;
-        lam[k] = o >= 0 ? kd[o] + t : t;
+        dorg = kdl[og];
+        const double bo2 = kbl[og] * kbl[og];
+        const double c0 = c - dorg;
+        const double outer = bn + fabs(c0) + tol;
+        double tlo = g >= 1 ? kdgm - dorg : -outer;
+        double thi = g < nk ? kdg - dorg : outer;
+        // start: the zero of the model at t = 0, -b_o^2 / r(0)
+        double s0 = 0.0;
+        for (int j = sub; j < nk; j += G)
+            if (j != og) s0 += kbl[j] * kbl[j] * rcp_nr(kdl[j] - dorg);
+        const double r0 = c0 - group_sum(s0);
+        double t = r0 != 0.0 ? -bo2 / r0 : 0.5 * (tlo + thi);
+        if (!(tlo < t && t < thi) || t == 0.0) t = 0.5 * (tlo + thi);
+        ok = false;
+        for (int it = 0; it < 80; ++it) {
+            double R = 0.0, Rd = 0.0, Ab = 0.0;
+            for (int j = sub; j < nk; j += G) {
+                const double r = rcp_nr((kdl[j] - dorg) - t);
+                const double sj = j != og ? kbl[j] * kbl[j] * r : 0.0;
+                R += sj;
+                Rd += sj * r;
+                Ab += fabs(sj);
+            }
+            R = group_sum(R);
+            Rd = group_sum(Rd);
+            Ab = group_sum(Ab);
+            const double rt_ = c0 - t - R, rdt = -1.0 - Rd;
+            const double bt = bo2 * rcp_nr(t);
+            const double gv = rt_ + bt;
+            if (fabs(gv) <= 8.0 * kEps * (fabs(c0) + fabs(t) + Ab + fabs(bt))) { ok = true; break; }
+            if (gv > 0.0) tlo = t; else thi = t;
+            if (thi - tlo <= 4.0 * kEps * fmax(fabs(tlo), fabs(thi))) { ok = true; break; }
+            const double beta = rdt, alpha = rt_ - t * rdt;
+            const double disc = alpha * alpha - 4.0 * beta * bo2;
+            double tn = 0.5 * (tlo + thi);
+            if (disc >= 0.0) {
+                const double q = -0.5 * (alpha + copysign(sqrt(disc), alpha));
+                const double x1 = beta != 0.0 ? q * rcp_nr(beta) : tn, x2 = q != 0.0 ? bo2 * rcp_nr(q) : tn;
+                const bool in1 = tlo < x1 && x1 < thi, in2 = tlo < x2 && x2 < thi;
+                if (in1 && in2) tn = fabs(x1 - t) <= fabs(x2 - t) ? x1 : x2;
+                else if (in1) tn = x1;
+                else if (in2) tn = x2;
+            }
+            if (fabs(tn - t) <= 2.0 * kEps * fabs(t)) { ok = true; break; }
+            t = tn;
+            if (t == 0.0) break;
+        }
+        tg = t;
     }
     if (__ballot(!ok) != 0) return false;
-    __syncthreads();
-    // 3. the border from the roots: l_k - d_i = t_k - (d_i - d_{o_k})
-    auto dl = [&](int i, int kk) { return ro[kk] >= 0 ? (kd[i] - kd[ro[kk]]) - rt[kk] : kd[i] - rt[kk]; };
-    if (lane < nk) {
-        const int i = lane;
-        double pr = -dl(i, i) * dl(i, i + 1);
-        for (int j = 0; j < i; ++j) pr *= dl(i, j) * rcp_nr(kd[i] - kd[j]);
-        for (int j = i + 1; j < nk; ++j) pr *= dl(i, j + 1) * rcp_nr(kd[i] - kd[j]);
-        bh[i] = copysign(sqrt(fmax(pr, 0.0)), kb[i]);
+    // back to one root per lane: lane k <= nk takes group k's root
+    const int src = (lane <= nk ? lane : 0) << lg;
+    const int o = __shfl(og, src, kWave);
+    const double dor = __shfl(dorg, src, kWave), t = __shfl(tg, src, kWave);
+    if (lane <= nk) {
+        dors[lane] = dor;
+        rts[lane] = t;
     }
     __syncthreads();
-    // 4. eigenvectors in the sorted coordinates (rows 0..n-1 the sorted
-    // poles, row n the corner), one column per lane, into A (no longer needed)
+    // 3. the border from the roots (lane i < nk); with nk > 0 every root has
+    // a pole, and l_k - d_i = t_k - (d_i - d_{o_k}) = -((d_i - d_{o_k}) - t_k)
+    if (lane < nk) {
+        const int i = lane;
+        double pr = -((kd - dor) - t) * ((kd - dors[i + 1]) - rts[i + 1]);
+#pragma unroll 4
+        for (int j = 0; j < nk; ++j) {
+            // roots j (below i) and j + 1 (above)
+            const double num = j < i ? (kd - dors[j]) - rts[j] : (kd - dors[j + 1]) - rts[j + 1];
+            const double den = j == i ? 1.0 : kd - kdl[j];
+            pr *= j == i ? 1.0 : num * rcp_nr(den);
+        }
+        bhs[i] = copysign(sqrt(fmax(pr, 0.0)), kb);
+    }
+    __syncthreads();
+    // the deflated lanes' sorted row: the (lane - nk - 1)-th row not kept
+    int row = n;
+    for (int i = 0, cnt = lane - (nk + 1); cnt >= 0 && i < n; ++i)
+        if (!((kmask >> i) & 1ull)) {
+            if (cnt == 0) { row = i; break; }
+            --cnt;
+        }
+    const double ldefl = __shfl(dsl, row < n ? row : 0, kWave);
+    // 4. eigenvector p (lane p < m) in the sorted coordinates (rows 0..n-1
+    // the sorted poles, row n the corner), one column per lane, into A (no
+    // longer needed): roots p <= nk take (b_j / (l_p - d_j) ..., 1)
+    // normalized; the deflated poles, in sorted order after the roots, their
+    // unit vectors.
     double *X = A;
+    double lam = 0.0;
     if (lane < m) {
         const int p = lane;
-        for (int r = 0; r < m; ++r) X[r * me + p] = 0.0;
+        for (int r = 0; r < n; ++r) X[r * me + p] = 0.0;
         if (p <= nk) {
+            lam = o >= 0 ? dor + t : t;
             double nrm = 1.0;
+#pragma unroll 4
             for (int j = 0; j < nk; ++j) {
-                const double v = -bh[j] * rcp_nr(dl(j, p));
-                X[kix[j] * me + p] = v;
+                const double v = -bhs[j] * rcp_nr((kdl[j] - dor) - t);
+                X[kixs[j] * me + p] = v;
                 nrm = fma(v, v, nrm);
             }
             const double inv = rsq_nr(nrm);
-            for (int j = 0; j < nk; ++j) X[kix[j] * me + p] *= inv;
+#pragma unroll 4
+            for (int j = 0; j < nk; ++j) X[kixs[j] * me + p] *= inv;
             X[n * me + p] = inv;
         } else {
-            // the deflated poles, in sorted order, after the roots
-            int cnt = p - (nk + 1), i = 0;
-            for (; i < n; ++i) {
-                const bool kept = (kmask >> i) & 1ull;
-                if (!kept) {
-                    if (cnt == 0) break;
-                    --cnt;
-                }
-            }
-            X[i * me + p] = 1.0;
-            lam[p] = ds[i];
+            X[row * me + p] = 1.0;
+            X[n * me + p] = 0.0;
+            lam = ldefl;
         }
-    }
-    __syncthreads();
-    // undo the rotations (last first) on the rows, one column per lane
-    const int nr = nrot_s;
-    if (lane < m) {
+        // undo the rotations (last first) on the rows
         for (int q = nr - 1; q >= 0; --q) {
             const int i = ri[q];
             const double cq = rc[q], sq = rs[q];
-            const double xi = X[i * me + lane], xj = X[(i + 1) * me + lane];
-            X[i * me + lane] = cq * xi + sq * xj;
-            X[(i + 1) * me + lane] = -sq * xi + cq * xj;
+            const double xi = X[i * me + p], xj = X[(i + 1) * me + p];
+            X[i * me + p] = cq * xi + sq * xj;
+            X[(i + 1) * me + p] = -sq * xi + cq * xj;
         }
     }
+    // ascending order (ties by index)
+    int lr = 0;
+    for (int q = 0; q < m; ++q) {
+        const double lq = lane_val(lam, q);
+        lr += (lq < lam) || (lq == lam && q < lane);
+    }
+    if (lane < m) theta[lr] = lam;
     __syncthreads();
-    // ascending order; Y(:, rank) = Z X(orig rows, p): original row k < n is sorted row ip[k]
-    if (lane < m) {
-        const int p = lane;
-        const double lp = lam[p];
-        int rank = 0;
-        for (int q = 0; q < m; ++q) rank += (lam[q] < lp) || (lam[q] == lp && q < p);
-        theta[rank] = lp;
-        for (int r = 0; r < m; ++r) {
-            double y = 0.0;
-            for (int kk = 0; kk < m; ++kk) y += Z[r * me + kk] * X[(kk < n ? ip[kk] : n) * me + p];
-            Y[(size_t)rank * ldy + r] = y;
+    // Y(:, rank_c) = Z X(original rows, c); sorted row s is original row pm_s.
+    // Lane l computes rows (l >> 5) + 2i of column l & 31.
+    const int cc = lane & 31;
+    const int rk = __shfl(lr, cc, kWave);
+    if (cc < m) {
+        for (int r = lane >> 5; r < m; r += 2) {
+            double y;
+            if (zid) {
+                y = X[(r < n ? ips[r] : n) * me + cc];
+            } else {
+                const double *zr = Z + r * me;
+                y = zr[n] * X[n * me + cc];
+#pragma unroll 4
+                for (int s = 0; s < n; ++s) y = fma(zr[pms[s]], X[s * me + cc], y);
+            }
+            Y[(size_t)rk * ldy + r] = y;
         }
     }
     return true;
@@ -409,6 +506,26 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, double *thet
 // ---------------------------------------------------------------------------
 constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
 
+// The last column of H from the border kernel's partial rows (brows <= 4 x 64
+// rows, stride bld, m <= kDeferBorderMax values wanted) in one wavefront:
+// lane l adds rows l, l + 64, ... in that order, then a fixed butterfly.
+__device__ void fold_border_rows(const double *__restrict__ bpart, int brows, int bld, int m, double *hcol) {
+    double acc[kDeferBorderMax];
+#pragma unroll
+    for (int c = 0; c < kDeferBorderMax; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDeferRows / kWave; ++q) {
+        const int r = lane_id() + q * kWave;
+        if (r < brows) {
+#pragma unroll
+            for (int c = 0; c < kDeferBorderMax; ++c)
+                if (c < m) acc[c] += bpart[(size_t)r * bld + c];
+        }
+    }
+    const int idx = wave_reduce_scatter<double, kDeferBorderMax>(acc);
+    if ((lane_id() & (kWave / kDeferBorderMax - 1)) == 0 && idx < m) hcol[idx] = acc[0];
+}
+
 __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, double *__restrict__ theta,
                                                    double *__restrict__ Y, int ldy, int mprev, JDStatus *st,
                                                    const double *__restrict__ bpart, int brows, int bld) {
@@ -420,59 +537,123 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
     __shared__ int pp[kRRMax / 2], qq[kRRMax / 2];
     __shared__ int rotates[2];  // some pair of the round rotates (by round parity)
     __shared__ double fro2;
+    __shared__ double hcol[kDeferBorderMax];  // the last column of H, when folded here
     const int tid = threadIdx.x;
-    if (bpart) {
-        // the new last column of H from the border kernel's partial rows
-        // (m <= kDeferBorderMax values, brows <= 4 x 64 rows): lane l adds
-        // rows l, l + 64, ..., then a fixed butterfly; H is written (row and
-        // column) before anything below reads it
-        if (tid < kWave) {
-            double acc[kDeferBorderMax];
+    // warm start: H = [H1 H12; H12' H22] with H1 = Yp diag(theta) Yp' from the
+    // previous call (theta and Y still hold it): start from
+    // [diag(theta) Yp'H12; H12'Yp H22] and accumulate onto Z = diag(Yp, I)
+    const bool warm = mprev >= 1 && mprev < m;
+    const int mp = warm ? mprev : 0;
+    if (blockDim.x == kWave) {
+        // me <= 32, one wavefront: lane l builds column l & 31, rows (l >> 5) + 2q.
+        // The loads of Yp, theta and H are issued together with those of the
+        // border's partial rows, before anything waits on them.  With border
+        // rows, row and column m - 1 of H come from the fold instead of Hin.
+        const int j = tid & 31, i0 = tid >> 5;
+        const bool bcol = bpart != nullptr;
+        double zr[16], ar[16];
 #pragma unroll
-            for (int j = 0; j < kDeferBorderMax; ++j) acc[j] = 0.0;
-#pragma unroll
-            for (int q = 0; q < kDeferRows / kWave; ++q) {
-                const int r = tid + q * kWave;
-                if (r < brows) {
-#pragma unroll
-                    for (int j = 0; j < kDeferBorderMax; ++j)
-                        if (j < m) acc[j] += bpart[(size_t)r * bld + j];
+        for (int q = 0; q < 16; ++q) {
+            const int i = i0 + 2 * q;
+            double z = i == j ? 1.0 : 0.0, a = 0.0;
+            if (i < me && j < me) {
+                const bool inh = i < m && j < m && !(bcol && (i == m - 1 || j == m - 1));
+                if (warm) {
+                    if (i < mp && j < mp) z = Y[(size_t)j * ldy + i];
+                    else if (i < mp && j < m && inh) z = Hin[(size_t)j * ldh + i];  // H12, staged in Z
+                    if (i == j && i < mp) a = theta[i];
+                    else if (i >= mp && j >= mp && inh) a = Hin[(size_t)j * ldh + i];
+                } else if (inh) {
+                    a = Hin[(size_t)j * ldh + i];
                 }
             }
-            const int idx = wave_reduce_scatter<double, kDeferBorderMax>(acc);
-            if ((lane_id() & (kWave / kDeferBorderMax - 1)) == 0 && idx < m) {
-                Hin[(size_t)(m - 1) * ldh + idx] = acc[0];
-                Hin[(size_t)idx * ldh + (m - 1)] = acc[0];
+            zr[q] = z;
+            ar[q] = a;
+        }
+        if (bcol) {
+            // the new last column of H from the border kernel's partial rows
+            // (m <= kDeferBorderMax values, brows <= 4 x 64 rows): lane l adds
+            // rows l, l + 64, ..., then a fixed butterfly
+            fold_border_rows(bpart, brows, bld, m, hcol);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = i0 + 2 * q;
+            if (i < me && j < me) {
+                double z = zr[q], a = ar[q];
+                if (bcol && i < m && j < m && (i == m - 1 || j == m - 1)) {
+                    const double h = hcol[i == m - 1 ? j : i];
+                    if (warm && i < mp) z = h;                    // H12
+                    else if (!warm || (i >= mp && j >= mp)) a = h;  // H, H22
+                }
+                Z[i * me + j] = z;
+                A[i * me + j] = a;
+            }
+        }
+        __syncthreads();
+        if (warm) {
+            // A12 = Yp' H12 from LDS, then Z's upper-right block back to zero
+            for (int t = tid; t < mp * (m - mp); t += blockDim.x) {
+                const int i = t % mp, c = mp + t / mp;
+                double v = 0.0;
+                for (int r = 0; r < mp; ++r) v += Z[r * me + i] * Z[r * me + c];
+                A[i * me + c] = v;
+                A[c * me + i] = v;
+            }
+            __syncthreads();
+            for (int t = tid; t < mp * (me - mp); t += blockDim.x) Z[(t % mp) * me + mp + t / mp] = 0.0;
+            __syncthreads();
+        }
+    } else {
+        // me > 32 (no border rows: those come only with m <= kDeferBorderMax)
+        if (warm) {
+            for (int t = tid; t < me * me; t += blockDim.x) {
+                const int i = t / me, j = t % me;
+                Z[t] = (i < mp && j < mp) ? Y[(size_t)j * ldy + i] : (i == j ? 1.0 : 0.0);
+                A[t] = (i == j && i < mp) ? theta[i]
+                                          : ((i >= mp && j >= mp && i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0);
+            }
+            __syncthreads();
+            for (int t = tid; t < mp * (m - mp); t += blockDim.x) {
+                const int i = t % mp, c = mp + t / mp;
+                double v = 0.0;
+                for (int r = 0; r < mp; ++r) v += Z[r * me + i] * Hin[(size_t)c * ldh + r];
+                A[i * me + c] = v;
+                A[c * me + i] = v;
+            }
+        } else {
+            for (int t = tid; t < me * me; t += blockDim.x) {
+                const int i = t / me, j = t % me;
+                A[t] = (i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0;
+                Z[t] = (i == j) ? 1.0 : 0.0;
             }
         }
         __syncthreads();
     }
-    if (mprev >= 1 && mprev < m) {
-        // H = [H1 H12; H12' H22] with H1 = Yp diag(theta) Yp' from the previous
-        // call (theta and Y still hold it): start from
-        // [diag(theta) Yp'H12; H12'Yp H22] and accumulate onto Z = diag(Yp, I)
-        const int mp = mprev;
-        for (int t = tid; t < me * me; t += blockDim.x) {
-            const int i = t / me, j = t % me;
-            Z[t] = (i < mp && j < mp) ? Y[(size_t)j * ldy + i] : (i == j ? 1.0 : 0.0);
-            A[t] = (i == j && i < mp) ? theta[i] : ((i >= mp && j >= mp && i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0);
+    // H's folded border back to global memory, after everything else
+    auto flush_border = [&]() {
+        if (bpart && tid < m) {
+            Hin[(size_t)(m - 1) * ldh + tid] = hcol[tid];
+            Hin[(size_t)tid * ldh + (m - 1)] = hcol[tid];
+        }
+    };
+    // arrowhead (the leading m-1 block exactly diagonal, as it is by
+    // construction after a warm start from m - 1): the secular-equation path
+    if (blockDim.x == kWave && m >= 2 && m <= kArrowMax) {
+        bool offd = false;
+        if (!(warm && mp == m - 1))
+            for (int t = tid; t < (m - 1) * (m - 1); t += blockDim.x) {
+                const int i = t / (m - 1), j = t % (m - 1);
+                offd |= i != j && A[i * me + j] != 0.0;
+            }
+        if (__ballot(offd) == 0 && arrow_rr(m, me, A, Z, !warm, theta, Y, ldy)) {
+            flush_border();
+            if (tid == 0 && st) st->rr_sweeps = -1;  // the secular-equation path
+            return;
         }
         __syncthreads();
-        for (int t = tid; t < mp * (m - mp); t += blockDim.x) {
-            const int i = t % mp, c = mp + t / mp;
-            double v = 0.0;
-            for (int r = 0; r < mp; ++r) v += Z[r * me + i] * Hin[(size_t)c * ldh + r];
-            A[i * me + c] = v;
-            A[c * me + i] = v;
-        }
-    } else {
-        for (int t = tid; t < me * me; t += blockDim.x) {
-            const int i = t / me, j = t % me;
-            A[t] = (i < m && j < m) ? Hin[(size_t)j * ldh + i] : 0.0;
-            Z[t] = (i == j) ? 1.0 : 0.0;
-        }
     }
-    __syncthreads();
     {
         __shared__ double wsum[kWavesPerBlock];
         double f = 0.0;
@@ -484,19 +665,6 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
             double g = 0.0;
             for (int w = 0; w < (int)blockDim.x / kWave; ++w) g += wsum[w];
             fro2 = g;
-        }
-        __syncthreads();
-    }
-    // arrowhead (the leading m-1 block exactly diagonal): the secular-equation path
-    if (blockDim.x == kWave && m >= 2 && m <= kWave) {
-        bool offd = false;
-        for (int t = tid; t < (m - 1) * (m - 1); t += blockDim.x) {
-            const int i = t / (m - 1), j = t % (m - 1);
-            offd |= i != j && A[i * me + j] != 0.0;
-        }
-        if (__ballot(offd) == 0 && arrow_rr(m, me, A, Z, theta, Y, ldy)) {
-            if (tid == 0 && st) st->rr_sweeps = -1;  // the secular-equation path
-            return;
         }
         __syncthreads();
     }
@@ -606,6 +774,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
         theta[rank] = di;
         for (int r = 0; r < m; ++r) Y[(size_t)rank * ldy + r] = Z[r * me + i];
     }
+    flush_border();
     if (tid == 0 && st) st->rr_sweeps = sweeps;
 }
 
