@@ -29,7 +29,7 @@ bool converged(double rnorm, double theta, double tol) {
 // until a lock widens Q.  The graph holds kernel nodes only.
 template <typename T>
 struct PcgGraphs {
-    std::vector<hipGraphExec_t> exec;  // indexed by q
+    std::vector<hipGraphExec_t> exec;  // indexed by key
     ~PcgGraphs() {
         for (auto e : exec)
             if (e) (void)hipGraphExecDestroy(e);
@@ -206,6 +206,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         for (int c = 0; c < nz; ++c) { lam.push_back(0.0); resid.push_back(0.0); }
     }
     int nx = nz, m = 0, it = 0;
+    int pcg_q = -1;  // projector width of the last correction equation of this solve
     int y_rows = 0;  // order of the block of H that theta and Y diagonalize
     long long mvp = 0, inner = 0;
     long long start_col = 0;
@@ -319,11 +320,14 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         }
         // step 8: correction equation with Q = [X u]
         {
+            // Q = [X u]: with no lock since the last equation, only u is new
             const int q = nx + 1;
+            const bool inc = q == pcg_q;
+            pcg_q = q;
             auto enqueue = [&]() {
-                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, o.itmax, o.rtol_pcg, s);
+                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, o.itmax, o.rtol_pcg, s, inc);
             };
-            if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, s, enqueue), s));
+            if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(2 * q + (inc ? 1 : 0), s, enqueue), s));
             else enqueue();
         }
         src_is_t = true;

@@ -128,8 +128,10 @@ struct PcgWork {
 // One correction equation: t solves the projected system for theta (device
 // scalar), projector Q (row-major n x ldq, first q columns), right-hand side
 // -r (r double, plan order).  Enqueues everything; nothing is read back.
+// inc: the previous call on w had the same q and Q, except possibly its last
+// column (the products of the first q - 1 columns are then reused).
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s);
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc = false);
 
 }  // namespace lapeig

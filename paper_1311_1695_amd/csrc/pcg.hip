@@ -296,7 +296,13 @@ constexpr int kNarrowQ = 6;
 // init1: res = -r, t = 0, qq rows [Q_i | dinv_i Q_i]; partials r'r, -Q'r;
 // and this workgroup's share of K = Q'D^{-1}Q on the matrix cores (each
 // wavefront accumulates 4-row chunks into one 16x16 tile).
-template <typename T>
+// Inc: only the last column u of Q is new since the previous setup on this
+// work area (G Q, G D^{-1} Q and K of the others are still in place): qq
+// receives the two vectors u and D^{-1}u instead, and the partials also
+// carry Q'D^{-1}u, the new row of K.
+constexpr int kIncK = 1 + kPipeQ;   // where Q'D^{-1}u starts in the Inc partials
+constexpr int kIncNV = 32;          // Inc partial row: [r'r, -Q'r (kPipeQ), Q'D^{-1}u (kPipeQ)]
+template <typename T, bool Inc>
 __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__restrict__ r, T *__restrict__ res,
                                                      T *__restrict__ t, const T *__restrict__ Q, int ldq, int q,
                                                      const T *__restrict__ dinv, T *__restrict__ qq,
@@ -308,25 +314,40 @@ __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__rest
         st->breakdown = 0;
     }
     const int q2 = 2 * q;
-    T acc[kPP];
+    constexpr int NP = Inc ? kIncNV : kPP;
+    T acc[NP];
 #pragma unroll
-    for (int j = 0; j < kPP; ++j) acc[j] = T(0);
+    for (int j = 0; j < NP; ++j) acc[j] = T(0);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const T ri = (T)r[i];
         const T di = dinv[i];
         res[i] = -ri;
         t[i] = T(0);
         acc[0] += ri * ri;
+        if constexpr (Inc) {
+            const T dui = di * Q[(size_t)i * ldq + (q - 1)];
+            qq[i] = Q[(size_t)i * ldq + (q - 1)];
+            qq[(size_t)n + i] = dui;
 #pragma unroll
-        for (int j = 0; j < kPipeQ; ++j)
-            if (j < q) {
-                const T qij = Q[(size_t)i * ldq + j];
-                acc[1 + j] -= qij * ri;
-                qq[(size_t)i * q2 + j] = qij;
-                qq[(size_t)i * q2 + q + j] = di * qij;
-            }
+            for (int j = 0; j < kPipeQ; ++j)
+                if (j < q) {
+                    const T qij = Q[(size_t)i * ldq + j];
+                    acc[1 + j] -= qij * ri;
+                    acc[kIncK + j] += qij * dui;
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPipeQ; ++j)
+                if (j < q) {
+                    const T qij = Q[(size_t)i * ldq + j];
+                    acc[1 + j] -= qij * ri;
+                    qq[(size_t)i * q2 + j] = qij;
+                    qq[(size_t)i * q2 + q + j] = di * qij;
+                }
+        }
     }
-    write_partials<T, kPP>(acc, q + 1, part_out);
+    write_partials<T, NP>(acc, Inc ? kIncK + q : q + 1, part_out);
+    if constexpr (Inc) return;
 
     using V4 = typename Mfma<T>::v4;
     V4 kc = V4{T(0), T(0), T(0), T(0)};
@@ -356,15 +377,23 @@ __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__rest
 
 // init2: K = sum of the Gram tiles (one wavefront per entry); r0 = ||r||,
 // c0 = -Q'r, stop if r = 0; res -= Q c0; yh = D^{-1} res;  partials res'yh, Q'yh
-template <typename T>
+template <typename T, bool Inc>
 __global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res, T *__restrict__ yh,
                                                      const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
                                                      int q, const T *__restrict__ part_in, int nb_in,
                                                      T *__restrict__ part_out, const T *__restrict__ kpart, int nk,
                                                      T *__restrict__ kmat, PcgState<T> *st) {
-    __shared__ T tot[kPP];
-    fold_partials<T, kPP>(part_in, nb_in, q + 1, tot);
-    {
+    constexpr int NP = Inc ? kIncNV : kPP;
+    __shared__ T tot[NP];
+    fold_partials<T, NP>(part_in, nb_in, Inc ? kIncK + q : q + 1, tot);
+    if constexpr (Inc) {
+        // the new row and column of K; the rest is unchanged
+        if (blockIdx.x == 0 && threadIdx.x < q) {
+            const T v = tot[kIncK + threadIdx.x];
+            kmat[threadIdx.x * 16 + (q - 1)] = v;
+            kmat[(q - 1) * 16 + threadIdx.x] = v;
+        }
+    } else {
         const int lane = lane_id();
         for (int e = blockIdx.x * kWavesPerBlock + wave_id(); e < 256; e += gridDim.x * kWavesPerBlock) {
             T sum = T(0);
@@ -400,6 +429,16 @@ __global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res,
         for (int j = 0; j < kPipeQ; ++j) acc[1 + j] += qv[j] * yi;
     }
     write_partials<T, kPP>(acc, q + 1, part_out);
+}
+
+// Inc setup: the two new columns of G [Q | D^{-1}Q] (row-major, 2q wide),
+// G u and G D^{-1}u, from the vectors u and D^{-1}u that init1 left in ud.
+template <typename T, bool Wt>
+__global__ __launch_bounds__(kBlock) void k_pp_gq2(Graph g, Weights<T> w, const T *__restrict__ ud, int q,
+                                                   T *__restrict__ gqq) {
+    const size_t q2 = 2 * (size_t)q;
+    for_each_row<T, Wt, false>(g, w, ud, [&](int i, T, T yi, T) { gqq[i * q2 + (q - 1)] = yi; });
+    for_each_row<T, Wt, false>(g, w, ud + g.n, [&](int i, T, T yi, T) { gqq[i * q2 + (2 * q - 1)] = yi; });
 }
 
 // init3: c_y = Q'yh;  u = yh - Q c_y;  w~ = (G - theta I) u, gathered as
@@ -657,7 +696,7 @@ void enqueue_nv(const lap_plan &P, const double *theta, const T *Q, int ldq, int
 
 template <typename T, int QM>
 void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
-                          PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
+                          PcgWork<T> &w, int itmax, double rtol, bool inc, hipStream_t s) {
     const int n = P.n;
     const int gv = vgrid(n);
     const int gr = row_grid(P.g, pcg_max_groups());
@@ -670,11 +709,25 @@ void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, in
     const T *dinv = P.dinv<T>();
     const T tol = (T)rtol;
     T *wh0 = w.wh.get(), *wh1 = wh0 + n;
-    hipLaunchKernelGGL((k_pp_init1<T>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q, dinv,
-                       w.qq.get(), pa, w.kpart.get(), st);
-    if (q > 0) spmm<T>(P, q2, w.qq.get(), q2, w.gqq.get(), q2, nullptr, s);
-    hipLaunchKernelGGL((k_pp_init2<T>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq, q, pa, gv,
-                       pb, w.kpart.get(), gv, w.kmat.get(), st);
+    if (inc) {
+        hipLaunchKernelGGL((k_pp_init1<T, true>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q,
+                           dinv, w.qq.get(), pa, w.kpart.get(), st);
+        const int grow = row_grid(P.g, 1 << 20);
+        if (P.weighted)
+            hipLaunchKernelGGL((k_pp_gq2<T, true>), dim3(grow), dim3(kBlock), 0, s, P.g, P.weights<T>(), w.qq.get(),
+                               q, w.gqq.get());
+        else
+            hipLaunchKernelGGL((k_pp_gq2<T, false>), dim3(grow), dim3(kBlock), 0, s, P.g, P.weights<T>(), w.qq.get(),
+                               q, w.gqq.get());
+        hipLaunchKernelGGL((k_pp_init2<T, true>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq,
+                           q, pa, gv, pb, w.kpart.get(), gv, w.kmat.get(), st);
+    } else {
+        hipLaunchKernelGGL((k_pp_init1<T, false>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q,
+                           dinv, w.qq.get(), pa, w.kpart.get(), st);
+        if (q > 0) spmm<T>(P, q2, w.qq.get(), q2, w.gqq.get(), q2, nullptr, s);
+        hipLaunchKernelGGL((k_pp_init2<T, false>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq,
+                           q, pa, gv, pb, w.kpart.get(), gv, w.kmat.get(), st);
+    }
     if (P.weighted)
         hipLaunchKernelGGL((k_pp_init3<T, true, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
                            w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
@@ -703,9 +756,9 @@ void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, in
 // Projectors of up to kNarrowQ columns take the narrow instantiation.
 template <typename T>
 void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
-                       PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
-    if (q <= kNarrowQ) enqueue_pipelined_qm<T, kNarrowQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, s);
-    else enqueue_pipelined_qm<T, kPipeQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, s);
+                       PcgWork<T> &w, int itmax, double rtol, bool inc, hipStream_t s) {
+    if (q <= kNarrowQ) enqueue_pipelined_qm<T, kNarrowQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, inc, s);
+    else enqueue_pipelined_qm<T, kPipeQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, inc, s);
 }
 
 // The one-launch form unless the projector is too wide for it (or the
@@ -755,7 +808,7 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
         LAP_HIP(hipMemcpyAsync(th.get(), theta_host + c, sizeof(double), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_gather_col, dim3(gv), dim3(kBlock), 0, s, n, R + (size_t)c * n, map, r.get());
         if (use_pipelined(q))
-            enqueue_pipelined<T>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
+            enqueue_pipelined<T>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, false, s);
         else if (q <= 14)
             enqueue_nv<T, 16>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
         else
@@ -774,19 +827,19 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
 
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc) {
     LAP_REQUIRE(q >= 0 && q <= kMaxQ, LAP_EUNSUPPORTED, "projector wider than 62 columns");
     if (use_pipelined(q))
-        enqueue_pipelined<T>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
+        enqueue_pipelined<T>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, inc && q >= 1, s);
     else if (q <= 14)
         enqueue_nv<T, 16>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
     else
         enqueue_nv<T, 64>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
 }
 template void pcg_enqueue<float>(const lap_plan &, const double *, const float *, int, int, const double *, float *,
-                                 PcgWork<float> &, int, double, hipStream_t);
+                                 PcgWork<float> &, int, double, hipStream_t, bool);
 template void pcg_enqueue<double>(const lap_plan &, const double *, const double *, int, int, const double *,
-                                  double *, PcgWork<double> &, int, double, hipStream_t);
+                                  double *, PcgWork<double> &, int, double, hipStream_t, bool);
 
 lap_status pcg_entry(lap_plan *P, lap_dtype dt, int b, const double *theta_host, const double *Q, int q,
                      const double *R, double *T, int itmax, double rtol, int *iters_out, int flags, hipStream_t s) {
