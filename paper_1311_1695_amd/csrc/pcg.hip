@@ -292,6 +292,7 @@ struct PLay {
     static constexpr int N = NV <= 16 ? 16 : 32;  // row stride (a power of two)
 };
 constexpr int kNarrowQ = 6;
+constexpr int kMidQ = 10;
 
 // init1: res = -r, t = 0, qq rows [Q_i | dinv_i Q_i]; partials r'r, -Q'r;
 // and this workgroup's share of K = Q'D^{-1}Q on the matrix cores (each
@@ -758,6 +759,7 @@ template <typename T>
 void enqueue_pipelined(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
                        PcgWork<T> &w, int itmax, double rtol, bool inc, hipStream_t s) {
     if (q <= kNarrowQ) enqueue_pipelined_qm<T, kNarrowQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, inc, s);
+    else if (q <= kMidQ) enqueue_pipelined_qm<T, kMidQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, inc, s);
     else enqueue_pipelined_qm<T, kPipeQ>(P, theta, Q, ldq, q, r, t, w, itmax, rtol, inc, s);
 }
 
