@@ -46,9 +46,12 @@ struct PcgState {
     int total;  // products of all solves since the host last cleared it
 };
 
-// Workgroups of one PCG launch (bounded so that folding the partial sums
-// of the previous launch stays cheap in every workgroup).
-inline int pcg_max_groups() { return 2 * device_cu_count(); }
+// Workgroups of one PCG launch, bounded so that folding the partial sums of
+// the previous launch stays cheap in every workgroup: at most four per
+// compute unit (the scratch areas are sized for that), two for the vector
+// kernels; the one-launch iteration takes as many as fit at once.
+inline int pcg_max_groups() { return 4 * device_cu_count(); }
+inline int pcg_vec_groups() { return 2 * device_cu_count(); }
 
 template <typename S>
 void jd_orth(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,

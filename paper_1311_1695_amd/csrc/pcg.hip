@@ -650,8 +650,22 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
 
 inline int vgrid(int n) {
     int g = (n + kBlock - 1) / kBlock;
-    const int cap = pcg_max_groups();
+    const int cap = pcg_vec_groups();
     return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
+// Row grid cap of the one-launch iteration: as many workgroups as its
+// register use lets every compute unit hold at once (at most four per unit),
+// so that large graphs keep enough waves in flight in a single round.
+template <typename T, bool Wt, int QM>
+int pp_iter_groups() {
+    static const int groups = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pp_iter<T, Wt, QM>, kBlock, 0) != hipSuccess || nb < 1)
+            nb = 2;
+        return std::min(nb, 4) * device_cu_count();
+    }();
+    return groups;
 }
 
 template <typename T, int NV>
@@ -659,7 +673,7 @@ void enqueue_nv(const lap_plan &P, const double *theta, const T *Q, int ldq, int
                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
     const int n = P.n;
     const int gv = vgrid(n);
-    const int gr = row_grid(P.g, pcg_max_groups());
+    const int gr = row_grid(P.g, pcg_vec_groups());
     LAP_REQUIRE(w.gq.n >= (size_t)n * ldq, LAP_EDEVICE, "PCG work area too small for the projector");
     T *pa = w.part.get();
     T *pb = pa + (size_t)pcg_max_groups() * 64;
@@ -700,7 +714,7 @@ void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, in
                           PcgWork<T> &w, int itmax, double rtol, bool inc, hipStream_t s) {
     const int n = P.n;
     const int gv = vgrid(n);
-    const int gr = row_grid(P.g, pcg_max_groups());
+    const int gr = row_grid(P.g, P.weighted ? pp_iter_groups<T, true, QM>() : pp_iter_groups<T, false, QM>());
     const int q2 = 2 * q;
     LAP_REQUIRE(w.qq.n >= (size_t)n * q2 && w.kpart.n >= (size_t)gv * 256, LAP_EDEVICE,
                 "PCG work area too small for the projector");
