@@ -1045,12 +1045,21 @@ inline int defer_grid(int n) {
     return g < 1 ? 1 : (g > kDeferRows ? kDeferRows : g);
 }
 
+// Grid of the Gram-Schmidt passes: streaming kernels that large vectors
+// want spread over more workgroups than a deferred fold of kDeferRows rows
+// allows; their partial rows (two workgroups per compute unit at most) are
+// folded by the next pass and the norm's consumer in every workgroup.
+inline int orth_grid(int n) {
+    const int g = (n + kBlock - 1) / kBlock, cap = std::max(kDeferRows, 2 * device_cu_count());
+    return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
 template <typename S, int NV>
 static void orth_nv(int n, const double *B, int nb, const S *src, double *v, ReduceScratch &rs, JDStatus *st,
                     hipStream_t s) {
-    const int grid = defer_grid(n);
+    const int grid = orth_grid(n);
     rs.ensure_deferred();
-    double *pa = rs.dpart.get(), *pb = pa + (size_t)kDeferRows * 64;
+    double *pa = rs.dpart.get(), *pb = pa + (size_t)rs.darea * 64;
     hipLaunchKernelGGL((k_orth1<S, NV>), dim3(grid), dim3(kBlock), 0, s, pa, n, B, nb, src, v);
     hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, pa, grid, pb, n, B, nb, v, st, 1, 0);
     hipLaunchKernelGGL((k_orth2<NV>), dim3(grid), dim3(kBlock), 0, s, pb, grid, pa, n, B, nb, v, st, 0, 1);
@@ -1091,7 +1100,7 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
         // partial rows only; the Rayleigh-Ritz launch folds them into H
         const int grid = defer_grid(n);
         rs.ensure_deferred();
-        double *pb = rs.dpart.get() + (size_t)kDeferRows * 64;
+        double *pb = rs.dpart.get() + (size_t)rs.darea * 64;
         if (m + 1 <= 16)
             hipLaunchKernelGGL((k_hborder_part<16>), dim3(grid), dim3(kBlock), 0, s, pb, n, V, m, wcol);
         else

@@ -27,6 +27,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <memory>
@@ -211,11 +212,14 @@ struct ReduceScratch {
     int max_blocks = 0;
     int max_values = 0;
     void ensure(int blocks, int values);
-    // Deferred sums: two areas of kDeferRows x 64 doubles for per-workgroup
-    // partial rows that the consuming launch folds (no fence, no counter).
-    // After jd_orth: the 1-value rows of ||v||^2; after jd_hborder (m + 1 <=
-    // kDeferBorderMax): the rows of the H border (stride border_ld).
+    // Deferred sums: two areas of darea x 64 doubles for per-workgroup
+    // partial rows that the consuming launch folds (no fence, no counter);
+    // darea = max(kDeferRows, 2 workgroups per compute unit).
+    // After jd_orth: the 1-value rows of ||v||^2 (first area); after
+    // jd_hborder (m + 1 <= kDeferBorderMax): the rows of the H border
+    // (second area, stride border_ld, at most kDeferRows rows).
     DevBuf<double> dpart;
+    int darea = 0;
     const double *norm_rows = nullptr;
     int norm_nrows = 0;
     const double *border_rows = nullptr;

@@ -231,7 +231,10 @@ template void permute_rows<float>(const int *, int, int, const float *, float *,
 template void permute_rows<double>(const int *, int, int, const double *, double *, hipStream_t);
 
 void ReduceScratch::ensure_deferred() {
-    if (!dpart.get()) dpart.alloc(2 * (size_t)kDeferRows * 64);
+    if (!dpart.get()) {
+        darea = std::max(kDeferRows, 2 * device_cu_count());
+        dpart.alloc(2 * (size_t)darea * 64);
+    }
 }
 
 void ReduceScratch::ensure(int blocks, int values) {
