@@ -57,6 +57,23 @@ def kernel_sources_sha(files=("pcg.hip", "lapeig_dev.h", "lapeig_internal.h")) -
     return h.hexdigest()[:16]
 
 
+def random_read_rate(n, count, reps=5):
+    """Random 4-byte reads per second that the device serves from a vector
+    of about n FP32 values (bench_gather.hip, built by __graft_entry__.build:
+    indices hashed in registers, no index stream, no locality), or None if
+    the helper is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "bench_gather.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.bench_random_reads.argtypes = [ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double)]
+    rate = ctypes.c_double(0.0)
+    rc = lib.bench_random_reads(n, count, reps, ctypes.byref(rate))
+    return rate.value if rc == 0 else None
+
+
 def time_spmv(lap, torch, plan, n, reps=200, dtype=None):
     """Average duration of the FP32 product kernel: `reps` back-to-back
     launches captured in a graph and replayed between two HIP events on the
@@ -411,10 +428,18 @@ def main():
         Lb = gg.workload(name, SEED)
         pb = lap.Plan(Lb)
         tb = time_spmv(lap, torch, pb, Lb.n, reps=200)
-        ab = spmv_bytes(Lb.n, Lb.nnz - Lb.n, 4)
+        nnz_a = Lb.nnz - Lb.n  # one neighbour gather per off-diagonal entry
+        ab = spmv_bytes(Lb.n, nnz_a, 4)
+        g_spmv = nnz_a / tb
+        # at least 16M reads per launch, so that the launch itself does not count
+        g_rand = random_read_rate(Lb.n, max(nnz_a, 1 << 24))
         large.append({"workload": name, "n": Lb.n, "nnz": Lb.nnz, "alg_bytes_per_launch": ab,
                       "avg_launch_us": round(tb * 1e6, 3), "GB/s": round(ab / tb / 1e9, 1),
-                      "frac": round(ab / tb / 1e9 / HBM_PEAK_GBS, 4)})
+                      "frac": round(ab / tb / 1e9 / HBM_PEAK_GBS, 4),
+                      "gathers_per_s": round(g_spmv / 1e9, 1),
+                      "random_read_rate_per_s": None if g_rand is None else round(g_rand / 1e9, 1),
+                      "frac_of_random_read_rate": None if g_rand is None else round(g_spmv / g_rand, 3),
+                      "gather_unit": "1e9 4-byte reads per second"})
         pb.close()
         del Lb
     out["spmv"]["large_graphs"] = large
