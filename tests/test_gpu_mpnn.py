@@ -95,6 +95,7 @@ def test_start_block_changes_iterations_not_the_answer():
     plans = [lap.Plan(L) for L in train]
     targets = [lap.lap_eigs(p, 10, 1e-6, evecs_on_device=True).evecs[1:].contiguous() for p in plans]
     net = lap.Mpnn(layers=2, hidden=32, random_channels=4, out_cols=9, seed=6)
+    untrained = lap.Mpnn(layers=2, hidden=32, random_channels=4, out_cols=9, seed=6)
     for step in range(200):
         g = step % len(plans)
         net.train_step(plans[g], targets[g], lr=3e-3, feature_seed=2)
@@ -105,6 +106,14 @@ def test_start_block_changes_iterations_not_the_answer():
     warm = lap.lap_eigs(plan, 10, 1e-8, precision="mixed", init=V0)
     print(f"held-out n={test_graph.n}: random start outer {cold.outer} mvp {cold.mvp}; "
           f"network start outer {warm.outer} mvp {warm.mvp}")
+    # what training gains on a graph it never saw: the block it proposes
+    # holds more of the true eigenspace (subspace loss 1 - ||X'Q||_F^2 / k)
+    # than the same network before training
+    X = lap.lap_eigs(plan, 10, 1e-8, evecs_on_device=True).evecs[1:].contiguous()
+    l_trained = net.loss_grad(plan, X, feature_seed=2, want_grad=False)[0]
+    l_untrained = untrained.loss_grad(plan, X, feature_seed=2, want_grad=False)[0]
+    print(f"held-out subspace loss: untrained {l_untrained:.4f}, trained {l_trained:.4f}")
+    assert l_trained < 0.85 * l_untrained
     assert cold.nconv == warm.nconv == 10
     assert np.allclose(cold.evals, warm.evals, rtol=1e-7, atol=1e-12)
     G = test_graph.to_scipy()
