@@ -150,10 +150,46 @@ struct Mfma<float> {
 // no atomics and no cache maintenance inside either kernel.
 constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : v <= 2 ? 2 : v <= 4 ? 4 : v <= 8 ? 8 : v <= 16 ? 16 : v <= 32 ? 32 : 64; }
 
+// x of lane (lane ^ M) for M = 1, 2, 4, 8 by data-parallel moves on the
+// vector ALU (quad permutations for 1 and 2; for 4 the row shifted by four
+// lanes one way or the other by lane bit 2; for 8 the 16-lane row rotated
+// by eight), 16 and 32 through the LDS crossbar (ds_bpermute).  The partner
+// is the same either way, so results do not depend on the route.  Every
+// lane of the wavefront must be active.
+template <int M>
+__device__ __forceinline__ int lane_xor32(int x) {
+    if constexpr (M == 1) {
+        return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+    } else if constexpr (M == 2) {
+        return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+    } else if constexpr (M == 4) {
+        const int from_up = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xF, 0xF, false);  // row_shl:4
+        const int from_dn = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+        return (threadIdx.x & 4) ? from_dn : from_up;
+    } else {
+        static_assert(M == 8, "M must be 1, 2, 4 or 8");
+        return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    }
+}
+template <int M, typename T>
+__device__ __forceinline__ T lane_xor(T v) {
+    if constexpr (M >= 16) {
+        return __shfl_xor(v, M, kWave);
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, lane_xor32<M>(__builtin_bit_cast(int, v)));
+    } else {
+        static_assert(sizeof(T) == 8, "4- or 8-byte types only");
+        const long long b = __builtin_bit_cast(long long, v);
+        const unsigned lo = (unsigned)lane_xor32<M>((int)b), hi = (unsigned)lane_xor32<M>((int)(b >> 32));
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)hi << 32) | lo));
+    }
+}
+
 // Reduce-scatter of NV per-lane values over the wavefront (NV a power of
 // two): each butterfly step trades half of the remaining values with the
 // partner lane, so NV values cost NV - 1 + log2(64 / NV) shuffles instead of
-// 6 NV.  Afterwards v[0] holds the wavefront total of value idx, where idx
+// 6 NV (the four lowest steps move data on the vector ALU, lane_xor).
+// Afterwards v[0] holds the wavefront total of value idx, where idx
 // collects the halving bits of the lane; lanes that agree on them hold the
 // same total, and every total is added in one fixed order.
 template <typename T, int NV, int CNT, int M>
@@ -166,12 +202,12 @@ __device__ __forceinline__ void rs_step(T (&v)[NV], int lane, int &idx) {
             for (int i = 0; i < half; ++i) {
                 const T keep = up ? v[half + i] : v[i];
                 const T give = up ? v[i] : v[half + i];
-                v[i] = keep + __shfl_xor(give, M, kWave);
+                v[i] = keep + lane_xor<M>(give);
             }
             if (up) idx += half;
             rs_step<T, NV, half, M / 2>(v, lane, idx);
         } else {
-            v[0] += __shfl_xor(v[0], M, kWave);
+            v[0] += lane_xor<M>(v[0]);
             rs_step<T, NV, 1, M / 2>(v, lane, idx);
         }
     }
