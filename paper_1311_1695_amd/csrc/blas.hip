@@ -505,6 +505,11 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, bool zid, do
 // Output: theta ascending (ties by index), Y column-major (ld = ldy).
 // ---------------------------------------------------------------------------
 constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
+// Threads of the Rayleigh-Ritz launch above 32 columns: two wavefronts per
+// SIMD hide each other's LDS latency in the rounds (m = 60: 1.68 -> 1.10 ms
+// against four wavefronts), and the register budget of 2 per SIMD leaves
+// the one-wavefront arrowhead path unspilled.
+constexpr int kRRThreads = 512;
 
 // The last column of H from the border kernel's partial rows (brows <= 4 x 64
 // rows, stride bld, m <= kDeferBorderMax values wanted) in one wavefront:
@@ -526,7 +531,26 @@ __device__ void fold_border_rows(const double *__restrict__ bpart, int brows, in
     if ((lane_id() & (kWave / kDeferBorderMax - 1)) == 0 && idx < m) hcol[idx] = acc[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, double *__restrict__ theta,
+// One 2x2 block of a Jacobi round, A(pk, pl) with pair k's rows and pair l's
+// columns: the row rotation of k, then the column rotation of l (the same
+// operations in the same order as a rows pass followed by a columns pass);
+// on the rotated pair's own block (k == l) the off-diagonal entries are 0.
+__device__ __forceinline__ void rotate_block(double sk, double ck, double sl, double cl, bool own, double &apr,
+                                             double &apc, double &aqr, double &aqc) {
+    if (sk != 0.0) {
+        const double npr = ck * apr - sk * aqr, nqr = sk * apr + ck * aqr;
+        const double npc = ck * apc - sk * aqc, nqc = sk * apc + ck * aqc;
+        apr = npr; aqr = nqr; apc = npc; aqc = nqc;
+    }
+    if (sl != 0.0) {
+        const double npr = cl * apr - sl * apc, npc = sl * apr + cl * apc;
+        const double nqr = cl * aqr - sl * aqc, nqc = sl * aqr + cl * aqc;
+        apr = npr; apc = npc; aqr = nqr; aqc = nqc;
+    }
+    if (own) { apc = 0.0; aqr = 0.0; }
+}
+
+__global__ __launch_bounds__(kRRThreads) void k_rr_eig(int m, double *Hin, int ldh, double *__restrict__ theta,
                                                    double *__restrict__ Y, int ldy, int mprev, JDStatus *st,
                                                    const double *__restrict__ bpart, int brows, int bld) {
     extern __shared__ double lds[];
@@ -655,7 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
         __syncthreads();
     }
     {
-        __shared__ double wsum[kWavesPerBlock];
+        __shared__ double wsum[kRRThreads / kWave];
         double f = 0.0;
         for (int t = tid; t < me * me; t += blockDim.x) f += A[t] * A[t];
         f = wave_sum(f);
@@ -670,19 +694,13 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
     }
     const double tol = 2.220446049250313e-16 * sqrt(fro2) / (double)me;
     const int half = me / 2;
-    // items of the rotation phase, walked with a stride of blockDim.x in
-    // row-major order of (k, l) over half x half and of (i, k) over me x half
-    const int k0 = tid / half, l0 = tid % half;
-    const int dk = (int)blockDim.x / half, dl = (int)blockDim.x % half;
-    const int i0 = tid / half, kz0 = tid % half;
-    const int di = dk, dkz = dl;
     int sweeps = 0;
     for (; sweeps < 60 && me > 1; ++sweeps) {
         // A sweep rotates exactly the pairs with |a_pq| > tol, so when no
         // off-diagonal entry exceeds tol it would change nothing: stop here
         // instead of running it.
         {
-            __shared__ double wmax[kWavesPerBlock];
+            __shared__ double wmax[kRRThreads / kWave];
             double mx = 0.0;
             for (int t = tid; t < me * me; t += blockDim.x)
                 if (t / me < t % me) mx = fmax(mx, fabs(A[t]));
@@ -732,33 +750,47 @@ __global__ __launch_bounds__(kBlock) void k_rr_eig(int m, double *Hin, int ldh, 
             // applies the row rotation of k and then the column rotation of l
             // to its block, the same operations in the same order as a rows
             // pass followed by a columns pass.  Z <- ZJ likewise by (row, pair).
-            for (int k = k0, l = l0; k < half; k += dk, l += dl) {
-                if (l >= half) { l -= half; ++k; if (k >= half) break; }
-                const double sk = sn[k], sl = sn[l], ck = cs[k], cl = cs[l];
-                const int p = pp[k], q = qq[k], r = pp[l], c2 = qq[l];
-                if (sk == 0.0 && sl == 0.0) continue;
-                double apr = A[p * me + r], apc = A[p * me + c2], aqr = A[q * me + r], aqc = A[q * me + c2];
-                if (sk != 0.0) {
-                    const double npr = ck * apr - sk * aqr, nqr = sk * apr + ck * aqr;
-                    const double npc = ck * apc - sk * aqc, nqc = sk * apc + ck * aqc;
-                    apr = npr; aqr = nqr; apc = npc; aqc = nqc;
+            // Items e = tid, tid + blockDim.x, ... in pairs: both items'
+            // parameters and entries are read before either is computed, so
+            // a thread waits for LDS once per pair of items.
+            const int nA = half * half, nZ = me * half, bd = (int)blockDim.x;
+            for (int e = tid; e < nA; e += 2 * bd) {
+                const int e2 = e + bd;
+                const bool two = e2 < nA;
+                const int ka = e / half, la = e - ka * half;
+                const int kb = two ? e2 / half : ka, lb = two ? e2 - kb * half : la;
+                const double ska = sn[ka], sla = sn[la], cka = cs[ka], cla = cs[la];
+                const double skb = sn[kb], slb = sn[lb], ckb = cs[kb], clb = cs[lb];
+                const int pa = pp[ka], qa = qq[ka], ra = pp[la], ca = qq[la];
+                const int pb = pp[kb], qb = qq[kb], rb = pp[lb], cb = qq[lb];
+                double a0 = A[pa * me + ra], a1 = A[pa * me + ca], a2 = A[qa * me + ra], a3 = A[qa * me + ca];
+                double b0 = A[pb * me + rb], b1 = A[pb * me + cb], b2 = A[qb * me + rb], b3 = A[qb * me + cb];
+                if (!(ska == 0.0 && sla == 0.0)) {
+                    rotate_block(ska, cka, sla, cla, ka == la, a0, a1, a2, a3);
+                    A[pa * me + ra] = a0; A[pa * me + ca] = a1; A[qa * me + ra] = a2; A[qa * me + ca] = a3;
                 }
-                if (sl != 0.0) {
-                    const double npr = cl * apr - sl * apc, npc = sl * apr + cl * apc;
-                    const double nqr = cl * aqr - sl * aqc, nqc = sl * aqr + cl * aqc;
-                    apr = npr; apc = npc; aqr = nqr; aqc = nqc;
+                if (two && !(skb == 0.0 && slb == 0.0)) {
+                    rotate_block(skb, ckb, slb, clb, kb == lb, b0, b1, b2, b3);
+                    A[pb * me + rb] = b0; A[pb * me + cb] = b1; A[qb * me + rb] = b2; A[qb * me + cb] = b3;
                 }
-                if (k == l) { apc = 0.0; aqr = 0.0; }  // the rotated pair's own entries
-                A[p * me + r] = apr; A[p * me + c2] = apc; A[q * me + r] = aqr; A[q * me + c2] = aqc;
             }
-            for (int i = i0, k = kz0; i < me; i += di, k += dkz) {
-                if (k >= half) { k -= half; ++i; if (i >= me) break; }
-                const double sk = sn[k], ck = cs[k];
-                const int p = pp[k], q = qq[k];
-                if (sk == 0.0) continue;
-                const double zp = Z[i * me + p], zq = Z[i * me + q];
-                Z[i * me + p] = ck * zp - sk * zq;
-                Z[i * me + q] = sk * zp + ck * zq;
+            for (int e = tid; e < nZ; e += 2 * bd) {
+                const int e2 = e + bd;
+                const bool two = e2 < nZ;
+                const int ia = e / half, ka = e - ia * half;
+                const int ib = two ? e2 / half : ia, kb = two ? e2 - ib * half : ka;
+                const double ska = sn[ka], cka = cs[ka], skb = sn[kb], ckb = cs[kb];
+                const int pa = pp[ka], qa = qq[ka], pb = pp[kb], qb = qq[kb];
+                const double zpa = Z[ia * me + pa], zqa = Z[ia * me + qa];
+                const double zpb = Z[ib * me + pb], zqb = Z[ib * me + qb];
+                if (ska != 0.0) {
+                    Z[ia * me + pa] = cka * zpa - ska * zqa;
+                    Z[ia * me + qa] = ska * zpa + cka * zqa;
+                }
+                if (two && skb != 0.0) {
+                    Z[ib * me + pb] = ckb * zpb - skb * zqb;
+                    Z[ib * me + qb] = skb * zpb + ckb * zqb;
+                }
             }
             __syncthreads();
         }
@@ -1126,9 +1158,10 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
 }
 
 void jd_rr(int m, double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
-           int mprev, const ReduceScratch *border) {
+           int mprev, const ReduceScratch *border, bool wide) {
     const double *bpart = border ? border->border_rows : nullptr;
     LAP_REQUIRE(!bpart || m <= kDeferBorderMax, LAP_EDEVICE, "border partial rows for too large an H");
+    LAP_REQUIRE(!bpart || !wide, LAP_EDEVICE, "border partial rows are folded by the one-wavefront launch only");
     LAP_REQUIRE(m >= 1 && m <= kRRMax, LAP_EUNSUPPORTED, "projected matrix larger than 96");
     const int me = (m + 1) & ~1;
     const size_t lds = 2 * (size_t)me * me * sizeof(double);
@@ -1138,9 +1171,9 @@ void jd_rr(int m, double *H, int ldh, double *theta, double *Y, int ldy, JDStatu
                                     2 * kRRMax * kRRMax * (int)sizeof(double)));
         attr_set = true;
     }
-    // up to 32 columns a single wavefront does it: every barrier of the
-    // round-by-round rotations is then nearly free
-    const int threads = me <= 32 ? kWave : kBlock;
+    // up to 32 columns a single wavefront does it (every barrier of the
+    // round-by-round rotations is then nearly free), above it kRRThreads
+    const int threads = me <= 32 && !wide ? kWave : kRRThreads;
     hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(threads), lds, s, m, H, ldh, theta, Y, ldy, mprev, st, bpart,
                        bpart ? border->border_nrows : 0, bpart ? border->border_ld : 0);
     LAP_HIP(hipGetLastError());

@@ -197,7 +197,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
     // SVQB of Vn's `cur` columns; result into dest (ld); returns the kept count
     auto svqb = [&](int cur, double rel, double abs_thr, double *dest, int lddest) -> int {
         ts_tn<double>(n, Vn.get(), b, cur, Vn.get(), b, cur, S.get(), b, nullptr, 0, 1.0, bs, s);
-        jd_rr(cur, S.get(), b, Sth.get(), Sz.get(), b, nullptr, s);
+        jd_rr(cur, S.get(), b, Sth.get(), Sz.get(), b, nullptr, s, 0, nullptr, true);
         blk_svqb(cur, Sth.get(), Sz.get(), b, rel, abs_thr, M.get(), b, bst.get(), s);
         LAP_HIP(hipMemcpyAsync(hb.h, bst.get(), sizeof(BlockStatus), hipMemcpyDeviceToHost, s));
         if (pcg_pending) LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
@@ -247,7 +247,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         int bu = 0;
         for (;;) {
             // warm start when theta and Y still diagonalize the leading block
-            jd_rr(m, H.get(), ldh, theta.get(), Y.get(), mmax, nullptr, s, y_rows < m ? y_rows : 0);
+            jd_rr(m, H.get(), ldh, theta.get(), Y.get(), mmax, nullptr, s, y_rows < m ? y_rows : 0, nullptr, true);
             y_rows = m;
             Vb = XV.get() + nx;
             bu = std::min(std::min(b, m), k - nx);

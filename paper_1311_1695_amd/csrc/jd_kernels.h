@@ -68,9 +68,10 @@ void jd_hborder(int n, const double *V, int m, const double *wcol, double *H, in
 // since (warm start); 0: none.  border: the partial rows that jd_hborder
 // left for the last column of H, folded (and written to H) first, or null
 // (then H is only read).  st->rr_sweeps: -1 after the secular-equation
-// path, else the Jacobi sweeps.
+// path, else the Jacobi sweeps.  wide: H is not an arrowhead (block JD), so
+// even m <= 32 takes the many-wavefront Jacobi launch.
 void jd_rr(int m, double *H, int ldh, double *theta, double *Y, int ldy, JDStatus *st, hipStream_t s,
-           int mprev = 0, const ReduceScratch *border = nullptr);
+           int mprev = 0, const ReduceScratch *border = nullptr, bool wide = false);
 template <typename T>
 void jd_ritz(int n, const double *V, const double *W, int m, const double *Y, const double *theta, double *u,
              double *r, T *Q, int ldq, int qcol, ReduceScratch &rs, JDStatus *st, hipStream_t s,
