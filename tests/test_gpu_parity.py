@@ -315,6 +315,40 @@ def test_eigs_cl30k_vs_oracle_jd(precision):
     check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
 
 
+@functools.lru_cache(maxsize=None)
+def cl330k_block_fp64():
+    """The 8 smallest pairs of the 330k-vertex graph by block JD (b = 8, FP64)."""
+    L = graph("cl330k")
+    r = lap.lap_eigs(lap.Plan(L), 8, 1e-8, precision="fp64", block=8, m_min=8, m_max=24)
+    return r
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_eigs_large_graph_at_full_size(precision):
+    """The Chung-Lu graph of 330k vertices (n = 297,292 after the largest
+    component), full size, in the launch configuration of the bench (its
+    product grid, the Gram-Schmidt grid and the PCG grid all exceed what the
+    smaller graphs use).  Too large for the oracle's JD, so it is checked by
+    what holds at any size: residuals recomputed on the host within the
+    tolerance, orthonormal eigenvectors, the zero pair, and the eigenvalues
+    of single-vector JD in this precision against those of block JD in FP64,
+    two independent paths (each certified value lies within its residual,
+    1e-8 lambda, of an eigenvalue)."""
+    L = graph("cl330k")
+    plan = lap.Plan(L)
+    r = lap.lap_eigs(plan, 8, 1e-8, precision=precision)
+    assert r.nconv == 8 and r.ncomp == 1
+    _certified(L, r, 1e-8)
+    assert abs(r.evals[0]) <= 1e-12
+    x0 = r.evecs[:, 0]
+    assert np.allclose(np.abs(x0), 1.0 / np.sqrt(L.n), rtol=0, atol=1e-10)
+    assert np.all(np.diff(r.evals) >= 0)
+    b = cl330k_block_fp64()
+    assert b.nconv == 8
+    _certified(L, b, 1e-8)
+    assert np.allclose(r.evals, b.evals, rtol=2e-8, atol=1e-13), (r.evals, b.evals)
+
+
 def test_eigs_weighted_vs_oracle_jd():
     L = graph("cl30k_w")
     plan = lap.Plan(L)
