@@ -423,7 +423,7 @@ def main():
                    "avg_launch_us": round(t_spmv * 1e6, 3)}
     # the same product on the large power-law graphs of the other workloads,
     # where it moves tens of megabytes per launch instead of under one
-    large = []
+    large, pcg_large = [], []
     for name in ("cl330k", "cl1m_tc"):
         Lb = gg.workload(name, SEED)
         pb = lap.Plan(Lb)
@@ -440,9 +440,20 @@ def main():
                       "random_read_rate_per_s": None if g_rand is None else round(g_rand / 1e9, 1),
                       "frac_of_random_read_rate": None if g_rand is None else round(g_spmv / g_rand, 3),
                       "gather_unit": "1e9 4-byte reads per second"})
+        # the dominant kernel at the same sizes: one pipelined PCG iteration,
+        # q = 10, FP32, timed as in the roofline leg
+        try:
+            tp = time_pcg_iteration(lap, torch, np, pb, Lb.n, q=PCG_Q)
+            ap = pcg_iter_bytes(Lb.n, nnz_a, PCG_Q)
+            pcg_large.append({"workload": name, "n": Lb.n, "q": PCG_Q, "alg_bytes_per_launch": ap,
+                              "avg_launch_us": round(tp * 1e6, 3), "GB/s": round(ap / tp / 1e9, 1),
+                              "frac": round(ap / tp / 1e9 / HBM_PEAK_GBS, 4)})
+        except AssertionError:  # an FP32 breakdown ended a timing call early
+            pcg_large.append({"workload": name, "n": Lb.n, "q": PCG_Q, "avg_launch_us": None})
         pb.close()
         del Lb
     out["spmv"]["large_graphs"] = large
+    out["pcg_large_graphs"] = {"kernel": "k_pp_iter<float> (one projected PCG iteration)", "runs": pcg_large}
     if args.extra:
         out["configs"] = extra_configs(lap, torch, gg, np)
     if args.warmstart:
