@@ -187,33 +187,6 @@ __device__ __forceinline__ int lane_val(int x, int l) { return __builtin_amdgcn_
 
 constexpr int kArrowMax = 32;  // largest arrowhead of the secular-equation path
 
-// x of lane (lane ^ M), M = 1, 2 or 4, by data-parallel primitives (no LDS
-// round trip): quad permutations for 1 and 2; for 4, the row shifted by four
-// lanes one way or the other, by the lane's bit 2.  All lanes involved must
-// be active.
-template <int M>
-__device__ __forceinline__ double xor_lane(double x) {
-    const long long b = __double_as_longlong(x);
-    int lo = (int)b, hi = (int)(b >> 32);
-    if constexpr (M == 1) {
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
-    } else if constexpr (M == 2) {
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
-    } else {
-        static_assert(M == 4, "M must be 1, 2 or 4");
-        const int lo_up = __builtin_amdgcn_update_dpp(0, lo, 0x104, 0xF, 0xF, false);  // row_shl:4
-        const int hi_up = __builtin_amdgcn_update_dpp(0, hi, 0x104, 0xF, 0xF, false);
-        const int lo_dn = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xF, 0xF, false);  // row_shr:4
-        const int hi_dn = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xF, 0xF, false);
-        const bool up = (threadIdx.x & 4) != 0;
-        lo = up ? lo_dn : lo_up;
-        hi = up ? hi_dn : hi_up;
-    }
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 // ---------------------------------------------------------------------------
 // Eigenpairs of an arrowhead matrix A = [diag(d) b; b' c] (m x m, n = m - 1
 // poles), the form the projected matrix takes in every Rayleigh-Ritz step of
@@ -327,9 +300,9 @@ __device__ bool arrow_rr(int m, int me, double *A, const double *Z, bool zid, do
     const int G = 1 << lg;
     const int g = lane >> lg, sub = lane & (G - 1);
     auto group_sum = [&](double v) {
-        v += xor_lane<1>(v);
-        if (G >= 4) v += xor_lane<2>(v);
-        if (G >= 8) v += xor_lane<4>(v);
+        v += lane_xor<1>(v);
+        if (G >= 4) v += lane_xor<2>(v);
+        if (G >= 8) v += lane_xor<4>(v);
         return v;
     };
     bool ok = true;
