@@ -230,7 +230,7 @@ lap_status lap_pcg(lap_plan *plan, lap_dtype dtype, int b, const double *theta,
                    double rtol, int *iters_out, int flags, void *stream);
 
 /* Many independent graphs at once (the batched form of Algorithm 2): one
- * persistent launch, captured in a hipGraph, in which each 512-thread
+ * persistent launch, captured in a hipGraph, in which each 1024-thread
  * workgroup runs the whole single-vector solver for one graph with all its
  * reductions in LDS, taking graphs largest first from a device queue.
  * Each graph is validated as in lap_plan_create and must be connected

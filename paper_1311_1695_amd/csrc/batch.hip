@@ -1,6 +1,6 @@
 // Batched Jacobi-Davidson: many independent graphs in one persistent launch.
 //
-// One 512-thread workgroup runs the whole of Algorithm 2 for one graph
+// One 1024-thread workgroup runs the whole of Algorithm 2 for one graph
 // (orthogonalization, the MVP, the H border, eig(H), Ritz pair,
 // certificate, deflation, restart and the projected PCG), with every
 // reduction inside the workgroup (wavefront shuffles + LDS), so workgroups
@@ -19,7 +19,7 @@ namespace lapeig {
 
 namespace {
 
-constexpr int kBT = 512;             // threads per workgroup
+constexpr int kBT = 1024;            // threads per workgroup
 constexpr int kBW = kBT / kWave;     // wavefronts per workgroup
 constexpr int kBM = kBatchMaxM;      // largest basis (m_max)
 constexpr int kBK = kBatchMaxK;      // largest k
