@@ -12,6 +12,8 @@
 // Precision as in the single-graph solver: FP32 products and PCG in mixed
 // mode, FP64 for W = GV, orthogonalization, H, Ritz pairs and certificates.
 // Graphs are connected (checked on the host), so the zero pair is e/sqrt(n).
+// The launch takes all the LDS a workgroup may have; the PCG direction, the
+// vector every inner product gathers from, lives there when the graph fits.
 #include "lapeig_dev.h"
 #include "batch_kernels.h"
 
@@ -198,7 +200,7 @@ __device__ __forceinline__ double splitmix_b(unsigned long long seed, unsigned l
 }
 
 template <typename T, bool WT>
-__device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh) {
+__device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
     const BGraph G = a.graphs[gid];
     const int n = G.n, k = G.k, tid = threadIdx.x;
     const int mmax = a.m_max, mmin = a.m_min;
@@ -215,6 +217,8 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh) {
     T *Q = wt;                            // n x k row-major
     T *t = Q + (size_t)n * k;
     T *res = t + n, *p = res + n, *s = p + n, *y = s + n;
+    // the PCG direction, which every product gathers from, stays in LDS when it fits
+    if (n <= a.lds_elems) p = lds;
     double lam[kBK], rlock[kBK];
     // zero pair: e / sqrt(n) (connected graph)
     const double e0 = 1.0 / sqrt((double)n);
@@ -577,6 +581,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh) {
 template <typename T, bool WT>
 __global__ __launch_bounds__(kBT) void k_batch_jd(BatchArgs a) {
     __shared__ Shared sh;
+    extern __shared__ __align__(16) unsigned char batch_lds[];
     for (;;) {
         if (threadIdx.x == 0)
             sh.job = (int)__hip_atomic_fetch_add(a.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -584,7 +589,7 @@ __global__ __launch_bounds__(kBT) void k_batch_jd(BatchArgs a) {
         const int job = sh.job;
         __syncthreads();
         if (job >= a.ngraphs) break;
-        solve_graph<T, WT>(a, a.order[job], sh);
+        solve_graph<T, WT>(a, a.order[job], sh, reinterpret_cast<T *>(batch_lds));
     }
 }
 
@@ -594,14 +599,38 @@ __global__ void k_batch_reset(unsigned *queue) {
 
 }  // namespace
 
+namespace {
+
+// Launches k on all of the LDS that one workgroup may have beyond the
+// kernel's static arrays (the PCG direction of graphs that fit goes there).
+template <typename T, bool WT>
+void launch_jd(BatchArgs a, int grid, hipStream_t s) {
+    auto *k = k_batch_jd<T, WT>;
+    int dev = 0, max_lds = 0;
+    hipFuncAttributes fa{};
+    size_t dyn = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k)) == hipSuccess && max_lds > (int)fa.sharedSizeBytes)
+        dyn = ((size_t)max_lds - fa.sharedSizeBytes) & ~(size_t)15;
+    if (dyn > 0 && hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)dyn) != hipSuccess)
+        dyn = 0;
+    (void)hipGetLastError();  // a failed query leaves the global-memory path
+    a.lds_elems = (int)(dyn / sizeof(T));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kBT), dyn, s, a);
+}
+
+}  // namespace
+
 void batch_launch(const BatchArgs &a, bool mixed, bool weighted, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a.queue);
     if (mixed) {
-        if (weighted) hipLaunchKernelGGL((k_batch_jd<float, true>), dim3(grid), dim3(kBT), 0, s, a);
-        else hipLaunchKernelGGL((k_batch_jd<float, false>), dim3(grid), dim3(kBT), 0, s, a);
+        if (weighted) launch_jd<float, true>(a, grid, s);
+        else launch_jd<float, false>(a, grid, s);
     } else {
-        if (weighted) hipLaunchKernelGGL((k_batch_jd<double, true>), dim3(grid), dim3(kBT), 0, s, a);
-        else hipLaunchKernelGGL((k_batch_jd<double, false>), dim3(grid), dim3(kBT), 0, s, a);
+        if (weighted) launch_jd<double, true>(a, grid, s);
+        else launch_jd<double, false>(a, grid, s);
     }
     LAP_HIP(hipGetLastError());
 }

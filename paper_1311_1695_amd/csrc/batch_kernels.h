@@ -37,6 +37,7 @@ struct BatchArgs {
     int m_min, m_max, itmax, kmax;
     double tol, rtol_pcg;
     unsigned long long seed;
+    int lds_elems;           // PCG elements the launch's dynamic LDS holds (set by batch_launch)
 };
 
 void batch_launch(const BatchArgs &a, bool mixed, bool weighted, int grid, hipStream_t s);
