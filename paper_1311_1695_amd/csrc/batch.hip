@@ -13,7 +13,7 @@
 // mode, FP64 for W = GV, orthogonalization, H, Ritz pairs and certificates.
 // Graphs are connected (checked on the host), so the zero pair is e/sqrt(n).
 // The launch takes all the LDS a workgroup may have; the PCG direction, the
-// vector every inner product gathers from, lives there when the graph fits.
+// vector every inner product gathers from, lives there as far as it fits.
 #include "lapeig_dev.h"
 #include "batch_kernels.h"
 
@@ -74,10 +74,21 @@ struct GView {
     const double *w64;
 };
 
+// The PCG direction: entries [0, cap) in the workgroup's LDS, the rest in the
+// graph's workspace.  Vertices come in decreasing degree, so the LDS part
+// takes the entries that the products gather most often.
+template <typename T>
+struct SplitVec {
+    T *lds, *mem;
+    int cap;
+    __device__ __forceinline__ T &operator[](int i) const { return i < cap ? lds[i] : mem[i]; }
+};
+
 // y_i = sum_j w_ij (x_i - x_j) for the rows of one graph: rows [0, nlong)
 // one wavefront each, the rest one thread each.  f(i, x_i, y_i, q_i).
-template <typename T, bool WT, bool QF, class F>
-__device__ void wg_rows(const GView &g, const T *__restrict__ x, F &&f) {
+// x: a pointer, or any vector with operator[] (the split PCG direction)
+template <typename T, bool WT, bool QF, class X, class F>
+__device__ void wg_rows(const GView &g, const X &x, F &&f) {
     const int lane = lane_id();
     for (int r = wave_id(); r < g.nlong; r += kBW) {
         const T xi = x[r];
@@ -217,8 +228,8 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
     T *Q = wt;                            // n x k row-major
     T *t = Q + (size_t)n * k;
     T *res = t + n, *p = res + n, *s = p + n, *y = s + n;
-    // the PCG direction, which every product gathers from, stays in LDS when it fits
-    if (n <= a.lds_elems) p = lds;
+    // the PCG direction, which every product gathers from, in LDS as far as it fits
+    const SplitVec<T> pv{lds, p, n < a.lds_elems ? n : a.lds_elems};
     double lam[kBK], rlock[kBK];
     // zero pair: e / sqrt(n) (connected graph)
     const double e0 = 1.0 / sqrt((double)n);
@@ -473,7 +484,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
 #pragma unroll
                 for (int j = 0; j < kBK; ++j)
                     if (j < q) proj += Q[(size_t)i * k + j] * c1[j];
-                p[i] = y[i] - proj;
+                pv[i] = y[i] - proj;
             }
             __syncthreads();
             int its = 0;
@@ -483,7 +494,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 T a1[kBK], pa = T(0);
 #pragma unroll
                 for (int j = 0; j < kBK; ++j) a1[j] = T(0);
-                wg_rows<T, WT, false>(gv, p, [&](int i, T pi, T yi, T) {
+                wg_rows<T, WT, false>(gv, pv, [&](int i, T pi, T yi, T) {
                     const T si = yi - th * pi;
                     s[i] = si;
                     pa += pi * si;
@@ -504,7 +515,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 ++mvp;
                 if (!(pap > T(0))) {
                     if (pit == 1)
-                        for (int i = tid; i < n; i += kBT) t[i] = p[i];
+                        for (int i = tid; i < n; i += kBT) t[i] = pv[i];
                     its = pit;
                     __syncthreads();
                     break;
@@ -516,7 +527,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
 #pragma unroll
                     for (int j = 0; j < kBK; ++j)
                         if (j < q) proj += Q[(size_t)i * k + j] * c2[j];
-                    t[i] += alpha * p[i];
+                    t[i] += alpha * pv[i];
                     res[i] -= alpha * (s[i] - proj);
                 }
                 __syncthreads();
@@ -542,7 +553,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
 #pragma unroll
                     for (int j = 0; j < kBK; ++j)
                         if (j < q) proj += Q[(size_t)i * k + j] * c1[j];
-                    p[i] = (y[i] - proj) + beta * p[i];
+                    pv[i] = (y[i] - proj) + beta * pv[i];
                 }
                 __syncthreads();
             }

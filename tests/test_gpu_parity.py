@@ -531,10 +531,11 @@ def test_batch_weighted_and_reuse():
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_batch_direction_in_lds_and_in_memory(precision):
-    # the PCG direction of a graph stays in the workgroup's LDS when it fits
-    # (about 37k vertices in FP32, 18k in FP64 on a 160 KB part): a 42k-vertex
-    # graph takes the global-memory path in both precisions, a 3k-vertex one
-    # the LDS path, in the same launch; both against the single-graph solver
+    # the PCG direction of a graph lives in the workgroup's LDS as far as it
+    # fits (about 37k vertices in FP32, 18k in FP64 on a 160 KB part), the
+    # rest in memory: a 42k-vertex graph splits it in both precisions, a
+    # 3k-vertex one keeps it whole in LDS, in the same launch; both against
+    # the single-graph solver
     graphs = gg.pa_batch(1, 4242, n_lo=42000, n_hi=42000, ms=(2,)) + gg.pa_batch(1, 4243, n_lo=3000, n_hi=3000, ms=(3,))
     assert graphs[0].n > 160 * 1024 // 4
     out = lap.lap_eigs_batch(graphs, 5, 1e-8, precision=precision)
