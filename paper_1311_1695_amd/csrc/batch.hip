@@ -84,6 +84,34 @@ struct SplitVec {
     __device__ __forceinline__ T &operator[](int i) const { return i < cap ? lds[i] : mem[i]; }
 };
 
+// Visits this thread's rows i = tid, tid + kBT, ... in that order: ld(i)
+// loads a row's operands, op(i, loaded) uses them.  With 4-byte T two rows
+// go at a time (both loads in flight together); FP64 operands take one row
+// per step, since two would not fit the 128-register budget.
+template <typename T, class Ld, class Op>
+__device__ __forceinline__ void row_pass(int n, Ld &&ld, Op &&op) {
+    if constexpr (sizeof(T) == 4) {
+        for (int i = threadIdx.x; i < n; i += 2 * kBT) {
+            const int i2 = i + kBT;
+            const bool two = i2 < n;
+            const auto a = ld(i);
+            const auto b = ld(two ? i2 : i);
+            op(i, a);
+            if (two) op(i2, b);
+        }
+    } else {
+        for (int i = threadIdx.x; i < n; i += kBT) op(i, ld(i));
+    }
+}
+
+// operands of one row of a PCG pass
+template <typename T>
+struct RowQ {
+    T q[kBK];
+    T a, b, c, d;
+    int e0, e1;
+};
+
 // y_i = sum_j w_ij (x_i - x_j) for the rows of one graph: rows [0, nlong)
 // one wavefront each, the rest one thread each.  f(i, x_i, y_i, q_i).
 // x: a pointer, or any vector with operator[] (the split PCG direction)
@@ -469,28 +497,39 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 T acc[kBK], rr = T(0);
 #pragma unroll
                 for (int j = 0; j < kBK; ++j) acc[j] = T(0);
-                for (int i = tid; i < n; i += kBT) {
-                    T ri = res[i];
-                    T proj = T(0);
+                row_pass<T>(
+                    n,
+                    [&](int i) {
+                        RowQ<T> o;
 #pragma unroll
-                    for (int j = 0; j < kBK; ++j)
-                        if (j < q) proj += Q[(size_t)i * k + j] * cq[j];
-                    ri -= proj;
-                    res[i] = ri;
-                    const int d = gv.rp[i + 1] - gv.rp[i];
-                    T dsum = T(0);
-                    if (WT) {
-                        for (int e = gv.rp[i]; e < gv.rp[i + 1]; ++e) dsum += sizeof(T) == 4 ? (T)gv.w32[e] : (T)gv.w64[e];
-                    } else {
-                        dsum = (T)d;
-                    }
-                    const T yi = dsum > T(0) ? ri / dsum : ri;
-                    y[i] = yi;
-                    rr += ri * yi;
+                        for (int j = 0; j < kBK; ++j) o.q[j] = j < q ? Q[(size_t)i * k + j] : T(0);
+                        o.a = res[i];
+                        o.e0 = gv.rp[i];
+                        o.e1 = gv.rp[i + 1];
+                        return o;
+                    },
+                    [&](int i, const RowQ<T> &o) {
+                        T ri = o.a;
+                        T proj = T(0);
 #pragma unroll
-                    for (int j = 0; j < kBK; ++j)
-                        if (j < q) acc[j] += Q[(size_t)i * k + j] * yi;
-                }
+                        for (int j = 0; j < kBK; ++j)
+                            if (j < q) proj += o.q[j] * cq[j];
+                        ri -= proj;
+                        res[i] = ri;
+                        const int e0 = o.e0, e1 = o.e1;
+                        T dsum = T(0);
+                        if (WT) {
+                            for (int e = e0; e < e1; ++e) dsum += sizeof(T) == 4 ? (T)gv.w32[e] : (T)gv.w64[e];
+                        } else {
+                            dsum = (T)(e1 - e0);
+                        }
+                        const T yi = dsum > T(0) ? ri / dsum : ri;
+                        y[i] = yi;
+                        rr += ri * yi;
+#pragma unroll
+                        for (int j = 0; j < kBK; ++j)
+                            if (j < q) acc[j] += o.q[j] * yi;
+                    });
                 T pk[kBK + 2];
                 pack_q<T, kBK + 2>(acc, q, rr, pk);
                 wg_sum<T, kBK + 2>(pk, q + 1, sh);
@@ -546,14 +585,26 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 }
                 const T alpha = rho / pap;
                 // t += alpha p; res -= alpha (s - Q c2)
-                for (int i = tid; i < n; i += kBT) {
-                    T proj = T(0);
+                row_pass<T>(
+                    n,
+                    [&](int i) {
+                        RowQ<T> o;
 #pragma unroll
-                    for (int j = 0; j < kBK; ++j)
-                        if (j < q) proj += Q[(size_t)i * k + j] * c2[j];
-                    t[i] += alpha * pv[i];
-                    res[i] -= alpha * (s[i] - proj);
-                }
+                        for (int j = 0; j < kBK; ++j) o.q[j] = j < q ? Q[(size_t)i * k + j] : T(0);
+                        o.a = pv[i];
+                        o.b = s[i];
+                        o.c = res[i];
+                        o.d = t[i];
+                        return o;
+                    },
+                    [&](int i, const RowQ<T> &o) {
+                        T proj = T(0);
+#pragma unroll
+                        for (int j = 0; j < kBK; ++j)
+                            if (j < q) proj += o.q[j] * c2[j];
+                        t[i] = o.d + alpha * o.a;
+                        res[i] = o.c - alpha * (o.b - proj);
+                    });
                 __syncthreads();
                 T zero[kBK];
 #pragma unroll
@@ -564,7 +615,9 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 for (int j = 0; j < kBK; ++j) c1[j] = j < q ? (T)sh.out[j] : T(0);
                 __syncthreads();
                 double a2[1] = {0.0};
-                for (int i = tid; i < n; i += kBT) a2[0] += (double)res[i] * (double)res[i];
+                row_pass<T>(
+                    n, [&](int i) { return res[i]; },
+                    [&](int, T ri) { a2[0] += (double)ri * (double)ri; });
                 wg_sum<double, 1>(a2, 1, sh);
                 const T rn2 = (T)sqrt(sh.out[0]);
                 __syncthreads();
@@ -572,13 +625,23 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 if (rn2 <= (T)a.rtol_pcg * r0 || pit == a.itmax) break;
                 const T beta = rho_new / rho;
                 rho = rho_new;
-                for (int i = tid; i < n; i += kBT) {
-                    T proj = T(0);
+                row_pass<T>(
+                    n,
+                    [&](int i) {
+                        RowQ<T> o;
 #pragma unroll
-                    for (int j = 0; j < kBK; ++j)
-                        if (j < q) proj += Q[(size_t)i * k + j] * c1[j];
-                    pv[i] = (y[i] - proj) + beta * pv[i];
-                }
+                        for (int j = 0; j < kBK; ++j) o.q[j] = j < q ? Q[(size_t)i * k + j] : T(0);
+                        o.a = y[i];
+                        o.b = pv[i];
+                        return o;
+                    },
+                    [&](int i, const RowQ<T> &o) {
+                        T proj = T(0);
+#pragma unroll
+                        for (int j = 0; j < kBK; ++j)
+                            if (j < q) proj += o.q[j] * c1[j];
+                        pv[i] = (o.a - proj) + beta * o.b;
+                    });
                 __syncthreads();
             }
             inner += its;
