@@ -707,14 +707,17 @@ void launch_jd(BatchArgs a, int grid, hipStream_t s) {
     int dev = 0, max_lds = 0;
     hipFuncAttributes fa{};
     size_t dyn = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-        hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k)) == hipSuccess && max_lds > (int)fa.sharedSizeBytes)
-        dyn = ((size_t)max_lds - fa.sharedSizeBytes) & ~(size_t)15;
+    // a failed query leaves the global-memory path (and its error is cleared)
+    bool ok = hipGetDevice(&dev) == hipSuccess &&
+              hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+              hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k)) == hipSuccess;
+    if (ok && max_lds > (int)fa.sharedSizeBytes) dyn = ((size_t)max_lds - fa.sharedSizeBytes) & ~(size_t)15;
     if (dyn > 0 && hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)dyn) != hipSuccess)
+                                       (int)dyn) != hipSuccess) {
+        ok = false;
         dyn = 0;
-    (void)hipGetLastError();  // a failed query leaves the global-memory path
+    }
+    if (!ok) (void)hipGetLastError();
     a.lds_elems = (int)(dyn / sizeof(T));
     hipLaunchKernelGGL(k, dim3(grid), dim3(kBT), dyn, s, a);
 }
