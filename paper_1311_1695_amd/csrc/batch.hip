@@ -312,8 +312,18 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             for (int i = tid; i < n; i += kBT) {
                 double vi = (pass == 0 && from_t) ? (double)t[i] : v[i];
                 if (pass > 0) {
+                    // four columns per step (their loads in flight together), in column order
                     double sub = 0.0;
-                    for (int j = 0; j < nb; ++j) sub += basis(j, i) * sh.coef[j];
+                    int j = 0;
+                    for (; j + 3 < nb; j += 4) {
+                        const double b0 = basis(j, i), b1 = basis(j + 1, i), b2 = basis(j + 2, i),
+                                     b3 = basis(j + 3, i);
+                        sub += b0 * sh.coef[j];
+                        sub += b1 * sh.coef[j + 1];
+                        sub += b2 * sh.coef[j + 2];
+                        sub += b3 * sh.coef[j + 3];
+                    }
+                    for (; j < nb; ++j) sub += basis(j, i) * sh.coef[j];
                     vi -= sub;
                 }
                 v[i] = vi;
@@ -370,7 +380,16 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             double acc[2] = {0.0, 0.0};
             for (int i = tid; i < n; i += kBT) {
                 double ui = 0.0, gi = 0.0;
-                for (int j = 0; j < m; ++j) {
+                int j = 0;
+                for (; j + 1 < m; j += 2) {
+                    const double v0 = V[(size_t)j * n + i], v1 = V[(size_t)(j + 1) * n + i];
+                    const double w0 = W[(size_t)j * n + i], w1 = W[(size_t)(j + 1) * n + i];
+                    ui += v0 * sh.Y[j];
+                    gi += w0 * sh.Y[j];
+                    ui += v1 * sh.Y[j + 1];
+                    gi += w1 * sh.Y[j + 1];
+                }
+                for (; j < m; ++j) {
                     ui += V[(size_t)j * n + i] * sh.Y[j];
                     gi += W[(size_t)j * n + i] * sh.Y[j];
                 }
