@@ -328,9 +328,19 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 }
                 v[i] = vi;
                 if (pass < 2) {
+                    // four columns per step, loaded at clamped (valid) indices so the
+                    // loads are unconditional and in flight together
 #pragma unroll
-                    for (int j = 0; j < NVB - 1; ++j)
-                        if (j < nb) acc[j] += basis(j, i) * vi;
+                    for (int j0 = 0; j0 < NVB - 1; j0 += 4) {
+                        if (j0 < nb) {
+                            double b[4];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) b[c] = basis(min(j0 + c, nb - 1), i);
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if (j0 + c < NVB - 1 && j0 + c < nb) acc[j0 + c] += b[c] * vi;
+                        }
+                    }
                 } else {
                     acc[0] += vi * vi;
                 }
@@ -361,8 +371,16 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             for (int i = tid; i < n; i += kBT) {
                 const double wi = wc[i];
 #pragma unroll
-                for (int j = 0; j < kBM; ++j)
-                    if (j <= m) acc[j] += V[(size_t)j * n + i] * wi;
+                for (int j0 = 0; j0 < kBM; j0 += 4) {
+                    if (j0 <= m) {
+                        double b[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) b[c] = V[(size_t)min(j0 + c, m) * n + i];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (j0 + c <= m) acc[j0 + c] += b[c] * wi;
+                    }
+                }
             }
             wg_sum<double, NVB>(acc, m + 1, sh);
             for (int j = tid; j <= m; j += kBT) {
