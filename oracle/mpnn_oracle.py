@@ -198,3 +198,18 @@ def init_params(cfg: Config, seed: int) -> np.ndarray:
         at += r * c + c
         layers.append((W, np.zeros(c)))
     return pack(cfg, layers)
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015, Algorithm 1), written out plainly
+    in FP64: first and second moment averages of the gradient, their bias
+    corrections by 1 - beta^step, then a step of lr times the corrected
+    first moment over (the square root of the corrected second moment plus
+    eps).  step counts from 1.  Returns (new params, new m, new v)."""
+    g = np.asarray(grad, dtype=np.float64)
+    m_new = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v_new = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m_new / (1.0 - beta1 ** step)
+    v_hat = v_new / (1.0 - beta2 ** step)
+    p_new = np.asarray(params, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p_new, m_new, v_new

@@ -348,10 +348,21 @@ def workload(name: str, seed: int) -> LaplacianCSR:
     return WORKLOADS[name][0](seed)
 
 
-def pa_batch(num: int, seed: int, n_lo: int = 1000, n_hi: int = 20000, ms=(2, 3, 4)):
-    """A batch of uneven preferential-attachment graphs: graph g has
-    n ~ U{n_lo..n_hi}, m ~ U(ms), and its own seed derived from ``seed``."""
+def _pa_batch_sizes(num, seed, n_lo, n_hi, ms):
     rng = _rng(seed)
     ns = rng.integers(n_lo, n_hi + 1, size=num)
     mm = rng.choice(np.asarray(ms), size=num)
+    return ns, mm
+
+
+def pa_batch(num: int, seed: int, n_lo: int = 1000, n_hi: int = 20000, ms=(2, 3, 4)):
+    """A batch of uneven preferential-attachment graphs: graph g has
+    n ~ U{n_lo..n_hi}, m ~ U(ms), and its own seed derived from ``seed``."""
+    ns, mm = _pa_batch_sizes(num, seed, n_lo, n_hi, ms)
     return [_pa_lcc(int(ns[g]), int(mm[g]), seed * 1000 + g, f"pa_b{g}") for g in range(num)]
+
+
+def pa_batch_member(g: int, num: int, seed: int, n_lo: int = 1000, n_hi: int = 20000, ms=(2, 3, 4)):
+    """Graph g of pa_batch(num, seed, ...) alone."""
+    ns, mm = _pa_batch_sizes(num, seed, n_lo, n_hi, ms)
+    return _pa_lcc(int(ns[g]), int(mm[g]), seed * 1000 + g, f"pa_b{g}")

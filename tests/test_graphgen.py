@@ -65,3 +65,11 @@ def test_pa_batch_sizes():
     for g in graphs:
         assert 1000 <= g.n <= 2000
         _is_laplacian(g)
+
+
+def test_pa_batch_member_is_the_batch_graph():
+    graphs = gg.pa_batch(5, 17)
+    for g in range(5):
+        one = gg.pa_batch_member(g, 5, 17)
+        assert one.n == graphs[g].n
+        assert np.array_equal(one.rowptr, graphs[g].rowptr) and np.array_equal(one.col, graphs[g].col)

@@ -106,3 +106,40 @@ def test_output_is_orthogonal_to_the_zero_space():
     Yh, _ = mo.forward(cfg, mo.init_params(cfg, 1), gr, 2)
     assert gr.Z.shape[1] == 2
     assert np.abs(gr.Z.T @ Yh).max() < 1e-12
+
+
+def test_adam_closed_forms():
+    """Pins of the Adam reference (Kingma & Ba 2015, Algorithm 1) that do not
+    restate its code: the first step from zero moments and every step under a
+    constant gradient move by lr * g / (|g| + eps) (the bias corrections make
+    the corrected moments g and g^2 exactly), zero gradient only decays the
+    moments, and a two-step hand example."""
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(50)
+    g = rng.standard_normal(50) * np.logspace(-3, 2, 50)
+    lr = 0.01
+    p1, m1, v1 = mo.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr)
+    assert np.allclose(p1, p - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+    # constant gradient: the same step every time
+    pt, mt, vt = p, np.zeros(50), np.zeros(50)
+    for t in range(1, 40):
+        prev = pt
+        pt, mt, vt = mo.adam_step(pt, g, mt, vt, t, lr)
+        assert np.allclose(pt - prev, -lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-16)
+    # zero gradient: the moments decay by beta1 and beta2
+    p2, m2, v2 = mo.adam_step(pt, np.zeros(50), mt, vt, 40, lr)
+    assert np.allclose(m2, 0.9 * mt, rtol=1e-15) and np.allclose(v2, 0.999 * vt, rtol=1e-15)
+    # hand example, g = +1 then -1, lr = 1, eps = 0:
+    #   step 1: m = 0.1, v = 0.001, m_hat = 1, v_hat = 1 -> move -1
+    #   step 2: m = 0.09 - 0.1 = -0.01, v = 0.000999 + 0.001 = 0.001999,
+    #           m_hat = -0.01 / 0.19, v_hat = 0.001999 / 0.001999 = 1 -> move +1/19
+    q1, a1, b1 = mo.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, 1.0, eps=0.0)
+    assert abs(q1[0] + 1.0) < 1e-15 and abs(a1[0] - 0.1) < 1e-16 and abs(b1[0] - 0.001) < 1e-18
+    q2, a2, b2 = mo.adam_step(q1, -np.ones(1), a1, b1, 2, 1.0, eps=0.0)
+    assert abs(a2[0] + 0.01) < 1e-16 and abs(b2[0] - 0.001999) < 1e-17
+    assert abs(q2[0] - (-1.0 + 1.0 / 19.0)) < 1e-14
+    # the step opposes the gradient and is invariant to scaling g and eps together
+    s1, _, _ = mo.adam_step(p, 1e3 * g, np.zeros(50), np.zeros(50), 1, lr, eps=1e-5)
+    assert np.allclose(s1, p1, rtol=0, atol=1e-14)
+    assert np.all(np.sign(p1 - p) == -np.sign(g))
