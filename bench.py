@@ -1,16 +1,24 @@
 """Benchmark: time to the k smallest Laplacian eigenpairs at relative
-residual 1e-8 on one MI355X, plus the SpMV bandwidth of the product kernel.
+residual 1e-8 on one MI355X, FP32 + learned warm start against plain FP64
+Jacobi-Davidson, plus the bandwidth of the Laplacian product.
 
-Workload (one "step" = one full Jacobi-Davidson solve, lap_eigs, with the
-plan already resident in HBM): Chung-Lu power-law graph, exponent 2.2,
-n = 30,000, mean degree 4, largest connected component (24,137 vertices,
-142,967 nonzeros for seed 1001); k = 10 smallest eigenpairs (the zero pair
-included), certified at ||Gu - theta u|| <= 1e-8 min(theta, 1); mixed
-precision (FP32 products and PCG, FP64 outer iteration).  The same solve in
-plain FP64 is timed beside it, and the CPU oracle (the paper's FP64
-Algorithm 2 with IC(0)) on the host cores.
+Workload (one "step" = inference of the warm-start network plus one full
+Jacobi-Davidson solve, lap_eigs, started from the network's block, with the
+plan already resident in HBM): the collaboration-like graph, Chung-Lu
+exponent 2.3, n = 1.1M, mean degree 7, triadic closure p = 0.3, largest
+connected component (1,032,939 vertices, 10,697,907 nonzeros of G for seed
+1001); k = 10 smallest eigenpairs (the zero pair included), each certified
+at ||Gu - theta u|| <= 1e-8 min(theta, 1) in FP64; mixed precision (FP32
+products and PCG, FP64 outer iteration).  The network is trained first, on
+the GPU, on eigenvectors that lap_eigs computes for graphs of the same
+family with n <= 50k.  Beside it: the 2 x 2 table {mixed, FP64} x {random
+start, network start}, the per-pair error against the FP64 oracle's
+eigenvalues (tests/golden, written by an oracle-only script), the product's
+bandwidth (FP32, FP64, 20-column block), a copy bandwidth, the other
+workloads, and the CPU oracle on a bounded sample of the same solve.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--sweep]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-configs]
+    python bench.py --sweep          # product bandwidth on graphs past the 256 MB MALL
 
 Prints one JSON line.
 """
@@ -20,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import statistics
 import sys
 import time
@@ -32,21 +41,28 @@ HBM_PEAK_GBS = 8000.0
 SEED = 1001
 K_PAIRS = 10
 TOL = 1e-8
+WORKLOAD = "cl1m_tc"
+GOLDEN = os.path.join(ROOT, "tests", "golden", "cl1m_tc_k10.json")
+PCG_Q = 10  # projector width of the roofline measurement: [zero vector, 8 locked, u] at the last pair
+# training graphs of the warm-start network: the same family, n <= 50k
+TRAIN_GRAPHS = [(10000, 101), (20000, 102), (30000, 103), (40000, 104), (50000, 105),
+                (15000, 106), (25000, 107), (35000, 108), (45000, 109)]
+TRAIN_STEPS = 450
+NET = dict(layers=2, hidden=32, random_channels=4, out_cols=9, seed=7)
 
 
-def spmv_bytes(n: int, nnz_a: int, elem: int = 4) -> int:
-    """Algorithmic bytes of one unweighted Laplacian product: row pointers,
-    column indices, one compulsory read of x and one write of y."""
-    return 4 * (n + 1) + 4 * nnz_a + 2 * elem * n
+def spmv_bytes(n: int, nnz_a: int, elem: int = 4, b: int = 1) -> int:
+    """Algorithmic bytes of one unweighted Laplacian product over b columns:
+    row pointers, column indices, one compulsory read of X and one write of
+    Y (n x b values each)."""
+    return 4 * (n + 1) + 4 * nnz_a + 2 * elem * b * n
 
 
 def pcg_iter_bytes(n: int, nnz_a: int, q: int, elem: int = 4) -> int:
-    """Algorithmic bytes of one iteration launch of the projected PCG
-    (k_pp_iter, unweighted): the CSR structure, one compulsory read of the
-    gathered vector wh, nine n-vectors read (dinv, t, res, u, w, p, s, q, z)
-    and nine written (t, res, u, w, wh, p, s, q, z), and the rows of Q, GQ
-    and G D^-1 Q (3q values per row)."""
-    return 4 * (n + 1) + 4 * nnz_a + elem * n * (1 + 9 + 9) + 3 * q * elem * n
+    """Algorithmic bytes of one projected-PCG iteration with the two-sided
+    preconditioner (I-QQ')D^-1(I-QQ'): one product plus (4q + 18) n-vectors
+    of the working precision."""
+    return spmv_bytes(n, nnz_a, elem) + (4 * q + 18) * n * elem
 
 
 def kernel_sources_sha(files=("pcg.hip", "lapeig_dev.h", "lapeig_internal.h")) -> str:
@@ -59,9 +75,8 @@ def kernel_sources_sha(files=("pcg.hip", "lapeig_dev.h", "lapeig_internal.h")) -
 
 def random_read_rate(n, count, reps=5):
     """Random 4-byte reads per second that the device serves from a vector
-    of about n FP32 values (bench_gather.hip, built by __graft_entry__.build:
-    indices hashed in registers, no index stream, no locality), or None if
-    the helper is not built."""
+    of about n FP32 values (bench_gather.hip: indices hashed in registers, no
+    index stream, no locality), or None if the helper is not built."""
     import ctypes
     path = os.path.join(ROOT, "bench_gather.so")
     if not os.path.exists(path):
@@ -74,12 +89,12 @@ def random_read_rate(n, count, reps=5):
     return rate.value if rc == 0 else None
 
 
-def time_spmv(lap, torch, plan, n, reps=200, dtype=None):
-    """Average duration of the FP32 product kernel: `reps` back-to-back
-    launches captured in a graph and replayed between two HIP events on the
-    stream they run on, so host launch gaps are not counted."""
+def time_spmv(lap, torch, plan, n, reps=200, dtype=None, b=1):
+    """Average duration of the product kernel: `reps` back-to-back launches
+    captured in a graph and replayed between two HIP events on the stream
+    they run on, so host launch gaps are not counted."""
     dtype = dtype or torch.float32
-    x = torch.randn(n, dtype=dtype, device="cuda")
+    x = torch.randn((n, b) if b > 1 else (n,), dtype=dtype, device="cuda")
     y = torch.empty_like(x)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -107,7 +122,25 @@ def time_spmv(lap, torch, plan, n, reps=200, dtype=None):
     return best  # seconds per launch
 
 
-PCG_Q = 10  # projector width of the roofline measurement: k = 10 pairs, as in the solve's last steps
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a
+    buffer far larger than the 256 MB MALL."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(s)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * nbytes / t
 
 
 def time_pcg_iteration(lap, torch, np, plan, n, q=PCG_Q, reps=5):
@@ -115,8 +148,7 @@ def time_pcg_iteration(lap, torch, np, plan, n, q=PCG_Q, reps=5):
     lap_pcg with rtol = 1e-30 runs exactly itmax iteration launches, so the
     difference of a 40- and a 10-iteration call, timed with HIP events on
     the stream lap_pcg launches on, divided by 30, is one launch (its
-    dispatch gap included).  (Beyond about 50 iterations the FP32
-    recurrences of this system lose positivity and stop early.)  Q = [1/sqrt(n), q-1 random orthonormal
+    dispatch gap included).  Q = [1/sqrt(n), q-1 random orthonormal
     columns], theta = 0: the projected operator is positive definite, so no
     breakdown ends the iteration early."""
     rng = np.random.default_rng(5)
@@ -147,8 +179,10 @@ def time_pcg_iteration(lap, torch, np, plan, n, q=PCG_Q, reps=5):
     return (run(40) - run(10)) / 30.0
 
 
-def traffic_from_profile(sha: str, nbytes_alg: int):
-    path = os.path.join(ROOT, "profiles", "pp_iter_f32_cl30k_pmc.json")
+def traffic_from_profile(sha: str):
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pp_iter_f32_cl1m_tc_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -158,23 +192,37 @@ def traffic_from_profile(sha: str, nbytes_alg: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(L, k, tol, budget_s=12.0):
+def host_info():
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(L, golden, budget_outer=6):
+    """The CPU oracle (FP64 Algorithm 2 with IC(0), paper parameters, one
+    thread) on a bounded sample of the same solve: the first `budget_outer`
+    outer iterations (IC(0) set-up included), scaled to the full solve by
+    the products the full oracle solve needs (tests/golden, measured by the
+    oracle-only script at the same graph, seed and k)."""
     import oracle
-    times = []
-    res = None
-    t_end = time.perf_counter() + budget_s
-    while True:
-        t0 = time.perf_counter()
-        res = oracle.jd(L, k, tol, precond=oracle.PREC_IC0, seed=1)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() > t_end or len(times) >= 20:
-            break
-    return statistics.median(times), len(times), res
+    t0 = time.perf_counter()
+    res = oracle.jd(L, K_PAIRS, TOL, precond=oracle.PREC_IC0, seed=1, kmax=budget_outer)
+    dt = time.perf_counter() - t0
+    full_mvp = golden["oracle"]["mvp"] if golden else None
+    est = dt / res.mvp * full_mvp if (full_mvp and res.mvp) else None
+    return dt, res, est, full_mvp
 
 
-def certify(L, r, tol):
-    """Largest relative residual ||Gx - lx|| / min(l, 1) over the non-zero pairs,
-    recomputed on the host in FP64."""
+def certify(L, r):
+    """Largest relative residual ||Gx - lx|| / min(l, 1) over the non-zero
+    pairs, recomputed on the host in FP64."""
     import numpy as np
     G = L.to_scipy()
     res = np.linalg.norm(G @ r.evecs - r.evecs * r.evals, axis=0)
@@ -182,105 +230,138 @@ def certify(L, r, tol):
     return float(np.max(res[pos] / np.minimum(r.evals[pos], 1.0))) if pos.any() else 0.0
 
 
+def pair_errors(evals, golden):
+    """|theta_gpu - theta_oracle| / theta_oracle per pair (absolute for the
+    zero pair)."""
+    ref = golden["evals"]
+    out = []
+    for a, b in zip(evals, ref):
+        out.append(float(abs(a - b) / b) if b > 0 else float(abs(a - b)))
+    return out
+
+
+def median_time(fn, reps, torch):
+    times, last = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        last = fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    return statistics.median(times), times, last
+
+
+def train_network(lap, torch, gg, np):
+    """Train the warm-start network on the GPU on eigenvectors that lap_eigs
+    computes for same-family graphs with n <= 50k (k = 10, tol 1e-6)."""
+    t0 = time.perf_counter()
+    train = [gg.collaboration(n, s) for n, s in TRAIN_GRAPHS]
+    t_gen = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    plans = [lap.Plan(L) for L in train]
+    targets = [lap.lap_eigs(p, K_PAIRS, 1e-6, evecs_on_device=True).evecs[1:].contiguous() for p in plans]
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t1
+    net = lap.Mpnn(**NET)
+    losses = []
+    t2 = time.perf_counter()
+    for s in range(TRAIN_STEPS):
+        g = s % len(plans)
+        losses.append(net.train_step(plans[g], targets[g], lr=3e-3, feature_seed=1 + (s // len(plans)) % 4))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t2
+    for p in plans:
+        p.close()
+    info = {"train_graphs_n": [L.n for L in train], "train_steps": TRAIN_STEPS, "params": net.num_params,
+            **{k: v for k, v in NET.items() if k != "seed"},
+            "targets_s": round(t_targets, 3), "train_s": round(t_train, 3), "graph_gen_s": round(t_gen, 2),
+            "loss_first": round(float(np.mean(losses[:len(plans)])), 4),
+            "loss_last": round(float(np.mean(losses[-len(plans):])), 4)}
+    return net, info
+
+
 def extra_configs(lap, torch, gg, np, reps=3):
     """The other workloads: plain FP64 JD on the preferential-attachment
-    graph (n = 5000, k = 10) and block JD (b = 20) on the Chung-Lu
-    exponent-2.1 graph (n = 330,000, k = 20), mixed and FP64."""
+    graph (n = 5000, k = 10), mixed vs FP64 on the Chung-Lu exponent-2.2
+    graph (n = 30,000, k = 10), block JD (b = 20) on the Chung-Lu
+    exponent-2.1 graph (n = 330,000, k = 20), and the batch of 256 uneven
+    preferential-attachment graphs (5 pairs each, one launch)."""
     out = []
     runs = [
-        ("pa5k", 10, 1e-8, [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed"))]),
-        ("cl330k", 20, 1e-8, [("mixed_block20", dict(precision="mixed", block=20, m_min=20, m_max=60)),
-                              ("fp64_block20", dict(precision="fp64", block=20, m_min=20, m_max=60)),
-                              ("mixed_single", dict(precision="mixed", m_min=5, m_max=10))]),
+        ("pa5k", 10, [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed"))]),
+        ("cl30k", 10, [("mixed", dict(precision="mixed")), ("fp64", dict(precision="fp64"))]),
+        ("cl330k", 20, [("mixed_block20", dict(precision="mixed", block=20, m_min=20, m_max=60)),
+                        ("fp64_block20", dict(precision="fp64", block=20, m_min=20, m_max=60))]),
     ]
-    for name, k, tol, variants in runs:
+    for name, k, variants in runs:
         L = gg.workload(name, SEED)
         plan = lap.Plan(L)
-        entry = {"workload": name, "n": L.n, "nnz": L.nnz, "k": k, "tol": tol, "runs": {}}
+        entry = {"workload": name, "n": L.n, "nnz": L.nnz, "k": k, "tol": TOL, "runs": {}}
         for label, kw in variants:
-            r = lap.lap_eigs(plan, k, tol, seed=1, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                r = lap.lap_eigs(plan, k, tol, seed=1, **kw)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / reps
+            lap.lap_eigs(plan, k, TOL, seed=1, **kw)
+            dt, _, r = median_time(lambda: lap.lap_eigs(plan, k, TOL, seed=1, **kw), reps, torch)
             entry["runs"][label] = {"s": round(dt, 5), "mvp": r.mvp, "outer": r.outer, "inner": r.inner,
-                                    "nconv": r.nconv, "max_rel_residual": certify(L, r, tol),
+                                    "nconv": r.nconv, "max_rel_residual": certify(L, r),
                                     "lambda2": float(r.evals[1]), "lambda_k": float(r.evals[-1])}
         plan.close()
         out.append(entry)
-    # a batch of 256 uneven preferential-attachment graphs, 5 pairs each, one launch
     graphs = gg.pa_batch(256, SEED)
     b = lap.lap_batch_create(graphs)
+    sum_nnz = sum(g.nnz for g in graphs)
     entry = {"workload": "pa_batch256", "graphs": len(graphs), "sum_n": sum(g.n for g in graphs),
-             "sum_nnz": sum(g.nnz for g in graphs), "k": 5, "tol": 1e-8, "runs": {}}
+             "sum_nnz": sum_nnz, "k": 5, "tol": TOL, "runs": {}}
     for label, prec in (("mixed", "mixed"), ("fp64", "fp64")):
-        lap.lap_batch_eigs(b, 5, 1e-8, precision=prec)
-        t0 = time.perf_counter()
-        res = lap.lap_batch_eigs(b, 5, 1e-8, precision=prec)
-        dt = time.perf_counter() - t0
-        worst = max(certify(L, r, 1e-8) for L, r in zip(graphs[:16], res[:16]))
+        lap.lap_batch_eigs(b, 5, TOL, precision=prec)
+        dt, _, res = median_time(lambda: lap.lap_batch_eigs(b, 5, TOL, precision=prec), 2, torch)
+        worst = max(certify(L, r) for L, r in zip(graphs, res))
         entry["runs"][label] = {"s": round(dt, 4), "mvp_total": int(sum(r.mvp for r in res)),
                                 "nconv_min": int(min(r.nconv for r in res)),
-                                "max_rel_residual_first16": worst}
+                                "max_rel_residual": worst}
     b.close()
     out.append(entry)
     return out
 
 
-def warm_start_config(lap, torch, gg, np, reps=2):
-    """The collaboration-like graph (Chung-Lu exponent 2.3, n = 1.1M, mean
-    degree 7, triadic closure 0.3, largest component), k = 10 at 1e-8: JD
-    started from the learned network's block vs from the seeded random
-    vector (mixed precision), and plain FP64 JD from the random vector.
-    The network (2 layers, width 32, 4 random channels, 9 columns) is
-    trained first, on the GPU, on six graphs of the same family with
-    n <= 20k whose eigenvectors lap_eigs computes (tol 1e-6)."""
-    t0 = time.perf_counter()
-    train = [gg.collaboration(n, s) for n, s in [(8000, 101), (12000, 102), (16000, 103), (20000, 104),
-                                                 (10000, 105), (14000, 106)]]
-    plans = [lap.Plan(L) for L in train]
-    targets = [lap.lap_eigs(p, 10, 1e-6, evecs_on_device=True).evecs[1:].contiguous() for p in plans]
-    net = lap.Mpnn(layers=2, hidden=32, random_channels=4, out_cols=9, seed=7)
-    losses = []
-    for s in range(400):
-        g = s % len(plans)
-        losses.append(net.train_step(plans[g], targets[g], lr=3e-3, feature_seed=1 + (s // len(plans)) % 4))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    for p in plans:
-        p.close()
-    L = gg.workload("cl1m_tc", SEED)
-    plan = lap.Plan(L)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    V0 = net.infer(plan, feature_seed=1)
-    torch.cuda.synchronize()
-    t_infer = time.perf_counter() - t1
-    entry = {"workload": "cl1m_tc", "n": L.n, "nnz": L.nnz, "k": 10, "tol": 1e-8,
-             "network": {"layers": 2, "hidden": 32, "random_channels": 4, "out_cols": 9,
-                         "params": net.num_params, "train_steps": 400, "train_s": round(t_train, 3),
-                         "loss_first": round(float(np.mean(losses[:6])), 4),
-                         "loss_last": round(float(np.mean(losses[-6:])), 4),
-                         "infer_ms": round(t_infer * 1e3, 3)},
-             "runs": {}}
-    variants = [("mixed_warm", dict(precision="mixed", init=V0)), ("mixed_random", dict(precision="mixed")),
-                ("fp64_random", dict(precision="fp64"))]
-    for label, kw in variants:
-        best, r = None, None
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r = lap.lap_eigs(plan, 10, 1e-8, seed=1, **kw)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t
-            best = dt if best is None else min(best, dt)
-        entry["runs"][label] = {"s": round(best, 5), "mvp": r.mvp, "outer": r.outer, "inner": r.inner,
-                                "nconv": r.nconv, "max_rel_residual": certify(L, r, 1e-8)}
-    entry["runs"]["mixed_warm"]["s_with_inference"] = round(entry["runs"]["mixed_warm"]["s"] + t_infer, 5)
-    plan.close()
-    return entry
+def spmv_entries(lap, torch, gg, np, L, plan):
+    """Bandwidth of the Laplacian product on the headline graph: FP32 and
+    FP64 on one vector, FP32 on a 20-column block, with the gather rate and
+    the random-read rate of the device beside it."""
+    n, nnz_a = L.n, L.nnz - L.n
+    out = []
+    for label, dt, b, elem in (("f32_b1", torch.float32, 1, 4), ("f64_b1", torch.float64, 1, 8),
+                               ("f32_b20", torch.float32, 20, 4)):
+        t = time_spmv(lap, torch, plan, n, reps=100 if b > 1 else 200, dtype=dt, b=b)
+        ab = spmv_bytes(n, nnz_a, elem, b)
+        out.append({"kernel": "k_spmv" if b == 1 else "k_spmm", "dtype": label.split("_")[0], "b": b,
+                    "alg_bytes_per_launch": ab, "avg_launch_us": round(t * 1e6, 3),
+                    "GB/s": round(ab / t / 1e9, 1), "frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
+                    "gathers_per_s_1e9": round(nnz_a / t / 1e9, 1)})
+    rr = random_read_rate(n, max(nnz_a, 1 << 24))
+    return out, (None if rr is None else round(rr / 1e9, 1))
+
+
+def sweep(lap, torch, gg, np):
+    """The product on the collaboration-like generator at n = 1.1M, 4.4M and
+    8.8M (the FP32 working set grows past the 256 MB MALL)."""
+    rows = []
+    for n in (1_100_000, 4_400_000, 8_800_000):
+        t0 = time.perf_counter()
+        L = gg.collaboration(n, SEED)
+        tg = time.perf_counter() - t0
+        plan = lap.Plan(L)
+        nnz_a = L.nnz - L.n
+        for label, dt, b, elem in (("f32", torch.float32, 1, 4), ("f64", torch.float64, 1, 8),
+                                   ("f32", torch.float32, 20, 4)):
+            t = time_spmv(lap, torch, plan, L.n, reps=50, dtype=dt, b=b)
+            ab = spmv_bytes(L.n, nnz_a, elem, b)
+            rows.append({"n_generated": n, "n": L.n, "nnz": L.nnz, "dtype": label, "b": b,
+                         "alg_bytes_per_launch": ab, "avg_launch_us": round(t * 1e6, 2),
+                         "GB/s": round(ab / t / 1e9, 1), "frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
+                         "gen_s": round(tg, 1)})
+            print(json.dumps(rows[-1]), flush=True)
+        plan.close()
+        del L
+    return rows
 
 
 def main():
@@ -288,18 +369,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--spmv-graph", default="cl30k",
-                    help="workload of the --spmv-only leg (cl30k, cl330k, cl1m_tc)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--spmv-only", action="store_true", help="only the product kernel loop (for profiling)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads")
+    ap.add_argument("--spmv-only", default=None, metavar="GRAPH",
+                    help="only the product kernel loop on one workload (for profiling)")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the PCG iteration timing and a copy of known size (for profiling)")
-    ap.add_argument("--extra", action="store_true",
-                    help="also time the other workloads (pa5k FP64; cl330k block JD; batch)")
+                    help="only the PCG iteration timing on the headline graph and a copy of known size "
+                         "(for profiling)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the headline solves, no training (random start; for profiling)")
     ap.add_argument("--block-only", action="store_true",
                     help="only block JD (b = 20, mixed) on the 330k-vertex graph (for profiling)")
-    ap.add_argument("--warmstart", action="store_true",
-                    help="also time the learned warm start on the 1.1M-vertex collaboration graph")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the product bandwidth on generated graphs of 1.1M, 4.4M and 8.8M vertices")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build",
@@ -314,23 +396,39 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lap.load_library()
+    if args.sweep:
+        rows = sweep(lap, torch, gg, np)
+        print(json.dumps({"spmv_sweep": rows, "copy_GB/s": round(copy_bandwidth(torch) / 1e9, 1)}))
+        return
     if args.block_only:
         Lb = gg.workload("cl330k", SEED)
         pb = lap.Plan(Lb)
         kw = dict(precision="mixed", block=20, m_min=20, m_max=60)
         lap.lap_eigs(pb, 20, TOL, seed=1, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(2):
-            rb = lap.lap_eigs(pb, 20, TOL, seed=1, **kw)
-        torch.cuda.synchronize()
-        print(json.dumps({"workload": "cl330k", "block": 20, "s": (time.perf_counter() - t0) / 2,
-                          "outer": rb.outer, "inner": rb.inner, "mvp": rb.mvp, "nconv": rb.nconv}))
+        dt, _, rb = median_time(lambda: lap.lap_eigs(pb, 20, TOL, seed=1, **kw), 2, torch)
+        print(json.dumps({"workload": "cl330k", "block": 20, "s": dt, "outer": rb.outer, "inner": rb.inner,
+                          "mvp": rb.mvp, "nconv": rb.nconv}))
         return
-    L = gg.workload("cl30k", SEED)
+    if args.spmv_only:
+        Ls = gg.workload(args.spmv_only, SEED)
+        ps = lap.Plan(Ls)
+        t = time_spmv(lap, torch, ps, Ls.n, reps=500)
+        cb = copy_bandwidth(torch, 256 << 20, reps=20)
+        print(json.dumps({"workload": args.spmv_only, "spmv_s": t, "alg_bytes": spmv_bytes(Ls.n, Ls.nnz - Ls.n),
+                          "copy_bytes_each_way": 256 << 20, "copy_GB/s": round(cb / 1e9, 1)}))
+        return
+
+    t0 = time.perf_counter()
+    L = gg.workload(WORKLOAD, SEED)
+    t_gen = time.perf_counter() - t0
     st = L.stats()
     nnz_a = L.nnz - L.n
+    t0 = time.perf_counter()
     plan = lap.Plan(L)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    print(f"bench: {WORKLOAD} n={L.n} nnz={L.nnz} generated in {t_gen:.1f}s, plan {t_plan:.2f}s",
+          file=sys.stderr, flush=True)
 
     # ---- the dominant kernel, one PCG iteration launch: live timing for the roofline
     t_pcg = time_pcg_iteration(lap, torch, np, plan, L.n)
@@ -341,131 +439,110 @@ def main():
         for _ in range(20):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"pcg_iter_s": t_pcg, "alg_bytes": alg_pcg, "copy_bytes_each_way": a.numel() * 4}))
-        return
-    # ---- the plain product kernel, for the SpMV bandwidth of the metric
-    if args.spmv_only and args.spmv_graph != "cl30k":
-        L = gg.workload(args.spmv_graph, SEED)
-        nnz_a = L.nnz - L.n
-        plan = lap.Plan(L)
-    t_spmv = time_spmv(lap, torch, plan, L.n, reps=2000 if args.spmv_only else 500)
-    alg = spmv_bytes(L.n, nnz_a, 4)
-    if args.spmv_only:
-        # a plain copy of known size, for calibrating HBM counters
-        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(20):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"workload": args.spmv_graph, "spmv_s": t_spmv, "alg_bytes": alg,
+        print(json.dumps({"workload": WORKLOAD, "pcg_iter_s": t_pcg, "alg_bytes": alg_pcg,
                           "copy_bytes_each_way": a.numel() * 4}))
         return
+    if args.solve_only:
+        for prec in ("mixed", "fp64"):
+            lap.lap_eigs(plan, K_PAIRS, TOL, precision=prec, seed=1)
+            dt, _, r = median_time(lambda: lap.lap_eigs(plan, K_PAIRS, TOL, precision=prec, seed=1), 2, torch)
+            print(json.dumps({"precision": prec, "s": dt, "outer": r.outer, "mvp": r.mvp}), flush=True)
+        return
 
-    def solve(precision):
-        return lap.lap_eigs(plan, K_PAIRS, TOL, precision=precision, seed=1)
+    golden = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as fh:
+            golden = json.load(fh)
+        assert golden["n"] == L.n and golden["nnz"] == L.nnz, "golden file does not match the workload"
+
+    net, net_info = train_network(lap, torch, gg, np)
+    print(f"bench: network trained, loss {net_info['loss_first']} -> {net_info['loss_last']}",
+          file=sys.stderr, flush=True)
+
+    def step(precision="mixed"):
+        V0 = net.infer(plan, feature_seed=1)
+        return lap.lap_eigs(plan, K_PAIRS, TOL, precision=precision, seed=1, init=V0)
 
     for _ in range(args.warmup):
-        solve("mixed")
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
     for _ in range(args.steps):
-        runs.append(solve("mixed"))
+        runs.append(step())
     torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / args.steps
+    t_step = (time.perf_counter() - t0) / args.steps
     r = runs[-1]
 
-    # plain FP64 Jacobi-Davidson on the same GPU, same seed
-    solve("fp64")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f64 = []
-    for _ in range(max(3, args.steps // 2)):
-        f64.append(solve("fp64"))
-    torch.cuda.synchronize()
-    t_fp64 = (time.perf_counter() - t0) / len(f64)
-    rf = f64[-1]
+    # inference alone
+    t_inf, _, V0 = median_time(lambda: net.infer(plan, feature_seed=1), 5, torch)
+    # the 2 x 2 table: {mixed, FP64} x {random, network}, same seeds
+    table = {}
+    cells = [("mixed_network", dict(precision="mixed", init=V0)), ("mixed_random", dict(precision="mixed")),
+             ("fp64_network", dict(precision="fp64", init=V0)), ("fp64_random", dict(precision="fp64"))]
+    for label, kw in cells:
+        lap.lap_eigs(plan, K_PAIRS, TOL, seed=1, **kw)
+        dt, times, rr = median_time(lambda: lap.lap_eigs(plan, K_PAIRS, TOL, seed=1, **kw), 3, torch)
+        table[label] = {"solve_s": round(dt, 5), "mvp": rr.mvp, "outer": rr.outer, "inner": rr.inner,
+                        "nconv": rr.nconv, "max_rel_residual": certify(L, rr)}
+        if golden:
+            table[label]["max_pair_err_vs_oracle"] = max(pair_errors(rr.evals, golden))
+    t_fp64 = table["fp64_random"]["solve_s"]
 
     G = L.to_scipy()
     resid = np.linalg.norm(G @ r.evecs - r.evecs * r.evals, axis=0)
     out = {
         "metric": METRIC,
-        "value": round(t_mixed, 6),
+        "value": round(t_step, 6),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_mixed * 1e3, 4),
+        "ms_per_step": round(t_step * 1e3, 4),
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "chung_lu_gamma2.2_n30000_deg4_lcc", "n": L.n, "nnz": L.nnz,
-                   "d_max": st["d_max"], "leaf_frac": round(st["leaf_frac"], 4), "k": K_PAIRS, "tol": TOL,
-                   "precision": "mixed", "seed": SEED},
+        "config": {"workload": "collaboration_like_chung_lu_gamma2.3_n1.1M_deg7_triadic0.3_lcc", "name": WORKLOAD,
+                   "n": L.n, "nnz": L.nnz, "d_max": st["d_max"], "leaf_frac": round(st["leaf_frac"], 4),
+                   "k": K_PAIRS, "tol": TOL, "precision": "mixed", "start": "learned network block",
+                   "step": "network inference + lap_eigs from its block", "seed": SEED},
         "solve": {"mvp": r.mvp, "outer": r.outer, "inner": r.inner, "nconv": r.nconv,
                   "max_rel_residual": float(np.max(resid[1:] / np.minimum(r.evals[1:], 1.0))),
-                  "evals": [float(x) for x in r.evals]},
-        "fp64_jd": {"s": round(t_fp64, 6), "mvp": rf.mvp, "outer": rf.outer, "inner": rf.inner,
-                    "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3)},
+                  "evals": [float(x) for x in r.evals],
+                  "pair_err_vs_oracle": pair_errors(r.evals, golden) if golden else None,
+                  "oracle_evals_tol": golden["oracle_tol"] if golden else None},
+        "speedup_vs_fp64_random": round(t_fp64 / t_step, 3),
+        "start_x_precision": table,
+        "inference_s": round(t_inf, 5),
+        "network": net_info,
+        "plan_create_s": round(t_plan, 3),
     }
     sha = kernel_sources_sha()
     achieved = alg_pcg / t_pcg / 1e9
-    out["roofline"] = {"kernel": f"k_pp_iter<float> (one projected PCG iteration, q={PCG_Q})", "bound": "hbm",
-                       "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_from_profile(sha, alg_pcg),
+    out["roofline"] = {"kernel": f"k_pp_iter<float> (one projected PCG iteration, q={PCG_Q}, {WORKLOAD})",
+                       "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_from_profile(sha),
                        "alg_bytes_per_launch": alg_pcg, "avg_launch_us": round(t_pcg * 1e6, 3),
                        "kernel_sources_sha": sha}
-    a_spmv = alg / t_spmv / 1e9
-    out["spmv"] = {"kernel": "k_spmv<float> (unweighted Laplacian product, b=1)", "GB/s": round(a_spmv, 2),
-                   "frac": round(a_spmv / HBM_PEAK_GBS, 5), "alg_bytes_per_launch": alg,
-                   "avg_launch_us": round(t_spmv * 1e6, 3)}
-    # the same product on the large power-law graphs of the other workloads,
-    # where it moves tens of megabytes per launch instead of under one
-    large, pcg_large = [], []
-    for name in ("cl330k", "cl1m_tc"):
-        Lb = gg.workload(name, SEED)
-        pb = lap.Plan(Lb)
-        tb = time_spmv(lap, torch, pb, Lb.n, reps=200)
-        nnz_a = Lb.nnz - Lb.n  # one neighbour gather per off-diagonal entry
-        ab = spmv_bytes(Lb.n, nnz_a, 4)
-        g_spmv = nnz_a / tb
-        # at least 16M reads per launch, so that the launch itself does not count
-        g_rand = random_read_rate(Lb.n, max(nnz_a, 1 << 24))
-        large.append({"workload": name, "n": Lb.n, "nnz": Lb.nnz, "alg_bytes_per_launch": ab,
-                      "avg_launch_us": round(tb * 1e6, 3), "GB/s": round(ab / tb / 1e9, 1),
-                      "frac": round(ab / tb / 1e9 / HBM_PEAK_GBS, 4),
-                      "gathers_per_s": round(g_spmv / 1e9, 1),
-                      "random_read_rate_per_s": None if g_rand is None else round(g_rand / 1e9, 1),
-                      "frac_of_random_read_rate": None if g_rand is None else round(g_spmv / g_rand, 3),
-                      "gather_unit": "1e9 4-byte reads per second"})
-        # the dominant kernel at the same sizes: one pipelined PCG iteration,
-        # q = 10, FP32, timed as in the roofline leg
-        try:
-            tp = time_pcg_iteration(lap, torch, np, pb, Lb.n, q=PCG_Q)
-            ap = pcg_iter_bytes(Lb.n, nnz_a, PCG_Q)
-            pcg_large.append({"workload": name, "n": Lb.n, "q": PCG_Q, "alg_bytes_per_launch": ap,
-                              "avg_launch_us": round(tp * 1e6, 3), "GB/s": round(ap / tp / 1e9, 1),
-                              "frac": round(ap / tp / 1e9 / HBM_PEAK_GBS, 4)})
-        except AssertionError:  # an FP32 breakdown ended a timing call early
-            pcg_large.append({"workload": name, "n": Lb.n, "q": PCG_Q, "avg_launch_us": None})
-        pb.close()
-        del Lb
-    out["spmv"]["large_graphs"] = large
-    out["pcg_large_graphs"] = {"kernel": "k_pp_iter<float> (one projected PCG iteration)", "runs": pcg_large}
-    if args.extra:
+    sp, rr_rate = spmv_entries(lap, torch, gg, np, L, plan)
+    out["spmv"] = {"workload": WORKLOAD, "runs": sp, "random_read_rate_1e9_per_s": rr_rate,
+                   "copy_GB/s": round(copy_bandwidth(torch) / 1e9, 1)}
+    plan.close()
+    net.close()
+    if not args.no_configs:
         out["configs"] = extra_configs(lap, torch, gg, np)
-    if args.warmstart:
-        out["warm_start"] = warm_start_config(lap, torch, gg, np)
     if not args.no_cpu:
-        t_cpu, reps, cres = cpu_baseline(L, K_PAIRS, TOL)
-        out["cpu_baseline"] = {"value": round(t_cpu, 4), "unit": "s", "cores": 1, "kind": "oracle",
-                               "sample": f"full solve of the same workload (k={K_PAIRS}, tol={TOL}), "
-                                         f"median of {reps} runs; FP64 Algorithm 2 with IC(0), m_min 5, "
-                                         f"m_max 10, ITMAX 20, delta_PCG 1e-2",
-                               "mvp": cres.mvp, "outer": cres.outer,
-                               "speedup_gpu_vs_cpu": round(t_cpu / t_mixed, 2)}
+        t_cpu, cres, est, full_mvp = cpu_baseline(L, golden)
+        out["cpu_baseline"] = {"value": None if est is None else round(est, 2), "unit": "s", "cores": 1,
+                               "kind": "oracle", **host_info(),
+                               "sample": f"oracle (FP64 Algorithm 2, IC(0), paper parameters, one thread) on the "
+                                         f"same graph, k={K_PAIRS}, tol={TOL}, seed 1: first {cres.outer} outer "
+                                         f"iterations ({cres.mvp} products, IC(0) set-up included) in "
+                                         f"{t_cpu:.2f}s, scaled by the {full_mvp} products of the full oracle "
+                                         f"solve", "sample_s": round(t_cpu, 3), "sample_mvp": cres.mvp,
+                               "speedup_gpu_vs_cpu": None if est is None else round(est / t_step, 1)}
     print(json.dumps(out))
 
 

@@ -84,8 +84,11 @@ typedef struct {
     uint64_t seed;       /* SplitMix64 stream for start vectors */
     const double *init;  /* optional start block, n x init_cols column-major, caller's
                             vertex order; NULL for a seeded random start.  The solver
-                            orthogonalizes it, so any columns will do; the answer is
-                            certified either way and only the iteration count changes */
+                            orthogonalizes it, so any columns will do; columns with a
+                            non-finite entry, or inside the span of what is already in
+                            the basis, are skipped (info->warm_start_used counts the
+                            others) and the seeded random start takes over.  The answer
+                            is certified either way and only the iteration count changes */
     int init_cols;
     int init_on_device;  /* 0: init is host memory; 1: device memory */
 } lap_eigs_opts;
@@ -93,10 +96,15 @@ typedef struct {
 typedef struct {
     int nconv;           /* certified pairs returned (the first nconv entries) */
     int ncomp;           /* connected components = multiplicity of eigenvalue 0 */
-    int outer;           /* outer iterations (correction equations solved) */
+    int outer;           /* outer iterations: correction equations solved (steps that
+                            only load the caller's start block are not counted) */
     int inner;           /* PCG iterations, summed over the columns */
     long long mvp;       /* Laplacian-vector products; a b-column product counts b */
     double seconds;      /* wall time of the call */
+    int warm_start_used; /* columns of opts.init that entered the search space; 0 when no
+                            start block was given or none was usable (every column
+                            non-finite or inside the span of the deflated vectors), in
+                            which case the seeded random start took their place */
 } lap_eigs_info;
 
 void lap_eigs_default_opts(lap_eigs_opts *opts);
@@ -292,8 +300,27 @@ typedef struct {
 typedef struct lap_mpnn lap_mpnn;
 
 lap_status lap_mpnn_create(const lap_mpnn_config *cfg, lap_mpnn **out);
+
+/* Keeping a trained network (checkpoint of the warm-start network and of its
+ * optimizer).  lap_mpnn_save writes a versioned file: the line "LAPEIG-MPNN",
+ * a one-line JSON header {"format": 1, "layers", "hidden", "random_channels",
+ * "out_cols", "seed", "num_params", "adam_step", "payload_bytes", "dtype":
+ * "float32-le", "fnv1a64"}, then the parameters and Adam's two moment
+ * vectors (num_params float32 values each, little-endian, the flat order of
+ * lap_mpnn_get_params); it writes path.tmp and renames it over path.
+ * lap_mpnn_load checks the whole file on the host before any HIP call
+ * (magic, format, configuration limits, num_params against the
+ * configuration, payload size, FNV-1a checksum of the payload, finite
+ * values) and then creates the network on the current device with those
+ * parameters and that Adam state, so training resumes where it stopped.
+ * Errors: LAP_EINVAL (NULL arguments, unreadable or malformed file, failed
+ * write), LAP_EUNSUPPORTED (a newer format), LAP_ENOMEM / LAP_EDEVICE. */
+lap_status lap_mpnn_save(const lap_mpnn *net, const char *path);
+lap_status lap_mpnn_load(const char *path, lap_mpnn **out);
 void lap_mpnn_destroy(lap_mpnn *net);
 int64_t lap_mpnn_num_params(const lap_mpnn *net);
+/* The configuration a network was created (or loaded) with; LAP_EINVAL on NULL. */
+lap_status lap_mpnn_get_config(const lap_mpnn *net, lap_mpnn_config *cfg);
 lap_status lap_mpnn_get_params(const lap_mpnn *net, float *params);
 lap_status lap_mpnn_set_params(lap_mpnn *net, const float *params); /* also resets Adam */
 lap_status lap_mpnn_infer(lap_mpnn *net, lap_plan *plan, uint64_t feature_seed, double *V0, void *stream);

@@ -43,6 +43,7 @@ EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap
             "lap_plan_set_layout", "lap_plan_layout", "lap_plan_autotune",
             "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
+            "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
             "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
@@ -79,7 +80,8 @@ class _MpnnConfig(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [("nconv", ctypes.c_int), ("ncomp", ctypes.c_int), ("outer", ctypes.c_int),
-                ("inner", ctypes.c_int), ("mvp", ctypes.c_longlong), ("seconds", ctypes.c_double)]
+                ("inner", ctypes.c_int), ("mvp", ctypes.c_longlong), ("seconds", ctypes.c_double),
+                ("warm_start_used", ctypes.c_int)]
 
 
 def library_path() -> str:
@@ -134,12 +136,15 @@ def load_library():
     lib.lap_mpnn_infer.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
     lib.lap_mpnn_loss_grad.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int, f64p, f32p, vp]
     lib.lap_mpnn_train_step.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int, ctypes.c_float, f64p, vp]
+    lib.lap_mpnn_save.argtypes = [vp, ctypes.c_char_p]
+    lib.lap_mpnn_load.argtypes = [ctypes.c_char_p, P(vp)]
+    lib.lap_mpnn_get_config.argtypes = [vp, P(_MpnnConfig)]
     lib.lap_status_string.argtypes = [ctypes.c_int]
     lib.lap_status_string.restype = ctypes.c_char_p
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
     for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
-                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch"]:
+                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -249,6 +254,7 @@ class EigResult:
     mvp: int
     seconds: float
     status: int
+    warm_start_used: int = 0
 
 
 def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0, block=1, seed=1, init=None):
@@ -300,7 +306,7 @@ def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noc
     nc = info.nconv
     vec = X[:nc] if evecs_on_device else X[:nc].T.copy()
     return EigResult(ev[:nc].copy(), vec, res[:nc].copy(), nc, info.ncomp, info.outer, info.inner,
-                     int(info.mvp), info.seconds, code)
+                     int(info.mvp), info.seconds, code, info.warm_start_used)
 
 
 def lap_eigs_csr(L, k, tol, **kw) -> EigResult:
@@ -505,6 +511,23 @@ class Mpnn:
                                                   int(X.shape[0]), float(lr), ctypes.byref(loss),
                                                   _stream_handle(stream)))
         return loss.value
+
+    def save(self, path):
+        """Write the parameters and the Adam state to `path` (lap_mpnn_save)."""
+        _check(load_library().lap_mpnn_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        """A network created from a file written by save (lap_mpnn_load)."""
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.lap_mpnn_load(os.fsencode(path), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.num_params = int(lib.lap_mpnn_num_params(h))
+        self.cfg = _MpnnConfig()
+        _check(lib.lap_mpnn_get_config(h, ctypes.byref(self.cfg)))
+        return self
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

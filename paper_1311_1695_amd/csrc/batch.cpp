@@ -270,6 +270,7 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
             infos[g].inner = hres[g].inner;
             infos[g].mvp = hres[g].mvp;
             infos[g].seconds = secs;
+            infos[g].warm_start_used = 0;
         }
     }
     if (status == LAP_ENOCONV) set_error("some graphs reached the outer-iteration limit (see infos[g].nconv)");

@@ -105,9 +105,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_normalize(const double *__restr
                                                            double *__restrict__ vcol,
                                                            double *__restrict__ wcol) {
     const double s = norm_scale(norm_rows, norm_nrows, st);
+    // a degenerate direction (s = 0, possibly from a non-finite input) leaves
+    // exact zero columns, never 0 * inf or 0 * NaN
     for_each_row<double, Wt, false>(g, w, v, [&](int i, double xi, double yi, double) {
-        vcol[i] = xi * s;
-        wcol[i] = yi * s;
+        vcol[i] = s != 0.0 ? xi * s : 0.0;
+        wcol[i] = s != 0.0 ? yi * s : 0.0;
     });
 }
 
@@ -960,7 +962,8 @@ __global__ __launch_bounds__(kBlock) void k_scale_copy(const double *__restrict_
                                                        JDStatus *st, int n, const double *__restrict__ v,
                                                        double *__restrict__ out) {
     const double sc = norm_scale(norm_rows, norm_nrows, st);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = v[i] * sc;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[i] = sc != 0.0 ? v[i] * sc : 0.0;
 }
 
 inline int vec_grid(int n) {

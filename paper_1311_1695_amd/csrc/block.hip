@@ -564,6 +564,13 @@ __global__ void k_cm_to_rm(int n, int b, const double *__restrict__ in, const in
     }
 }
 
+// flags[c] != 0 when column c of the n x b column-major block holds a
+// non-finite entry (flags cleared by the caller)
+__global__ void k_nonfinite_cols(int n, int b, const double *__restrict__ in, int *__restrict__ flags) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < (size_t)n * b; t += (size_t)gridDim.x * blockDim.x)
+        if (!isfinite(in[t])) atomicOr(flags + t / n, 1);
+}
+
 inline int bgrid(size_t work) {
     size_t g = (work + kBlock - 1) / kBlock;
     const size_t cap = 4 * (size_t)device_cu_count();
@@ -625,6 +632,11 @@ template void blk_zero_space<double>(int, int, const int *, const double *, doub
 
 void blk_cm_to_rm(int n, int b, const double *in, const int *map, double *out, int ldo, hipStream_t s) {
     hipLaunchKernelGGL(k_cm_to_rm, dim3(bgrid((size_t)n * b)), dim3(kBlock), 0, s, n, b, in, map, out, ldo);
+    LAP_HIP(hipGetLastError());
+}
+
+void blk_nonfinite_cols(int n, int b, const double *in, int *flags_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_nonfinite_cols, dim3(bgrid((size_t)n * b)), dim3(kBlock), 0, s, n, b, in, flags_dev);
     LAP_HIP(hipGetLastError());
 }
 

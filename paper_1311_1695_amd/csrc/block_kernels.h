@@ -72,6 +72,8 @@ template <typename T>
 void blk_zero_space(int n, int nz, const int *comp, const double *isz, double *XV, int ldb, T *Q, int ldq,
                     hipStream_t s);
 void blk_extract(int n, int nc, const double *in, int ldi, double *out, hipStream_t s);
+// flags_dev[c] |= 1 for each column c of the n x b column-major block with a non-finite entry
+void blk_nonfinite_cols(int n, int b, const double *in, int *flags_dev, hipStream_t s);
 // out[map[i] * ldo + c] = in[i + c n] (map NULL: identity)
 void blk_cm_to_rm(int n, int b, const double *in, const int *map, double *out, int ldo, hipStream_t s);
 template <typename T>

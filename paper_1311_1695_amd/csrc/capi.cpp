@@ -136,6 +136,14 @@ void lap_mpnn_destroy(lap_mpnn *m) {
 
 int64_t lap_mpnn_num_params(const lap_mpnn *m) { return m ? (int64_t)m->nparams : 0; }
 
+lap_status lap_mpnn_get_config(const lap_mpnn *m, lap_mpnn_config *cfg) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(m && cfg, LAP_EINVAL, "network or config is NULL");
+    *cfg = m->cfg;
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
 lap_status lap_mpnn_get_params(const lap_mpnn *m, float *params) {
     LAP_GUARD_BEGIN
     LAP_REQUIRE(m && params, LAP_EINVAL, "network or params is NULL");

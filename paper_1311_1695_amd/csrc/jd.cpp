@@ -205,7 +205,11 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         if (nz > 0) jd_zero_space<T>(n, nz, P->d_comp.get(), isz.get(), B.get(), Q.get(), ldq, s);
         for (int c = 0; c < nz; ++c) { lam.push_back(0.0); resid.push_back(0.0); }
     }
+    // it: correction equations solved (the documented outer-iteration count);
+    // steps: expansions of the search space, the loading of a start block included
     int nx = nz, m = 0, it = 0;
+    long long steps = 0;
+    const long long max_steps = 2LL * kmax + mmax + 64;
     int pcg_q = -1;  // projector width of the last correction equation of this solve
     int y_rows = 0;  // order of the block of H that theta and Y diagonalize
     long long mvp = 0, inner = 0;
@@ -214,7 +218,8 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
 
     // start vectors: the caller's block (renumbered) or seeded random columns
     DevBuf<double> init_dev;
-    int init_left = 0, init_next = 0;
+    int init_left = 0, init_next = 0, init_used = 0;
+    bool src_from_init = false;  // the direction being added is a column of the caller's block
     if (o.init && o.init_cols > 0) {
         init_dev.alloc((size_t)n * o.init_cols);
         DevBuf<double> tmp((size_t)n * o.init_cols);
@@ -225,11 +230,16 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         LAP_HIP(hipStreamSynchronize(s));
         init_left = std::min(o.init_cols, mmax - 1);
     }
+    // a column of the caller's block while any is left (one that is
+    // non-finite or lies in span[X V] comes out of the orthogonalization as
+    // a degenerate direction and is dropped), then seeded random columns
     auto next_start = [&]() -> const double * {
         if (init_left > 0) {
             --init_left;
+            src_from_init = true;
             return init_dev.get() + (size_t)(init_next++) * n;
         }
+        src_from_init = false;
         jd_random(n, o.seed, start_col++, P->d_iperm.get(), vrand.get(), s);
         return vrand.get();
     };
@@ -239,13 +249,13 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     if (nx < k) src = next_start();
 
     while (nx < k) {
-        if (it >= kmax) {
+        if (it >= kmax || steps >= max_steps) {
             status = LAP_ENOCONV;
             set_error("outer-iteration limit " + std::to_string(kmax) + " reached with " + std::to_string(nx) +
                       " of " + std::to_string(k) + " pairs certified");
             break;
         }
-        ++it;
+        ++steps;
         // step 2: orthogonalize against [X | V]; step 3: normalize, w = G v
         if (src_is_t) jd_orth<T>(n, B.get(), nx + m, t.get(), v.get(), rs, st.get(), s);
         else jd_orth<double>(n, B.get(), nx + m, src, v.get(), rs, st.get(), s);
@@ -269,13 +279,15 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
                        hm, ++seq);
             wait_published(hm, seq, s);
             if (first && hm->degenerate) {
-                // the new direction lay in span[X V]: drop it, take a fresh start vector
+                // the new direction lay in span[X V] (or was not finite): drop
+                // it, take a fresh start vector
                 --m;
                 need_pcg = false;
                 src_is_t = false;
                 src = next_start();
                 break;
             }
+            if (first && src_from_init && !src_is_t) ++init_used;
             first = false;
             const double th = hm->theta, rn = hm->rnorm;
             if (!std::isfinite(th) || !std::isfinite(rn))
@@ -329,8 +341,10 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
             };
             if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(2 * q + (inc ? 1 : 0), s, enqueue), s));
             else enqueue();
+            ++it;
         }
         src_is_t = true;
+        src_from_init = false;
     }
     {
         // inner products of all correction equations of this solve
@@ -351,6 +365,7 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         info->inner = (int)inner;
         info->mvp = mvp;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        info->warm_start_used = init_used;
     }
     return status;
 }

@@ -166,15 +166,25 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         src_cols = b;
         src_is_t = false;
     };
+    int init_used = 0;
     if (o.init && o.init_cols > 0) {
-        // the caller's start vectors (column-major, caller order) first, then random columns
+        // the caller's start vectors (column-major, caller order) first, then
+        // random columns; a column with a non-finite entry is left out (its
+        // place keeps a random column)
         const int c0 = std::min(o.init_cols, b);
         DevBuf<double> tmp((size_t)n * c0);
+        DevBuf<int> bad(c0);
         LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * c0,
                                 o.init_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        LAP_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int) * c0, s));
+        blk_nonfinite_cols(n, c0, tmp.get(), bad.get(), s);
+        std::vector<int> hbad(c0);
+        LAP_HIP(hipMemcpyAsync(hbad.data(), bad.get(), sizeof(int) * c0, hipMemcpyDeviceToHost, s));
         blk_random(n, b, o.seed, colbase, P->d_iperm.get(), Vn.get(), b, s);
         colbase += b;
-        blk_cm_to_rm(n, c0, tmp.get(), P->d_perm.get(), Vn.get(), b, s);
+        LAP_HIP(hipStreamSynchronize(s));
+        for (int c = 0; c < c0; ++c)
+            if (!hbad[c]) blk_cm_to_rm(n, 1, tmp.get() + (size_t)c * n, P->d_perm.get(), Vn.get() + init_used++, b, s);
         LAP_HIP(hipStreamSynchronize(s));
         src_cols = b;
         src_is_t = false;
@@ -330,6 +340,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         info->inner = (int)inner;
         info->mvp = mvp;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        info->warm_start_used = init_used;
     }
     return status;
 }

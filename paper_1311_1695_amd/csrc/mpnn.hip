@@ -232,14 +232,15 @@ __global__ __launch_bounds__(kBlock) void k_loss(int p, int kx, const float *__r
 }
 
 __global__ void k_adam(long long np, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
-                       float *__restrict__ v, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+                       float *__restrict__ v, float lr, float b1, float b2, float omb1, float omb2, float eps,
+                       float inv_bc1, float inv_bc2) {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < np; t += (long long)gridDim.x * blockDim.x) {
         const float gt = g[t];
-        const float mt = b1 * m[t] + (1.f - b1) * gt;
-        const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+        const float mt = b1 * m[t] + omb1 * gt;
+        const float vt = b2 * v[t] + omb2 * gt * gt;
         m[t] = mt;
         v[t] = vt;
-        w[t] -= lr * (mt / bc1) / (sqrtf(vt / bc2) + eps);
+        w[t] -= lr * (mt * inv_bc1) / (sqrtf(vt * inv_bc2) + eps);
     }
 }
 
@@ -437,10 +438,14 @@ double mpnn_loss_grad(lap_mpnn *m, const lap_plan &P, uint64_t seed, const doubl
 
 void mpnn_adam(lap_mpnn *m, float lr, hipStream_t s) {
     ++m->step;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float bc1 = 1.f - std::pow(b1, (float)m->step), bc2 = 1.f - std::pow(b2, (float)m->step);
+    // Adam (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8).  The bias
+    // corrections 1 - beta^t are formed in double: in single precision
+    // 1 - 0.999^t loses about five digits to cancellation for small t.
+    const double b1 = 0.9, b2 = 0.999;
+    const double bc1 = 1.0 - std::pow(b1, (double)m->step), bc2 = 1.0 - std::pow(b2, (double)m->step);
     hipLaunchKernelGGL(k_adam, dim3(egrid(m->nparams)), dim3(kBlock), 0, s, m->nparams, m->params.get(),
-                       m->grad.get(), m->adam_m.get(), m->adam_v.get(), lr, b1, b2, 1e-8f, bc1, bc2);
+                       m->grad.get(), m->adam_m.get(), m->adam_v.get(), lr, (float)b1, (float)b2, (float)(1.0 - b1),
+                       (float)(1.0 - b2), 1e-8f, (float)(1.0 / bc1), (float)(1.0 / bc2));
     LAP_HIP(hipGetLastError());
 }
 

@@ -164,3 +164,86 @@ def test_eigs_options_default_to_a_host_start_block():
     o = lap._Opts()
     lib.lap_eigs_default_opts(ctypes.byref(o))
     assert o.init_on_device == 0 and o.init_cols == 0 and not o.init
+
+
+def _net_file(path, *, magic=b"LAPEIG-MPNN\n", fmt=1, layers=1, hidden=4, rc=0, oc=2, num_params=None,
+              step=3, payload=None, checksum=None, payload_bytes=None, drop=None):
+    """A network file in the documented format (lapeig.h, lap_mpnn_save),
+    written here field by field so each check of the loader can be hit."""
+    # per layer a 2 F_in x F_out matrix and F_out biases (F_0 = 3 + rc)
+    dims = [3 + rc] + [hidden] * layers + [oc]
+    np_ = sum(2 * dims[i] * dims[i + 1] + dims[i + 1] for i in range(layers + 1))
+    if num_params is None:
+        num_params = np_
+    if payload is None:
+        rng = np.random.default_rng(0)
+        payload = np.concatenate([rng.standard_normal(2 * np_), rng.random(np_)]).astype("<f4").tobytes()
+    h = 0xcbf29ce484222325
+    for byte in payload:  # FNV-1a 64
+        h = ((h ^ byte) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    fields = {"format": fmt, "layers": layers, "hidden": hidden, "random_channels": rc, "out_cols": oc,
+              "seed": 5, "num_params": num_params, "adam_step": step,
+              "payload_bytes": len(payload) if payload_bytes is None else payload_bytes,
+              "dtype": "float32-le", "fnv1a64": "%016x" % (h if checksum is None else checksum)}
+    if drop:
+        del fields[drop]
+    import json
+    with open(path, "wb") as fh:
+        fh.write(magic)
+        fh.write((json.dumps(fields) + "\n").encode())
+        fh.write(payload)
+    return np_
+
+
+def _load_code(path):
+    lib = lap.load_library()
+    h = ctypes.c_void_p()
+    code = lib.lap_mpnn_load(os.fsencode(path) if path is not None else None, ctypes.byref(h))
+    assert not h.value
+    return code
+
+
+def test_network_file_is_checked_before_the_device(tmp_path):
+    """lap_mpnn_load reads and checks the whole file on the host: every
+    malformed file is rejected with LAP_EINVAL (LAP_EUNSUPPORTED for a newer
+    format) before any HIP call; a valid one gets past the checks and only
+    then meets the missing device."""
+    p = str(tmp_path / "net.bin")
+    assert _load_code(None) == lap.LAP_EINVAL
+    assert _load_code(str(tmp_path / "missing.bin")) == lap.LAP_EINVAL
+    cases = [dict(magic=b"NOT-A-NET\n"), dict(fmt=2), dict(layers=9), dict(hidden=0), dict(hidden=33),
+             dict(rc=17), dict(oc=0), dict(oc=32), dict(step=-1), dict(num_params=7), dict(payload_bytes=12),
+             dict(checksum=1), dict(drop="fnv1a64"), dict(drop="num_params")]
+    for kw in cases:
+        _net_file(p, **kw)
+        want = lap.LAP_EUNSUPPORTED if kw.get("fmt") == 2 else lap.LAP_EINVAL
+        assert _load_code(p) == want, kw
+    n = _net_file(p)
+    good = open(p, "rb").read()
+    with open(p, "wb") as fh:  # truncated payload
+        fh.write(good[:-4])
+    assert _load_code(p) == lap.LAP_EINVAL
+    with open(p, "wb") as fh:  # trailing bytes
+        fh.write(good + b"\0")
+    assert _load_code(p) == lap.LAP_EINVAL
+    bad = np.concatenate([np.full(2 * n, np.nan), np.ones(n)]).astype("<f4").tobytes()
+    _net_file(p, payload=bad)  # non-finite values (checksum valid)
+    assert _load_code(p) == lap.LAP_EINVAL
+    neg = np.concatenate([np.zeros(2 * n), -np.ones(n)]).astype("<f4").tobytes()
+    _net_file(p, payload=neg)  # negative second moments
+    assert _load_code(p) == lap.LAP_EINVAL
+    _net_file(p)
+    if not _has_gpu():
+        assert _load_code(p) == lap.LAP_EDEVICE
+    lib = lap.load_library()
+    assert lib.lap_mpnn_save(None, os.fsencode(p)) == lap.LAP_EINVAL
+    cfg = lap._MpnnConfig()
+    assert lib.lap_mpnn_get_config(None, ctypes.byref(cfg)) == lap.LAP_EINVAL
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False

@@ -73,6 +73,65 @@ def test_loss_and_gradient_match_the_fp64_reference(weighted):
     assert np.linalg.norm(V - Yh) <= 1e-4 * np.linalg.norm(Yh)
 
 
+def test_adam_step_matches_the_fp64_reference():
+    """k_adam against oracle/mpnn_oracle.adam_step: three consecutive
+    training steps, each fed the gradient the GPU computed for the current
+    parameters (read back through loss_grad, which leaves the Adam state
+    alone), the moments carried on the reference side in FP64."""
+    L, X = small_case(False)
+    cfg = mo.Config(layers=2, hidden=16, random_channels=4, out_cols=5)
+    net = lap.Mpnn(layers=2, hidden=16, random_channels=4, out_cols=5, seed=3)
+    plan = lap.Plan(L)
+    Xt = _tensor(X)
+    lr = 5e-3
+    p = net.get_params().astype(np.float64)
+    m = np.zeros(cfg.num_params())
+    v = np.zeros(cfg.num_params())
+    for step in range(1, 4):
+        _, g = net.loss_grad(plan, Xt, feature_seed=9)
+        net.train_step(plan, Xt, lr=lr, feature_seed=9)
+        got = net.get_params().astype(np.float64)
+        ref, m, v = mo.adam_step(p, g.astype(np.float64), m, v, step, lr)
+        # FP32 update: rounding of w (2^-24 |w|) plus a few ulps of the step (<= lr)
+        err = np.abs(got - ref)
+        assert np.all(err <= 2e-7 * np.abs(ref) + 2e-6 * lr), (step, float(err.max()),
+                                                              float(np.max(err / (np.abs(ref) + lr))))
+        assert np.abs(got - p).max() > 0.5 * lr  # the parameters did move
+        p = got
+
+
+def test_save_and_load_round_trip(tmp_path):
+    """lap_mpnn_save then lap_mpnn_load: the same configuration, parameters
+    bit for bit, the same inferred block, and the same Adam state (one more
+    training step on each gives the same parameters)."""
+    L, X = small_case(False)
+    plan = lap.Plan(L)
+    Xt = _tensor(X)
+    net = lap.Mpnn(layers=2, hidden=16, random_channels=3, out_cols=5, seed=11)
+    for _ in range(3):
+        net.train_step(plan, Xt, lr=4e-3, feature_seed=2)
+    path = str(tmp_path / "net.lapmpnn")
+    net.save(path)
+    other = lap.Mpnn.load(path)
+    assert (other.cfg.layers, other.cfg.hidden, other.cfg.random_channels, other.cfg.out_cols, other.cfg.seed) == \
+        (2, 16, 3, 5, 11)
+    assert np.array_equal(other.get_params(), net.get_params())
+    assert torch.equal(other.infer(plan, feature_seed=2), net.infer(plan, feature_seed=2))
+    net.train_step(plan, Xt, lr=4e-3, feature_seed=2)
+    other.train_step(plan, Xt, lr=4e-3, feature_seed=2)
+    assert np.array_equal(other.get_params(), net.get_params())
+    # the file is what lapeig.h documents: magic, JSON header, 3 x num_params floats
+    import json
+    with open(path, "rb") as fh:
+        assert fh.readline() == b"LAPEIG-MPNN\n"
+        hdr = json.loads(fh.readline())
+        payload = fh.read()
+    assert hdr["format"] == 1 and hdr["num_params"] == net.num_params and hdr["adam_step"] == 3
+    assert len(payload) == hdr["payload_bytes"] == 12 * net.num_params
+    assert np.array_equal(np.frombuffer(payload[:4 * net.num_params], dtype="<f4"),
+                          lap.Mpnn.load(path).get_params())
+
+
 def test_training_on_the_gpu_lowers_the_loss():
     graphs = [chung_lu_tc(3000, s) for s in (31, 32, 33)]
     plans = [lap.Plan(L) for L in graphs]

@@ -68,6 +68,16 @@ def graph(name):
     raise KeyError(name)
 
 
+@functools.lru_cache(maxsize=None)
+def golden(fname):
+    """Stored oracle results (tests/golden, written by make_golden.py from
+    the CPU oracle only)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", fname)) as fh:
+        return json.load(fh)
+
+
 def _plan(name):
     return lap.Plan(graph(name))
 
@@ -253,6 +263,44 @@ def test_pcg_fp32_reaches_tolerance_and_tracks_oracle(name, nlock):
     assert np.linalg.norm(t - t_ref) <= 2e-3 * np.linalg.norm(t_ref)
 
 
+# Indefinite projected systems: Q = the q smallest eigenvectors, r random
+# and orthogonal to Q, theta above lambda_q (the next eigenvalue), so the
+# projected operator has a negative direction and p'(G - theta I)p <= 0 ends
+# the iteration (Algorithm 2 step 8 with a non-definite operator).  The
+# oracle's FP64 run stops at the iteration given in the comment; in FP32 the
+# deciding value p'Ap must keep its sign, which holds when it is far from
+# rounding level, so the stopping step must agree exactly and t within an
+# FP32 bound.
+@pytest.mark.parametrize("name,q,factor", [
+    ("pa5k", 1, 1.1),     # stops after 9 products
+    ("cl30k", 1, 1.9),    # 10
+    ("cl30k_w", 1, 3.0),  # 8
+    ("pa5k", 2, 1.9),     # 3
+    ("cl30k", 2, 30.0),   # 1: no step taken, t = M(-r)
+])
+def test_pcg_fp32_breakdown_matches_oracle(name, q, factor):
+    L = graph(name)
+    lam, V = oracle_ref(name, 6)
+    Q = V[:, :q]
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(L.n)
+    r -= Q @ (Q.T @ r)
+    theta = float(lam[q] * factor)
+    t_ref, mvp_ref, br_ref = oracle.pcg_correction(L, theta, Q, r, precond=oracle.PREC_JACOBI, itmax=20, rtol=1e-2)
+    assert br_ref
+    plan = lap.Plan(L)
+    Qt = torch.tensor(Q.T.copy(), device="cuda")
+    Rt = torch.tensor(r[None, :].copy(), device="cuda")
+    for dtype, tol in (("f32", 2e-4), ("f64", 1e-9)):
+        Tt = torch.zeros_like(Rt)
+        its = lap.lap_pcg(plan, theta, Qt, Rt, Tt, itmax=20, rtol=1e-2, dtype=dtype)
+        t = Tt.cpu().numpy()[0]
+        assert int(its[0]) == mvp_ref, (dtype, int(its[0]), mvp_ref)
+        err = np.linalg.norm(t - t_ref) / np.linalg.norm(t_ref)
+        assert err <= tol, (dtype, err)
+        assert np.abs(Q.T @ t).max() <= 1e-5 * np.linalg.norm(t)
+
+
 def test_pcg_multiple_columns_and_plan_order():
     L, Q, theta, r = _pcg_case("cl30k", 4, 9)
     plan = lap.Plan(L)
@@ -328,12 +376,11 @@ def test_eigs_large_graph_at_full_size(precision):
     """The Chung-Lu graph of 330k vertices (n = 297,292 after the largest
     component), full size, in the launch configuration of the bench (its
     product grid, the Gram-Schmidt grid and the PCG grid all exceed what the
-    smaller graphs use).  Too large for the oracle's JD, so it is checked by
-    what holds at any size: residuals recomputed on the host within the
-    tolerance, orthonormal eigenvectors, the zero pair, and the eigenvalues
-    of single-vector JD in this precision against those of block JD in FP64,
-    two independent paths (each certified value lies within its residual,
-    1e-8 lambda, of an eigenvalue)."""
+    smaller graphs use): single-vector JD against the oracle's eigenvalues
+    (tests/golden/cl330k_k20.json, FP64 Algorithm 2 at tol 1e-9, about three
+    minutes on one core), residuals recomputed on the host, orthonormal
+    eigenvectors, the zero pair, and block JD in FP64 as an independent
+    second GPU path."""
     L = graph("cl330k")
     plan = lap.Plan(L)
     r = lap.lap_eigs(plan, 8, 1e-8, precision=precision)
@@ -343,6 +390,9 @@ def test_eigs_large_graph_at_full_size(precision):
     x0 = r.evecs[:, 0]
     assert np.allclose(np.abs(x0), 1.0 / np.sqrt(L.n), rtol=0, atol=1e-10)
     assert np.all(np.diff(r.evals) >= 0)
+    gold = golden("cl330k_k20.json")
+    ref = np.asarray(gold["evals"][:8])
+    assert np.all(np.abs(r.evals - ref) <= 1e-8 * ref + 1e-13), (r.evals, ref)
     b = cl330k_block_fp64()
     assert b.nconv == 8
     _certified(L, b, 1e-8)
@@ -398,6 +448,40 @@ def test_eigs_start_block_and_sign_convention():
     for j in range(r.nconv):
         x = r.evecs[:, j]
         assert x[np.argmax(np.abs(x))] > 0
+
+
+@pytest.mark.parametrize("block", [1, 4])
+def test_eigs_start_block_fallbacks(block):
+    """A start block is used column by column; columns with a non-finite
+    entry or inside the span of what the basis holds are skipped
+    (info.warm_start_used counts the others) and the seeded random start
+    takes over.  The certified answer is the same in every case; outer
+    iterations count correction equations only."""
+    L = graph("pa5k")
+    w, V = dense_ref("pa5k")
+    plan = lap.Plan(L)
+    kw = dict(block=block, m_min=8, m_max=20) if block > 1 else {}
+    good = V[:, 1:5] + 1e-3 * np.random.default_rng(1).standard_normal((L.n, 4))
+    nan = good.copy()
+    nan[7, :] = np.nan
+    mixed = good.copy()
+    mixed[3, 1] = np.inf
+    dup = np.concatenate([good[:, :2], good[:, :2], np.ones((L.n, 1))], axis=1)  # 2 new + 2 copies + the zero vector
+    base = lap.lap_eigs(plan, 6, 1e-8, **kw)
+    assert base.warm_start_used == 0
+    for init, used in ((good, 4), (nan, 0), (mixed, 3), (dup, 2)):
+        r = lap.lap_eigs(plan, 6, 1e-8, init=init, **kw)
+        assert r.nconv == 6
+        _certified(L, r, 1e-8)
+        check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
+        if block == 1:
+            assert r.warm_start_used == used, (r.warm_start_used, used)
+        else:  # the block path drops non-finite columns before its orthogonalization
+            assert r.warm_start_used == {4: 4, 0: 0, 3: 3, 2: 4}[used]  # at most b columns
+    # near-eigenvectors as the start: few correction equations, none spent loading
+    r = lap.lap_eigs(plan, 5, 1e-8, init=V[:, 1:5], **kw)
+    assert r.nconv == 5 and r.warm_start_used == 4
+    assert r.outer <= base.outer
 
 
 def test_eigs_kmax_exhaustion_and_errors():
