@@ -194,6 +194,22 @@ lap_status lap_eigs_csr(const lap_csr *L, int k, double tol, const lap_eigs_opts
 lap_status lap_spmv(lap_plan *plan, lap_dtype dtype, int b, const void *X, void *Y,
                     const double *shift, int flags, void *stream);
 
+/* lap_spmv without any device allocation, for callers that cannot allocate:
+ * code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, semantics and results (bit for bit) as
+ * lap_spmv.  Its scratch -- the renumbered copies of X and Y when flags lacks
+ * LAP_ORDER_PLAN, the shifts, and the partial sums of the hub rows of a
+ * block product -- lives in one fixed 64 MiB device array that each GPU the
+ * library runs on holds until the process ends; a call whose scratch would
+ * exceed it (about 2 n b element bytes in the caller's order, for example
+ * n b > 4M in FP64) returns LAP_EINVAL.  The plan must live on the current
+ * device (else LAP_EINVAL).  All calls on one GPU share that array: calls
+ * that overlap in time on one GPU (several streams or threads) race.  A
+ * shift is copied to the device on the stream (hipMemcpyAsync from host
+ * memory).  Asynchronous on stream. */
+lap_status lap_spmv_noalloc(lap_plan *plan, lap_dtype dtype, int b, const void *X, void *Y,
+                            const double *shift, int flags, void *stream);
+
 /* Block orthogonalization (Algorithm 2 step 2, double precision):
  * W <- an orthonormal basis of (I - Q Q') W, by classical Gram-Schmidt
  * applied twice against Q, then twice within W column by column; columns

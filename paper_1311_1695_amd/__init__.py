@@ -44,7 +44,7 @@ EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap
             "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
             "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
-            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
+            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_spmv_noalloc", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
 
@@ -113,6 +113,7 @@ def load_library():
     lib.lap_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p, P(_Info)]
     lib.lap_eigs_csr.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info)]
     lib.lap_spmv.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
+    lib.lap_spmv_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
     lib.lap_orth.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, ip, vp]
     lib.lap_sym_eig.argtypes = [ctypes.c_int, vp, vp, vp, ip, vp]
     lib.lap_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, f64p, vp, ctypes.c_int, vp, vp, ctypes.c_int,
@@ -144,7 +145,7 @@ def load_library():
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
     for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
-                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config"]:
+                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -338,6 +339,22 @@ def lap_spmv(plan: Plan, X, Y, shift=None, plan_order=False, stream=None):
     _check(lib.lap_spmv(plan._h, _dtype_code(X), b, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                         None if sh is None else sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                         LAP_ORDER_PLAN if plan_order else 0, _stream_handle(stream)))
+
+
+def lap_spmv_noalloc(plan: Plan, X, Y, shift=None, plan_order=False, stream=None):
+    """lap_spmv without device allocation (its scratch is a fixed device
+    array of the library); same arguments and results."""
+    lib = load_library()
+    if X.dtype != Y.dtype or X.shape != Y.shape or not X.is_contiguous() or not Y.is_contiguous():
+        raise LapError(LAP_EINVAL, "X and Y must be contiguous tensors of one shape and dtype")
+    b = 1 if X.dim() == 1 else int(X.shape[1])
+    sh = None
+    if shift is not None:
+        sh = np.ascontiguousarray(np.broadcast_to(np.asarray(shift, dtype=np.float64), (b,)))
+    _check(lib.lap_spmv_noalloc(plan._h, _dtype_code(X), b, ctypes.c_void_p(X.data_ptr()),
+                                ctypes.c_void_p(Y.data_ptr()),
+                                None if sh is None else sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                LAP_ORDER_PLAN if plan_order else 0, _stream_handle(stream)))
 
 
 def lap_orth(Q, W, stream=None) -> int:

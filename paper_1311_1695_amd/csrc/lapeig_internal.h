@@ -204,6 +204,11 @@ template <typename T>
 void spmm(const lap_plan &P, int b, const T *X, T *Y, const double *shift_dev, hipStream_t s);
 template <typename T>
 void spmm(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, hipStream_t s);
+// the same with the per-chunk partial sums of the hub rows in `part`
+// (P.g.nchunks x b values) instead of the plan's own area (null: the plan's)
+template <typename T>
+void spmm_part(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, T *part,
+               hipStream_t s);
 
 // Reduction scratch: per-block partial sums and a completion counter.
 struct ReduceScratch {

@@ -170,7 +170,7 @@ void spmv(const lap_plan &P, const T *x, T *y, double sigma, hipStream_t s) {
 
 template <typename T, int BL>
 static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
-                        hipStream_t s) {
+                        T *part_in, hipStream_t s) {
     const Graph &g = P.g;
     long long units = (long long)g.nslices * BL;
     if (g.nchunks > units) units = g.nchunks;
@@ -179,10 +179,14 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
     if (grid > (1 << 20)) grid = 1 << 20;
     T *part = nullptr;
     if (g.nchunks > 0) {
-        const size_t bytes = (size_t)g.nchunks * b * sizeof(T);
-        lap_plan &mp = const_cast<lap_plan &>(P);
-        LAP_REQUIRE(mp.chunk_part.n >= bytes, LAP_EDEVICE, "block-product scratch not reserved");
-        part = reinterpret_cast<T *>(mp.chunk_part.get());
+        if (part_in) {
+            part = part_in;
+        } else {
+            const size_t bytes = (size_t)g.nchunks * b * sizeof(T);
+            lap_plan &mp = const_cast<lap_plan &>(P);
+            LAP_REQUIRE(mp.chunk_part.n >= bytes, LAP_EDEVICE, "block-product scratch not reserved");
+            part = reinterpret_cast<T *>(mp.chunk_part.get());
+        }
     }
     if (P.weighted)
         hipLaunchKernelGGL((k_spmm<T, true, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx, Y,
@@ -197,14 +201,20 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
 }
 
 template <typename T>
+void spmm_part(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, T *part,
+               hipStream_t s) {
+    if (b <= 1) spmm_launch<T, 1>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+    else if (b <= 2) spmm_launch<T, 2>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+    else if (b <= 4) spmm_launch<T, 4>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+    else if (b <= 8) spmm_launch<T, 8>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+    else if (b <= 16) spmm_launch<T, 16>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+    else if (b <= 32) spmm_launch<T, 32>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+    else spmm_launch<T, 64>(P, b, X, ldx, Y, ldy, shift_dev, part, s);
+}
+
+template <typename T>
 void spmm(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, hipStream_t s) {
-    if (b <= 1) spmm_launch<T, 1>(P, b, X, ldx, Y, ldy, shift_dev, s);
-    else if (b <= 2) spmm_launch<T, 2>(P, b, X, ldx, Y, ldy, shift_dev, s);
-    else if (b <= 4) spmm_launch<T, 4>(P, b, X, ldx, Y, ldy, shift_dev, s);
-    else if (b <= 8) spmm_launch<T, 8>(P, b, X, ldx, Y, ldy, shift_dev, s);
-    else if (b <= 16) spmm_launch<T, 16>(P, b, X, ldx, Y, ldy, shift_dev, s);
-    else if (b <= 32) spmm_launch<T, 32>(P, b, X, ldx, Y, ldy, shift_dev, s);
-    else spmm_launch<T, 64>(P, b, X, ldx, Y, ldy, shift_dev, s);
+    spmm_part<T>(P, b, X, ldx, Y, ldy, shift_dev, nullptr, s);
 }
 
 template <typename T>
@@ -226,6 +236,10 @@ template void spmv<double>(const lap_plan &, const double *, double *, double, h
 template void spmm<float>(const lap_plan &, int, const float *, float *, const double *, hipStream_t);
 template void spmm<double>(const lap_plan &, int, const double *, double *, const double *, hipStream_t);
 template void spmm<float>(const lap_plan &, int, const float *, int, float *, int, const double *, hipStream_t);
+template void spmm_part<float>(const lap_plan &, int, const float *, int, float *, int, const double *, float *,
+                               hipStream_t);
+template void spmm_part<double>(const lap_plan &, int, const double *, int, double *, int, const double *, double *,
+                                hipStream_t);
 template void spmm<double>(const lap_plan &, int, const double *, int, double *, int, const double *, hipStream_t);
 template void permute_rows<float>(const int *, int, int, const float *, float *, hipStream_t);
 template void permute_rows<double>(const int *, int, int, const double *, double *, hipStream_t);
