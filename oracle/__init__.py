@@ -24,7 +24,8 @@ _DEFAULT_LIB = os.path.join(_HERE, "liblapeig_oracle.so")
 _LIB_PATH = os.environ.get("LAPEIG_ORACLE_LIB") or _DEFAULT_LIB
 _lib = None
 
-PREC_NONE, PREC_JACOBI, PREC_IC0 = 0, 1, 2
+PREC_NONE, PREC_JACOBI, PREC_IC0, PREC_FSAI = 0, 1, 2, 3
+FSAI_TAU = 1e-8  # the shift of S = G + tau D in the solvers' FSAI (see lapeig_oracle.c)
 
 
 def build(force: bool = True) -> str:
@@ -44,7 +45,12 @@ class _JDOpts(ctypes.Structure):
     _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("itmax", ctypes.c_int),
                 ("rtol_pcg", ctypes.c_double), ("kmax", ctypes.c_int),
                 ("precond", ctypes.c_int), ("criterion", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("fsai_pos", ctypes.POINTER(ctypes.c_int))]
+
+
+class _DacgOpts(ctypes.Structure):
+    _fields_ = [("itmax", ctypes.c_int), ("precond", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("fsai_pos", ctypes.POINTER(ctypes.c_int))]
 
 
 class _JDInfo(ctypes.Structure):
@@ -80,6 +86,20 @@ def _load():
                                        ctypes.c_int, f64p, f64p, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_double, f64p, i32p]
     lib.orc_pcg_correction.restype = ctypes.c_int
+    lib.orc_pcg_correction_ex.argtypes = [ctypes.c_int, i32p, i32p, f64p, ctypes.c_double,
+                                          ctypes.c_int, f64p, f64p, ctypes.c_int, i32p, ctypes.c_int,
+                                          ctypes.c_double, f64p, i32p]
+    lib.orc_pcg_correction_ex.restype = ctypes.c_int
+    lib.orc_fsai_create.argtypes = [ctypes.c_int, i32p, i32p, f64p, i32p, ctypes.c_double]
+    lib.orc_fsai_create.restype = ctypes.c_void_p
+    lib.orc_fsai_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc_fsai_nnz.argtypes = [ctypes.c_void_p]
+    lib.orc_fsai_nnz.restype = ctypes.c_int
+    lib.orc_fsai_export.argtypes = [ctypes.c_void_p, i32p, i32p, f64p]
+    lib.orc_fsai_apply.argtypes = [ctypes.c_void_p, f64p, f64p]
+    lib.orc_dacg.argtypes = [ctypes.c_int, i32p, i32p, f64p, ctypes.c_int, ctypes.c_double,
+                             P(_DacgOpts), f64p, f64p, f64p, P(_JDInfo)]
+    lib.orc_dacg.restype = ctypes.c_int
     lib.orc_start_value.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.orc_start_value.restype = ctypes.c_double
     lib.orc_jd.argtypes = [ctypes.c_int, i32p, i32p, f64p, ctypes.c_int, ctypes.c_double,
@@ -182,8 +202,48 @@ class IC0:
             self._h = None
 
 
-def pcg_correction(L, theta, Q, r, precond=PREC_JACOBI, itmax=20, rtol=1e-2):
+class FSAI:
+    """Factorized sparse approximate inverse Z of S = G + tau D in a vertex
+    order (pos[v] = position of vertex v; None = natural order): P = Z'Z
+    (the approximate-inverse preconditioner of the Conclusion)."""
+
+    def __init__(self, L, pos=None, tau=FSAI_TAU):
+        lib = _load()
+        self._keep, (rp, cl, vl) = _csr(L)
+        self.n = L.n
+        self._pos = None if pos is None else np.ascontiguousarray(pos, dtype=np.int32)
+        pp = None if self._pos is None else self._pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        self._h = lib.orc_fsai_create(L.n, rp, cl, vl, pp, float(tau))
+
+    def matrix(self):
+        """Z as a scipy CSR matrix (rows and columns are vertex indices)."""
+        import scipy.sparse as sp
+        lib = _load()
+        nnz = lib.orc_fsai_nnz(self._h)
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        cl = np.empty(nnz, dtype=np.int32)
+        vl = np.empty(nnz)
+        lib.orc_fsai_export(self._h, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                            cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                            vl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return sp.csr_matrix((vl, cl, rp), shape=(self.n, self.n))
+
+    def apply(self, r):
+        lib = _load()
+        r, rp = _f64(r)
+        z = np.empty(self.n)
+        lib.orc_fsai_apply(self._h, rp, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return z
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_fsai_destroy(self._h)
+            self._h = None
+
+
+def pcg_correction(L, theta, Q, r, precond=PREC_JACOBI, itmax=20, rtol=1e-2, pos=None):
     """PCG on (I-QQ')(G-theta I)(I-QQ') t = -r (Algorithm 2 step 8).
+    pos: the vertex order of FSAI (precond=PREC_FSAI), None = natural.
     Returns (t, mvp, breakdown)."""
     lib = _load()
     keep, (rp, cl, vl) = _csr(L)
@@ -192,10 +252,12 @@ def pcg_correction(L, theta, Q, r, precond=PREC_JACOBI, itmax=20, rtol=1e-2):
     r, rpp = _f64(r)
     t = np.empty(n)
     br = ctypes.c_int(0)
-    mvp = lib.orc_pcg_correction(n, rp, cl, vl, float(theta), Q.shape[1],
-                                 Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rpp,
-                                 int(precond), int(itmax), float(rtol),
-                                 t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(br))
+    posa = None if pos is None else np.ascontiguousarray(pos, dtype=np.int32)
+    pp = None if posa is None else posa.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    mvp = lib.orc_pcg_correction_ex(n, rp, cl, vl, float(theta), Q.shape[1],
+                                    Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rpp,
+                                    int(precond), pp, int(itmax), float(rtol),
+                                    t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(br))
     return t, int(mvp), bool(br.value)
 
 
@@ -218,14 +280,16 @@ class JDResult:
 
 
 def jd(L, k, tol, *, m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0,
-       precond=PREC_IC0, criterion=0, seed=1) -> JDResult:
+       precond=PREC_IC0, criterion=0, seed=1, fsai_pos=None) -> JDResult:
     """Algorithm 2 for the k smallest eigenpairs of G (k counts the zero
     pairs).  Paper defaults: m_min 5, m_max 10, ITMAX 20, delta_PCG 1e-2,
     IC(0) preconditioning (Section 4)."""
     lib = _load()
     keep, (rp, cl, vl) = _csr(L)
     n = L.n
-    opts = _JDOpts(m_min, m_max, itmax, rtol_pcg, kmax, precond, criterion, seed)
+    posa = None if fsai_pos is None else np.ascontiguousarray(fsai_pos, dtype=np.int32)
+    opts = _JDOpts(m_min, m_max, itmax, rtol_pcg, kmax, precond, criterion, seed,
+                   None if posa is None else posa.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     info = _JDInfo()
     ev = np.zeros(k)
     X = np.zeros(n * k)
@@ -234,6 +298,29 @@ def jd(L, k, tol, *, m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0,
                     ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(info))
+    nc = info.nconv
+    return JDResult(evals=ev[:nc].copy(), evecs=X.reshape(k, n).T[:, :nc].copy(),
+                    res=res[:nc].copy(), nconv=nc, ncomp=info.ncomp, outer=info.outer,
+                    inner=info.inner, mvp=int(info.mvp), nfloor=info.nfloor, status=int(st))
+
+
+def dacg(L, k, tol, *, itmax=0, precond=PREC_IC0, seed=1, fsai_pos=None) -> JDResult:
+    """Algorithm 3 (DACG) for the k smallest eigenpairs of G (k counts the
+    zero pairs).  outer = pairs computed, inner = nonlinear CG iterations,
+    mvp = Laplacian products."""
+    lib = _load()
+    keep, (rp, cl, vl) = _csr(L)
+    n = L.n
+    posa = None if fsai_pos is None else np.ascontiguousarray(fsai_pos, dtype=np.int32)
+    opts = _DacgOpts(itmax, precond, seed, None if posa is None else posa.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    info = _JDInfo()
+    ev = np.zeros(k)
+    X = np.zeros(n * k)
+    res = np.zeros(k)
+    st = lib.orc_dacg(n, rp, cl, vl, int(k), float(tol), ctypes.byref(opts),
+                      ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(info))
     nc = info.nconv
     return JDResult(evals=ev[:nc].copy(), evecs=X.reshape(k, n).T[:, :nc].copy(),
                     res=res[:nc].copy(), nconv=nc, ncomp=info.ncomp, outer=info.outer,

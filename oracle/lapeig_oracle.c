@@ -20,12 +20,18 @@
  *   orc_mgs             modified Gram-Schmidt, Algorithm 2 step 2
  *   orc_ic0_*           incomplete Cholesky with no fill-in, the
  *                       preconditioner of Section 4
+ *   orc_fsai_*          factorized sparse approximate inverse, the
+ *                       approximate-inverse preconditioner that the
+ *                       Conclusion proposes for parallel machines
  *   orc_pcg_correction  PCG on the projected correction equation,
  *                       Algorithm 2 step 8 with M = (I-QQ')P(I-QQ')
  *                       (comments on Algorithm 2; eq. JDsismorethanone)
  *   orc_jd              Algorithm 2 with deflation against converged
  *                       vectors and the m_min/m_max restart (Section 3.2)
  *   orc_start_value     SplitMix64 counter-based start vectors
+ *   orc_dacg            Algorithm 3: DACG, the eigenpairs one by one by a
+ *                       deflated preconditioned nonlinear CG on the
+ *                       Rayleigh quotient (Section 3.3)
  *
  * Readings of points the paper leaves open are marked READING in the code.
  */
@@ -296,20 +302,177 @@ ORC_API void orc_ic0_apply(const orc_ic0 *K, const double *r, double *z) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Preconditioner P (Section 4 uses IC(0); the Jacobi choice D^{-1} is */
-/* the one the GPU path applies).                                      */
+/* FSAI, the factorized sparse approximate inverse of Kolotilina and   */
+/* Yeremin (as reviewed by Benzi): the "approximate inverse            */
+/* preconditioner" that the Conclusion proposes, applied as a product  */
+/* of sparse matrices.  P = Z'Z ~ S^{-1}, Z lower triangular in a      */
+/* vertex order (pos[v] = position of vertex v; NULL = natural order). */
+/* Row v of Z lives on P_v = {v} and the neighbours u of v with        */
+/* pos[u] < pos[v]; its values solve the local system                  */
+/*     S[P_v, P_v] g = e_v,   Z[v, P_v] = g / sqrt(g_v),               */
+/* with S = G + tau D, so that (Z S Z')_vv = 1 and (Z S)_vu = 0 for    */
+/* u in P_v, u != v.                                                   */
+/* READING: tau (1e-8 in the solvers) keeps every local system         */
+/* definite when P_v is a whole connected component (G alone is        */
+/* singular there); a vertex with no edge gets Z_vv = 1.               */
 /* ------------------------------------------------------------------ */
-enum { ORC_PREC_NONE = 0, ORC_PREC_JACOBI = 1, ORC_PREC_IC0 = 2 };
+typedef struct {
+    int n;
+    int *rowptr; /* row v of Z (vertex index), entries in ascending column */
+    int *col;
+    double *val;
+} orc_fsai;
+
+/* G(a, b) from the CSR (columns sorted): binary search in row a. */
+static double lap_entry(int n, const int *rowptr, const int *col, const double *val, int a, int b) {
+    (void)n;
+    int lo = rowptr[a], hi = rowptr[a + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        if (col[mid] == b) return val[mid];
+        if (col[mid] < b) lo = mid + 1; else hi = mid - 1;
+    }
+    return 0.0;
+}
+
+/* Solve the symmetric positive definite m x m system A g = b in place
+ * (A column-major, overwritten by its Cholesky factor; b by g).
+ * Returns 0, or -1 if a pivot is not positive. */
+static int dense_spd_solve(int m, double *A, double *b) {
+    for (int j = 0; j < m; ++j) {
+        double d = A[j + (size_t)j * m];
+        for (int k = 0; k < j; ++k) d -= A[j + (size_t)k * m] * A[j + (size_t)k * m];
+        if (!(d > 0.0)) return -1;
+        d = sqrt(d);
+        A[j + (size_t)j * m] = d;
+        for (int i = j + 1; i < m; ++i) {
+            double s = A[i + (size_t)j * m];
+            for (int k = 0; k < j; ++k) s -= A[i + (size_t)k * m] * A[j + (size_t)k * m];
+            A[i + (size_t)j * m] = s / d;
+        }
+    }
+    for (int i = 0; i < m; ++i) { /* L y = b */
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= A[i + (size_t)k * m] * b[k];
+        b[i] = s / A[i + (size_t)i * m];
+    }
+    for (int i = m - 1; i >= 0; --i) { /* L' g = y */
+        double s = b[i];
+        for (int k = i + 1; k < m; ++k) s -= A[k + (size_t)i * m] * b[k];
+        b[i] = s / A[i + (size_t)i * m];
+    }
+    return 0;
+}
+
+ORC_API orc_fsai *orc_fsai_create(int n, const int *rowptr, const int *col, const double *val,
+                                  const int *pos, double tau) {
+    orc_fsai *Z = (orc_fsai *)calloc(1, sizeof(orc_fsai));
+    Z->n = n;
+    Z->rowptr = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    Z->rowptr[0] = 0;
+    int cnt = 0;
+    for (int v = 0; v < n; ++v) {
+        int pv = pos ? pos[v] : v;
+        for (int p = rowptr[v]; p < rowptr[v + 1]; ++p) {
+            int u = col[p];
+            if (u != v && (pos ? pos[u] : u) < pv) ++cnt;
+        }
+        ++cnt; /* v itself */
+        Z->rowptr[v + 1] = cnt;
+    }
+    Z->col = (int *)malloc(sizeof(int) * (size_t)cnt);
+    Z->val = (double *)malloc(sizeof(double) * (size_t)cnt);
+    for (int v = 0; v < n; ++v) {
+        int pv = pos ? pos[v] : v;
+        int w = Z->rowptr[v];
+        /* P_v in ascending vertex index (the CSR columns are sorted) */
+        for (int p = rowptr[v]; p < rowptr[v + 1]; ++p) {
+            int u = col[p];
+            if (u == v) { Z->col[w++] = v; continue; }
+            if ((pos ? pos[u] : u) < pv) Z->col[w++] = u;
+        }
+        if (w == Z->rowptr[v]) Z->col[w++] = v; /* a row without its diagonal entry */
+        int m = Z->rowptr[v + 1] - Z->rowptr[v];
+        const int *P = Z->col + Z->rowptr[v];
+        double *A = (double *)malloc(sizeof(double) * (size_t)m * m);
+        double *g = (double *)malloc(sizeof(double) * (size_t)m);
+        int iv = -1;
+        for (int a = 0; a < m; ++a) {
+            if (P[a] == v) iv = a;
+            g[a] = 0.0;
+            for (int b = 0; b < m; ++b) {
+                double e = lap_entry(n, rowptr, col, val, P[a], P[b]);
+                if (a == b) e *= 1.0 + tau; /* S = G + tau D on the diagonal */
+                A[a + (size_t)b * m] = e;
+            }
+        }
+        g[iv] = 1.0;
+        double *Zv = Z->val + Z->rowptr[v];
+        if (m == 1 && !(A[0] > 0.0)) {
+            Zv[0] = 1.0; /* no edge: identity row */
+        } else if (dense_spd_solve(m, A, g) == 0 && g[iv] > 0.0) {
+            double sc = 1.0 / sqrt(g[iv]);
+            for (int a = 0; a < m; ++a) Zv[a] = g[a] * sc;
+        } else {
+            /* not reached for tau > 0 on a Laplacian; keep a Jacobi row */
+            for (int a = 0; a < m; ++a) Zv[a] = 0.0;
+            double d = lap_entry(n, rowptr, col, val, v, v);
+            Zv[iv] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+        }
+        free(A);
+        free(g);
+    }
+    return Z;
+}
+
+ORC_API void orc_fsai_destroy(orc_fsai *Z) {
+    if (!Z) return;
+    free(Z->rowptr); free(Z->col); free(Z->val); free(Z);
+}
+
+ORC_API int orc_fsai_nnz(const orc_fsai *Z) { return Z->rowptr[Z->n]; }
+
+/* Z in CSR (rowptr n+1, col and val nnz), vertex indices. */
+ORC_API void orc_fsai_export(const orc_fsai *Z, int *rowptr, int *col, double *val) {
+    memcpy(rowptr, Z->rowptr, sizeof(int) * (size_t)(Z->n + 1));
+    memcpy(col, Z->col, sizeof(int) * (size_t)Z->rowptr[Z->n]);
+    memcpy(val, Z->val, sizeof(double) * (size_t)Z->rowptr[Z->n]);
+}
+
+/* z = Z'(Z r) */
+ORC_API void orc_fsai_apply(const orc_fsai *Z, const double *r, double *z) {
+    int n = Z->n;
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int v = 0; v < n; ++v) {
+        double s = 0.0;
+        for (int e = Z->rowptr[v]; e < Z->rowptr[v + 1]; ++e) s += Z->val[e] * r[Z->col[e]];
+        y[v] = s;
+    }
+    for (int i = 0; i < n; ++i) z[i] = 0.0;
+    for (int v = 0; v < n; ++v)
+        for (int e = Z->rowptr[v]; e < Z->rowptr[v + 1]; ++e) z[Z->col[e]] += Z->val[e] * y[v];
+    free(y);
+}
+
+#define ORC_FSAI_TAU 1e-8
+
+/* ------------------------------------------------------------------ */
+/* Preconditioner P (Section 4 uses IC(0); the Jacobi choice D^{-1} is */
+/* the one the GPU path applies by default; FSAI per the Conclusion).  */
+/* ------------------------------------------------------------------ */
+enum { ORC_PREC_NONE = 0, ORC_PREC_JACOBI = 1, ORC_PREC_IC0 = 2, ORC_PREC_FSAI = 3 };
 
 typedef struct {
     int kind;
     const orc_ic0 *ic0;
     double *dinv;
+    const orc_fsai *fsai;
 } orc_prec;
 
 static void prec_apply(const orc_prec *P, int n, const double *r, double *z) {
     if (P->kind == ORC_PREC_IC0) orc_ic0_apply(P->ic0, r, z);
     else if (P->kind == ORC_PREC_JACOBI) for (int i = 0; i < n; ++i) z[i] = P->dinv[i] * r[i];
+    else if (P->kind == ORC_PREC_FSAI) orc_fsai_apply(P->fsai, r, z);
     else memcpy(z, r, sizeof(double) * (size_t)n);
 }
 
@@ -394,22 +557,34 @@ static int pcg_correction(const orc_lap *L, double theta, int q, const double *Q
     return mvp;
 }
 
-/* Public wrapper: precond 0 = none, 1 = Jacobi (D^{-1}), 2 = IC(0).
+/* Public wrapper: precond 0 = none, 1 = Jacobi (D^{-1}), 2 = IC(0),
+ * 3 = FSAI in the order pos (NULL: natural order).
  * Q: n x q column-major orthonormal; r, t: n.  Returns MVPs. */
+ORC_API int orc_pcg_correction_ex(int n, const int *rowptr, const int *col, const double *val,
+                                  double theta, int q, const double *Q, const double *r,
+                                  int precond, const int *pos, int itmax, double rtol, double *t,
+                                  int *breakdown) {
+    orc_lap L = {n, rowptr, col, val};
+    orc_prec P = {precond, NULL, NULL, NULL};
+    int nfloor = 0;
+    orc_ic0 *K = NULL;
+    orc_fsai *Z = NULL;
+    if (precond == ORC_PREC_IC0) { K = orc_ic0_create(n, rowptr, col, val, &nfloor); P.ic0 = K; }
+    if (precond == ORC_PREC_JACOBI) P.dinv = diag_inverse(&L);
+    if (precond == ORC_PREC_FSAI) { Z = orc_fsai_create(n, rowptr, col, val, pos, ORC_FSAI_TAU); P.fsai = Z; }
+    int mvp = pcg_correction(&L, theta, q, Q, r, &P, itmax, rtol, t, breakdown);
+    orc_ic0_destroy(K);
+    orc_fsai_destroy(Z);
+    free(P.dinv);
+    return mvp;
+}
+
 ORC_API int orc_pcg_correction(int n, const int *rowptr, const int *col, const double *val,
                                double theta, int q, const double *Q, const double *r,
                                int precond, int itmax, double rtol, double *t,
                                int *breakdown) {
-    orc_lap L = {n, rowptr, col, val};
-    orc_prec P = {precond, NULL, NULL};
-    int nfloor = 0;
-    orc_ic0 *K = NULL;
-    if (precond == ORC_PREC_IC0) { K = orc_ic0_create(n, rowptr, col, val, &nfloor); P.ic0 = K; }
-    if (precond == ORC_PREC_JACOBI) P.dinv = diag_inverse(&L);
-    int mvp = pcg_correction(&L, theta, q, Q, r, &P, itmax, rtol, t, breakdown);
-    orc_ic0_destroy(K);
-    free(P.dinv);
-    return mvp;
+    return orc_pcg_correction_ex(n, rowptr, col, val, theta, q, Q, r, precond, NULL, itmax, rtol, t,
+                                 breakdown);
 }
 
 /* ------------------------------------------------------------------ */
@@ -437,6 +612,7 @@ typedef struct {
     int precond;        /* ORC_PREC_*; Section 4 uses IC(0) */
     int criterion;      /* 0: ||r|| <= tol min(theta,1); 1: ||r|| < tol theta (Section 4) */
     uint64_t seed;      /* start-vector stream */
+    const int *fsai_pos; /* vertex order of FSAI (NULL: natural order) */
 } orc_jd_opts;
 
 typedef struct {
@@ -496,10 +672,12 @@ ORC_API int orc_jd(int n, const int *rowptr, const int *col, const double *val, 
     }
     free(label);
 
-    orc_prec P = {o->precond, NULL, NULL};
+    orc_prec P = {o->precond, NULL, NULL, NULL};
     orc_ic0 *K = NULL;
+    orc_fsai *Zf = NULL;
     if (o->precond == ORC_PREC_IC0) { K = orc_ic0_create(n, rowptr, col, val, &info->nfloor); P.ic0 = K; }
     if (o->precond == ORC_PREC_JACOBI) P.dinv = diag_inverse(&L);
+    if (o->precond == ORC_PREC_FSAI) { Zf = orc_fsai_create(n, rowptr, col, val, o->fsai_pos, ORC_FSAI_TAU); P.fsai = Zf; }
 
     double *V = (double *)calloc((size_t)n * m_max, sizeof(double));
     double *W = (double *)calloc((size_t)n * m_max, sizeof(double));
@@ -648,8 +826,152 @@ done:
         free(idx);
     }
     orc_ic0_destroy(K);
+    orc_fsai_destroy(Zf);
     free(P.dinv);
     free(X); free(lam); free(rlock); free(V); free(W); free(V2); free(W2); free(H); free(Hs);
     free(Theta); free(Y); free(v); free(u); free(r); free(Lu); free(t); free(Q);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 3 (DACG): the eigenpairs one after the other, each by      */
+/* minimizing the Rayleigh quotient q(x) = x'Gx / x'x over the vectors  */
+/* orthogonal to those already computed (the columns of U), with a      */
+/* preconditioned nonlinear conjugate gradient (the DACG of Bergamaschi,*/
+/* Gambolati and Pini that the paper cites):                           */
+/*   q_k = x_k'G x_k / x_k'x_k,  g_k = 2 (G x_k - q_k x_k) / x_k'x_k   */
+/*   h_k = P g_k;  beta_k = g_k'h_k / g_{k-1}'h_{k-1}  (beta_0 = 0)    */
+/*   p_k = (I - UU') h_k + beta_k p_{k-1}    (deflated direction)       */
+/*   x_{k+1} = x_k - alpha_k p_k, alpha_k minimizing q on span{x, p}:   */
+/*   the smaller eigenpair of the 2 x 2 pencil ([x p]'G[x p], [x p]'[x p]) */
+/* Per iteration: one product (G p; G x follows by the same update),    */
+/* one preconditioner application, one deflation of the direction       */
+/* (the three costs the comments on Algorithm 3 list).                  */
+/* READINGS: the zero pairs (component indicators) are locked first, as */
+/* in JD; the stopping test is JD's certificate ||G x - q x|| <=        */
+/* tol min(q, 1) ||x|| (it implies the paper's ||Gx - qx|| / q <= tol   */
+/* for unit x); x_0 is the seeded start vector made orthogonal to U;    */
+/* itmax limits the iterations of each pair (then status 1 and the      */
+/* certified prefix).                                                   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int itmax;          /* iterations per pair; <= 0 means 20000 */
+    int precond;        /* ORC_PREC_* */
+    uint64_t seed;
+    const int *fsai_pos;
+} orc_dacg_opts;
+
+ORC_API int orc_dacg(int n, const int *rowptr, const int *col, const double *val, int k, double tol,
+                     const orc_dacg_opts *o, double *evals, double *evecs, double *res, orc_jd_info *info) {
+    orc_lap L = {n, rowptr, col, val};
+    int itmax = o->itmax > 0 ? o->itmax : 20000;
+    memset(info, 0, sizeof(*info));
+    double *U = (double *)calloc((size_t)n * (size_t)(k > 0 ? k : 1), sizeof(double));
+    int nu = 0;
+    int *label = (int *)malloc(sizeof(int) * (size_t)n);
+    int ncomp = orc_components(n, rowptr, col, label);
+    info->ncomp = ncomp;
+    for (int c = 0; c < ncomp && nu < k; ++c) {
+        double *x = U + (size_t)nu * n;
+        int cnt = 0;
+        for (int i = 0; i < n; ++i) if (label[i] == c) ++cnt;
+        for (int i = 0; i < n; ++i) x[i] = label[i] == c ? 1.0 / sqrt((double)cnt) : 0.0;
+        evals[nu] = 0.0;
+        if (res) {
+            double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+            lap_apply(&L, x, tmp);
+            res[nu] = nrm2(n, tmp);
+            free(tmp);
+        }
+        ++nu;
+    }
+    free(label);
+    orc_prec P = {o->precond, NULL, NULL, NULL};
+    orc_ic0 *K = NULL;
+    orc_fsai *Zf = NULL;
+    if (o->precond == ORC_PREC_IC0) { K = orc_ic0_create(n, rowptr, col, val, &info->nfloor); P.ic0 = K; }
+    if (o->precond == ORC_PREC_JACOBI) P.dinv = diag_inverse(&L);
+    if (o->precond == ORC_PREC_FSAI) { Zf = orc_fsai_create(n, rowptr, col, val, o->fsai_pos, ORC_FSAI_TAU); P.fsai = Zf; }
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *gx = (double *)malloc(sizeof(double) * (size_t)n);
+    double *g = (double *)malloc(sizeof(double) * (size_t)n);
+    double *h = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *gp = (double *)malloc(sizeof(double) * (size_t)n);
+    int status = 0;
+    uint64_t start_col = 0;
+    while (nu < k) {
+        /* x_0: seeded, orthogonal to U (step 1) */
+        for (int i = 0; i < n; ++i) x[i] = orc_start_value(o->seed, start_col * (uint64_t)n + i);
+        ++start_col;
+        orc_mgs(n, nu, U, x);
+        scal(n, 1.0 / nrm2(n, x), x);
+        lap_apply(&L, x, gx);
+        ++info->mvp;
+        double gh_prev = 0.0;
+        int it, done = 0;
+        for (it = 0; it < itmax; ++it) {
+            double f = dot(n, x, x), c = dot(n, x, gx);
+            double q = c / f;
+            /* residual, and the stopping test (step 3) */
+            double rn2 = 0.0;
+            for (int i = 0; i < n; ++i) { double r = gx[i] - q * x[i]; rn2 += r * r; g[i] = 2.0 * r / f; }
+            double scale = q < 1.0 ? q : 1.0;
+            if (sqrt(rn2 / f) <= tol * scale) { done = 1; break; }
+            /* preconditioned gradient, conjugate direction, deflation (step 2) */
+            prec_apply(&P, n, g, h);
+            double gh = dot(n, g, h);
+            double beta = it == 0 ? 0.0 : gh / gh_prev;
+            gh_prev = gh;
+            project_out(n, nu, U, h);
+            for (int i = 0; i < n; ++i) p[i] = h[i] + (it == 0 ? 0.0 : beta * p[i]);
+            /* the line search: the smaller eigenpair of the 2 x 2 pencil */
+            lap_apply(&L, p, gp);
+            ++info->mvp;
+            double a = dot(n, p, gp), b = dot(n, x, gp), d = dot(n, p, p), e = dot(n, x, p);
+            double A2 = f * d - e * e, B2 = a * f + c * d - 2.0 * b * e, C2 = c * a - b * b;
+            double disc = B2 * B2 - 4.0 * A2 * C2;
+            if (disc < 0.0) disc = 0.0;
+            double mu = 2.0 * C2 / (B2 + sqrt(disc));
+            double den1 = a - mu * d, den2 = b - mu * e;
+            double alpha = fabs(den1) >= fabs(den2) ? den2 / den1 : (c - mu * f) / den2;
+            axpy(n, -alpha, p, x);
+            axpy(n, -alpha, gp, gx);
+        }
+        info->inner += it;
+        info->outer += 1;
+        if (!done) { status = 1; break; }
+        /* step 4: lock u_j = x / ||x||, certified with a fresh product */
+        double xn = nrm2(n, x);
+        double *u = U + (size_t)nu * n;
+        for (int i = 0; i < n; ++i) u[i] = x[i] / xn;
+        lap_apply(&L, u, gx);
+        ++info->mvp;
+        double theta = dot(n, u, gx);
+        double rn2 = 0.0;
+        for (int i = 0; i < n; ++i) { double r = gx[i] - theta * u[i]; rn2 += r * r; }
+        evals[nu] = theta;
+        if (res) res[nu] = sqrt(rn2);
+        ++nu;
+    }
+    info->nconv = nu;
+    info->status = status;
+    /* ascending order (the sequential minimization yields it, up to clusters) */
+    for (int i = 0; i < nu; ++i) {
+        int bsel = i;
+        for (int j = i + 1; j < nu; ++j) if (evals[j] < evals[bsel]) bsel = j;
+        if (bsel != i) {
+            double t = evals[i]; evals[i] = evals[bsel]; evals[bsel] = t;
+            if (res) { t = res[i]; res[i] = res[bsel]; res[bsel] = t; }
+            for (int r = 0; r < n; ++r) {
+                t = U[(size_t)i * n + r]; U[(size_t)i * n + r] = U[(size_t)bsel * n + r]; U[(size_t)bsel * n + r] = t;
+            }
+        }
+    }
+    memcpy(evecs, U, sizeof(double) * (size_t)n * (size_t)nu);
+    orc_ic0_destroy(K);
+    orc_fsai_destroy(Zf);
+    free(P.dinv);
+    free(U); free(x); free(gx); free(g); free(h); free(p); free(gp);
     return status;
 }

@@ -37,6 +37,10 @@ MUTANTS = {
     "jd_no_deflation_against_locked": ("double vn = orc_mgs(n, nx, X, v);",
                                        "double vn = orc_mgs(n, 0, X, v);"),
     "splitmix_constant": ("0x94d049bb133111ebULL", "0x94d049bb133111ecULL"),
+    "fsai_unscaled_row": ("double sc = 1.0 / sqrt(g[iv]);", "double sc = 1.0 / g[iv];"),
+    "fsai_missing_shift": ("if (a == b) e *= 1.0 + tau;", "if (a == b) e *= 1.0;"),
+    "fsai_no_transpose": ("for (int e = Z->rowptr[v]; e < Z->rowptr[v + 1]; ++e) z[Z->col[e]] += Z->val[e] * y[v];",
+                          "for (int e = Z->rowptr[v]; e < Z->rowptr[v + 1]; ++e) z[v] += Z->val[e] * y[Z->col[e]];"),
     "components_merge": ("if (label[j] < 0) { label[j] = ncomp; queue[tail++] = j; }",
                          "if (label[j] < 0) { label[j] = 0; queue[tail++] = j; }"),
 }

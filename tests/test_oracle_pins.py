@@ -240,10 +240,92 @@ def test_ic0_singular_laplacian_is_finite():
 
 
 # ---------------------------------------------------------------------------
+# FSAI, the factorized sparse approximate inverse (the approximate-inverse
+# preconditioner of the Conclusion; Kolotilina & Yeremin).  Its defining
+# conditions, checked with scipy products: for S = G + tau D, every row v of
+# Z satisfies (Z S)_{v,u} = 0 for the other u of its pattern and
+# (Z S Z')_{vv} = 1; with a full lower pattern Z is the exact inverse
+# Cholesky factor, Z S Z' = I.
+# ---------------------------------------------------------------------------
+
+def _fsai_cases():
+    tree = gg.laplacian_from_edges(9, np.array([0, 0, 1, 1, 2, 5, 6, 6]), np.array([1, 2, 3, 4, 5, 6, 7, 8]),
+                                   name="tree9")
+    u, v = gg.chung_lu_edges(600, 2.2, 4.0, 31)
+    w = gg.integer_weights(u.shape[0], 32)
+    n2, u, v, w = gg.largest_component(600, u, v, w)
+    weighted = gg.laplacian_from_edges(n2, u, v, w, name="cl600w")
+    union = gg.disjoint_union(gg.path_graph(2), gg.star_graph(6), gg.workload("pa5k", 5))
+    return [tree, weighted, union, gg.workload("pa5k", 7)]
+
+
+@pytest.mark.parametrize("L", _fsai_cases(), ids=lambda g: g.name[:20])
+@pytest.mark.parametrize("order", ["natural", "degree"])
+def test_fsai_defining_conditions(L, order):
+    import scipy.sparse as sp
+    pos = None
+    if order == "degree":
+        deg = np.diff(L.rowptr) - 1
+        perm = np.lexsort((np.arange(L.n), -deg))
+        pos = np.empty(L.n, dtype=np.int32)
+        pos[perm] = np.arange(L.n)
+    F = oracle.FSAI(L, pos=pos)
+    Z = F.matrix()
+    G = L.to_scipy()
+    tau = oracle.FSAI_TAU
+    S = (G + tau * sp.diags(G.diagonal())).tocsr()
+    ZS = (Z @ S).tocsr()
+    ZSZ = (Z @ S @ Z.T).tocsr()
+    rank = np.arange(L.n) if pos is None else pos
+    for v in range(L.n):
+        cols = Z.indices[Z.indptr[v]:Z.indptr[v + 1]]
+        # the pattern: v and its neighbours earlier in the order
+        nb = L.col[L.rowptr[v]:L.rowptr[v + 1]]
+        want = sorted([v] + [int(c) for c in nb if c != v and rank[c] < rank[v]])
+        assert sorted(cols.tolist()) == want
+        if G[v, v] == 0:
+            continue
+        # rounding bound: a few eps times the condition of the local system
+        # (large only where the pattern covers a whole component, S = G + tau D)
+        tol = 1e-14 * np.linalg.cond(S[cols][:, cols].toarray()) + 1e-12
+        assert abs(ZSZ[v, v] - 1.0) <= tol
+        row = ZS.getrow(v).toarray().ravel()
+        others = [c for c in cols if c != v]
+        if others:
+            assert np.abs(row[others]).max() <= tol * np.abs(row).max()
+    # the application is Z'(Z r)
+    r = np.random.default_rng(3).standard_normal(L.n)
+    assert np.allclose(F.apply(r), Z.T @ (Z @ r), rtol=1e-13, atol=1e-13 * np.abs(Z.T @ (Z @ r)).max())
+
+
+def test_fsai_full_pattern_is_the_inverse_cholesky_factor():
+    # on the complete graph every earlier vertex is a neighbour, so the
+    # pattern is the whole lower triangle and Z S Z' = I exactly
+    import scipy.sparse as sp
+    L = gg.complete_graph(9)
+    Z = oracle.FSAI(L).matrix().toarray()
+    G = L.dense()
+    S = G + oracle.FSAI_TAU * np.diag(np.diag(G))
+    assert np.allclose(Z @ S @ Z.T, np.eye(9), atol=1e-9)
+    assert np.allclose(np.triu(Z, 1), 0.0)
+    # and Z'Z = S^{-1}
+    assert np.allclose(Z.T @ Z, np.linalg.inv(S), rtol=1e-6, atol=1e-6 * np.abs(np.linalg.inv(S)).max())
+
+
+def test_jd_with_fsai_vs_dense_brute_force():
+    L = gg.workload("pa5k", 11)
+    r = oracle.jd(L, 8, 1e-10, precond=oracle.PREC_FSAI)
+    w, V = np.linalg.eigh(L.dense())
+    check_against_reference(r.evals, r.evecs, w[:40], V[:, :40], val_rtol=1e-8, angle_tol=1e-6)
+    j = oracle.jd(L, 8, 1e-10, precond=oracle.PREC_JACOBI)
+    assert r.mvp < j.mvp  # a preconditioner closer to S^{-1} takes fewer products
+
+
+# ---------------------------------------------------------------------------
 # PCG on the projected correction equation (Algorithm 2 step 8)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec", [oracle.PREC_NONE, oracle.PREC_JACOBI, oracle.PREC_IC0])
+@pytest.mark.parametrize("prec", [oracle.PREC_NONE, oracle.PREC_JACOBI, oracle.PREC_IC0, oracle.PREC_FSAI])
 def test_pcg_without_projection_solves_spd_system(prec):
     # Q empty and theta below the spectrum: (G - theta I) is SPD and PCG run
     # to convergence must give numpy's dense solution
@@ -265,7 +347,7 @@ def test_pcg_without_projection_solves_spd_system(prec):
     assert np.allclose(t, exact, rtol=1e-9, atol=1e-9 * np.abs(exact).max())
 
 
-@pytest.mark.parametrize("prec", [oracle.PREC_JACOBI, oracle.PREC_IC0])
+@pytest.mark.parametrize("prec", [oracle.PREC_JACOBI, oracle.PREC_IC0, oracle.PREC_FSAI])
 def test_pcg_projected_system_solution(prec):
     # with Q = [e/sqrt(n), x2] and theta below lambda_3 the projected operator
     # is SPD on Q-perp; the exact solution t = B y with B an orthonormal basis
