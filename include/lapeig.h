@@ -91,7 +91,22 @@ typedef struct {
                             is certified either way and only the iteration count changes */
     int init_cols;
     int init_on_device;  /* 0: init is host memory; 1: device memory */
+    int precond;         /* lap_precond: P of the preconditioner M = (I-QQ')P(I-QQ') */
 } lap_eigs_opts;
+
+/* The preconditioner P of the correction equation (comments on Algorithm 2).
+ * The paper uses IC(0) (Section 4), whose triangular solves are sequential;
+ * its Conclusion proposes approximate-inverse preconditioners, applied as
+ * products of sparse matrices, for parallel machines.
+ *   LAP_PRECOND_JACOBI: P = D^{-1} (the default).
+ *   LAP_PRECOND_FSAI:   P = Z'Z, the factorized sparse approximate inverse
+ *     (Kolotilina & Yeremin) of G + 1e-8 D: Z lower triangular in the plan's
+ *     vertex order with the pattern of G's lower triangle, row v solving
+ *     (G + 1e-8 D)[P_v, P_v] g = e_v, Z[v, P_v] = g / sqrt(g_v).  Built once
+ *     per plan on first use (host, multi-threaded) and kept on the device in
+ *     FP64 and FP32; each application is two sparse products.  Single-vector
+ *     solver only (block and batched solves return LAP_EUNSUPPORTED). */
+typedef enum { LAP_PRECOND_JACOBI = 0, LAP_PRECOND_FSAI = 1 } lap_precond;
 
 typedef struct {
     int nconv;           /* certified pairs returned (the first nconv entries) */
@@ -191,6 +206,7 @@ lap_status lap_eigs_csr(const lap_csr *L, int k, double tol, const lap_eigs_opts
  * the plan's internal order (no renumbering passes).  Asynchronous on
  * stream.  Supported b: 1..64. */
 #define LAP_ORDER_PLAN 1
+#define LAP_PCG_FSAI 2   /* lap_pcg flag: P = the plan's FSAI factor instead of D^{-1} */
 lap_status lap_spmv(lap_plan *plan, lap_dtype dtype, int b, const void *X, void *Y,
                     const double *shift, int flags, void *stream);
 
@@ -240,7 +256,7 @@ lap_status lap_sym_eig(int m, const double *H, double *theta, double *Y, int *sw
 /* PCG on the projected correction equations (Algorithm 2 step 8):
  *   (I - QQ')(G - theta_c I)(I - QQ') t_c = -r_c,  t_c orthogonal to Q,
  * for each column c < b, with the preconditioner M = (I-QQ')P(I-QQ') and
- * P = D^{-1} (Jacobi).  t_0 = 0; column c stops when its residual norm is
+ * P = D^{-1} (Jacobi) or the FSAI factor (flag LAP_PCG_FSAI).  t_0 = 0; column c stops when its residual norm is
  * <= rtol * ||r_c||, after itmax iterations, or when p'(G - theta_c I)p
  * <= 0 (then the current t_c, or M(-r_c) if no step was taken).
  * theta: host, b doubles.  Q: device n x q column-major orthonormal, in the
@@ -248,10 +264,40 @@ lap_status lap_sym_eig(int m, const double *H, double *theta, double *Y, int *sw
  * R: device n x b column-major (r_c); T: device n x b column-major output.
  * dtype: arithmetic of the iteration (LAP_F32 or LAP_F64; inputs and
  * outputs stay double).  iters_out: host, b ints (PCG iterations per
- * column) or NULL.  Synchronizes stream.  Supported q <= 62, b <= 32. */
+ * column) or NULL.  flags: LAP_ORDER_PLAN as for lap_spmv, LAP_PCG_FSAI for
+ * P = Z'Z (LAP_PRECOND_FSAI).  Synchronizes stream.  Supported q <= 62, b <= 32. */
 lap_status lap_pcg(lap_plan *plan, lap_dtype dtype, int b, const double *theta,
                    const double *Q, int q, const double *R, double *T, int itmax,
                    double rtol, int *iters_out, int flags, void *stream);
+
+/* Consumers of the smallest eigenpairs (Section 2).
+ *
+ * lap_fiedler_bisect: spectral bisection with prescribed sizes.  Relaxing the
+ *   +-1/2 entries of the minimum-cut problem to real ones gives the minimum
+ *   n1 n2 lambda_2 / n at x = (n1 - n2)/(2n) e + sqrt(n1 n2/n) v_2, so the
+ *   first side is the set of the n1 vertices where the Fiedler vector v_2 is
+ *   smallest (equal entries taken by increasing vertex index).
+ *   fiedler: device, n doubles, caller order (the second column lap_eigs
+ *   returns on a connected graph; any finite vector is accepted).
+ *   part: device, n int32, caller order: 0 on the first side, 1 on the other.
+ *   cut: host double or NULL: the sum of the weights of the edges between
+ *   the sides (x'Gx for x = +-1/2, eq. (1)), which is >= n1 n2 lambda_2 / n.
+ *   0 <= n1 <= n; a non-finite entry gives LAP_EINVAL.  Synchronizes stream.
+ *
+ * lap_pinv_apply: the approximations of the pseudo-inverse G^+ used for
+ *   current-flow betweenness, from k computed pairs:
+ *     sigma = 0:  Y = T^(k) X = sum_j (1/lambda_j) v_j v_j' X
+ *     sigma > 0:  Y = S^(k) X = X/sigma - (1/sigma) sum_{lambda_j = 0} v_j v_j' X
+ *                                + sum_{lambda_j > 0} (1/lambda_j - 1/sigma) v_j v_j' X
+ *   with j over the k pairs; the zero pairs (one per connected component)
+ *   take the place of v_1 = e/sqrt(n).  evals: host, k values >= 0 (zero
+ *   exactly for the zero pairs, as lap_eigs returns them); evecs: device
+ *   n x k column-major, orthonormal; X, Y: device n x b column-major (Y must
+ *   not overlap X).  1 <= k <= 64.  Synchronizes stream. */
+lap_status lap_fiedler_bisect(lap_plan *plan, const double *fiedler, int n1, int32_t *part, double *cut,
+                              void *stream);
+lap_status lap_pinv_apply(int n, int k, const double *evals, const double *evecs, double sigma, int b,
+                          const double *X, double *Y, void *stream);
 
 /* Many independent graphs at once (the batched form of Algorithm 2): one
  * persistent launch, captured in a hipGraph, in which each 1024-thread

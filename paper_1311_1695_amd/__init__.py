@@ -38,12 +38,14 @@ LAP_OK, LAP_EINVAL, LAP_ENOTLAPLACIAN, LAP_ENOMEM, LAP_EDEVICE, LAP_ENOCONV, LAP
 LAP_F32, LAP_F64 = 0, 1
 LAP_PREC_FP64, LAP_PREC_MIXED = 0, 1
 LAP_ORDER_PLAN = 1
+LAP_PCG_FSAI = 2
+LAP_PRECOND_JACOBI, LAP_PRECOND_FSAI = 0, 1
 
 EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
             "lap_plan_set_layout", "lap_plan_layout", "lap_plan_autotune",
             "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
-            "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
+            "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config", "lap_fiedler_bisect", "lap_pinv_apply",
             "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_spmv_noalloc", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
@@ -70,7 +72,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("itmax", ctypes.c_int),
                 ("rtol_pcg", ctypes.c_double), ("kmax", ctypes.c_int), ("precision", ctypes.c_int),
                 ("block", ctypes.c_int), ("seed", ctypes.c_uint64), ("init", ctypes.POINTER(ctypes.c_double)),
-                ("init_cols", ctypes.c_int), ("init_on_device", ctypes.c_int)]
+                ("init_cols", ctypes.c_int), ("init_on_device", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class _MpnnConfig(ctypes.Structure):
@@ -140,12 +142,15 @@ def load_library():
     lib.lap_mpnn_save.argtypes = [vp, ctypes.c_char_p]
     lib.lap_mpnn_load.argtypes = [ctypes.c_char_p, P(vp)]
     lib.lap_mpnn_get_config.argtypes = [vp, P(_MpnnConfig)]
+    lib.lap_fiedler_bisect.argtypes = [vp, vp, ctypes.c_int, vp, f64p, vp]
+    lib.lap_pinv_apply.argtypes = [ctypes.c_int, ctypes.c_int, f64p, vp, ctypes.c_double, ctypes.c_int, vp, vp, vp]
     lib.lap_status_string.argtypes = [ctypes.c_int]
     lib.lap_status_string.restype = ctypes.c_char_p
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
     for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
-                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config"]:
+                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
+                 "lap_fiedler_bisect", "lap_pinv_apply"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -258,13 +263,16 @@ class EigResult:
     warm_start_used: int = 0
 
 
-def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0, block=1, seed=1, init=None):
+def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0, block=1, seed=1, init=None,
+          precond="jacobi"):
     lib = load_library()
     o = _Opts()
     lib.lap_eigs_default_opts(ctypes.byref(o))
     o.m_min, o.m_max, o.itmax, o.rtol_pcg, o.kmax = m_min, m_max, itmax, rtol_pcg, kmax
     o.precision = {"mixed": LAP_PREC_MIXED, "fp64": LAP_PREC_FP64}[precision] if isinstance(precision, str) else int(precision)
     o.block, o.seed = block, seed
+    o.precond = {"jacobi": LAP_PRECOND_JACOBI, "fsai": LAP_PRECOND_FSAI}[precond] if isinstance(precond, str) \
+        else int(precond)
     keep = None
     if init is not None and hasattr(init, "data_ptr"):
         # a torch tensor on the device, (p, n) row-major = n x p column-major
@@ -393,9 +401,11 @@ def lap_sym_eig(H, stream=None):
     return theta, Yc.t(), sw.value
 
 
-def lap_pcg(plan: Plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_order=False, stream=None):
+def lap_pcg(plan: Plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_order=False, stream=None,
+            precond="jacobi"):
     """PCG on the projected correction equations; Q: (q, n), R and T: (b, n)
-    float64 device tensors.  Returns the iterations per column."""
+    float64 device tensors; precond 'jacobi' (D^-1) or 'fsai'.  Returns the
+    iterations per column."""
     lib = load_library()
     b = int(R.shape[0])
     th = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, dtype=np.float64), (b,)))
@@ -405,9 +415,45 @@ def lap_pcg(plan: Plan, theta, Q, R, T, itmax=20, rtol=1e-2, dtype="f32", plan_o
                        th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        ctypes.c_void_p(Q.data_ptr()) if q else ctypes.c_void_p(0), q,
                        ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(T.data_ptr()), int(itmax), float(rtol),
-                       its.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), LAP_ORDER_PLAN if plan_order else 0,
+                       its.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       (LAP_ORDER_PLAN if plan_order else 0) | (LAP_PCG_FSAI if precond == "fsai" else 0),
                        _stream_handle(stream)))
     return its
+
+
+def lap_fiedler_bisect(plan: Plan, fiedler, n1: int, stream=None):
+    """Spectral bisection: (part, cut) with part an int32 device tensor (0 for
+    the n1 vertices of smallest Fiedler entry, ties by index) and cut the
+    weight of the edges between the sides.  fiedler: float64 device tensor
+    of n entries, caller order."""
+    import torch
+    if fiedler.dtype != torch.float64 or fiedler.numel() != plan.n or not fiedler.is_contiguous():
+        raise LapError(LAP_EINVAL, "fiedler must be a contiguous float64 device tensor of n entries")
+    part = torch.empty(plan.n, dtype=torch.int32, device=fiedler.device)
+    cut = ctypes.c_double(0.0)
+    _check(load_library().lap_fiedler_bisect(plan._h, ctypes.c_void_p(fiedler.data_ptr()), int(n1),
+                                             ctypes.c_void_p(part.data_ptr()), ctypes.byref(cut),
+                                             _stream_handle(stream)))
+    return part, cut.value
+
+
+def lap_pinv_apply(evals, evecs, X, sigma=0.0, stream=None):
+    """Y = T^(k) X (sigma = 0) or S^(k) X (sigma > 0).  evals: k host values;
+    evecs: (k, n) float64 device tensor (row j = eigenvector j); X: (b, n)
+    float64 device tensor.  Returns Y like X."""
+    import torch
+    ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+    k, n = int(evecs.shape[0]), int(evecs.shape[1])
+    if X.dim() == 1:
+        X = X[None, :]
+    if not (evecs.is_contiguous() and X.is_contiguous()) or X.shape[1] != n or ev.size != k:
+        raise LapError(LAP_EINVAL, "evecs (k, n), X (b, n) contiguous float64, k eigenvalues")
+    Y = torch.empty_like(X)
+    _check(load_library().lap_pinv_apply(n, k, ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.c_void_p(evecs.data_ptr()), float(sigma), int(X.shape[0]),
+                                         ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                         _stream_handle(stream)))
+    return Y
 
 
 class Batch:

@@ -136,6 +136,7 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
     LAP_REQUIRE(o.m_max <= kBatchMaxM && o.m_min >= 1 && o.m_min < o.m_max, LAP_EUNSUPPORTED,
                 "the batched solver supports m_max <= 16");
     LAP_REQUIRE(o.block == 1, LAP_EUNSUPPORTED, "the batched solver corrects one pair per outer iteration");
+    LAP_REQUIRE(o.precond == LAP_PRECOND_JACOBI, LAP_EUNSUPPORTED, "the batched solver preconditions with D^{-1}");
     const int nb = B->nb;
     for (int g = 0; g < nb; ++g)
         LAP_REQUIRE(k < B->n[g], LAP_EINVAL, "graph " + std::to_string(g) + " has n <= k");

@@ -115,6 +115,7 @@ void lap_eigs_default_opts(lap_eigs_opts *o) {
     o->init = nullptr;
     o->init_cols = 0;
     o->init_on_device = 0;
+    o->precond = LAP_PRECOND_JACOBI;
 }
 
 lap_status lap_mpnn_create(const lap_mpnn_config *cfg, lap_mpnn **out) {
@@ -303,9 +304,14 @@ static void check_opts(const lap_eigs_opts &o, int n) {
     LAP_REQUIRE(o.init_cols >= 0 && (o.init_cols == 0 || o.init != nullptr), LAP_EINVAL,
                 "init_cols > 0 needs an init block");
     LAP_REQUIRE(o.init_on_device == 0 || o.init_on_device == 1, LAP_EINVAL, "init_on_device must be 0 or 1");
-    if (o.init && !o.init_on_device)  // a device block is checked by the solver's non-finite guards
-        for (long long t = 0; t < (long long)n * o.init_cols; ++t)
-            LAP_REQUIRE(std::isfinite(o.init[t]), LAP_EINVAL, "init block holds non-finite values");
+    LAP_REQUIRE(o.precond == LAP_PRECOND_JACOBI || o.precond == LAP_PRECOND_FSAI, LAP_EINVAL,
+                "precond must be LAP_PRECOND_JACOBI or LAP_PRECOND_FSAI");
+    LAP_REQUIRE(o.precond == LAP_PRECOND_JACOBI || o.block <= 1, LAP_EUNSUPPORTED,
+                "the FSAI preconditioner is available to the single-vector solver (block = 1)");
+    // columns of a start block with non-finite entries are not an error: the
+    // solvers skip them (host and device blocks alike) and report the columns
+    // used in lap_eigs_info.warm_start_used
+    (void)n;
 }
 
 lap_status lap_eigs(lap_plan *p, int k, double tol, const lap_eigs_opts *opts, double *evals, double *evecs,
@@ -422,9 +428,32 @@ lap_status lap_pcg(lap_plan *p, lap_dtype dt, int b, const double *theta, const 
     LAP_REQUIRE(theta && R && T, LAP_EINVAL, "theta, R or T is NULL");
     LAP_REQUIRE(itmax >= 1, LAP_EINVAL, "itmax must be >= 1");
     LAP_REQUIRE(rtol > 0.0 && std::isfinite(rtol), LAP_EINVAL, "rtol must be > 0");
-    LAP_REQUIRE((flags & ~LAP_ORDER_PLAN) == 0, LAP_EINVAL, "unknown flags");
+    LAP_REQUIRE((flags & ~(LAP_ORDER_PLAN | LAP_PCG_FSAI)) == 0, LAP_EINVAL, "unknown flags");
     for (int c = 0; c < b; ++c) LAP_REQUIRE(std::isfinite(theta[c]), LAP_EINVAL, "non-finite theta");
     return lapeig::pcg_entry(p, dt, b, theta, Q, q, R, T, itmax, rtol, iters_out, flags, (hipStream_t)stream);
+    LAP_GUARD_END
+}
+
+lap_status lap_fiedler_bisect(lap_plan *p, const double *fiedler, int n1, int32_t *part, double *cut,
+                              void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p != nullptr, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(fiedler && part, LAP_EINVAL, "fiedler or part is NULL");
+    LAP_REQUIRE(n1 >= 0 && n1 <= p->n, LAP_EINVAL, "need 0 <= n1 <= n");
+    return lapeig::fiedler_bisect(p, fiedler, n1, part, cut, (hipStream_t)stream);
+    LAP_GUARD_END
+}
+
+lap_status lap_pinv_apply(int n, int k, const double *evals, const double *evecs, double sigma, int b,
+                          const double *X, double *Y, void *stream) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(n >= 1 && k >= 1 && b >= 1, LAP_EINVAL, "need n, k, b >= 1");
+    LAP_REQUIRE(k <= 64, LAP_EUNSUPPORTED, "k must not exceed 64");
+    LAP_REQUIRE(evals && evecs && X && Y, LAP_EINVAL, "evals, evecs, X or Y is NULL");
+    LAP_REQUIRE(std::isfinite(sigma) && sigma >= 0.0, LAP_EINVAL, "sigma must be 0 (T) or > 0 (S)");
+    for (int j = 0; j < k; ++j)
+        LAP_REQUIRE(std::isfinite(evals[j]) && evals[j] >= 0.0, LAP_EINVAL, "eigenvalues must be finite and >= 0");
+    return lapeig::pinv_apply(n, k, evals, evecs, sigma, b, X, Y, (hipStream_t)stream);
     LAP_GUARD_END
 }
 

@@ -128,7 +128,7 @@ void wait_published(const HostMirror *hm, unsigned seq, hipStream_t s) {
 // of the same shape (n, k, m_max) and inner-solve settings.
 template <typename T>
 struct JdWork : SolverCache {
-    int n, k, mmax, itmax;
+    int n, k, mmax, itmax, precond;
     double rtol;
     DevBuf<double> B, W, H, theta, Y, v, u, r, gu, vrand, isz;
     DevBuf<T> Q, t;
@@ -139,8 +139,8 @@ struct JdWork : SolverCache {
     PcgGraphs<T> graphs;
     DevBuf<double> outbuf;  // eigenvectors on their way to host memory
     OwnStream own;          // the solver's stream
-    JdWork(int n_, int k_, int mmax_, int itmax_, double rtol_)
-        : n(n_), k(k_), mmax(mmax_), itmax(itmax_), rtol(rtol_) {
+    JdWork(int n_, int k_, int mmax_, int itmax_, double rtol_, int precond_)
+        : n(n_), k(k_), mmax(mmax_), itmax(itmax_), precond(precond_), rtol(rtol_) {
         B.alloc((size_t)n * (k + mmax));
         W.alloc((size_t)n * mmax);
         H.alloc((size_t)mmax * mmax);
@@ -154,8 +154,8 @@ struct JdWork : SolverCache {
         rs.ensure(std::max(4 * device_cu_count(), 1), 64);
         pw.ensure(n, k);
     }
-    bool fits(int n_, int k_, int mmax_, int itmax_, double rtol_) const {
-        return n == n_ && k == k_ && mmax == mmax_ && itmax == itmax_ && rtol == rtol_;
+    bool fits(int n_, int k_, int mmax_, int itmax_, double rtol_, int precond_) const {
+        return n == n_ && k == k_ && mmax == mmax_ && itmax == itmax_ && rtol == rtol_ && precond == precond_;
     }
 };
 
@@ -175,10 +175,12 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     const int nz = std::min(P->ncomp, k);
     const int ldq = k;
 
+    const bool fsai = o.precond == LAP_PRECOND_FSAI;
+    if (fsai) fsai_ensure(P);
     auto *cache = dynamic_cast<JdWork<T> *>(P->jd_cache.get());
-    if (!cache || !cache->fits(n, k, mmax, o.itmax, o.rtol_pcg)) {
+    if (!cache || !cache->fits(n, k, mmax, o.itmax, o.rtol_pcg, o.precond)) {
         P->jd_cache.reset();
-        P->jd_cache.reset(cache = new JdWork<T>(n, k, mmax, o.itmax, o.rtol_pcg));
+        P->jd_cache.reset(cache = new JdWork<T>(n, k, mmax, o.itmax, o.rtol_pcg, o.precond));
     }
     JdWork<T> &wk = *cache;
     hipStream_t s = wk.own.s;
@@ -337,7 +339,8 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
             const bool inc = q == pcg_q;
             pcg_q = q;
             auto enqueue = [&]() {
-                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, o.itmax, o.rtol_pcg, s, inc);
+                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, o.itmax, o.rtol_pcg, s, inc,
+                               fsai);
             };
             if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(2 * q + (inc ? 1 : 0), s, enqueue), s));
             else enqueue();

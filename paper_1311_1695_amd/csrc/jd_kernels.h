@@ -134,8 +134,10 @@ struct PcgWork {
 // -r (r double, plan order).  Enqueues everything; nothing is read back.
 // inc: the previous call on w had the same q and Q, except possibly its last
 // column (the products of the first q - 1 columns are then reused).
+// fsai: P = Z'Z (the plan's FSAI factor, fsai_ensure first) instead of D^{-1},
+// in the two-launch form with the two FSAI products between its launches.
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc = false);
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc = false, bool fsai = false);
 
 }  // namespace lapeig

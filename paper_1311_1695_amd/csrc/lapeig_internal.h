@@ -124,6 +124,20 @@ struct Weights {
 
 }  // namespace lapeig
 
+namespace lapeig {
+// FSAI factor Z of S = G + tau D in plan order (P = Z'Z ~ S^{-1}), stored
+// along the CSR of A: for entry e of row i, zv[e] = Z(i, col[e]) when
+// col[e] < i (row i of Z, the lower part [rowptr[i], mid[i])) and
+// Z(col[e], i) when col[e] > i (column i of Z, the upper part
+// [mid[i], rowptr[i+1])); zd[i] = Z(i, i).
+template <typename T>
+struct FsaiView {
+    const int *rowptr = nullptr, *col = nullptr, *mid = nullptr;
+    const T *zv = nullptr, *zd = nullptr;
+    int n = 0, n_wave = 0;  // rows [0, n_wave) are summed by a wavefront each
+};
+}  // namespace lapeig
+
 // The opaque plan of the C ABI.
 namespace lapeig {
 // Work areas a solver keeps in its plan between calls (device buffers and
@@ -157,6 +171,15 @@ struct lap_plan {
     lapeig::DevBuf<double> d_shift;
     lapeig::DevBuf<char> tmp_x, tmp_y;
     lapeig::DevBuf<char> chunk_part;  // per-chunk partial sums of the block product
+    // FSAI preconditioner (built on first use, plan order; see fsai.cpp)
+    bool fsai_ready = false;
+    double fsai_tau = 0.0;
+    int fsai_max_row = 0;  // largest |P_v| of the factor
+    lapeig::DevBuf<int> d_fsai_mid;
+    lapeig::DevBuf<double> d_fsai_zv64, d_fsai_zd64;
+    lapeig::DevBuf<float> d_fsai_zv32, d_fsai_zd32;
+    template <typename T>
+    lapeig::FsaiView<T> fsai() const;
     std::unique_ptr<lapeig::SolverCache> jd_cache;   // single-vector solver work areas
     std::unique_ptr<lapeig::SolverCache> jdb_cache;  // block solver work areas
     // plan-order CSR of A on the host (rebuilding the row classes needs it)
@@ -168,6 +191,15 @@ struct lap_plan {
     template <typename T>
     const T *dinv() const;
 };
+
+template <>
+inline lapeig::FsaiView<float> lap_plan::fsai<float>() const {
+    return {d_rowptr.get(), d_col.get(), d_fsai_mid.get(), d_fsai_zv32.get(), d_fsai_zd32.get(), n, g.n_long};
+}
+template <>
+inline lapeig::FsaiView<double> lap_plan::fsai<double>() const {
+    return {d_rowptr.get(), d_col.get(), d_fsai_mid.get(), d_fsai_zv64.get(), d_fsai_zd64.get(), n, g.n_long};
+}
 
 template <>
 inline lapeig::Weights<float> lap_plan::weights<float>() const {
@@ -194,6 +226,20 @@ void build_layout(lap_plan *plan, int long_threshold, int huge_threshold);
 
 // ------------------------------------------------------------- tune.cpp
 void autotune(lap_plan *plan, lap_dtype dt, int b, int target, const char *cache_path, lap_tune_info *info);
+
+// -------------------------------------------------------- consumers.hip
+// Spectral bisection by the Fiedler vector f (device, caller order): part
+// (device, caller order) = 0 for the n1 smallest entries (ties by index),
+// 1 otherwise; cut (host or null) = weight of the edges between the sides.
+lap_status fiedler_bisect(lap_plan *P, const double *f, int n1, int *part, double *cut, hipStream_t s);
+// Y = T^(k) X (sigma = 0) or S^(k) X (sigma > 0); V, X, Y device column-major.
+lap_status pinv_apply(int n, int k, const double *evals, const double *V, double sigma, int b, const double *X,
+                      double *Y, hipStream_t s);
+
+// ------------------------------------------------------------- fsai.cpp
+constexpr double kFsaiTau = 1e-8;
+// Builds the FSAI factor of the plan once (host, then uploaded); no-op when built.
+void fsai_ensure(lap_plan *P);
 
 // ------------------------------------------------------------- spmv.hip
 // y = (G - sigma I) x, b = 1, plan order.

@@ -64,7 +64,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init1(int n, const double *__res
 
 // init2: r0 = ||r||, c0 = -Q'r;  res -= Q c0 (project the right-hand side);
 // y = D^{-1} res;  partials res'y, Q'y
-template <typename T, int NV>
+// With FSAI the preconditioned vector comes from the two launches that
+// follow (k_fsai_lo, k_fsai_up), which also leave the partial sums: here
+// only the projection of res.
+template <typename T, int NV, bool FSAI>
 __global__ __launch_bounds__(kBlock) void k_pcg_init2(int n, T *__restrict__ res, T *__restrict__ y,
                                                       const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
                                                       int q, const T *__restrict__ part_in, int nb_in,
@@ -88,6 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init2(int n, T *__restrict__ res
             if (j < q) proj += qi[j] * tot[1 + j];
         const T ri = res[i] - proj;
         res[i] = ri;
+        if (FSAI) continue;
         const T yi = dinv[i] * ri;
         y[i] = yi;
         acc[0] += ri * yi;
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init2(int n, T *__restrict__ res
         for (int j = 0; j < NV - 1; ++j)
             if (j < q) acc[1 + j] += qi[j] * yi;
     }
-    write_partials<T, NV>(acc, q + 1, part_out);
+    if (!FSAI) write_partials<T, NV>(acc, q + 1, part_out);
 }
 
 // KA.  INIT (first iteration): fold rho = res'y and c1 = Q'y of init2, beta
@@ -192,7 +196,7 @@ struct UpRow {
     T t, p, res, s, dinv, qv[NV];
 };
 
-template <typename T, int NV>
+template <typename T, int NV, bool FSAI>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t, T *__restrict__ res,
                                                        const T *__restrict__ p, const T *__restrict__ s,
                                                        T *__restrict__ y, const T *__restrict__ dinv,
@@ -256,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
         t[i] = d.t + alpha * d.p;
         const T ri = d.res - alpha * (d.s - proj);
         res[i] = ri;
+        if (FSAI) continue;
         const T yi = d.dinv * ri;
         y[i] = yi;
         acc[0] += ri * ri;
@@ -263,7 +268,88 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T *__restrict__ t,
 #pragma unroll
         for (int j = 0; j < NQ; ++j) acc[2 + j] += qval(j) * yi;
     }
-    write_partials<T, NV>(acc, q + 2, part_out);
+    if (!FSAI) write_partials<T, NV>(acc, q + 2, part_out);
+}
+
+// ---------------------------------------------------------------------------
+// FSAI application y = (Z'Z) res in two launches (the preconditioner
+// P = Z'Z, fsai.cpp), each a sparse product along the CSR of A:
+//   k_fsai_lo   h = Z res:  h_i = Z_ii res_i + sum over the lower part of row i
+//   k_fsai_up   y = Z'h:    y_i = Z_ii h_i + sum over the upper part of row i,
+//               then the partial sums the next KA folds: res'res (not at
+//               INIT), res'y and Q'y (the projection of M = (I-QQ')P(I-QQ')
+//               happens there, through c1 = Q'y)
+// Rows [0, n_wave), the high-degree ones, are summed by a wavefront each,
+// the others by one lane each, in a fixed order.  Both are no-ops once the
+// iteration has stopped (launch number sq, see stopped()).
+// ---------------------------------------------------------------------------
+template <typename T, bool UPPER>
+__device__ __forceinline__ T fsai_row_lane(const FsaiView<T> &f, int i, const T *__restrict__ x) {
+    const int e0 = UPPER ? f.mid[i] : f.rowptr[i];
+    const int e1 = UPPER ? f.rowptr[i + 1] : f.mid[i];
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        const int c0 = f.col[e], c1 = f.col[e + 1], c2 = f.col[e + 2], c3 = f.col[e + 3];
+        const T z0 = f.zv[e], z1 = f.zv[e + 1], z2 = f.zv[e + 2], z3 = f.zv[e + 3];
+        a0 += z0 * x[c0];
+        a1 += z1 * x[c1];
+        a2 += z2 * x[c2];
+        a3 += z3 * x[c3];
+    }
+    for (; e < e1; ++e) a0 += f.zv[e] * x[f.col[e]];
+    return (a0 + a1) + (a2 + a3);
+}
+
+template <typename T, bool UPPER>
+__device__ __forceinline__ T fsai_row_wave(const FsaiView<T> &f, int i, const T *__restrict__ x) {
+    const int e0 = UPPER ? f.mid[i] : f.rowptr[i];
+    const int e1 = UPPER ? f.rowptr[i + 1] : f.mid[i];
+    T a = T(0);
+    for (int e = e0 + lane_id(); e < e1; e += kWave) a += f.zv[e] * x[f.col[e]];
+    return wave_sum(a);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fsai_lo(FsaiView<T> f, const T *__restrict__ x, T *__restrict__ h,
+                                                    const PcgState<T> *st, int sq) {
+    if (stopped(st, sq)) return;
+    const int waves = gridDim.x * kWavesPerBlock;
+    for (int i = blockIdx.x * kWavesPerBlock + wave_id(); i < f.n_wave; i += waves) {
+        const T s = fsai_row_wave<T, false>(f, i, x);
+        if (lane_id() == 0) h[i] = f.zd[i] * x[i] + s;
+    }
+    for (int i = f.n_wave + blockIdx.x * blockDim.x + threadIdx.x; i < f.n; i += gridDim.x * blockDim.x)
+        h[i] = f.zd[i] * x[i] + fsai_row_lane<T, false>(f, i, x);
+}
+
+template <typename T, int NV, bool INIT>
+__global__ __launch_bounds__(kBlock) void k_fsai_up(FsaiView<T> f, const T *__restrict__ h, T *__restrict__ y,
+                                                    const T *__restrict__ res, const T *__restrict__ Q, int ldq, int q,
+                                                    T *__restrict__ part_out, const PcgState<T> *st, int sq) {
+    if (stopped(st, sq)) return;
+    constexpr int OFF = INIT ? 1 : 2;  // [res'res,] res'y, Q'y
+    T acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = T(0);
+    auto row_done = [&](int i, T yi) {
+        y[i] = yi;
+        const T ri = res[i];
+        if (!INIT) acc[0] += ri * ri;
+        acc[OFF - 1] += ri * yi;
+        const T *qi = Q + (size_t)i * ldq;
+#pragma unroll
+        for (int j = 0; j < NV - OFF; ++j)
+            if (j < q) acc[OFF + j] += qi[j] * yi;
+    };
+    const int waves = gridDim.x * kWavesPerBlock;
+    for (int i = blockIdx.x * kWavesPerBlock + wave_id(); i < f.n_wave; i += waves) {
+        const T s = fsai_row_wave<T, true>(f, i, h);
+        if (lane_id() == 0) row_done(i, f.zd[i] * h[i] + s);
+    }
+    for (int i = f.n_wave + blockIdx.x * blockDim.x + threadIdx.x; i < f.n; i += gridDim.x * blockDim.x)
+        row_done(i, f.zd[i] * h[i] + fsai_row_lane<T, true>(f, i, h));
+    write_partials<T, NV>(acc, q + OFF, part_out);
 }
 
 // ===========================================================================
@@ -670,10 +756,14 @@ int pp_iter_groups() {
 
 template <typename T, int NV>
 void enqueue_nv(const lap_plan &P, const double *theta, const T *Q, int ldq, int q, const double *r, T *t,
-                PcgWork<T> &w, int itmax, double rtol, hipStream_t s) {
+                PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool fsai = false) {
     const int n = P.n;
     const int gv = vgrid(n);
     const int gr = row_grid(P.g, pcg_vec_groups());
+    const FsaiView<T> fz = fsai ? P.fsai<T>() : FsaiView<T>{};
+    LAP_REQUIRE(!fsai || P.fsai_ready, LAP_EDEVICE, "FSAI factor not built");
+    const int gz = pcg_vec_groups();  // grid of the FSAI launches
+    T *hbuf = w.u.get();              // Z res (the pipelined form's u is free here)
     LAP_REQUIRE(w.gq.n >= (size_t)n * ldq, LAP_EDEVICE, "PCG work area too small for the projector");
     T *pa = w.part.get();
     T *pb = pa + (size_t)pcg_max_groups() * 64;
@@ -683,28 +773,48 @@ void enqueue_nv(const lap_plan &P, const double *theta, const T *Q, int ldq, int
     T *gq = w.gq.get();
     if (q > 0) spmm<T>(P, q, Q, ldq, gq, ldq, nullptr, s);
     hipLaunchKernelGGL((k_pcg_init1<T, NV>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q, pa, st);
-    hipLaunchKernelGGL((k_pcg_init2<T, NV>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), w.y.get(), dinv, Q, ldq,
-                       q, pa, gv, pb, st);
+    int nb_y = gv;  // partial rows the next KA folds
+    if (fsai) {
+        hipLaunchKernelGGL((k_pcg_init2<T, NV, true>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), w.y.get(), dinv,
+                           Q, ldq, q, pa, gv, pb, st);
+        hipLaunchKernelGGL((k_fsai_lo<T>), dim3(gz), dim3(kBlock), 0, s, fz, w.res.get(), hbuf, st, 2);
+        hipLaunchKernelGGL((k_fsai_up<T, NV, true>), dim3(gz), dim3(kBlock), 0, s, fz, hbuf, w.y.get(), w.res.get(),
+                           Q, ldq, q, pb, st, 2);
+        nb_y = gz;
+    } else {
+        hipLaunchKernelGGL((k_pcg_init2<T, NV, false>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), w.y.get(), dinv,
+                           Q, ldq, q, pa, gv, pb, st);
+    }
     for (int it = 1; it <= itmax; ++it) {
         const int sq = 2 * it;
+        const int gv_in = nb_y;
         if (it == 1) {
             if (P.weighted)
                 hipLaunchKernelGGL((k_pcg_ps<T, NV, true, true>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(),
-                                   theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv, pa, st, sq, it, tol);
+                                   theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv_in, pa, st, sq, it, tol);
             else
                 hipLaunchKernelGGL((k_pcg_ps<T, NV, false, true>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(),
-                                   theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv, pa, st, sq, it, tol);
+                                   theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv_in, pa, st, sq, it, tol);
         } else {
             if (P.weighted)
                 hipLaunchKernelGGL((k_pcg_ps<T, NV, true, false>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(),
-                                   theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv, pa, st, sq, it, tol);
+                                   theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv_in, pa, st, sq, it, tol);
             else
                 hipLaunchKernelGGL((k_pcg_ps<T, NV, false, false>), dim3(gr), dim3(kBlock), 0, s, P.g,
-                                   P.weights<T>(), theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv, pa,
-                                   st, sq, it, tol);
+                                   P.weights<T>(), theta, w.y.get(), w.p.get(), w.s.get(), Q, gq, ldq, q, pb, gv_in,
+                                   pa, st, sq, it, tol);
         }
-        hipLaunchKernelGGL((k_pcg_update<T, NV>), dim3(gv), dim3(kBlock), 0, s, n, t, w.res.get(), w.p.get(),
-                           w.s.get(), w.y.get(), dinv, Q, ldq, q, pa, gr, pb, st, sq + 1, it);
+        if (fsai) {
+            hipLaunchKernelGGL((k_pcg_update<T, NV, true>), dim3(gv), dim3(kBlock), 0, s, n, t, w.res.get(),
+                               w.p.get(), w.s.get(), w.y.get(), dinv, Q, ldq, q, pa, gr, pb, st, sq + 1, it);
+            // launches sq + 2: no-ops after a stop decided by KA or KB of this iteration
+            hipLaunchKernelGGL((k_fsai_lo<T>), dim3(gz), dim3(kBlock), 0, s, fz, w.res.get(), hbuf, st, sq + 2);
+            hipLaunchKernelGGL((k_fsai_up<T, NV, false>), dim3(gz), dim3(kBlock), 0, s, fz, hbuf, w.y.get(),
+                               w.res.get(), Q, ldq, q, pb, st, sq + 2);
+        } else {
+            hipLaunchKernelGGL((k_pcg_update<T, NV, false>), dim3(gv), dim3(kBlock), 0, s, n, t, w.res.get(),
+                               w.p.get(), w.s.get(), w.y.get(), dinv, Q, ldq, q, pa, gr, pb, st, sq + 1, it);
+        }
     }
     LAP_HIP(hipGetLastError());
 }
@@ -810,6 +920,8 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
                        double *Tout, int itmax, double rtol, int *iters_out, int flags, hipStream_t s) {
     const int n = P->n;
     const bool plan_order = flags & LAP_ORDER_PLAN;
+    const bool fsai = flags & LAP_PCG_FSAI;
+    if (fsai) fsai_ensure(P);
     const int *map = plan_order ? nullptr : P->d_perm.get();
     const int *imap = plan_order ? nullptr : P->d_iperm.get();
     const int ldq = q > 0 ? q : 1;
@@ -823,12 +935,12 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
     for (int c = 0; c < b; ++c) {
         LAP_HIP(hipMemcpyAsync(th.get(), theta_host + c, sizeof(double), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_gather_col, dim3(gv), dim3(kBlock), 0, s, n, R + (size_t)c * n, map, r.get());
-        if (use_pipelined(q))
+        if (!fsai && use_pipelined(q))
             enqueue_pipelined<T>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, false, s);
         else if (q <= 14)
-            enqueue_nv<T, 16>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
+            enqueue_nv<T, 16>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s, fsai);
         else
-            enqueue_nv<T, 64>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s);
+            enqueue_nv<T, 64>(*P, th.get(), Qr.get(), ldq, q, r.get(), t.get(), w, itmax, rtol, s, fsai);
         hipLaunchKernelGGL((k_scatter_t<T>), dim3(gv), dim3(kBlock), 0, s, n, t.get(), imap, Tout + (size_t)c * n);
         PcgState<T> hs;
         LAP_HIP(hipMemcpyAsync(&hs, w.st.get(), sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -843,19 +955,19 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
 
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc) {
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc, bool fsai) {
     LAP_REQUIRE(q >= 0 && q <= kMaxQ, LAP_EUNSUPPORTED, "projector wider than 62 columns");
-    if (use_pipelined(q))
+    if (!fsai && use_pipelined(q))
         enqueue_pipelined<T>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, inc && q >= 1, s);
     else if (q <= 14)
-        enqueue_nv<T, 16>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
+        enqueue_nv<T, 16>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s, fsai);
     else
-        enqueue_nv<T, 64>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s);
+        enqueue_nv<T, 64>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s, fsai);
 }
 template void pcg_enqueue<float>(const lap_plan &, const double *, const float *, int, int, const double *, float *,
-                                 PcgWork<float> &, int, double, hipStream_t, bool);
+                                 PcgWork<float> &, int, double, hipStream_t, bool, bool);
 template void pcg_enqueue<double>(const lap_plan &, const double *, const double *, int, int, const double *,
-                                  double *, PcgWork<double> &, int, double, hipStream_t, bool);
+                                  double *, PcgWork<double> &, int, double, hipStream_t, bool, bool);
 
 lap_status pcg_entry(lap_plan *P, lap_dtype dt, int b, const double *theta_host, const double *Q, int q,
                      const double *R, double *T, int itmax, double rtol, int *iters_out, int flags, hipStream_t s) {

@@ -6,7 +6,8 @@ the CPU oracle and the input generators):
   JD with a 20-column block, mixed precision and FP64;
 * the collaboration-like graph, n = 1,032,939: 10 smallest pairs, mixed
   precision from the seeded random start and from a trained network's
-  block, FP64 from the random start;
+  block (single-vector JD and block JD with a 10-column block), with the
+  FSAI preconditioner, and FP64 from the random start;
 * the 256 preferential-attachment graphs of the batch workload (n up to
   20k; in FP64 the largest keep part of their PCG direction in memory), 5
   pairs each, both precisions, in the one-launch batched solver.
@@ -126,15 +127,20 @@ def trained_network():
     return net
 
 
-@pytest.mark.parametrize("precision,start", [("mixed", "random"), ("mixed", "network"), ("fp64", "random")])
+@pytest.mark.parametrize("precision,start", [("mixed", "random"), ("mixed", "network"), ("fp64", "random"),
+                                             ("mixed", "fsai"), ("mixed", "block_network")])
 def test_collaboration_1m_k10_vs_oracle(precision, start):
     gold = golden("cl1m_tc_k10.json")
     L = graph("cl1m_tc")
     assert (L.n, L.nnz) == (gold["n"], gold["nnz"])
     p = plan("cl1m_tc")
     kw = {}
-    if start == "network":
+    if start in ("network", "block_network"):
         kw["init"] = trained_network().infer(p, feature_seed=1)
+    if start == "block_network":
+        kw.update(block=10, m_min=20, m_max=50)
+    if start == "fsai":
+        kw["precond"] = "fsai"
     r = lap.lap_eigs(p, 10, TOL, precision=precision, seed=1, **kw)
     assert r.nconv == 10 and r.ncomp == 1
     err = check_values(r.evals, gold["evals"])

@@ -301,6 +301,60 @@ def test_pcg_fp32_breakdown_matches_oracle(name, q, factor):
         assert np.abs(Q.T @ t).max() <= 1e-5 * np.linalg.norm(t)
 
 
+# The FSAI preconditioner (P = Z'Z, the approximate inverse the paper's
+# Conclusion proposes): the oracle builds Z by its plain definition in the
+# same vertex order as the plan (plan.perm()[i] is the position of vertex i)
+# and runs the same projected PCG; FP64 must agree element by element.
+@pytest.mark.parametrize("name,q", [("pa5k", 2), ("cl30k", 11), ("cl30k_w", 5), ("star9000", 3),
+                                    ("mixed_union", 5), ("cl330k", 8)])
+def test_pcg_fsai_matches_oracle(name, q):
+    L, Q, theta, r = _pcg_case(name, q, 7)
+    plan = lap.Plan(L)
+    pos = plan.perm()
+    t_ref, mvp_ref, br_ref = oracle.pcg_correction(L, theta, Q, r, precond=oracle.PREC_FSAI, pos=pos, itmax=20,
+                                                   rtol=1e-2)
+    Qt = torch.tensor(Q.T.copy(), device="cuda")
+    Rt = torch.tensor(r[None, :].copy(), device="cuda")
+    Tt = torch.zeros_like(Rt)
+    its = lap.lap_pcg(plan, theta, Qt, Rt, Tt, itmax=20, rtol=1e-2, dtype="f64", precond="fsai")
+    t = Tt.cpu().numpy()[0]
+    assert its[0] == mvp_ref
+    assert np.linalg.norm(t - t_ref) <= 1e-9 * np.linalg.norm(t_ref)
+
+
+@pytest.mark.parametrize("name,nlock", [("pa5k", 1), ("cl30k", 10), ("cl30k_w", 4)])
+def test_pcg_fsai_fp32_tracks_oracle(name, nlock):
+    L, Q, theta, r = _jd_like_case(name, nlock, 8)
+    plan = lap.Plan(L)
+    t_ref, mvp_ref, br_ref = oracle.pcg_correction(L, theta, Q, r, precond=oracle.PREC_FSAI, pos=plan.perm(),
+                                                   itmax=20, rtol=1e-2)
+    Qt = torch.tensor(Q.T.copy(), device="cuda")
+    Rt = torch.tensor(r[None, :].copy(), device="cuda")
+    Tt = torch.zeros_like(Rt)
+    its = lap.lap_pcg(plan, theta, Qt, Rt, Tt, itmax=20, rtol=1e-2, dtype="f32", precond="fsai")
+    t = Tt.cpu().numpy()[0]
+    assert abs(int(its[0]) - mvp_ref) <= 1
+    assert np.linalg.norm(t - t_ref) <= 2e-3 * np.linalg.norm(t_ref)
+    assert np.abs(Q.T @ t).max() <= 1e-5 * np.linalg.norm(t)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_eigs_fsai_vs_oracle_and_fewer_products(precision):
+    L = graph("cl30k")
+    plan = lap.Plan(L)
+    r = lap.lap_eigs(plan, 10, 1e-8, precision=precision, precond="fsai")
+    assert r.nconv == 10
+    _certified(L, r, 1e-8)
+    w, V = oracle_ref("cl30k", 14)
+    check_against_reference(r.evals, r.evecs, w, V, val_rtol=1e-8, angle_tol=1e-6)
+    j = lap.lap_eigs(plan, 10, 1e-8, precision=precision)
+    print(f"cl30k {precision}: FSAI {r.mvp} products / {r.outer} outer, Jacobi {j.mvp} / {j.outer}")
+    assert r.mvp < j.mvp
+    with pytest.raises(lap.LapError) as e:
+        lap.lap_eigs(plan, 10, 1e-8, precond="fsai", block=4, m_min=8, m_max=20)
+    assert e.value.code == lap.LAP_EUNSUPPORTED
+
+
 def test_pcg_multiple_columns_and_plan_order():
     L, Q, theta, r = _pcg_case("cl30k", 4, 9)
     plan = lap.Plan(L)
