@@ -195,6 +195,46 @@ lap_status lap_eigs(lap_plan *plan, int k, double tol, const lap_eigs_opts *opts
                     double *evals, double *evecs, int evecs_on_device, double *res,
                     lap_eigs_info *info);
 
+/* The k smallest eigenpairs by DACG (Algorithm 3): one pair after the
+ * other, each minimizing the Rayleigh quotient over the vectors orthogonal
+ * to the pairs already found, by a nonlinear conjugate gradient
+ * preconditioned with D^{-1}, the search direction deflated against the
+ * found pairs, the step minimizing the quotient on span{x, p}.  Same
+ * arguments, outputs, certificate and zero-pair handling as lap_eigs; it
+ * works in double precision whatever opts->precision says.  opts->kmax
+ * limits the iterations of each pair (<= 0: 20000; then LAP_ENOCONV and the
+ * certified prefix), opts->seed picks the start vectors, opts->precond
+ * must be LAP_PRECOND_JACOBI (else LAP_EUNSUPPORTED); block and init are
+ * ignored.  info->outer counts the pairs DACG computed, info->inner its
+ * iterations, info->mvp the Laplacian products.  Its iteration count grows
+ * with lambda_j / (lambda_{j+1} - lambda_j) (eq. xi), so it suits few,
+ * well-separated pairs; k <= 62. */
+lap_status lap_eigs_dacg(lap_plan *plan, int k, double tol, const lap_eigs_opts *opts, double *evals,
+                         double *evecs, int evecs_on_device, double *res, lap_eigs_info *info);
+
+/* The k smallest eigenpairs by the Implicitly Restarted Lanczos Method on
+ * the inverse (Section 3.1, Algorithm 1 right): Lanczos on G^+ (G inverted
+ * on the complement of its zero space), each step solving G w = v_j by the
+ * projected PCG of lap_pcg (theta = 0, Q = the zero space, the two-launch
+ * form, to ||v_j - G w|| <= rtol_inner ||v_j||), full reorthogonalization,
+ * and thick restarts that keep the wanted Ritz vectors and the last Lanczos
+ * vector (with exact shifts the space of Sorensen's implicit restart),
+ * until the wanted Ritz values of G^+ -- the reciprocals of the smallest
+ * nonzero eigenvalues -- hold the certificate of lap_eigs.
+ *   m: Krylov size (0: max(3 w, w + 6), w = k minus the zero pairs; the
+ *      paper: about three times the wanted pairs); zero space + m + 1 <= 63.
+ *   rtol_inner <= 0: 1e-12 (the paper: proportional to the accuracy wanted;
+ *      a residual of G^+ is amplified by up to ||G|| in the residual of G).
+ *   itmax_inner <= 0: 1000 PCG iterations per step.
+ *   opts (or NULL): seed (the start vector), precond (Jacobi or FSAI),
+ *      kmax (restart limit; <= 0: 1000; then LAP_ENOCONV with the zero
+ *      pairs only).  Other fields are ignored; double precision.
+ * Outputs as lap_eigs; info->outer = Lanczos steps (inner solves),
+ * info->inner = PCG iterations, info->mvp = all Laplacian products. */
+lap_status lap_eigs_irlm(lap_plan *plan, int k, double tol, int m, double rtol_inner, int itmax_inner,
+                         const lap_eigs_opts *opts, double *evals, double *evecs, int evecs_on_device,
+                         double *res, lap_eigs_info *info);
+
 /* One-shot convenience: plan, solve, destroy. */
 lap_status lap_eigs_csr(const lap_csr *L, int k, double tol, const lap_eigs_opts *opts,
                         double *evals, double *evecs, double *res, lap_eigs_info *info);

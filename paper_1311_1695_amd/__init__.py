@@ -46,7 +46,7 @@ EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap
             "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
             "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config", "lap_fiedler_bisect", "lap_pinv_apply",
-            "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_spmv_noalloc", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
+            "lap_eigs", "lap_eigs_csr", "lap_eigs_dacg", "lap_eigs_irlm", "lap_spmv", "lap_spmv_noalloc", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
             "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
 
@@ -114,6 +114,10 @@ def load_library():
     lib.lap_plan_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p, P(_TuneInfo)]
     lib.lap_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p, P(_Info)]
     lib.lap_eigs_csr.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info)]
+    lib.lap_eigs_dacg.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p,
+                                  P(_Info)]
+    lib.lap_eigs_irlm.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                  P(_Opts), f64p, vp, ctypes.c_int, f64p, P(_Info)]
     lib.lap_spmv.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
     lib.lap_spmv_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, f64p, ctypes.c_int, vp]
     lib.lap_orth.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, ip, vp]
@@ -150,7 +154,7 @@ def load_library():
     lib.lap_last_error.restype = ctypes.c_char_p
     for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
                  "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
-                 "lap_fiedler_bisect", "lap_pinv_apply"]:
+                 "lap_fiedler_bisect", "lap_pinv_apply", "lap_eigs_dacg", "lap_eigs_irlm"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -289,11 +293,12 @@ def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0,
     return o, keep
 
 
-def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noconv=False, **kw) -> EigResult:
+def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noconv=False, _fn="lap_eigs",
+             _pre=(), **kw) -> EigResult:
     """The k smallest eigenpairs (k counts the zero eigenvalues).  Keyword
     options: precision ('mixed' | 'fp64'), m_min, m_max, itmax, rtol_pcg,
     kmax, block, seed, init (n x p numpy start block, or a (p, n) float64
-    device tensor such as Mpnn.infer returns)."""
+    device tensor such as Mpnn.infer returns), precond ('jacobi' | 'fsai')."""
     lib = load_library()
     o, keep = _opts(**kw)
     n = plan.n
@@ -307,7 +312,7 @@ def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noc
     else:
         X = np.zeros((k, n))
         xp = ctypes.c_void_p(X.ctypes.data)
-    code = lib.lap_eigs(plan._h, int(k), float(tol), ctypes.byref(o),
+    code = getattr(lib, _fn)(plan._h, int(k), float(tol), *_pre, ctypes.byref(o),
                         ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), xp, int(bool(evecs_on_device)),
                         res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(info))
     if code != LAP_OK and not (allow_noconv and code == LAP_ENOCONV):
@@ -316,6 +321,23 @@ def lap_eigs(plan: Plan, k: int, tol: float, *, evecs_on_device=False, allow_noc
     vec = X[:nc] if evecs_on_device else X[:nc].T.copy()
     return EigResult(ev[:nc].copy(), vec, res[:nc].copy(), nc, info.ncomp, info.outer, info.inner,
                      int(info.mvp), info.seconds, code, info.warm_start_used)
+
+
+def lap_eigs_dacg(plan: Plan, k: int, tol: float, **kw) -> EigResult:
+    """The k smallest eigenpairs by DACG (Algorithm 3); options as lap_eigs
+    (kmax: iterations per pair; seed; precond 'jacobi').  outer = pairs
+    computed by DACG, inner = its iterations."""
+    return lap_eigs(plan, k, tol, _fn="lap_eigs_dacg", **kw)
+
+
+def lap_eigs_irlm(plan: Plan, k: int, tol: float, *, m=0, rtol_inner=0.0, itmax_inner=0, **kw) -> EigResult:
+    """The k smallest eigenpairs by IRLM on G^+ with PCG inner solves
+    (Algorithm 1 right); m Krylov size, rtol_inner / itmax_inner of the inner
+    PCG (0: defaults), options as lap_eigs (seed, precond, kmax = restart
+    limit).  outer = Lanczos steps, inner = PCG iterations."""
+    return lap_eigs(plan, k, tol, _fn="lap_eigs_irlm",
+                    _pre=(ctypes.c_int(int(m)), ctypes.c_double(float(rtol_inner)), ctypes.c_int(int(itmax_inner))),
+                    **kw)
 
 
 def lap_eigs_csr(L, k, tol, **kw) -> EigResult:

@@ -32,25 +32,34 @@ __global__ __launch_bounds__(kBlock) void k_ts_tn(int n, const T *__restrict__ A
     for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = V4{T(0), T(0), T(0), T(0)};
+    // U of the wavefront's 4-row chunks per pass: all their loads are issued
+    // before the first multiply, and the chunks are accumulated in the same
+    // order as one at a time
+    constexpr int U = TI * TJ <= 2 ? 4 : 2;
     const int step = gridDim.x * kWavesPerBlock * 4;
-    for (int k0 = (blockIdx.x * kWavesPerBlock + wave) * 4; k0 < n; k0 += step) {
-        const int row = k0 + kk;
-        const bool ok = row < n;
-        T a[TI], b[TJ];
+    for (int k0 = (blockIdx.x * kWavesPerBlock + wave) * 4; k0 < n; k0 += U * step) {
+        T a[U][TI], b[U][TJ];
 #pragma unroll
-        for (int ti = 0; ti < TI; ++ti) {
-            const int col = ti * 16 + mi;
-            a[ti] = (ok && col < ka) ? A[(size_t)row * lda + col] : T(0);
+        for (int u = 0; u < U; ++u) {
+            const int row = k0 + u * step + kk;
+            const bool ok = row < n;
+#pragma unroll
+            for (int ti = 0; ti < TI; ++ti) {
+                const int col = ti * 16 + mi;
+                a[u][ti] = (ok && col < ka) ? A[(size_t)row * lda + col] : T(0);
+            }
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj) {
+                const int col = tj * 16 + mi;
+                b[u][tj] = (ok && col < kb) ? B[(size_t)row * ldb + col] : T(0);
+            }
         }
 #pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) {
-            const int col = tj * 16 + mi;
-            b[tj] = (ok && col < kb) ? B[(size_t)row * ldb + col] : T(0);
-        }
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int ti = 0; ti < TI; ++ti)
+            for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = Mfma<T>::mac(a[ti], b[tj], acc[ti][tj]);
+                for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = Mfma<T>::mac(a[u][ti], b[u][tj], acc[ti][tj]);
     }
     // sum the four wavefronts in a fixed order
     for (int w = 0; w < kWavesPerBlock; ++w) {

@@ -330,6 +330,40 @@ lap_status lap_eigs(lap_plan *p, int k, double tol, const lap_eigs_opts *opts, d
     LAP_GUARD_END
 }
 
+lap_status lap_eigs_dacg(lap_plan *p, int k, double tol, const lap_eigs_opts *opts, double *evals, double *evecs,
+                         int evecs_on_device, double *res, lap_eigs_info *info) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p != nullptr, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(k >= 1 && k < p->n, LAP_EINVAL, "need 1 <= k < n");
+    LAP_REQUIRE(tol > 0.0 && std::isfinite(tol), LAP_EINVAL, "tol must be > 0");
+    LAP_REQUIRE(evals != nullptr, LAP_EINVAL, "evals is NULL");
+    lap_eigs_opts o;
+    if (opts) o = *opts;
+    else lap_eigs_default_opts(&o);
+    LAP_REQUIRE(o.precond == LAP_PRECOND_JACOBI || o.precond == LAP_PRECOND_FSAI, LAP_EINVAL, "bad precond");
+    LAP_HIP(hipSetDevice(p->device));
+    return lapeig::dacg_solve(p, k, tol, o, evals, evecs, evecs_on_device, res, info);
+    LAP_GUARD_END
+}
+
+lap_status lap_eigs_irlm(lap_plan *p, int k, double tol, int m, double rtol_inner, int itmax_inner,
+                         const lap_eigs_opts *opts, double *evals, double *evecs, int evecs_on_device, double *res,
+                         lap_eigs_info *info) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(p != nullptr, LAP_EINVAL, "plan is NULL");
+    LAP_REQUIRE(k >= 1 && k < p->n, LAP_EINVAL, "need 1 <= k < n");
+    LAP_REQUIRE(tol > 0.0 && std::isfinite(tol), LAP_EINVAL, "tol must be > 0");
+    LAP_REQUIRE(evals != nullptr, LAP_EINVAL, "evals is NULL");
+    LAP_REQUIRE(m >= 0 && std::isfinite(rtol_inner) && itmax_inner >= 0, LAP_EINVAL,
+                "need m >= 0, finite rtol_inner, itmax_inner >= 0");
+    lap_eigs_opts o;
+    if (opts) o = *opts;
+    else lap_eigs_default_opts(&o);
+    LAP_HIP(hipSetDevice(p->device));
+    return lapeig::irlm_solve(p, k, tol, m, rtol_inner, itmax_inner, o, evals, evecs, evecs_on_device, res, info);
+    LAP_GUARD_END
+}
+
 lap_status lap_eigs_csr(const lap_csr *L, int k, double tol, const lap_eigs_opts *opts, double *evals,
                         double *evecs, double *res, lap_eigs_info *info) {
     lap_plan *p = nullptr;

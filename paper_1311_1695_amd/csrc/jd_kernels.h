@@ -136,8 +136,12 @@ struct PcgWork {
 // column (the products of the first q - 1 columns are then reused).
 // fsai: P = Z'Z (the plan's FSAI factor, fsai_ensure first) instead of D^{-1},
 // in the two-launch form with the two FSAI products between its launches.
+// classic: the two-launch form even where the pipelined one applies (its
+// recurrences keep the true residual closer to the computed one, which
+// accurate solves need).
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc = false, bool fsai = false);
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc = false, bool fsai = false,
+                 bool classic = false);
 
 }  // namespace lapeig

@@ -227,6 +227,18 @@ void build_layout(lap_plan *plan, int long_threshold, int huge_threshold);
 // ------------------------------------------------------------- tune.cpp
 void autotune(lap_plan *plan, lap_dtype dt, int b, int target, const char *cache_path, lap_tune_info *info);
 
+// -------------------------------------------------------------- dacg.hip
+// Algorithm 3 (DACG): k smallest pairs, FP64, Jacobi preconditioner;
+// o.kmax limits the iterations of each pair (0: 20000).
+lap_status dacg_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                      int evecs_on_device, double *res_out, lap_eigs_info *info);
+
+// -------------------------------------------------------------- irlm.hip
+// Lanczos on G^+ with PCG inner solves and thick restarts (Algorithm 1 right).
+lap_status irlm_solve(lap_plan *P, int k, double tol, int m, double rtol_inner, int itmax_inner,
+                      const lap_eigs_opts &o, double *evals, double *evecs, int evecs_on_device, double *res_out,
+                      lap_eigs_info *info);
+
 // -------------------------------------------------------- consumers.hip
 // Spectral bisection by the Fiedler vector f (device, caller order): part
 // (device, caller order) = 0 for the n1 smallest entries (ties by index),

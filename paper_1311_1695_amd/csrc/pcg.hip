@@ -955,9 +955,9 @@ lap_status pcg_entry_t(lap_plan *P, int b, const double *theta_host, const doubl
 
 template <typename T>
 void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq, int q, const double *r, T *t,
-                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc, bool fsai) {
+                 PcgWork<T> &w, int itmax, double rtol, hipStream_t s, bool inc, bool fsai, bool classic) {
     LAP_REQUIRE(q >= 0 && q <= kMaxQ, LAP_EUNSUPPORTED, "projector wider than 62 columns");
-    if (!fsai && use_pipelined(q))
+    if (!fsai && !classic && use_pipelined(q))
         enqueue_pipelined<T>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, inc && q >= 1, s);
     else if (q <= 14)
         enqueue_nv<T, 16>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s, fsai);
@@ -965,9 +965,9 @@ void pcg_enqueue(const lap_plan &P, const double *theta_dev, const T *Q, int ldq
         enqueue_nv<T, 64>(P, theta_dev, Q, ldq, q, r, t, w, itmax, rtol, s, fsai);
 }
 template void pcg_enqueue<float>(const lap_plan &, const double *, const float *, int, int, const double *, float *,
-                                 PcgWork<float> &, int, double, hipStream_t, bool, bool);
+                                 PcgWork<float> &, int, double, hipStream_t, bool, bool, bool);
 template void pcg_enqueue<double>(const lap_plan &, const double *, const double *, int, int, const double *,
-                                  double *, PcgWork<double> &, int, double, hipStream_t, bool, bool);
+                                  double *, PcgWork<double> &, int, double, hipStream_t, bool, bool, bool);
 
 lap_status pcg_entry(lap_plan *P, lap_dtype dt, int b, const double *theta_host, const double *Q, int q,
                      const double *R, double *T, int itmax, double rtol, int *iters_out, int flags, hipStream_t s) {
