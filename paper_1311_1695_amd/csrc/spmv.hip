@@ -64,13 +64,20 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
             }
         }
     }
-    const int units = g.nslices * BL;  // (slice, group of RPW rows)
+    // slice rows: lane groups of b lanes (not BL), 64 / b rows per pass, so a
+    // b that is not a power of two leaves at most b - 1 lanes idle; one
+    // lane per (row, column), a gather of neighbour j reads its b values
+    const int srpw = kWave / b;                 // rows per pass
+    const int spass = (kWave + srpw - 1) / srpw;  // passes per 64-row slice
+    const int sc = lane % b, ssub = lane / b;
+    const int units = g.nslices * spass;
     for (int u = gw; u < units; u += nw) {
-        const int s = u / BL;
-        const int grp = u % BL;
-        const int l = grp * RPW + sub;
+        const int s = u / spass;
+        const int grp = u % spass;
+        const int l = grp * srpw + ssub;
         const int r = g.n_long + s * kWave + l;
-        if (r < g.n && c < b) {
+        const int c = sc;
+        if (ssub < srpw && l < kWave && r < g.n) {
             const int off = g.sell_off[s];
             const int width = (g.sell_off[s + 1] - off) >> 6;
             const T xi = X[(size_t)r * ldx + c];
@@ -177,6 +184,13 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
     int grid = (int)((units + kWavesPerBlock - 1) / kWavesPerBlock);
     if (grid < 1) grid = 1;
     if (grid > (1 << 20)) grid = 1 << 20;
+    {  // slice passes of 64 / b rows
+        const int srpw = kWave / b;
+        const long long sunits = (long long)g.nslices * ((kWave + srpw - 1) / srpw);
+        const long long vunits = std::max<long long>(sunits, g.nchunks);
+        grid = (int)std::min<long long>((vunits + kWavesPerBlock - 1) / kWavesPerBlock, 1 << 20);
+        if (grid < 1) grid = 1;
+    }
     T *part = nullptr;
     if (g.nchunks > 0) {
         if (part_in) {
