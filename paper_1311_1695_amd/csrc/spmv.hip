@@ -1,5 +1,7 @@
 // Laplacian products: the matrix-vector product (MVP) of Section 3,
 // y = (G - sigma I) x, and its n x b block form, in plan order.
+#include <type_traits>
+
 #include "lapeig_dev.h"
 
 namespace lapeig {
@@ -12,6 +14,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Graph g, Weights<T> w, const T 
     for_each_row<T, W, false>(g, w, x, [&](int i, T xi, T yi, T) { y[i] = yi - sigma * xi; });
 }
 
+// V consecutive values moved by one V-wide load or store (the address is
+// aligned to V values: the host checks it before choosing V > 1)
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Pack {
+    T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> load_pack(const T *p) {
+    return *reinterpret_cast<const Pack<T, V> *>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void store_pack(T *p, const Pack<T, V> &x) {
+    *reinterpret_cast<Pack<T, V> *>(p) = x;
+}
+
 // Block product, n x b row-major (leading dimensions ldx, ldy).  A lane owns
 // one column c < BL of one row slot; a gather of neighbour j reads the b
 // contiguous values X[j, 0..b).
@@ -19,8 +36,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Graph g, Weights<T> w, const T 
 //     one wavefront per chunk with 64 / BL edge slots; a row of one chunk is
 //     written directly, longer rows leave per-chunk partial sums that
 //     k_spmm_combine adds in chunk order (deterministic);
-//   slice rows: 64 / BL rows per wavefront pass, one lane per (row, column).
-template <typename T, bool W, int BL>
+//   slice rows: see below.
+template <typename T, bool W, int BL, int V>
 __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
                                                  const T *__restrict__ X, int ldx, T *__restrict__ Y, int ldy,
                                                  const double *__restrict__ shift, T *__restrict__ part) {
@@ -64,45 +81,66 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
             }
         }
     }
-    // slice rows: lane groups of b lanes (not BL), 64 / b rows per pass, so a
-    // b that is not a power of two leaves at most b - 1 lanes idle; one
-    // lane per (row, column), a gather of neighbour j reads its b values
-    const int srpw = kWave / b;                 // rows per pass
-    const int spass = (kWave + srpw - 1) / srpw;  // passes per 64-row slice
-    const int sc = lane % b, ssub = lane / b;
-    const int units = g.nslices * spass;
-    for (int u = gw; u < units; u += nw) {
-        const int s = u / spass;
-        const int grp = u % spass;
-        const int l = grp * srpw + ssub;
-        const int r = g.n_long + s * kWave + l;
-        const int c = sc;
-        if (ssub < srpw && l < kWave && r < g.n) {
-            const int off = g.sell_off[s];
-            const int width = (g.sell_off[s + 1] - off) >> 6;
-            const T xi = X[(size_t)r * ldx + c];
-            T acc = T(0);
-            int t = 0;
-            for (; t + 3 < width; t += 4) {
-                const int a0 = off + t * kWave + l;
-                const int j0 = g.sell_col[a0], j1 = g.sell_col[a0 + kWave], j2 = g.sell_col[a0 + 2 * kWave],
-                          j3 = g.sell_col[a0 + 3 * kWave];
-                const T d0 = xi - X[(size_t)j0 * ldx + c], d1 = xi - X[(size_t)j1 * ldx + c];
-                const T d2 = xi - X[(size_t)j2 * ldx + c], d3 = xi - X[(size_t)j3 * ldx + c];
-                if (W) {
-                    acc += w.sell[a0] * d0; acc += w.sell[a0 + kWave] * d1;
-                    acc += w.sell[a0 + 2 * kWave] * d2; acc += w.sell[a0 + 3 * kWave] * d3;
-                } else {
-                    acc += d0; acc += d1; acc += d2; acc += d3;
+    // slice rows: a lane owns V consecutive columns of one row (one V-wide
+    // load per gather), b / V lanes per row and 64 / (b / V) rows per
+    // wavefront; a unit's rows run on across slice boundaries (each lane
+    // finds its own slice), so only the lanes past the last whole row group
+    // idle.  Edges go in batches of 8 independent gathers, then one of 4, then
+    // a last batch of 4 whose entries past the slice width read the row
+    // itself with weight 0 (exact zeros, as the slice padding does); every
+    // column adds its edges in slice order.
+    const int gl = b / V;
+    const int spr = kWave / gl;
+    const int vsub = lane / gl;
+    const int vc = (lane % gl) * V;
+    const int nsr = g.n - g.n_long;
+    const int sunits = (nsr + spr - 1) / spr;
+    for (int u = gw; u < sunits; u += nw) {
+        const int q = u * spr + vsub;
+        if (vsub >= spr || q >= nsr) continue;
+        const int r = g.n_long + q;
+        const int s = q >> 6;
+        const int off = g.sell_off[s] + (q & (kWave - 1));
+        const int width = (g.sell_off[s + 1] - g.sell_off[s]) >> 6;
+        const Pack<T, V> xi = load_pack<T, V>(X + (size_t)r * ldx + vc);
+        Pack<T, V> acc;
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc.v[e] = T(0);
+        auto batch = [&](int t, auto ucount, auto masked) {
+            constexpr int U = decltype(ucount)::value;
+            constexpr bool M = decltype(masked)::value;
+            int j[U];
+            T wt[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int tk = t + k;
+                const int a = off + (M && tk >= width ? width - 1 : tk) * kWave;
+                const int jj = g.sell_col[a];
+                j[k] = M && tk >= width ? r : jj;
+                if (W) wt[k] = M && tk >= width ? T(0) : w.sell[a];
+            }
+            Pack<T, V> xv[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) xv[k] = load_pack<T, V>(X + (size_t)j[k] * ldx + vc);
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    if (W) acc.v[e] += wt[k] * (xi.v[e] - xv[k].v[e]);
+                    else acc.v[e] += xi.v[e] - xv[k].v[e];
                 }
-            }
-            for (; t < width; ++t) {
-                const int at = off + t * kWave + l;
-                acc += (W ? w.sell[at] : T(1)) * (xi - X[(size_t)g.sell_col[at] * ldx + c]);
-            }
-            const T sh = shift ? T(shift[c]) : T(0);
-            Y[(size_t)r * ldy + c] = acc - sh * xi;
+        };
+        int t = 0;
+        for (; t + 8 <= width; t += 8) batch(t, std::integral_constant<int, 8>(), std::false_type());
+        if (t + 4 <= width) {
+            batch(t, std::integral_constant<int, 4>(), std::false_type());
+            t += 4;
         }
+        if (t < width) batch(t, std::integral_constant<int, 4>(), std::true_type());
+        Pack<T, V> out;
+#pragma unroll
+        for (int e = 0; e < V; ++e) out.v[e] = acc.v[e] - (shift ? T(shift[vc + e]) : T(0)) * xi.v[e];
+        store_pack<T, V>(Y + (size_t)r * ldy + vc, out);
     }
 }
 
@@ -175,22 +213,42 @@ void spmv(const lap_plan &P, const T *x, T *y, double sigma, hipStream_t s) {
     LAP_HIP(hipGetLastError());
 }
 
+// Widest lane vector V (values per lane in the slice rows, at most 16
+// bytes) that divides b, leaves at least four lanes per row (a gather
+// instruction then spans at most 16 rows: wider loads spread over more rows
+// measured slower), and keeps every row of X and Y aligned to V values.
+template <typename T>
+static int spmm_vec_width(int b, const T *X, int ldx, const T *Y, int ldy) {
+    for (int v = 16 / (int)sizeof(T); v > 1; v >>= 1) {
+        const uintptr_t al = (uintptr_t)v * sizeof(T);
+        if (b % v == 0 && b / v >= 4 && b / v <= kWave && ldx % v == 0 && ldy % v == 0 &&
+            (uintptr_t)X % al == 0 && (uintptr_t)Y % al == 0)
+            return v;
+    }
+    return 1;
+}
+
+template <typename T, int BL, int V>
+static void spmm_launch_v(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
+                          T *part, hipStream_t s) {
+    const Graph &g = P.g;
+    const int spr = kWave / (b / V);
+    const long long sunits = ((long long)(g.n - g.n_long) + spr - 1) / spr;
+    const long long units = std::max<long long>(sunits, g.nchunks);
+    const int grid = (int)std::max<long long>(1, std::min<long long>((units + kWavesPerBlock - 1) / kWavesPerBlock,
+                                                                     1 << 20));
+    if (P.weighted)
+        hipLaunchKernelGGL((k_spmm<T, true, BL, V>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx,
+                           Y, ldy, shift, part);
+    else
+        hipLaunchKernelGGL((k_spmm<T, false, BL, V>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
+                           ldx, Y, ldy, shift, part);
+}
+
 template <typename T, int BL>
 static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
                         T *part_in, hipStream_t s) {
     const Graph &g = P.g;
-    long long units = (long long)g.nslices * BL;
-    if (g.nchunks > units) units = g.nchunks;
-    int grid = (int)((units + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (grid < 1) grid = 1;
-    if (grid > (1 << 20)) grid = 1 << 20;
-    {  // slice passes of 64 / b rows
-        const int srpw = kWave / b;
-        const long long sunits = (long long)g.nslices * ((kWave + srpw - 1) / srpw);
-        const long long vunits = std::max<long long>(sunits, g.nchunks);
-        grid = (int)std::min<long long>((vunits + kWavesPerBlock - 1) / kWavesPerBlock, 1 << 20);
-        if (grid < 1) grid = 1;
-    }
     T *part = nullptr;
     if (g.nchunks > 0) {
         if (part_in) {
@@ -202,12 +260,10 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
             part = reinterpret_cast<T *>(mp.chunk_part.get());
         }
     }
-    if (P.weighted)
-        hipLaunchKernelGGL((k_spmm<T, true, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx, Y,
-                           ldy, shift, part);
-    else
-        hipLaunchKernelGGL((k_spmm<T, false, BL>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx, Y,
-                           ldy, shift, part);
+    const int v = spmm_vec_width<T>(b, X, ldx, Y, ldy);
+    if (v == 4) spmm_launch_v<T, BL, 4>(P, b, X, ldx, Y, ldy, shift, part, s);
+    else if (v == 2) spmm_launch_v<T, BL, 2>(P, b, X, ldx, Y, ldy, shift, part, s);
+    else spmm_launch_v<T, BL, 1>(P, b, X, ldx, Y, ldy, shift, part, s);
     if (g.n_multi > 0)
         hipLaunchKernelGGL((k_spmm_combine<T>), dim3(g.n_multi), dim3(kWave), 0, s, g, b, X, ldx, Y, ldy, shift,
                            part);

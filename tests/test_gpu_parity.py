@@ -108,7 +108,7 @@ def test_spmv_bitwise_on_integer_vectors(name, dtype):
 
 
 @pytest.mark.parametrize("name", ["cl30k", "cl30k_w", "star9000"])
-@pytest.mark.parametrize("b", [2, 5, 16, 20])
+@pytest.mark.parametrize("b", [2, 4, 5, 8, 10, 16, 20])
 def test_spmm_with_shift_bitwise(name, b):
     L = graph(name)
     plan = lap.Plan(L)
@@ -122,6 +122,30 @@ def test_spmm_with_shift_bitwise(name, b):
         lap.lap_spmv(plan, X, Y, shift=shift)
         torch.cuda.synchronize()
         assert np.array_equal(Y.double().cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("b,off_f32,off_f64", [(10, 1, 1), (4, 2, 1), (8, 1, 1), (20, 2, 1), (16, 3, 0)])
+def test_spmm_unaligned_rows_bitwise(b, off_f32, off_f64):
+    # X and Y start `off` values into their buffers, so the rows are aligned
+    # only to what that offset leaves: the product must take narrower lane
+    # vectors and still give the same result
+    L = graph("cl30k_w")
+    plan = lap.Plan(L)
+    rng = np.random.default_rng(100 + b)
+    x = rng.integers(-64, 64, size=(L.n, b)).astype(np.float64)
+    shift = rng.integers(-3, 4, size=b).astype(np.float64)
+    ref = np.stack([oracle.spmv(L, x[:, c]) - shift[c] * x[:, c] for c in range(b)], axis=1)
+    for tdt, off in ((torch.float32, off_f32), (torch.float64, off_f64)):
+        xb = torch.zeros(L.n * b + off, dtype=tdt, device="cuda")
+        yb = torch.full((L.n * b + off + 1,), 7.0, dtype=tdt, device="cuda")
+        X = xb[off:].view(L.n, b)
+        X.copy_(torch.tensor(x, dtype=tdt))
+        Y = yb[off:off + L.n * b].view(L.n, b)
+        lap.lap_spmv(plan, X, Y, shift=shift)
+        torch.cuda.synchronize()
+        assert np.array_equal(Y.double().cpu().numpy(), ref)
+        # nothing written outside Y
+        assert torch.all(yb[:off] == 7.0) and float(yb[-1]) == 7.0
 
 
 def test_spmv_plan_order_and_random_vectors():
