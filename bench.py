@@ -93,6 +93,23 @@ def random_read_rate(n, count, reps=5):
     return rate.value if rc == 0 else None
 
 
+def random_row_rate(n, b, count, reps=5):
+    """Random whole-row reads per second that the device serves from an
+    n x b FP32 row-major array (bench_gather.hip: b / 2 lanes per row with
+    8-byte loads, as the block product reads a neighbour; indices hashed in
+    registers, no locality), or None if the helper is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "bench_gather.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.bench_random_rows.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_double)]
+    rate = ctypes.c_double(0.0)
+    rc = lib.bench_random_rows(n, b, count, reps, ctypes.byref(rate))
+    return rate.value if rc == 0 else None
+
+
 def time_spmv(lap, torch, plan, n, reps=200, dtype=None, b=1):
     """Average duration of the product kernel: `reps` back-to-back launches
     captured in a graph and replayed between two HIP events on the stream
@@ -448,7 +465,9 @@ def main():
         for _ in range(20):
             b.copy_(a)
         torch.cuda.synchronize()
+        rows_rate = random_row_rate(L.n, HEADLINE["block"], max(nnz_a, 1 << 24))
         print(json.dumps({"workload": WORKLOAD, "block_product_s": t_blk, "block_alg_bytes": alg_blk,
+                          "row_gathers": nnz_a, "random_row_rate": rows_rate,
                           "pcg_iter_s": t_pcg, "alg_bytes": alg_pcg, "copy_bytes_each_way": a.numel() * 4}))
         return
     if args.solve_only:
@@ -552,6 +571,14 @@ def main():
                        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_from_profile(sha),
                        "alg_bytes_per_launch": alg_blk, "avg_launch_us": round(t_blk * 1e6, 3),
                        "kernel_sources_sha": sha}
+    rows_rate = random_row_rate(L.n, HEADLINE["block"], max(nnz_a, 1 << 24))
+    out["roofline"]["gather_bound"] = {
+        "what": "the product's neighbour-row gathers (nnz_A rows of b FP32 values per launch) against the rate "
+                "at which the device serves random whole-row reads from an array of the same shape "
+                "(bench_gather.hip, no index stream, no locality)",
+        "row_gathers_per_launch": nnz_a, "achieved_rows_per_s_1e9": round(nnz_a / t_blk / 1e9, 2),
+        "random_row_rate_1e9_per_s": None if rows_rate is None else round(rows_rate / 1e9, 2),
+        "frac": None if rows_rate is None else round(nnz_a / t_blk / rows_rate, 4)}
     a_pcg = alg_pcg / t_pcg / 1e9
     out["pcg_iteration"] = {"kernel": f"k_pp_iter<float> (one projected PCG iteration of single-vector JD, "
                                       f"q={PCG_Q}, {WORKLOAD})", "achieved_GB/s": round(a_pcg, 1),

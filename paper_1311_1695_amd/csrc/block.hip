@@ -541,6 +541,206 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__rest
     for (; t < tot; t += stride) P[t] = Z[t] + beta * P[t];
 }
 
+// ------------------------------------------- fused block PCG (b, q <= 16)
+// Same iteration, same per-column state and stop rules, with the residual
+// carried as R~: the step subtracts alpha S (not alpha (I-QQ')S) and the
+// projection is taken once per iteration afterwards.  With W = Q'D^{-1}Q
+// (formed once per solve), one tall-skinny pass over [Q | R~] gives every
+// coefficient the two projections of an iteration need:
+//   KT  alpha; X += alpha P; R~ -= alpha S;  partial tiles G1 = Q'R~,
+//       G2 = Q'D^{-1}R~ and column sums R~'R~, R~'D^{-1}R~  (matrix cores)
+//   KN  C1 = G1, C2 = G2 - W C1;  Res = R~ - Q C1 (so Q'Res = 0);
+//       ||Res||^2 = R~'R~ - |C1|^2;  rho' = Res'D^{-1}Res
+//       = R~'D^{-1}R~ - C1'G2 - C1'C2;  stop test, beta = rho'/rho;
+//       P = (D^{-1}Res - Q C2) + beta P = (I-QQ')D^{-1}Res + beta P;  R~ = Res
+// R~ starts each iteration orthogonal to Q, so C1 holds one step's drift
+// (alpha Q'S, small beside Res while Q holds Ritz vectors) and the two
+// expansions lose nothing to cancellation.  The per-workgroup partials of
+// KT form a (2*16 + 2) x 16 matrix (rows: G1, G2, R~'R~, R~'D^{-1}R~),
+// added by k_ts_reduce in a fixed order into kFusedLd-row totals.
+constexpr int kFusedLd = 34;
+
+// KT (WM = false) and, with WM, the same pass over [Q | D^{-1}Q] that gives
+// W in rows 16..31 of the totals.
+template <typename T, bool WM>
+__global__ __launch_bounds__(kBlock) void k_bpcg_kt(int n, int b, int q, T *__restrict__ X, T *__restrict__ R,
+                                                    const T *__restrict__ P, const T *__restrict__ S,
+                                                    const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
+                                                    T *__restrict__ part, BPcgState<T> *st, int it) {
+    using V4 = typename Mfma<T>::v4;
+    constexpr int PS = kFusedLd * 16;
+    __shared__ T red[PS];
+    const int lane = lane_id(), wave = wave_id();
+    const int mi = lane & 15, kk = lane >> 4;
+    T alpha = T(0);
+    bool step = false, brk1 = false;
+    if (!WM) {
+        if (!any_active(st, 0, b)) {
+            if (blockIdx.x == 0 && (int)threadIdx.x < b) st->act[1][threadIdx.x] = 0;
+            return;
+        }
+        if (mi < b) {
+            const int act = st->act[0][mi];
+            const T pap = st->tot_a[mi];
+            const bool brk = act && !(pap > T(0));  // the projected operator is indefinite along p
+            step = act && !brk;
+            brk1 = brk && it == 1;
+            alpha = step ? st->rho[(it + 1) & 1][mi] / pap : T(0);
+            if (blockIdx.x == 0 && (int)threadIdx.x < b) {  // wavefront 0, kk = 0: thread c owns column c
+                st->act[1][mi] = step;
+                if (brk) st->brk[mi] = it;
+                if (step) st->its[mi] = it;
+            }
+        }
+    }
+    V4 acc1 = V4{T(0), T(0), T(0), T(0)}, acc2 = acc1;
+    T s1 = T(0), s2 = T(0);
+    constexpr int U = 4;  // 4-row chunks per pass, all loads issued first
+    const int stride = gridDim.x * kWavesPerBlock * 4;
+    for (int k0 = (blockIdx.x * kWavesPerBlock + wave) * 4; k0 < n; k0 += U * stride) {
+        T a[U], v[U], d[U], x[U], p[U], sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = k0 + u * stride + kk;
+            const bool ok = row < n;
+            a[u] = (ok && mi < q) ? Q[(size_t)row * ldq + mi] : T(0);
+            d[u] = ok ? dinv[row] : T(0);
+            if (WM) {
+                v[u] = a[u];
+            } else {
+                const bool in = ok && mi < b;
+                const size_t e = (size_t)row * b + mi;
+                v[u] = in ? R[e] : T(0);
+                x[u] = (in && step) ? X[e] : T(0);
+                p[u] = (in && (step || brk1)) ? P[e] : T(0);
+                sv[u] = (in && step) ? S[e] : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!WM) {
+                const int row = k0 + u * stride + kk;
+                if (row < n && mi < b) {
+                    const size_t e = (size_t)row * b + mi;
+                    if (step) {
+                        X[e] = x[u] + alpha * p[u];
+                        v[u] = v[u] - alpha * sv[u];
+                        R[e] = v[u];
+                    } else if (brk1) {
+                        X[e] = p[u];  // no step was taken before the breakdown: M(-r)
+                    }
+                }
+            }
+            const T dv = d[u] * v[u];
+            acc1 = Mfma<T>::mac(a[u], v[u], acc1);
+            acc2 = Mfma<T>::mac(a[u], dv, acc2);
+            s1 += v[u] * v[u];
+            s2 += v[u] * dv;
+        }
+    }
+    s1 += __shfl_xor(s1, 16, kWave);
+    s1 += __shfl_xor(s1, 32, kWave);
+    s2 += __shfl_xor(s2, 16, kWave);
+    s2 += __shfl_xor(s2, 32, kWave);
+    // the four wavefronts in a fixed order
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = Mfma<T>::row(lane, r), j = lane & 15;
+                red[i * 16 + j] = (w == 0 ? T(0) : red[i * 16 + j]) + acc1[r];
+                red[(16 + i) * 16 + j] = (w == 0 ? T(0) : red[(16 + i) * 16 + j]) + acc2[r];
+            }
+            if (kk == 0) {
+                red[32 * 16 + mi] = (w == 0 ? T(0) : red[32 * 16 + mi]) + s1;
+                red[33 * 16 + mi] = (w == 0 ? T(0) : red[33 * 16 + mi]) + s2;
+            }
+        }
+        __syncthreads();
+    }
+    T *out = part + (size_t)blockIdx.x * PS;
+    for (int t = threadIdx.x; t < PS; t += blockDim.x) out[t] = red[t];
+}
+
+// KN.  tot: totals of KT (element (i, j) at i + j kFusedLd); totw: those of
+// the W pass.  Reads flags of slot 1, writes slot 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bpcg_kn(int n, int b, int q, T *__restrict__ R, T *__restrict__ P,
+                                                    const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
+                                                    const T *__restrict__ tot, const T *__restrict__ totw,
+                                                    BPcgState<T> *st, int it, T rtol) {
+    using V4 = typename Mfma<T>::v4;
+    constexpr int LD = kFusedLd;
+    __shared__ T c1s[16 * 16], c2s[16 * 16];  // [k][j]: Q column k, block column j
+    __shared__ T betas[16];
+    __shared__ int gos[16];
+    if (!any_active(st, 1, b)) {
+        if (blockIdx.x == 0 && (int)threadIdx.x < b) st->act[0][threadIdx.x] = 0;
+        return;
+    }
+    const int t = threadIdx.x;
+    const int kq = t >> 4, jc = t & 15;
+    const bool kin = kq < q && jc < b;
+    c1s[t] = kin ? tot[kq + jc * LD] : T(0);
+    __syncthreads();
+    T c2 = T(0);
+    if (kin) {
+        c2 = tot[16 + kq + jc * LD];
+        for (int m = 0; m < q; ++m) c2 -= totw[16 + kq + m * LD] * c1s[m * 16 + jc];
+    }
+    c2s[t] = c2;
+    __syncthreads();
+    if (t < 16) {
+        bool go = false;
+        T beta = T(0);
+        if (t < b) {
+            const int c = t;
+            T rr = tot[32 + c * LD], rho_new = tot[33 + c * LD];
+            for (int k = 0; k < q; ++k) {
+                const T g1 = c1s[k * 16 + c];
+                rr -= g1 * g1;
+                rho_new -= g1 * (tot[16 + k + c * LD] + c2s[k * 16 + c]);
+            }
+            const T rn = sqrt(rr > T(0) ? rr : T(0));
+            go = st->act[1][c] && !(rn <= rtol * st->r0[c]);
+            beta = go ? rho_new / st->rho[(it + 1) & 1][c] : T(0);
+            if (blockIdx.x == 0) {
+                st->act[0][c] = go;
+                if (go) st->rho[it & 1][c] = rho_new;
+            }
+        }
+        gos[t] = go;
+        betas[t] = beta;
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    const int mi = lane & 15, kk = lane >> 4;
+    const int nrb = (n + 15) / 16;
+    for (int rb = blockIdx.x * kWavesPerBlock + wave_id(); rb < nrb; rb += gridDim.x * kWavesPerBlock) {
+        const int r0 = rb * 16;
+        const int row = r0 + mi;
+        const bool rok = row < n;
+        V4 acc1 = V4{T(0), T(0), T(0), T(0)}, acc2 = acc1;
+        for (int k0 = 0; k0 < q; k0 += 4) {
+            const int kc = k0 + kk;
+            const T a = (rok && kc < q) ? Q[(size_t)row * ldq + kc] : T(0);
+            acc1 = Mfma<T>::mac(a, c1s[kc * 16 + mi], acc1);
+            acc2 = Mfma<T>::mac(a, c2s[kc * 16 + mi], acc2);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = r0 + Mfma<T>::row(lane, r), j = lane & 15;
+            if (i < n && j < b && gos[j]) {
+                const size_t e = (size_t)i * b + j;
+                const T res = R[e] - acc1[r];
+                R[e] = res;
+                const T z = dinv[i] * res - acc2[r];
+                P[e] = z + betas[j] * P[e];
+            }
+        }
+    }
+}
+
 // zero eigenvectors (normalized component indicators) into [X | V] and Q
 template <typename T>
 __global__ void k_zero_space_rm(int n, int nz, const int *__restrict__ comp, const double *__restrict__ isz,
@@ -693,9 +893,33 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         Zy = Z;
     }
     hipLaunchKernelGGL((k_bpcg_p0<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
+    const bool fused = b <= 16 && q <= 16;
+    const int gt = ts_grid(n);
+    const int rgrid = std::min((kFusedLd * 16 + kWavesPerBlock - 1) / kWavesPerBlock, 4 * device_cu_count());
+    const int gn = std::min((n + 63) / 64, 8 * device_cu_count());
+    if (fused) {
+        LAP_REQUIRE(w.kt_part.n >= (size_t)gt * kFusedLd * 16, LAP_EDEVICE, "block PCG work area too small");
+        // W = Q'D^{-1}Q, rows 16..31 of the totals
+        hipLaunchKernelGGL((k_bpcg_kt<T, true>), dim3(gt), dim3(kBlock), 0, s, n, b, q, nullptr, nullptr, nullptr,
+                           nullptr, dinv, Q, ldq, w.kt_part.get(), st, 0);
+        hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rgrid), dim3(kBlock), 0, s, gt, w.kt_part.get(), 16,
+                           kFusedLd * 16, kFusedLd, 16, w.kt_w.get(), kFusedLd, nullptr, 0, 0, T(1));
+    }
     for (int it = 1; it <= itmax; ++it) {
         // S = G P - P diag(theta);  Z = (I - QQ') S
         spmm<T>(P, b, w.p.get(), b, w.s.get(), b, theta_dev, s);
+        if (fused) {
+            hipLaunchKernelGGL((k_bpcg_pap<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.p.get(), w.s.get(), part, st);
+            fold(b, st->tot_a);
+            hipLaunchKernelGGL((k_bpcg_kt<T, false>), dim3(gt), dim3(kBlock), 0, s, n, b, q, X, w.res.get(),
+                               w.p.get(), w.s.get(), dinv, Q, ldq, w.kt_part.get(), st, it);
+            if (it == itmax) break;
+            hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rgrid), dim3(kBlock), 0, s, gt, w.kt_part.get(), 16,
+                               kFusedLd * 16, kFusedLd, 16, w.kt_tot.get(), kFusedLd, nullptr, 0, 0, T(1));
+            hipLaunchKernelGGL((k_bpcg_kn<T>), dim3(gn), dim3(kBlock), 0, s, n, b, q, w.res.get(), w.p.get(), dinv,
+                               Q, ldq, w.kt_tot.get(), w.kt_w.get(), st, it, (T)rtol);
+            continue;
+        }
         const T *Zs = w.s.get();
         if (q > 0) {
             ts_tn<T>(n, Q, ldq, q, w.s.get(), b, b, C, q, nullptr, 0, T(1), bs, s);

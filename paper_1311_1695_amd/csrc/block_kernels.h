@@ -39,6 +39,9 @@ struct BPcgState {
 template <typename T>
 struct BPcgWork {
     DevBuf<T> res, p, s, y, z, C, part;
+    // fused iteration (b, q <= 16): per-workgroup partial tiles, their
+    // totals, and the totals of the W = Q'D^{-1}Q pass (34 x 16 each)
+    DevBuf<T> kt_part, kt_tot, kt_w;
     DevBuf<BPcgState<T>> st;
     void ensure(int n, int b, int qmax) {
         if (res.get()) return;
@@ -46,6 +49,9 @@ struct BPcgWork {
         z.alloc((size_t)n * b);
         C.alloc((size_t)(qmax + 1) * b);
         part.alloc((size_t)(4 * device_cu_count() + kMaxBlock) * 64);
+        kt_part.alloc((size_t)2 * device_cu_count() * 34 * 16);
+        kt_tot.alloc(34 * 16);
+        kt_w.alloc(34 * 16);
         st.alloc(1);
     }
 };

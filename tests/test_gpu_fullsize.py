@@ -128,7 +128,8 @@ def trained_network():
 
 
 @pytest.mark.parametrize("precision,start", [("mixed", "random"), ("mixed", "network"), ("fp64", "random"),
-                                             ("mixed", "fsai"), ("mixed", "block_network")])
+                                             ("mixed", "fsai"), ("mixed", "block_network"),
+                                             ("mixed", "block_random"), ("fp64", "block_random")])
 def test_collaboration_1m_k10_vs_oracle(precision, start):
     gold = golden("cl1m_tc_k10.json")
     L = graph("cl1m_tc")
@@ -137,7 +138,7 @@ def test_collaboration_1m_k10_vs_oracle(precision, start):
     kw = {}
     if start in ("network", "block_network"):
         kw["init"] = trained_network().infer(p, feature_seed=1)
-    if start == "block_network":
+    if start in ("block_network", "block_random"):
         kw.update(block=10, m_min=20, m_max=50)
     if start == "fsai":
         kw["precond"] = "fsai"
