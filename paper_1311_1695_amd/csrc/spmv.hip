@@ -145,46 +145,37 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
 }
 
 // rows split into several chunks: Y = sum of the chunk partials (in chunk
-// order) - shift * x.  One wavefront per row of two chunks or more: the
-// row's partials (nch x b, contiguous) pass through LDS in tiles of 64
-// chunks, each tile loaded with all its loads in flight, and lane c < b adds
-// column c of the tile in chunk order.
+// order) - shift * x.  Lane groups of b lanes, 64 / b rows per wavefront:
+// lane c of a group adds column c of its row's partials (nch x b,
+// contiguous), eight loads in flight, in chunk order.
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_spmm_combine(Graph g, int b, const T *__restrict__ X, int ldx,
-                                                        T *__restrict__ Y, int ldy,
-                                                        const double *__restrict__ shift,
-                                                        const T *__restrict__ part) {
-    constexpr int kTile = kWave;  // chunks per tile
-    constexpr int kBatch = 16;    // loads in flight per lane
-    __shared__ T tile[kTile * 64];
-    const int r = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int first = g.chunk_off[r], nch = g.chunk_off[r + 1] - first;
-    T acc = T(0);
-    for (int u0 = 0; u0 < nch; u0 += kTile) {
-        const int cnt = (nch - u0 < kTile ? nch - u0 : kTile) * b;
-        const T *src = part + (size_t)(first + u0) * b;
-        for (int e0 = 0; e0 < cnt; e0 += kBatch * kWave) {
-            T v[kBatch];
+__global__ __launch_bounds__(kBlock) void k_spmm_combine(Graph g, int b, const T *__restrict__ X, int ldx,
+                                                         T *__restrict__ Y, int ldy,
+                                                         const double *__restrict__ shift,
+                                                         const T *__restrict__ part) {
+    const int lane = lane_id();
+    const int rpw = kWave / b;
+    const int sub = lane / b, c = lane % b;
+    const int gw = blockIdx.x * kWavesPerBlock + wave_id();
+    const int nw = gridDim.x * kWavesPerBlock;
+    const int units = (g.n_multi + rpw - 1) / rpw;
+    for (int u = gw; u < units; u += nw) {
+        const int r = u * rpw + sub;
+        if (sub >= rpw || r >= g.n_multi) continue;
+        const int first = g.chunk_off[r], nch = g.chunk_off[r + 1] - first;
+        const T *src = part + (size_t)first * b + c;
+        T acc = T(0);
+        int k = 0;
+        for (; k + 8 <= nch; k += 8) {
+            T v[8];
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int e = e0 + k * kWave + lane;
-                v[k] = e < cnt ? src[e] : T(0);
-            }
+            for (int m = 0; m < 8; ++m) v[m] = src[(size_t)(k + m) * b];
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int e = e0 + k * kWave + lane;
-                if (e < cnt) tile[e] = v[k];
-            }
+            for (int m = 0; m < 8; ++m) acc += v[m];
         }
-        __syncthreads();
-        if (lane < b)
-            for (int e = lane; e < cnt; e += b) acc += tile[e];
-        __syncthreads();
-    }
-    if (lane < b) {
-        const T sh = shift ? T(shift[lane]) : T(0);
-        Y[(size_t)r * ldy + lane] = acc - sh * X[(size_t)r * ldx + lane];
+        for (; k < nch; ++k) acc += src[(size_t)k * b];
+        const T sh = shift ? T(shift[c]) : T(0);
+        Y[(size_t)r * ldy + c] = acc - sh * X[(size_t)r * ldx + c];
     }
 }
 
@@ -264,9 +255,12 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
     if (v == 4) spmm_launch_v<T, BL, 4>(P, b, X, ldx, Y, ldy, shift, part, s);
     else if (v == 2) spmm_launch_v<T, BL, 2>(P, b, X, ldx, Y, ldy, shift, part, s);
     else spmm_launch_v<T, BL, 1>(P, b, X, ldx, Y, ldy, shift, part, s);
-    if (g.n_multi > 0)
-        hipLaunchKernelGGL((k_spmm_combine<T>), dim3(g.n_multi), dim3(kWave), 0, s, g, b, X, ldx, Y, ldy, shift,
-                           part);
+    if (g.n_multi > 0) {
+        const int rpw = kWave / b;
+        const int cunits = (g.n_multi + rpw - 1) / rpw;
+        hipLaunchKernelGGL((k_spmm_combine<T>), dim3((cunits + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock),
+                           0, s, g, b, X, ldx, Y, ldy, shift, part);
+    }
     LAP_HIP(hipGetLastError());
 }
 
