@@ -63,10 +63,13 @@ def spmv_bytes(n: int, nnz_a: int, elem: int = 4, b: int = 1) -> int:
 
 
 def pcg_iter_bytes(n: int, nnz_a: int, q: int, elem: int = 4) -> int:
-    """Algorithmic bytes of one projected-PCG iteration with the two-sided
-    preconditioner (I-QQ')D^-1(I-QQ'): one product plus (4q + 18) n-vectors
-    of the working precision."""
-    return spmv_bytes(n, nnz_a, elem) + (4 * q + 18) * n * elem
+    """Algorithmic bytes of one launch of the one-launch projected-PCG
+    iteration (two-sided preconditioner (I-QQ')D^-1(I-QQ')): the product's
+    row offsets and column indices, one read of the gathered vector, and
+    every other n-vector once: the 3q columns of Q, G Q and G D^-1 Q, D^-1
+    and eight iterate vectors read, nine vectors written (the product's
+    result stays in registers, so spmv_bytes' write of y is not counted)."""
+    return spmv_bytes(n, nnz_a, elem) - n * elem + (3 * q + 18) * n * elem
 
 
 def kernel_sources_sha(files=("spmv.hip", "lapeig_dev.h")) -> str:
@@ -103,6 +106,8 @@ def random_row_rate(n, b, count, reps=5):
     if not os.path.exists(path):
         return None
     lib = ctypes.CDLL(path)
+    if not hasattr(lib, "bench_random_rows"):
+        return None
     lib.bench_random_rows.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_double)]
     rate = ctypes.c_double(0.0)
@@ -395,6 +400,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads")
     ap.add_argument("--spmv-only", default=None, metavar="GRAPH",
                     help="only the product kernel loop on one workload (for profiling)")
+    ap.add_argument("--pcg-q", type=int, default=PCG_Q,
+                    help="projector width of the PCG-iteration timing of --roofline-only")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the PCG iteration timing on the headline graph and a copy of known size "
                          "(for profiling)")
@@ -457,8 +464,8 @@ def main():
     # beside it one iteration of the single-vector pipelined PCG
     t_blk = time_spmv(lap, torch, plan, L.n, reps=100, dtype=torch.float32, b=HEADLINE["block"])
     alg_blk = spmv_bytes(L.n, nnz_a, 4, HEADLINE["block"])
-    t_pcg = time_pcg_iteration(lap, torch, np, plan, L.n)
-    alg_pcg = pcg_iter_bytes(L.n, nnz_a, PCG_Q)
+    t_pcg = time_pcg_iteration(lap, torch, np, plan, L.n, q=args.pcg_q)
+    alg_pcg = pcg_iter_bytes(L.n, nnz_a, args.pcg_q)
     if args.roofline_only:
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -579,11 +586,14 @@ def main():
         "row_gathers_per_launch": nnz_a, "achieved_rows_per_s_1e9": round(nnz_a / t_blk / 1e9, 2),
         "random_row_rate_1e9_per_s": None if rows_rate is None else round(rows_rate / 1e9, 2),
         "frac": None if rows_rate is None else round(nnz_a / t_blk / rows_rate, 4)}
-    a_pcg = alg_pcg / t_pcg / 1e9
+    pcg_runs = []
+    for qq in (6, PCG_Q):
+        tq = t_pcg if qq == args.pcg_q else time_pcg_iteration(lap, torch, np, plan, L.n, q=qq)
+        aq = pcg_iter_bytes(L.n, nnz_a, qq)
+        pcg_runs.append({"q": qq, "achieved_GB/s": round(aq / tq / 1e9, 1), "frac": round(aq / tq / 1e9 / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_launch": aq, "avg_launch_us": round(tq * 1e6, 3)})
     out["pcg_iteration"] = {"kernel": f"k_pp_iter<float> (one projected PCG iteration of single-vector JD, "
-                                      f"q={PCG_Q}, {WORKLOAD})", "achieved_GB/s": round(a_pcg, 1),
-                            "frac": round(a_pcg / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg_pcg,
-                            "avg_launch_us": round(t_pcg * 1e6, 3)}
+                                      f"{WORKLOAD})", "runs": pcg_runs}
     sp, rr_rate = spmv_entries(lap, torch, gg, np, L, plan)
     out["spmv"] = {"workload": WORKLOAD, "runs": sp, "random_read_rate_1e9_per_s": rr_rate,
                    "copy_GB/s": round(copy_bandwidth(torch) / 1e9, 1)}

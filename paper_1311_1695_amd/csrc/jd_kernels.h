@@ -36,6 +36,10 @@ struct HostMirror {
 
 constexpr int kPipeQ = 14;  // widest projector of the one-launch-per-iteration PCG
 
+// Column stride of the PCG's column-major operands: n rounded up to 32
+// values, so every column starts on a 128-byte line as the vectors do.
+__host__ __device__ inline size_t col_ld(size_t n) { return (n + 31) & ~(size_t)31; }
+
 template <typename T>
 struct PcgState {
     T rho[2];   // rho = res' M res of the last two iterations, by parity
@@ -113,6 +117,9 @@ struct PcgWork {
     // pipelined form: u = M res, w ~ A u, wh = D^{-1} w (two buffers), q, z;
     // qq = [Q | D^{-1}Q] and gqq = G qq (row-major, 2q columns); K = Q'D^{-1}Q
     DevBuf<T> u, w, wh, qv, z, qq, gqq, kmat, kpart;
+    // the same operands column-major for the iterations: Q (q columns) and
+    // [G Q | G D^{-1}Q] (2q columns), ld n
+    DevBuf<T> qcm, gqcm;
     DevBuf<PcgState<T>> st;
     void ensure(int n, int ldq) {
         if (res.n < (size_t)n || !st.get()) {
@@ -125,7 +132,10 @@ struct PcgWork {
         }
         if (gq.n < (size_t)n * ldq) gq.alloc((size_t)n * ldq);
         const size_t wq = 2 * (size_t)std::min(ldq, kPipeQ);
-        if (qq.n < (size_t)n * wq) { qq.alloc((size_t)n * wq); gqq.alloc((size_t)n * wq); }
+        if (qq.n < (size_t)n * wq) {
+            qq.alloc((size_t)n * wq); gqq.alloc((size_t)n * wq);
+            qcm.alloc(col_ld(n) * (wq / 2)); gqcm.alloc(col_ld(n) * wq);
+        }
     }
 };
 

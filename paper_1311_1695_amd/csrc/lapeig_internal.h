@@ -11,7 +11,8 @@
 // which is G x for G = D - A (Section 2) with D_ii = sum_j w_ij, needs no
 // diagonal, and has no cancellation between d_i x_i and sum_j w_ij x_j.
 //   rows [0, n_huge)        degree > huge threshold: one workgroup per row (CSR)
-//   rows [n_huge, n_long)   degree > long threshold: one wavefront per row (CSR)
+//   rows [n_huge, n_long)   degree > long threshold (and the next rows up to a
+//                           multiple of 32): one wavefront per row (CSR)
 //   rows [n_long, n)        64-row slices, column-major inside a slice
 //                           ("sliced ELLPACK"): lane l of a wavefront owns row
 //                           n_long + 64 s + l and reads its s-th neighbour at

@@ -393,8 +393,8 @@ template <typename T, bool Inc>
 __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__restrict__ r, T *__restrict__ res,
                                                      T *__restrict__ t, const T *__restrict__ Q, int ldq, int q,
                                                      const T *__restrict__ dinv, T *__restrict__ qq,
-                                                     T *__restrict__ part_out, T *__restrict__ kpart,
-                                                     PcgState<T> *st) {
+                                                     T *__restrict__ qcm, T *__restrict__ part_out,
+                                                     T *__restrict__ kpart, PcgState<T> *st) {
     if (leader()) {
         st->stop_seq = 0;
         st->iters = 0;
@@ -412,9 +412,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__rest
         t[i] = T(0);
         acc[0] += ri * ri;
         if constexpr (Inc) {
-            const T dui = di * Q[(size_t)i * ldq + (q - 1)];
-            qq[i] = Q[(size_t)i * ldq + (q - 1)];
+            const T ui = Q[(size_t)i * ldq + (q - 1)];
+            const T dui = di * ui;
+            qq[i] = ui;
             qq[(size_t)n + i] = dui;
+            qcm[(size_t)(q - 1) * col_ld(n) + i] = ui;
 #pragma unroll
             for (int j = 0; j < kPipeQ; ++j)
                 if (j < q) {
@@ -430,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__rest
                     acc[1 + j] -= qij * ri;
                     qq[(size_t)i * q2 + j] = qij;
                     qq[(size_t)i * q2 + q + j] = di * qij;
+                    qcm[(size_t)j * col_ld(n) + i] = qij;
                 }
         }
     }
@@ -466,8 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_init1(int n, const double *__rest
 // c0 = -Q'r, stop if r = 0; res -= Q c0; yh = D^{-1} res;  partials res'yh, Q'yh
 template <typename T, bool Inc>
 __global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res, T *__restrict__ yh,
-                                                     const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
-                                                     int q, const T *__restrict__ part_in, int nb_in,
+                                                     const T *__restrict__ dinv, const T *__restrict__ Qc, int q, const T *__restrict__ part_in, int nb_in,
                                                      T *__restrict__ part_out, const T *__restrict__ kpart, int nk,
                                                      T *__restrict__ kmat, PcgState<T> *st) {
     constexpr int NP = Inc ? kIncNV : kPP;
@@ -499,12 +501,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res,
 #pragma unroll
     for (int j = 0; j < kPP; ++j) acc[j] = T(0);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const T *qi = Q + (size_t)i * ldq;
         T qv[kPipeQ];
         T proj = T(0);
 #pragma unroll
         for (int j = 0; j < kPipeQ; ++j) {
-            qv[j] = j < q ? qi[j] : T(0);
+            qv[j] = j < q ? Qc[(size_t)j * col_ld(n) + i] : T(0);
             proj += qv[j] * tot[1 + j];
         }
         const T ri = res[i] - proj;
@@ -522,10 +523,29 @@ __global__ __launch_bounds__(kBlock) void k_pp_init2(int n, T *__restrict__ res,
 // G u and G D^{-1}u, from the vectors u and D^{-1}u that init1 left in ud.
 template <typename T, bool Wt>
 __global__ __launch_bounds__(kBlock) void k_pp_gq2(Graph g, Weights<T> w, const T *__restrict__ ud, int q,
-                                                   T *__restrict__ gqq) {
-    const size_t q2 = 2 * (size_t)q;
-    for_each_row<T, Wt, false>(g, w, ud, [&](int i, T, T yi, T) { gqq[i * q2 + (q - 1)] = yi; });
-    for_each_row<T, Wt, false>(g, w, ud + g.n, [&](int i, T, T yi, T) { gqq[i * q2 + (2 * q - 1)] = yi; });
+                                                   T *__restrict__ gqc) {
+    const size_t ldc = col_ld(g.n);
+    for_each_row<T, Wt, false>(g, w, ud, [&](int i, T, T yi, T) { gqc[(size_t)(q - 1) * ldc + i] = yi; });
+    for_each_row<T, Wt, false>(g, w, ud + g.n, [&](int i, T, T yi, T) { gqc[(size_t)(2 * q - 1) * ldc + i] = yi; });
+}
+
+// out (column-major, ld n) = in (n x wd, row-major): 64-row tiles through LDS,
+// both sides coalesced
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rm_to_cm(int n, int wd, const T *__restrict__ in, T *__restrict__ out) {
+    __shared__ T tile[kWave * 2 * kPipeQ];
+    for (int r0 = blockIdx.x * kWave; r0 < n; r0 += gridDim.x * kWave) {
+        const int rows = min(kWave, n - r0);
+        const int cnt = rows * wd;
+        const T *src = in + (size_t)r0 * wd;
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) tile[e] = src[e];
+        __syncthreads();
+        for (int e = threadIdx.x; e < kWave * wd; e += blockDim.x) {
+            const int j = e / kWave, r = e % kWave;
+            if (r < rows) out[(size_t)j * col_ld(n) + r0 + r] = tile[r * wd + j];
+        }
+        __syncthreads();
+    }
 }
 
 // init3: c_y = Q'yh;  u = yh - Q c_y;  w~ = (G - theta I) u, gathered as
@@ -538,7 +558,7 @@ struct P3Row {
 
 template <typename T, bool Wt, int QM>
 __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, const double *__restrict__ theta,
-                                                     const T *__restrict__ Q, int ldq, const T *__restrict__ gqq,
+                                                     const T *__restrict__ Qc, const T *__restrict__ gqc,
                                                      int q, const T *__restrict__ dinv, const T *__restrict__ res,
                                                      const T *__restrict__ yh, T *__restrict__ u, T *__restrict__ wv,
                                                      T *__restrict__ wh, const T *__restrict__ part_in, int nb_in,
@@ -548,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, cons
     __shared__ T tot[kPP];
     fold_partials<T, kPP>(part_in, nb_in, q + 1, tot);
     if (stop_v != 0 && stop_v <= sq) return;
-    const int q2 = 2 * q;
+    const size_t ldc = col_ld(g.n);
     using L = PLay<QM>;
     T acc[L::N];
 #pragma unroll
@@ -557,8 +577,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_init3(Graph g, Weights<T> w, cons
         P3Row<T, QM> d;
 #pragma unroll
         for (int j = 0; j < QM; ++j) {
-            d.q[j] = j < q ? Q[(size_t)i * ldq + j] : T(0);
-            d.gq[j] = j < q ? gqq[(size_t)i * q2 + j] : T(0);
+            d.q[j] = j < q ? Qc[(size_t)j * ldc + i] : T(0);
+            d.gq[j] = j < q ? gqc[(size_t)j * ldc + i] : T(0);
         }
         d.dinv = dinv[i];
         d.res = res[i];
@@ -603,8 +623,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
     // arrives in preloaded SGPRs rather than after a kernel-argument load
     const T *__restrict__ part_in, PcgState<T> *st, int nb_in, int sq, int it, int q,
     const T *__restrict__ kmat, const double *__restrict__ theta, T rtol,
-    Graph g, Weights<T> w, const T *__restrict__ Q, int ldq,
-    const T *__restrict__ gqq, const T *__restrict__ dinv, T *__restrict__ t,
+    Graph g, Weights<T> w, const T *__restrict__ Qc,
+    const T *__restrict__ gqc, const T *__restrict__ dinv, T *__restrict__ t,
     T *__restrict__ res, T *__restrict__ u, T *__restrict__ wv, const T *__restrict__ wh_in,
     T *__restrict__ wh_out, T *__restrict__ p, T *__restrict__ s, T *__restrict__ qv, T *__restrict__ z,
     T *__restrict__ part_out) {
@@ -667,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
         st->total += 1;
     }
     __syncthreads();
-    const int q2 = 2 * q;
+    const size_t ldc = col_ld(g.n);
     const bool first = it == 0;
     T acc[L::N];
 #pragma unroll
@@ -676,9 +696,9 @@ __global__ __launch_bounds__(kBlock) void k_pp_iter(
         PIRow<T, QM> d;
 #pragma unroll
         for (int j = 0; j < QM; ++j) {
-            d.q[j] = j < q ? Q[(size_t)i * ldq + j] : T(0);
-            d.gq[j] = j < q ? gqq[(size_t)i * q2 + j] : T(0);
-            d.gdq[j] = j < q ? gqq[(size_t)i * q2 + q + j] : T(0);
+            d.q[j] = j < q ? Qc[(size_t)j * ldc + i] : T(0);
+            d.gq[j] = j < q ? gqc[(size_t)j * ldc + i] : T(0);
+            d.gdq[j] = j < q ? gqc[(size_t)(q + j) * ldc + i] : T(0);
         }
         d.dinv = dinv[i];
         d.t = t[i];
@@ -826,39 +846,47 @@ void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, in
     const int gv = vgrid(n);
     const int gr = row_grid(P.g, P.weighted ? pp_iter_groups<T, true, QM>() : pp_iter_groups<T, false, QM>());
     const int q2 = 2 * q;
-    LAP_REQUIRE(w.qq.n >= (size_t)n * q2 && w.kpart.n >= (size_t)gv * 256, LAP_EDEVICE,
-                "PCG work area too small for the projector");
+    LAP_REQUIRE(w.qq.n >= (size_t)n * q2 && w.qcm.n >= col_ld(n) * q && w.gqcm.n >= col_ld(n) * q2 &&
+                    w.kpart.n >= (size_t)gv * 256,
+                LAP_EDEVICE, "PCG work area too small for the projector");
     T *pa = w.part.get();
     T *pb = pa + (size_t)pcg_max_groups() * 64;
     PcgState<T> *st = w.st.get();
     const T *dinv = P.dinv<T>();
     const T tol = (T)rtol;
     T *wh0 = w.wh.get(), *wh1 = wh0 + n;
+    // the per-row operands of init3 and the iterations, column-major (one
+    // coalesced load per column): Q, then G Q and G D^{-1}Q
+    T *qc = w.qcm.get(), *gqc = w.gqcm.get();
     if (inc) {
         hipLaunchKernelGGL((k_pp_init1<T, true>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q,
-                           dinv, w.qq.get(), pa, w.kpart.get(), st);
+                           dinv, w.qq.get(), qc, pa, w.kpart.get(), st);
         const int grow = row_grid(P.g, 1 << 20);
         if (P.weighted)
             hipLaunchKernelGGL((k_pp_gq2<T, true>), dim3(grow), dim3(kBlock), 0, s, P.g, P.weights<T>(), w.qq.get(),
-                               q, w.gqq.get());
+                               q, gqc);
         else
             hipLaunchKernelGGL((k_pp_gq2<T, false>), dim3(grow), dim3(kBlock), 0, s, P.g, P.weights<T>(), w.qq.get(),
-                               q, w.gqq.get());
-        hipLaunchKernelGGL((k_pp_init2<T, true>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq,
-                           q, pa, gv, pb, w.kpart.get(), gv, w.kmat.get(), st);
+                               q, gqc);
+        hipLaunchKernelGGL((k_pp_init2<T, true>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, qc, q, pa,
+                           gv, pb, w.kpart.get(), gv, w.kmat.get(), st);
     } else {
         hipLaunchKernelGGL((k_pp_init1<T, false>), dim3(gv), dim3(kBlock), 0, s, n, r, w.res.get(), t, Q, ldq, q,
-                           dinv, w.qq.get(), pa, w.kpart.get(), st);
-        if (q > 0) spmm<T>(P, q2, w.qq.get(), q2, w.gqq.get(), q2, nullptr, s);
-        hipLaunchKernelGGL((k_pp_init2<T, false>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, Q, ldq,
-                           q, pa, gv, pb, w.kpart.get(), gv, w.kmat.get(), st);
+                           dinv, w.qq.get(), qc, pa, w.kpart.get(), st);
+        if (q > 0) {
+            spmm<T>(P, q2, w.qq.get(), q2, w.gqq.get(), q2, nullptr, s);
+            const int tg = std::min((n + kWave - 1) / kWave, 8 * device_cu_count());
+            hipLaunchKernelGGL((k_rm_to_cm<T>), dim3(tg), dim3(kBlock), 0, s, n, q2, w.gqq.get(), gqc);
+        }
+        hipLaunchKernelGGL((k_pp_init2<T, false>), dim3(gv), dim3(kBlock), 0, s, n, w.res.get(), wh1, dinv, qc, q,
+                           pa, gv, pb, w.kpart.get(), gv, w.kmat.get(), st);
     }
     if (P.weighted)
-        hipLaunchKernelGGL((k_pp_init3<T, true, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
-                           w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
+        hipLaunchKernelGGL((k_pp_init3<T, true, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, qc,
+                           gqc, q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
     else
-        hipLaunchKernelGGL((k_pp_init3<T, false, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, Q, ldq,
-                           w.gqq.get(), q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
+        hipLaunchKernelGGL((k_pp_init3<T, false, QM>), dim3(gr), dim3(kBlock), 0, s, P.g, P.weights<T>(), theta, qc,
+                           gqc, q, dinv, w.res.get(), wh1, w.u.get(), w.w.get(), wh0, pb, gv, pa, st, 2);
     for (int it = 0; it < itmax; ++it) {
         T *pin = (it & 1) ? pb : pa;
         T *pout = (it & 1) ? pa : pb;
@@ -866,14 +894,12 @@ void enqueue_pipelined_qm(const lap_plan &P, const double *theta, const T *Q, in
         T *hout = (it & 1) ? wh0 : wh1;
         if (P.weighted)
             hipLaunchKernelGGL((k_pp_iter<T, true, QM>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
-                               w.kmat.get(), theta, tol, P.g, P.weights<T>(), Q, ldq, w.gqq.get(), dinv, t,
-                               w.res.get(), w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(),
-                               w.z.get(), pout);
+                               w.kmat.get(), theta, tol, P.g, P.weights<T>(), qc, gqc, dinv, t, w.res.get(),
+                               w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(), w.z.get(), pout);
         else
             hipLaunchKernelGGL((k_pp_iter<T, false, QM>), dim3(gr), dim3(kBlock), 0, s, pin, st, gr, 3 + it, it, q,
-                               w.kmat.get(), theta, tol, P.g, P.weights<T>(), Q, ldq, w.gqq.get(), dinv, t,
-                               w.res.get(), w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(),
-                               w.z.get(), pout);
+                               w.kmat.get(), theta, tol, P.g, P.weights<T>(), qc, gqc, dinv, t, w.res.get(),
+                               w.u.get(), w.w.get(), hin, hout, w.p.get(), w.s.get(), w.qv.get(), w.z.get(), pout);
     }
     LAP_HIP(hipGetLastError());
 }

@@ -224,6 +224,10 @@ void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
     int n_long = 0, n_huge = 0;
     while (n_long < n && deg(n_long) > long_threshold) ++n_long;
     while (n_huge < n && deg(n_huge) > huge_threshold) ++n_huge;
+    // The slices start at a multiple of 32 rows, so that a slice's 64 values
+    // of any vector (FP32 or FP64) fill whole 128-byte lines: the up to 31
+    // rows that this moves into the long class are summed a wavefront per row.
+    n_long = std::min(n, (n_long + 31) & ~31);
 
     // 64-row column-major slices for rows [n_long, n)
     const int nslices = (n - n_long + kWave - 1) / kWave;
@@ -252,7 +256,7 @@ void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
     // long rows in chunks of kChunk edges (the block product splits them)
     std::vector<int> coff(n_long + 1, 0), crow;
     for (int r = 0; r < n_long; ++r) {
-        const int nc = (deg(r) + kChunk - 1) / kChunk;
+        const int nc = std::max(1, (deg(r) + kChunk - 1) / kChunk);  // a row of degree 0 still gets its chunk
         coff[r + 1] = coff[r] + nc;
         for (int c = 0; c < nc; ++c) crow.push_back(r);
     }
