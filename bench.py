@@ -367,6 +367,44 @@ def spmv_entries(lap, torch, gg, np, L, plan):
     return out, (None if rr is None else round(rr / 1e9, 1))
 
 
+def relabel(gg, np, L, perm):
+    """The same graph with vertex perm[k] renamed k."""
+    A = L.to_scipy().tocoo()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    r, c, v = inv[A.row], inv[A.col], A.data
+    up = r < c
+    w = -v[up]
+    return gg.laplacian_from_edges(L.n, r[up], c[up], None if np.all(w == 1.0) else w, name=L.name)
+
+
+def order_experiment(lap, torch, gg, np, orders):
+    """Products on the headline graph with the vertices of one degree in the
+    plan's hub order, or in the caller's order for three labellings of the
+    graph: the generator's, a random one, and reverse Cuthill-McKee (a
+    breadth-first locality order)."""
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    L0 = gg.workload(WORKLOAD, SEED)
+    for o in orders:
+        if o in ("hub", "caller_gen"):
+            L = L0
+        elif o == "caller_random":
+            L = relabel(gg, np, L0, np.random.default_rng(3).permutation(L0.n))
+        elif o == "caller_rcm":
+            L = relabel(gg, np, L0, reverse_cuthill_mckee(L0.to_scipy().tocsr(), symmetric_mode=True).astype(np.int64))
+        else:
+            raise SystemExit(f"unknown order {o}")
+        plan = lap.Plan(L, order="hub" if o == "hub" else "caller")
+        nnz_a = L.nnz - L.n
+        t1 = time_spmv(lap, torch, plan, L.n, reps=100, dtype=torch.float32, b=1)
+        t10 = time_spmv(lap, torch, plan, L.n, reps=100, dtype=torch.float32, b=10)
+        t10d = time_spmv(lap, torch, plan, L.n, reps=50, dtype=torch.float64, b=10)
+        print(json.dumps({"order": o, "workload": WORKLOAD, "row_gathers": nnz_a,
+                          "spmv_f32_us": round(t1 * 1e6, 2), "spmm_b10_f32_us": round(t10 * 1e6, 2),
+                          "spmm_b10_f64_us": round(t10d * 1e6, 2)}), flush=True)
+        plan.close()
+
+
 def sweep(lap, torch, gg, np):
     """The product on the collaboration-like generator at n = 1.1M, 4.4M and
     8.8M (the FP32 working set grows past the 256 MB MALL)."""
@@ -402,6 +440,10 @@ def main():
                     help="only the product kernel loop on one workload (for profiling)")
     ap.add_argument("--pcg-q", type=int, default=PCG_Q,
                     help="projector width of the PCG-iteration timing of --roofline-only")
+    ap.add_argument("--order-exp", nargs="*", default=None, metavar="ORDER",
+                    help="product timings of the headline graph under vertex orders inside a degree: hub (the "
+                         "plan's default), and the caller's order with the generator's, a random or a reverse "
+                         "Cuthill-McKee labelling (caller_gen, caller_random, caller_rcm); all four if none named")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the PCG iteration timing on the headline graph and a copy of known size "
                          "(for profiling)")
@@ -437,6 +479,9 @@ def main():
         dt, _, rb = median_time(lambda: lap.lap_eigs(pb, 20, TOL, seed=1, **kw), 2, torch)
         print(json.dumps({"workload": "cl330k", "block": 20, "s": dt, "outer": rb.outer, "inner": rb.inner,
                           "mvp": rb.mvp, "nconv": rb.nconv}))
+        return
+    if args.order_exp is not None:
+        order_experiment(lap, torch, gg, np, args.order_exp or ["hub", "caller_gen", "caller_random", "caller_rcm"])
         return
     if args.spmv_only:
         Ls = gg.workload(args.spmv_only, SEED)

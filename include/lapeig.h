@@ -131,6 +131,21 @@ void lap_eigs_default_opts(lap_eigs_opts *opts);
  * Errors: LAP_EINVAL (null pointers, n < 1), LAP_ENOTLAPLACIAN (first bad
  * row named in lap_last_error), LAP_ENOMEM / LAP_EDEVICE. */
 lap_status lap_plan_create(const lap_csr *L, void *stream, lap_plan **out);
+
+/* Vertex order inside one degree of the plan (the degree classes always come
+ * in decreasing degree, so the row classes stay prefixes).  HUB (what
+ * lap_plan_create uses): vertices whose first neighbour in plan order is the
+ * same (on power-law graphs nearly always their largest hub) sit side by
+ * side, so a slice's lanes gather from fewer cache lines.  CALLER: the
+ * caller's vertex order, for callers that bring their own locality order
+ * (for example reverse Cuthill-McKee) to compare against it. */
+typedef enum { LAP_PLAN_ORDER_HUB = 0, LAP_PLAN_ORDER_CALLER = 1 } lap_plan_order;
+
+/* lap_plan_create with the order inside a degree chosen by `order` (a
+ * lap_plan_order); LAP_EINVAL for any other value, before any device work.
+ * Results of every entry point are the same up to the rounding of sums taken
+ * in another order. */
+lap_status lap_plan_create_ex(const lap_csr *L, void *stream, int order, lap_plan **out);
 void lap_plan_destroy(lap_plan *plan);
 
 /* Row classes of the Laplacian product (an engineering choice; the paper

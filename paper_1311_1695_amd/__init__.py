@@ -8,7 +8,7 @@ memory and streams.  Importing this module never falls back to anything: if
 the compiled library is missing, every entry point raises.
 
 Entry points mirror the C ABI names:
-  lap_plan_create(L, stream=None) -> Plan
+  lap_plan_create(L, stream=None, order="hub") -> Plan
   lap_eigs(plan, k, tol, **opts)  -> EigResult
   lap_spmv(plan, X, Y, shift=None, plan_order=False, stream=None)
   lap_orth(Q, W, stream=None)     -> rank
@@ -40,8 +40,9 @@ LAP_PREC_FP64, LAP_PREC_MIXED = 0, 1
 LAP_ORDER_PLAN = 1
 LAP_PCG_FSAI = 2
 LAP_PRECOND_JACOBI, LAP_PRECOND_FSAI = 0, 1
+LAP_PLAN_ORDER_HUB, LAP_PLAN_ORDER_CALLER = 0, 1
 
-EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
+EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_create_ex", "lap_plan_destroy", "lap_plan_n", "lap_plan_perm",
             "lap_plan_set_layout", "lap_plan_layout", "lap_plan_autotune",
             "lap_mpnn_create", "lap_mpnn_destroy", "lap_mpnn_num_params", "lap_mpnn_get_params",
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
@@ -104,6 +105,7 @@ def load_library():
     lib.lap_eigs_default_opts.argtypes = [P(_Opts)]
     lib.lap_eigs_default_opts.restype = None
     lib.lap_plan_create.argtypes = [P(_Csr), vp, P(vp)]
+    lib.lap_plan_create_ex.argtypes = [P(_Csr), vp, ctypes.c_int, P(vp)]
     lib.lap_plan_destroy.argtypes = [vp]
     lib.lap_plan_destroy.restype = None
     lib.lap_plan_n.argtypes = [vp]
@@ -152,7 +154,7 @@ def load_library():
     lib.lap_status_string.restype = ctypes.c_char_p
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
-    for name in ["lap_plan_create", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
+    for name in ["lap_plan_create", "lap_plan_create_ex", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
                  "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
                  "lap_fiedler_bisect", "lap_pinv_apply", "lap_eigs_dacg", "lap_eigs_irlm"]:
         getattr(lib, name).restype = ctypes.c_int
@@ -189,11 +191,19 @@ def _csr_struct(L):
 class Plan:
     """A validated Laplacian resident on the current HIP device."""
 
-    def __init__(self, L, stream=None):
+    def __init__(self, L, stream=None, order="hub"):
+        """order: "hub" (lap_plan_create) or "caller" (lap_plan_create_ex with
+        LAP_PLAN_ORDER_CALLER: inside a degree, the caller's vertex order)."""
         lib = load_library()
+        if order not in ("hub", "caller"):
+            raise LapError(LAP_EINVAL, "order must be 'hub' or 'caller'")
         self._csr, self._keep = _csr_struct(L)
         h = ctypes.c_void_p()
-        _check(lib.lap_plan_create(ctypes.byref(self._csr), _stream_handle(stream), ctypes.byref(h)))
+        if order == "hub":
+            _check(lib.lap_plan_create(ctypes.byref(self._csr), _stream_handle(stream), ctypes.byref(h)))
+        else:
+            _check(lib.lap_plan_create_ex(ctypes.byref(self._csr), _stream_handle(stream), LAP_PLAN_ORDER_CALLER,
+                                          ctypes.byref(h)))
         self._h = h
         self.n = int(lib.lap_plan_n(h))
 
@@ -236,8 +246,8 @@ class Plan:
             pass
 
 
-def lap_plan_create(L, stream=None) -> Plan:
-    return Plan(L, stream)
+def lap_plan_create(L, stream=None, order="hub") -> Plan:
+    return Plan(L, stream, order=order)
 
 
 def lap_plan_set_layout(plan: Plan, long_threshold, huge_threshold):

@@ -236,12 +236,18 @@ const char *lap_status_string(lap_status s) {
 const char *lap_last_error(void) { return lapeig::get_error(); }
 
 lap_status lap_plan_create(const lap_csr *L, void *stream, lap_plan **out) {
+    return lap_plan_create_ex(L, stream, LAP_PLAN_ORDER_HUB, out);
+}
+
+lap_status lap_plan_create_ex(const lap_csr *L, void *stream, int order, lap_plan **out) {
     LAP_GUARD_BEGIN
     LAP_REQUIRE(out != nullptr, LAP_EINVAL, "out is NULL");
     *out = nullptr;
+    LAP_REQUIRE(order == LAP_PLAN_ORDER_HUB || order == LAP_PLAN_ORDER_CALLER, LAP_EINVAL,
+                "order must be LAP_PLAN_ORDER_HUB or LAP_PLAN_ORDER_CALLER");
     lap_plan *p = new lap_plan();
     try {
-        lapeig::build_plan(L, (hipStream_t)stream, p);
+        lapeig::build_plan(L, (hipStream_t)stream, p, order == LAP_PLAN_ORDER_HUB);
     } catch (...) {
         delete p;
         throw;

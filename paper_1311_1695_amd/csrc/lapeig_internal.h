@@ -220,8 +220,10 @@ namespace lapeig {
 // ------------------------------------------------------------- plan.cpp
 void validate_laplacian(const lap_csr *L);  // throws Failure (no HIP calls)
 // Validate (host), renumber, classify rows, build slices, upload.
-void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, int long_threshold = 32,
-                int huge_threshold = 512);
+// hub_order: inside a degree, group vertices by their first neighbour in plan
+// order (else keep the caller's order)
+void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *plan, bool hub_order = true,
+                int long_threshold = 32, int huge_threshold = 512);
 // Rebuild the row classes of an existing plan for other thresholds.
 void build_layout(lap_plan *plan, int long_threshold, int huge_threshold);
 

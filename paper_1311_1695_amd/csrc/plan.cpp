@@ -79,7 +79,7 @@ void upload(DevBuf<T> &dst, const std::vector<T> &src) {
 
 }  // namespace
 
-void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_threshold,
+void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, bool hub_order, int long_threshold,
                 int huge_threshold) {
     validate_laplacian(L);
     const int n = L->n;
@@ -108,11 +108,11 @@ void build_plan(const lap_csr *L, hipStream_t stream, lap_plan *P, int long_thre
     // side: a hub's neighbour list then falls into runs of consecutive
     // positions and the 64 lanes of a slice gather from fewer cache lines.
     // The key is formed twice, the second time against the refined order;
-    // remaining ties go by the caller's index.
+    // remaining ties go by the caller's index (all ties, without hub_order).
     std::vector<int> iperm(n), perm(n), first(n);
     std::iota(iperm.begin(), iperm.end(), 0);
     std::stable_sort(iperm.begin(), iperm.end(), [&](int a, int b) { return deg[a] > deg[b]; });
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < (hub_order ? 2 : 0); ++pass) {
         for (int p = 0; p < n; ++p) perm[iperm[p]] = p;
         for (int i = 0; i < n; ++i) {
             int f = n;

@@ -64,6 +64,28 @@ def test_valid_matrix_passes_validation_then_needs_a_device():
     assert err.code in (lap.LAP_EDEVICE, lap.LAP_ENOMEM)
 
 
+def test_plan_order_argument_checked_before_hip():
+    rp, cl, vl = _good()
+
+    class L:
+        pass
+    L.n, L.rowptr, L.col, L.val = 4, rp, cl, vl
+    lib = lap.load_library()
+    csr, keep = lap._csr_struct(L)
+    h = ctypes.c_void_p()
+    for bad in (-1, 2, 7):
+        assert lib.lap_plan_create_ex(ctypes.byref(csr), None, bad, ctypes.byref(h)) == lap.LAP_EINVAL
+        assert not h.value
+    with pytest.raises(lap.LapError) as e:
+        lap.Plan(L, order="rcm")
+    assert e.value.code == lap.LAP_EINVAL
+    # a valid order gets past the checks and then needs the device
+    for order in ("hub", "caller"):
+        with pytest.raises(lap.LapError) as e:
+            lap.Plan(L, order=order)
+        assert e.value.code in (lap.LAP_EDEVICE, lap.LAP_ENOMEM)
+
+
 @pytest.mark.parametrize("case", [
     "rowptr0", "rowptr_decreasing", "rowptr_end", "col_range", "col_unsorted", "col_duplicate",
     "nonfinite", "positive_offdiag", "asym_pattern", "asym_values", "bad_diagonal", "bad_diagonal_float",

@@ -148,6 +148,32 @@ def test_spmm_unaligned_rows_bitwise(b, off_f32, off_f64):
         assert torch.all(yb[:off] == 7.0) and float(yb[-1]) == 7.0
 
 
+@pytest.mark.parametrize("name", ["cl30k", "cl30k_w", "star9000"])
+def test_plan_caller_order_same_products(name):
+    # LAP_PLAN_ORDER_CALLER keeps the caller's order inside a degree; the
+    # products (integer data: exact) and the solve do not depend on it
+    L = graph(name)
+    rng = np.random.default_rng(21)
+    x = rng.integers(-64, 64, size=(L.n, 10)).astype(np.float64)
+    ref = np.stack([oracle.spmv(L, x[:, c]) for c in range(10)], axis=1)
+    vals = []
+    for order in ("hub", "caller"):
+        plan = lap.Plan(L, order=order)
+        for tdt in (torch.float32, torch.float64):
+            for cols in (1, 10):
+                X = torch.tensor(x[:, :cols] if cols > 1 else x[:, 0].copy(), dtype=tdt, device="cuda")
+                Y = torch.empty_like(X)
+                lap.lap_spmv(plan, X, Y)
+                torch.cuda.synchronize()
+                want = ref[:, :cols] if cols > 1 else ref[:, 0]
+                assert np.array_equal(Y.double().cpu().numpy(), want), (order, tdt, cols)
+        r = lap.lap_eigs(plan, 5, 1e-8, precision="mixed", seed=1)
+        assert r.nconv == 5
+        vals.append(np.asarray(r.evals))
+        plan.close()
+    assert np.allclose(vals[0], vals[1], rtol=1e-8, atol=1e-12)
+
+
 def test_spmv_plan_order_and_random_vectors():
     L = graph("cl30k")
     plan = lap.Plan(L)
