@@ -332,21 +332,38 @@ def extra_configs(lap, torch, gg, np, reps=3):
                                     "lambda2": float(r.evals[1]), "lambda_k": float(r.evals[-1])}
         plan.close()
         out.append(entry)
+    out.append(batch_entry(lap, torch, gg, np))
+    return out
+
+
+def batch_entry(lap, torch, gg, np):
+    """The batch of 256 uneven preferential-attachment graphs (5 pairs each,
+    one persistent launch) in both precisions: time, products, the
+    autotuned row-class threshold, and the aggregate product bandwidth:
+    every graph's products times its algorithmic product bytes (offsets,
+    indices, one read of x, one write of y, at the PCG's precision; the FP64
+    outer products are counted at that precision too), over the time."""
     graphs = gg.pa_batch(256, SEED)
     b = lap.lap_batch_create(graphs)
     sum_nnz = sum(g.nnz for g in graphs)
     entry = {"workload": "pa_batch256", "graphs": len(graphs), "sum_n": sum(g.n for g in graphs),
              "sum_nnz": sum_nnz, "k": 5, "tol": TOL, "runs": {}}
-    for label, prec in (("mixed", "mixed"), ("fp64", "fp64")):
+    for label, prec, elem in (("mixed", "mixed", 4), ("fp64", "fp64", 8)):
+        t0 = time.perf_counter()
+        thr, pass_s = b.autotune(prec)
+        t_tune = time.perf_counter() - t0
         lap.lap_batch_eigs(b, 5, TOL, precision=prec)
         dt, _, res = median_time(lambda: lap.lap_batch_eigs(b, 5, TOL, precision=prec), 2, torch)
         worst = max(certify(L, r) for L, r in zip(graphs, res))
+        prod_bytes = sum(int(r.mvp) * spmv_bytes(L.n, L.nnz - L.n, elem) for L, r in zip(graphs, res))
         entry["runs"][label] = {"s": round(dt, 4), "mvp_total": int(sum(r.mvp for r in res)),
                                 "nconv_min": int(min(r.nconv for r in res)),
-                                "max_rel_residual": worst}
+                                "max_rel_residual": worst, "long_threshold": thr,
+                                "autotune_s": round(t_tune, 3), "product_pass_us": round(pass_s * 1e6, 1),
+                                "aggregate_product_GB/s": round(prod_bytes / dt / 1e9, 1),
+                                "aggregate_product_frac": round(prod_bytes / dt / 1e9 / HBM_PEAK_GBS, 4)}
     b.close()
-    out.append(entry)
-    return out
+    return entry
 
 
 def spmv_entries(lap, torch, gg, np, L, plan):
@@ -444,6 +461,8 @@ def main():
                     help="product timings of the headline graph under vertex orders inside a degree: hub (the "
                          "plan's default), and the caller's order with the generator's, a random or a reverse "
                          "Cuthill-McKee labelling (caller_gen, caller_random, caller_rcm); all four if none named")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batch of 256 preferential-attachment graphs, both precisions")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the PCG iteration timing on the headline graph and a copy of known size "
                          "(for profiling)")
@@ -479,6 +498,11 @@ def main():
         dt, _, rb = median_time(lambda: lap.lap_eigs(pb, 20, TOL, seed=1, **kw), 2, torch)
         print(json.dumps({"workload": "cl330k", "block": 20, "s": dt, "outer": rb.outer, "inner": rb.inner,
                           "mvp": rb.mvp, "nconv": rb.nconv}))
+        return
+    if args.batch_only:
+        entry = batch_entry(lap, torch, gg, np)
+        entry["copy_GB/s"] = round(copy_bandwidth(torch, 256 << 20, reps=20) / 1e9, 1)
+        print(json.dumps(entry), flush=True)
         return
     if args.order_exp is not None:
         order_experiment(lap, torch, gg, np, args.order_exp or ["hub", "caller_gen", "caller_random", "caller_rcm"])

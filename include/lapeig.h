@@ -357,7 +357,8 @@ lap_status lap_pinv_apply(int n, int k, const double *evals, const double *evecs
 /* Many independent graphs at once (the batched form of Algorithm 2): one
  * persistent launch, captured in a hipGraph, in which each 1024-thread
  * workgroup runs the whole single-vector solver for one graph with all its
- * reductions in LDS, taking graphs largest first from a device queue.
+ * reductions in LDS, taking graphs largest first from a device queue; the
+ * row classes of its product are autotuned per batch (lap_batch_autotune).
  * Each graph is validated as in lap_plan_create and must be connected
  * (LAP_EUNSUPPORTED otherwise); 1 <= k <= 8, m_max <= 16, block = 1.
  * lap_batch_create validates, renumbers and uploads the graphs (host
@@ -375,6 +376,19 @@ typedef struct lap_batch lap_batch;
 lap_status lap_batch_create(const lap_csr *Ls, int nb, lap_batch **out);
 void lap_batch_destroy(lap_batch *batch);
 int32_t lap_batch_total_n(const lap_batch *batch);
+
+/* Row classes of the batched product: rows whose degree is above a threshold
+ * get a wavefront each, the others a thread each.  lap_batch_autotune times
+ * one product pass over all graphs of the batch for each candidate threshold
+ * (4, 8, ..., 256, and none long) in the given lap_precision's arithmetic and
+ * keeps the fastest for that precision; lap_batch_eigs does this by itself
+ * on its first call in a precision.  long_threshold / seconds (either may be
+ * NULL): the chosen threshold and the seconds per pass it measured.
+ * lap_batch_layout: the threshold in use for a precision and whether it was
+ * tuned (1) or is the default 32 (0).  Errors: LAP_EINVAL (NULL batch or
+ * outputs, unknown precision), LAP_EDEVICE. */
+lap_status lap_batch_autotune(lap_batch *batch, int precision, int32_t *long_threshold, double *seconds);
+lap_status lap_batch_layout(const lap_batch *batch, int precision, int32_t *long_threshold, int32_t *tuned);
 lap_status lap_batch_eigs(lap_batch *batch, int k, double tol, const lap_eigs_opts *opts, double *evals,
                           double *evecs, double *res, lap_eigs_info *infos, void *stream);
 lap_status lap_eigs_batch(const lap_csr *Ls, int nb, int k, double tol, const lap_eigs_opts *opts,

@@ -48,7 +48,7 @@ EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_create_ex", "l
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
             "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config", "lap_fiedler_bisect", "lap_pinv_apply",
             "lap_eigs", "lap_eigs_csr", "lap_eigs_dacg", "lap_eigs_irlm", "lap_spmv", "lap_spmv_noalloc", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
-            "lap_batch_destroy", "lap_batch_total_n", "lap_batch_eigs", "lap_eigs_batch",
+            "lap_batch_destroy", "lap_batch_total_n", "lap_batch_autotune", "lap_batch_layout", "lap_batch_eigs", "lap_eigs_batch",
             "lap_status_string", "lap_last_error"]
 
 
@@ -130,6 +130,8 @@ def load_library():
     lib.lap_batch_destroy.argtypes = [vp]
     lib.lap_batch_destroy.restype = None
     lib.lap_batch_total_n.argtypes = [vp]
+    lib.lap_batch_autotune.argtypes = [vp, ctypes.c_int, i32p, f64p]
+    lib.lap_batch_layout.argtypes = [vp, ctypes.c_int, i32p, i32p]
     lib.lap_batch_total_n.restype = ctypes.c_int32
     lib.lap_batch_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info), vp]
     lib.lap_eigs_batch.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p,
@@ -156,7 +158,8 @@ def load_library():
     lib.lap_last_error.restype = ctypes.c_char_p
     for name in ["lap_plan_create", "lap_plan_create_ex", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
                  "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
-                 "lap_fiedler_bisect", "lap_pinv_apply", "lap_eigs_dacg", "lap_eigs_irlm"]:
+                 "lap_fiedler_bisect", "lap_pinv_apply", "lap_eigs_dacg", "lap_eigs_irlm", "lap_batch_autotune",
+                 "lap_batch_layout"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -275,6 +278,14 @@ class EigResult:
     seconds: float
     status: int
     warm_start_used: int = 0
+
+
+def _precision_code(precision):
+    if isinstance(precision, str):
+        if precision not in ("mixed", "fp64"):
+            raise LapError(LAP_EINVAL, "precision must be 'mixed' or 'fp64'")
+        return LAP_PREC_MIXED if precision == "mixed" else LAP_PREC_FP64
+    return int(precision)
 
 
 def _opts(precision="mixed", m_min=5, m_max=10, itmax=20, rtol_pcg=1e-2, kmax=0, block=1, seed=1, init=None,
@@ -504,6 +515,21 @@ class Batch:
         h = ctypes.c_void_p()
         _check(lib.lap_batch_create(arr, len(graphs), ctypes.byref(h)))
         self._h = h
+
+    def autotune(self, precision="mixed"):
+        """Time the row-class thresholds of the batched product in that
+        precision and keep the fastest; returns (threshold, seconds per pass)."""
+        thr, secs = ctypes.c_int32(0), ctypes.c_double(0.0)
+        _check(load_library().lap_batch_autotune(self._h, _precision_code(precision), ctypes.byref(thr),
+                                                  ctypes.byref(secs)))
+        return int(thr.value), float(secs.value)
+
+    def layout(self, precision="mixed"):
+        """(threshold in use, tuned) for that precision."""
+        thr, tuned = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(load_library().lap_batch_layout(self._h, _precision_code(precision), ctypes.byref(thr),
+                                                ctypes.byref(tuned)))
+        return int(thr.value), bool(tuned.value)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

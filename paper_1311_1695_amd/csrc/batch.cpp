@@ -14,7 +14,10 @@ struct lap_batch {
     std::vector<int> n;                        // vertices per graph
     std::vector<std::vector<int>> perm;        // caller -> plan index, per graph
     std::vector<long long> rp_off, ci_off;
-    std::vector<int> nlong;
+    std::vector<std::vector<int>> degs;        // row degrees in plan order (decreasing), per graph
+    int long_threshold[2] = {32, 32};          // row-class threshold per precision (FP64, mixed)
+    bool tuned[2] = {false, false};
+    double tune_seconds[2] = {0.0, 0.0};
     lapeig::DevBuf<int> rowptr, col;
     lapeig::DevBuf<float> w32;
     lapeig::DevBuf<double> w64;
@@ -25,7 +28,15 @@ namespace lapeig {
 
 namespace {
 
-constexpr int kBatchLong = 32;  // rows above this degree get a wavefront each
+// Row-class thresholds the autotuner times: rows above the threshold get a
+// wavefront each, the others a thread each (the last candidate: none long).
+constexpr int kBatchLongCandidates[] = {4, 8, 16, 32, 64, 128, 256, 1 << 30};
+
+// rows of graph g with degree above thr (a prefix: degrees decrease)
+int nlong_of(const lap_batch *B, int g, int thr) {
+    const std::vector<int> &d = B->degs[g];
+    return (int)(std::upper_bound(d.begin(), d.end(), thr, [](int t, int v) { return t > v; }) - d.begin());
+}
 
 void pack(lap_batch *B, const lap_csr *Ls, int nb) {
     for (int g = 0; g < nb; ++g) {
@@ -89,10 +100,10 @@ void pack(lap_batch *B, const lap_csr *Ls, int nb) {
             acc += (int)tmp.size();
             rp_all.push_back(acc);
         }
-        int nl = 0;
-        while (nl < n && deg[iperm[nl]] > kBatchLong) ++nl;
+        std::vector<int> dsorted(n);
+        for (int p = 0; p < n; ++p) dsorted[p] = deg[iperm[p]];
         B->n.push_back(n);
-        B->nlong.push_back(nl);
+        B->degs.push_back(std::move(dsorted));
         B->perm.push_back(std::move(perm));
         B->total_n += n;
         B->total_nnz += acc;
@@ -113,6 +124,92 @@ void pack(lap_batch *B, const lap_csr *Ls, int nb) {
 
 }  // namespace
 
+// Seconds per product pass over the whole batch (one workgroup per graph,
+// the solver's row engine) for each threshold candidate: `reps` passes
+// captured in a graph on a stream of our own, replayed three times, best
+// replay.  Keeps the fastest candidate (ties: the smaller threshold).
+int batch_autotune(lap_batch *B, bool mixed, int reps, double *best_seconds) {
+    const int nb = B->nb;
+    const size_t elem = mixed ? 4 : 8;
+    std::vector<long long> voff(nb);
+    long long tot = 0;
+    for (int g = 0; g < nb; ++g) { voff[g] = tot; tot += B->n[g]; }
+    DevBuf<char> x((size_t)tot * elem), y((size_t)tot * elem);
+    DevBuf<long long> dvoff(nb);
+    DevBuf<BGraph> dg(nb);
+    LAP_HIP(hipMemset(x.get(), 0, (size_t)tot * elem));
+    LAP_HIP(hipMemcpy(dvoff.get(), voff.data(), sizeof(long long) * nb, hipMemcpyHostToDevice));
+    hipStream_t s = nullptr;
+    LAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraphExec_t ge = nullptr;
+    int best_thr = B->long_threshold[mixed ? 1 : 0];
+    double best = 1e300;
+    try {
+        LAP_HIP(hipEventCreate(&e0));
+        LAP_HIP(hipEventCreate(&e1));
+        const float *w32 = B->weighted ? B->w32.get() : nullptr;
+        const double *w64 = B->weighted ? B->w64.get() : nullptr;
+        for (int thr : kBatchLongCandidates) {
+            std::vector<BGraph> gd(nb);
+            for (int g = 0; g < nb; ++g) {
+                gd[g] = BGraph{};
+                gd[g].n = B->n[g];
+                gd[g].nlong = nlong_of(B, g, thr);
+                gd[g].rp = B->rp_off[g];
+                gd[g].ci = B->ci_off[g];
+            }
+            LAP_HIP(hipMemcpyAsync(dg.get(), gd.data(), sizeof(BGraph) * nb, hipMemcpyHostToDevice, s));
+            auto pass = [&]() {
+                batch_spmv_launch(dg.get(), nb, dvoff.get(), B->rowptr.get(), B->col.get(), w32, w64, mixed, x.get(),
+                                  y.get(), nb, s);
+            };
+            pass();  // code objects loaded, caches warm
+            LAP_HIP(hipStreamSynchronize(s));
+            hipGraph_t gr = nullptr;
+            LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int r = 0; r < reps; ++r) pass();
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &gr);
+                if (gr) (void)hipGraphDestroy(gr);
+                throw;
+            }
+            LAP_HIP(hipStreamEndCapture(s, &gr));
+            const hipError_t ierr = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            LAP_HIP(ierr);
+            double t = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                LAP_HIP(hipEventRecord(e0, s));
+                LAP_HIP(hipGraphLaunch(ge, s));
+                LAP_HIP(hipEventRecord(e1, s));
+                LAP_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                LAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+                t = std::min(t, 1e-3 * ms / reps);
+            }
+            LAP_HIP(hipGraphExecDestroy(ge));
+            ge = nullptr;
+            if (t < best) { best = t; best_thr = thr; }
+        }
+    } catch (...) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    LAP_HIP(hipStreamDestroy(s));
+    B->long_threshold[mixed ? 1 : 0] = best_thr;
+    B->tuned[mixed ? 1 : 0] = true;
+    B->tune_seconds[mixed ? 1 : 0] = best;
+    if (best_seconds) *best_seconds = best;
+    return best_thr;
+}
+
 lap_status batch_create(const lap_csr *Ls, int nb, lap_batch **out) {
     LAP_REQUIRE(Ls && nb >= 1 && out, LAP_EINVAL, "need graphs, nb >= 1 and an output handle");
     lap_batch *B = new lap_batch();
@@ -127,6 +224,11 @@ lap_status batch_create(const lap_csr *Ls, int nb, lap_batch **out) {
 }
 
 void batch_destroy(lap_batch *B) { delete B; }
+
+void batch_layout(const lap_batch *B, bool mixed, int *long_threshold, int *tuned) {
+    *long_threshold = B->long_threshold[mixed ? 1 : 0];
+    *tuned = B->tuned[mixed ? 1 : 0] ? 1 : 0;
+}
 int batch_total_n(const lap_batch *B) { return B ? (int)B->total_n : 0; }
 
 lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
@@ -140,6 +242,10 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
     const int nb = B->nb;
     for (int g = 0; g < nb; ++g)
         LAP_REQUIRE(k < B->n[g], LAP_EINVAL, "graph " + std::to_string(g) + " has n <= k");
+    const bool mixed = o.precision == LAP_PREC_MIXED;
+    // row classes: the autotuned threshold of this precision (tuned on first use)
+    if (!B->tuned[mixed ? 1 : 0]) batch_autotune(B, mixed, 5, nullptr);
+    const int thr = B->long_threshold[mixed ? 1 : 0];
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
     // descriptors and workspace offsets
     std::vector<BGraph> gd(nb);
@@ -148,7 +254,7 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
         const long long n = B->n[g];
         BGraph &d = gd[g];
         d.n = (int)n;
-        d.nlong = B->nlong[g];
+        d.nlong = nlong_of(B, g, thr);
         d.k = k;
         d.pad = 0;
         d.rp = B->rp_off[g];
@@ -216,7 +322,7 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
     hipGraph_t graph = nullptr;
     LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
-        batch_launch(a, o.precision == LAP_PREC_MIXED, B->weighted, grid, s);
+        batch_launch(a, mixed, B->weighted, grid, s);
     } catch (...) {
         (void)hipStreamEndCapture(s, &graph);
         if (graph) (void)hipGraphDestroy(graph);

@@ -732,6 +732,26 @@ __global__ void k_batch_reset(unsigned *queue) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
 }
 
+// The solver's product on every graph of the batch (y = G x, graph g's
+// vectors at voff[g]), one workgroup per graph as in the solver, for timing
+// the row-class threshold candidates.
+template <typename T, bool WT>
+__global__ __launch_bounds__(kBT) void k_batch_spmv(const BGraph *__restrict__ graphs, int ngraphs,
+                                                    const long long *__restrict__ voff, const int *__restrict__ rowptr,
+                                                    const int *__restrict__ col, const float *__restrict__ w32,
+                                                    const double *__restrict__ w64, const T *__restrict__ x,
+                                                    T *__restrict__ y) {
+    for (int gi = blockIdx.x; gi < ngraphs; gi += gridDim.x) {
+        const BGraph G = graphs[gi];
+        const GView gv{G.n, G.nlong, rowptr + G.rp, col + G.ci, w32 ? w32 + G.ci : nullptr,
+                       w64 ? w64 + G.ci : nullptr};
+        const T *xg = x + voff[gi];
+        T *yg = y + voff[gi];
+        wg_rows<T, WT, false>(gv, xg, [&](int i, T, T yi, T) { yg[i] = yi; });
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -760,6 +780,28 @@ void launch_jd(BatchArgs a, int grid, hipStream_t s) {
 }
 
 }  // namespace
+
+void batch_spmv_launch(const BGraph *graphs, int ngraphs, const long long *voff, const int *rowptr, const int *col,
+                       const float *w32, const double *w64, bool mixed, const void *x, void *y, int grid,
+                       hipStream_t s) {
+    const bool wt = w32 != nullptr;
+    if (mixed) {
+        if (wt)
+            hipLaunchKernelGGL((k_batch_spmv<float, true>), dim3(grid), dim3(kBT), 0, s, graphs, ngraphs, voff, rowptr,
+                               col, w32, w64, (const float *)x, (float *)y);
+        else
+            hipLaunchKernelGGL((k_batch_spmv<float, false>), dim3(grid), dim3(kBT), 0, s, graphs, ngraphs, voff,
+                               rowptr, col, w32, w64, (const float *)x, (float *)y);
+    } else {
+        if (wt)
+            hipLaunchKernelGGL((k_batch_spmv<double, true>), dim3(grid), dim3(kBT), 0, s, graphs, ngraphs, voff,
+                               rowptr, col, w32, w64, (const double *)x, (double *)y);
+        else
+            hipLaunchKernelGGL((k_batch_spmv<double, false>), dim3(grid), dim3(kBT), 0, s, graphs, ngraphs, voff,
+                               rowptr, col, w32, w64, (const double *)x, (double *)y);
+    }
+    LAP_HIP(hipGetLastError());
+}
 
 void batch_launch(const BatchArgs &a, bool mixed, bool weighted, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a.queue);

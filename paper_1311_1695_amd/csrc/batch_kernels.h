@@ -41,5 +41,10 @@ struct BatchArgs {
 };
 
 void batch_launch(const BatchArgs &a, bool mixed, bool weighted, int grid, hipStream_t s);
+// y = G x on every graph with the solver's row engine (x, y: FP32 when mixed,
+// else FP64; graph g's entries at voff[g]); w32 non-null for weighted batches
+void batch_spmv_launch(const BGraph *graphs, int ngraphs, const long long *voff, const int *rowptr, const int *col,
+                       const float *w32, const double *w64, bool mixed, const void *x, void *y, int grid,
+                       hipStream_t s);
 
 }  // namespace lapeig

@@ -509,6 +509,30 @@ void lap_batch_destroy(lap_batch *b) { lapeig::batch_destroy(b); }
 
 int32_t lap_batch_total_n(const lap_batch *b) { return lapeig::batch_total_n(b); }
 
+lap_status lap_batch_autotune(lap_batch *b, int precision, int32_t *long_threshold, double *seconds) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(b != nullptr, LAP_EINVAL, "batch is NULL");
+    LAP_REQUIRE(precision == LAP_PREC_FP64 || precision == LAP_PREC_MIXED, LAP_EINVAL, "unknown precision");
+    double secs = 0.0;
+    const int thr = lapeig::batch_autotune(b, precision == LAP_PREC_MIXED, 5, &secs);
+    if (long_threshold) *long_threshold = thr;
+    if (seconds) *seconds = secs;
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
+lap_status lap_batch_layout(const lap_batch *b, int precision, int32_t *long_threshold, int32_t *tuned) {
+    LAP_GUARD_BEGIN
+    LAP_REQUIRE(b && long_threshold && tuned, LAP_EINVAL, "batch or output pointer is NULL");
+    LAP_REQUIRE(precision == LAP_PREC_FP64 || precision == LAP_PREC_MIXED, LAP_EINVAL, "unknown precision");
+    int thr = 0, tu = 0;
+    lapeig::batch_layout(b, precision == LAP_PREC_MIXED, &thr, &tu);
+    *long_threshold = thr;
+    *tuned = tu;
+    return LAP_OK;
+    LAP_GUARD_END
+}
+
 lap_status lap_batch_eigs(lap_batch *b, int k, double tol, const lap_eigs_opts *opts, double *evals, double *evecs,
                           double *res, lap_eigs_info *infos, void *stream) {
     LAP_GUARD_BEGIN

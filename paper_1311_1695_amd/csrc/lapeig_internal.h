@@ -313,6 +313,11 @@ lap_status pcg_entry(lap_plan *P, lap_dtype dt, int b, const double *theta_host,
 int device_cu_count();
 
 lap_status batch_create(const lap_csr *Ls, int nb, lap_batch **out);
+// time the row-class threshold candidates for the precision; keeps and
+// returns the fastest (seconds per product pass over the batch in *secs)
+int batch_autotune(lap_batch *B, bool mixed, int reps, double *secs);
+// the threshold in use for the precision and whether it was tuned
+void batch_layout(const lap_batch *B, bool mixed, int *long_threshold, int *tuned);
 void batch_destroy(lap_batch *B);
 int batch_total_n(const lap_batch *B);
 lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,

@@ -64,6 +64,15 @@ def test_valid_matrix_passes_validation_then_needs_a_device():
     assert err.code in (lap.LAP_EDEVICE, lap.LAP_ENOMEM)
 
 
+def test_batch_autotune_and_layout_argument_checks():
+    lib = lap.load_library()
+    thr, tuned, secs = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    assert lib.lap_batch_autotune(None, lap.LAP_PREC_MIXED, ctypes.byref(thr), ctypes.byref(secs)) == lap.LAP_EINVAL
+    assert lib.lap_batch_layout(None, lap.LAP_PREC_MIXED, ctypes.byref(thr), ctypes.byref(tuned)) == lap.LAP_EINVAL
+    with pytest.raises(lap.LapError):
+        lap._precision_code("bf16")
+
+
 def test_plan_order_argument_checked_before_hip():
     rp, cl, vl = _good()
 

@@ -718,6 +718,29 @@ def test_batch_weighted_and_reuse():
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_autotuned_row_classes(precision):
+    # the first solve in a precision times the row-class thresholds and keeps
+    # the fastest; every threshold gives the same certified answer
+    graphs = small_batch()
+    b = lap.lap_batch_create(graphs)
+    assert b.layout(precision) == (32, False)
+    out = lap.lap_batch_eigs(b, 5, 1e-8, precision=precision)
+    thr, tuned = b.layout(precision)
+    assert tuned and thr in (4, 8, 16, 32, 64, 128, 256, 1 << 30)
+    other = "fp64" if precision == "mixed" else "mixed"
+    assert b.layout(other) == (32, False)  # tuned per precision
+    thr2, secs = b.autotune(precision)
+    assert thr2 in (4, 8, 16, 32, 64, 128, 256, 1 << 30) and secs > 0
+    again = lap.lap_batch_eigs(b, 5, 1e-8, precision=precision)
+    for L, r, r2 in zip(graphs, out, again):
+        assert r.nconv == 5 and r2.nconv == 5
+        _certified(L, r, 1e-8)
+        _certified(L, r2, 1e-8)
+        assert np.allclose(r.evals, r2.evals, rtol=1e-8, atol=1e-12)
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_batch_direction_in_lds_and_in_memory(precision):
     # the PCG direction of a graph lives in the workgroup's LDS as far as it
     # fits (about 37k vertices in FP32, 18k in FP64 on a 160 KB part), the
