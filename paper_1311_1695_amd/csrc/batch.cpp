@@ -2,11 +2,37 @@
 // renumbering, packing (largest job first), one graph-captured persistent
 // launch, and unpacking into the caller's vertex order.
 #include <algorithm>
+#include <memory>
 #include <chrono>
 #include <cmath>
 #include <numeric>
 
 #include "batch_kernels.h"
+
+namespace lapeig {
+// Device buffers and the captured launch of the last solve, reused while the
+// key (k, options, precision, threshold) stays the same: a repeated solve is
+// one graph launch and the copies of its results.
+struct BatchWork {
+    int k = 0, m_min = 0, m_max = 0, itmax = 0, kmax = 0, precision = -1, thr = -1;
+    double tol = 0.0, rtol = 0.0;
+    uint64_t seed = 0;
+    std::vector<BGraph> gd;
+    long long ov = 0;
+    DevBuf<BGraph> dg;
+    DevBuf<int> dord;
+    DevBuf<unsigned> dq;
+    DevBuf<double> ws64, outv, outl, outr, unp;
+    DevBuf<double> ws32;  // PCG workspace, 8 bytes per element
+    DevBuf<BResult> dres;
+    hipStream_t s = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchWork() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+}  // namespace lapeig
 
 struct lap_batch {
     int nb = 0;
@@ -21,7 +47,10 @@ struct lap_batch {
     lapeig::DevBuf<int> rowptr, col;
     lapeig::DevBuf<float> w32;
     lapeig::DevBuf<double> w64;
+    lapeig::DevBuf<int> dperm;             // every graph's caller -> plan map, concatenated
+    lapeig::DevBuf<long long> dperm_off;   // where graph g's map starts
     long long total_n = 0, total_nnz = 0;
+    std::unique_ptr<lapeig::BatchWork> work;
 };
 
 namespace lapeig {
@@ -107,6 +136,18 @@ void pack(lap_batch *B, const lap_csr *Ls, int nb) {
         B->perm.push_back(std::move(perm));
         B->total_n += n;
         B->total_nnz += acc;
+    }
+    {
+        std::vector<int> pall;
+        std::vector<long long> poff;
+        for (int g = 0; g < nb; ++g) {
+            poff.push_back((long long)pall.size());
+            pall.insert(pall.end(), B->perm[g].begin(), B->perm[g].end());
+        }
+        B->dperm.alloc(pall.size());
+        B->dperm_off.alloc(poff.size());
+        LAP_HIP(hipMemcpy(B->dperm.get(), pall.data(), sizeof(int) * pall.size(), hipMemcpyHostToDevice));
+        LAP_HIP(hipMemcpy(B->dperm_off.get(), poff.data(), sizeof(long long) * poff.size(), hipMemcpyHostToDevice));
     }
     B->rowptr.alloc(rp_all.size());
     B->col.alloc(std::max<size_t>(ci_all.size(), 1));
@@ -247,128 +288,117 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
     if (!B->tuned[mixed ? 1 : 0]) batch_autotune(B, mixed, 5, nullptr);
     const int thr = B->long_threshold[mixed ? 1 : 0];
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
-    // descriptors and workspace offsets
-    std::vector<BGraph> gd(nb);
-    long long w64 = 0, w32 = 0, ov = 0;
-    for (int g = 0; g < nb; ++g) {
-        const long long n = B->n[g];
-        BGraph &d = gd[g];
-        d.n = (int)n;
-        d.nlong = nlong_of(B, g, thr);
-        d.k = k;
-        d.pad = 0;
-        d.rp = B->rp_off[g];
-        d.ci = B->ci_off[g];
-        d.w64 = w64;
-        d.w32 = w32;
-        d.out_vec = ov;
-        d.out_val = (long long)g * k;
-        w64 += n * (k + 2LL * o.m_max + 4);
-        w32 += n * (k + 5LL);
-        ov += n * k;
-    }
-    // largest job first
-    std::vector<int> order(nb);
-    std::iota(order.begin(), order.end(), 0);
-    {
-        std::vector<long long> nnz(nb);
-        for (int g = 0; g < nb; ++g) nnz[g] = (g + 1 < nb ? B->ci_off[g + 1] : B->total_nnz) - B->ci_off[g];
-        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nnz[a] > nnz[c]; });
-    }
-    DevBuf<BGraph> dg(nb);
-    DevBuf<int> dord(nb);
-    DevBuf<unsigned> dq(1);
-    DevBuf<double> ws64(w64), ws32(w32), outv(ov), outl((size_t)nb * k), outr((size_t)nb * k);
-    DevBuf<BResult> dres(nb);
-    hipStream_t s = nullptr;
+    if (!B->work) B->work.reset(new BatchWork());
+    BatchWork &W = *B->work;
+    const bool same = W.exec && W.k == k && W.m_min == o.m_min && W.m_max == o.m_max && W.itmax == o.itmax &&
+                      W.kmax == kmax && W.precision == o.precision && W.thr == thr && W.tol == tol &&
+                      W.rtol == o.rtol_pcg && W.seed == o.seed;
     LAP_HIP(hipStreamSynchronize(user));
-    LAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    struct SG {
-        hipStream_t s;
-        hipGraphExec_t e = nullptr;
-        ~SG() {
-            if (e) (void)hipGraphExecDestroy(e);
-            if (s) (void)hipStreamDestroy(s);
+    if (!W.s) LAP_HIP(hipStreamCreateWithFlags(&W.s, hipStreamNonBlocking));
+    hipStream_t s = W.s;
+    if (!same) {
+        if (W.exec) {
+            LAP_HIP(hipGraphExecDestroy(W.exec));
+            W.exec = nullptr;
         }
-    } guard{s};
-    LAP_HIP(hipMemcpyAsync(dg.get(), gd.data(), sizeof(BGraph) * nb, hipMemcpyHostToDevice, s));
-    LAP_HIP(hipMemcpyAsync(dord.get(), order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
-    LAP_HIP(hipMemsetAsync(outl.get(), 0, sizeof(double) * nb * k, s));
-    LAP_HIP(hipMemsetAsync(outr.get(), 0, sizeof(double) * nb * k, s));
-    BatchArgs a{};
-    a.ngraphs = nb;
-    a.graphs = dg.get();
-    a.order = dord.get();
-    a.queue = dq.get();
-    a.rowptr = B->rowptr.get();
-    a.col = B->col.get();
-    a.w32 = B->weighted ? B->w32.get() : nullptr;
-    a.w64 = B->weighted ? B->w64.get() : nullptr;
-    a.ws64 = ws64.get();
-    a.ws32 = ws32.get();
-    a.out_vec = outv.get();
-    a.out_val = outl.get();
-    a.out_res = outr.get();
-    a.results = dres.get();
-    a.m_min = o.m_min;
-    a.m_max = o.m_max;
-    a.itmax = o.itmax;
-    a.kmax = kmax;
-    a.tol = tol;
-    a.rtol_pcg = o.rtol_pcg;
-    a.seed = o.seed;
-    const int grid = std::min(nb, device_cu_count());
-    // one persistent launch, captured in a graph (queue reset + solver)
-    hipGraph_t graph = nullptr;
-    LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    try {
-        batch_launch(a, mixed, B->weighted, grid, s);
-    } catch (...) {
-        (void)hipStreamEndCapture(s, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        throw;
+        // descriptors and workspace offsets
+        W.gd.assign(nb, BGraph{});
+        long long w64 = 0, w32 = 0, ov = 0;
+        for (int g = 0; g < nb; ++g) {
+            const long long n = B->n[g];
+            BGraph &d = W.gd[g];
+            d.n = (int)n;
+            d.nlong = nlong_of(B, g, thr);
+            d.k = k;
+            d.pad = 0;
+            d.rp = B->rp_off[g];
+            d.ci = B->ci_off[g];
+            d.w64 = w64;
+            d.w32 = w32;
+            d.out_vec = ov;
+            d.out_val = (long long)g * k;
+            w64 += n * (k + 2LL * o.m_max + 4);
+            w32 += n * (k + 5LL);
+            ov += n * k;
+        }
+        W.ov = ov;
+        // largest job first
+        std::vector<int> order(nb);
+        std::iota(order.begin(), order.end(), 0);
+        {
+            std::vector<long long> nnz(nb);
+            for (int g = 0; g < nb; ++g) nnz[g] = (g + 1 < nb ? B->ci_off[g + 1] : B->total_nnz) - B->ci_off[g];
+            std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nnz[a] > nnz[c]; });
+        }
+        if (W.dg.n < (size_t)nb) { W.dg.alloc(nb); W.dord.alloc(nb); W.dres.alloc(nb); }
+        if (!W.dq.get()) W.dq.alloc(1);
+        if (W.ws64.n < (size_t)w64) W.ws64.alloc(w64);
+        if (W.ws32.n < (size_t)w32) W.ws32.alloc(w32);
+        if (W.outv.n < (size_t)ov) { W.outv.alloc(ov); W.unp.alloc(ov); }
+        if (W.outl.n < (size_t)nb * k) { W.outl.alloc((size_t)nb * k); W.outr.alloc((size_t)nb * k); }
+        LAP_HIP(hipMemcpyAsync(W.dg.get(), W.gd.data(), sizeof(BGraph) * nb, hipMemcpyHostToDevice, s));
+        LAP_HIP(hipMemcpyAsync(W.dord.get(), order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+        BatchArgs a{};
+        a.ngraphs = nb;
+        a.graphs = W.dg.get();
+        a.order = W.dord.get();
+        a.queue = W.dq.get();
+        a.rowptr = B->rowptr.get();
+        a.col = B->col.get();
+        a.w32 = B->weighted ? B->w32.get() : nullptr;
+        a.w64 = B->weighted ? B->w64.get() : nullptr;
+        a.ws64 = W.ws64.get();
+        a.ws32 = W.ws32.get();
+        a.out_vec = W.outv.get();
+        a.out_val = W.outl.get();
+        a.out_res = W.outr.get();
+        a.results = W.dres.get();
+        a.m_min = o.m_min;
+        a.m_max = o.m_max;
+        a.itmax = o.itmax;
+        a.kmax = kmax;
+        a.tol = tol;
+        a.rtol_pcg = o.rtol_pcg;
+        a.seed = o.seed;
+        const int grid = std::min(nb, device_cu_count());
+        // one graph: queue reset, the persistent solver, the eigenvectors
+        // into the caller's order
+        hipGraph_t graph = nullptr;
+        LAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            batch_launch(a, mixed, B->weighted, grid, s);
+            batch_unpack_launch(W.dg.get(), W.dres.get(), B->dperm.get(), B->dperm_off.get(), nb, W.outv.get(),
+                                W.unp.get(), s);
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        LAP_HIP(hipStreamEndCapture(s, &graph));
+        hipError_t err = hipGraphInstantiate(&W.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (err != hipSuccess) W.exec = nullptr;
+        LAP_HIP(err);
+        W.k = k; W.m_min = o.m_min; W.m_max = o.m_max; W.itmax = o.itmax; W.kmax = kmax;
+        W.precision = o.precision; W.thr = thr; W.tol = tol; W.rtol = o.rtol_pcg; W.seed = o.seed;
     }
-    LAP_HIP(hipStreamEndCapture(s, &graph));
-    hipError_t err = hipGraphInstantiate(&guard.e, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    LAP_HIP(err);
-    LAP_HIP(hipGraphLaunch(guard.e, s));
+    LAP_HIP(hipGraphLaunch(W.exec, s));
     // results
     std::vector<BResult> hres(nb);
-    std::vector<double> hv(ov), hl((size_t)nb * k), hr((size_t)nb * k);
-    LAP_HIP(hipMemcpyAsync(hres.data(), dres.get(), sizeof(BResult) * nb, hipMemcpyDeviceToHost, s));
-    LAP_HIP(hipMemcpyAsync(hl.data(), outl.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
-    LAP_HIP(hipMemcpyAsync(hr.data(), outr.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
-    if (evecs) LAP_HIP(hipMemcpyAsync(hv.data(), outv.get(), sizeof(double) * ov, hipMemcpyDeviceToHost, s));
+    std::vector<double> hl((size_t)nb * k), hr((size_t)nb * k);
+    LAP_HIP(hipMemcpyAsync(hres.data(), W.dres.get(), sizeof(BResult) * nb, hipMemcpyDeviceToHost, s));
+    LAP_HIP(hipMemcpyAsync(hl.data(), W.outl.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
+    LAP_HIP(hipMemcpyAsync(hr.data(), W.outr.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
+    if (evecs) LAP_HIP(hipMemcpyAsync(evecs, W.unp.get(), sizeof(double) * W.ov, hipMemcpyDeviceToHost, s));
     LAP_HIP(hipStreamSynchronize(s));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     lap_status status = LAP_OK;
     for (int g = 0; g < nb; ++g) {
-        const int n = B->n[g];
         const int nc = std::min(hres[g].nconv, k);
         if (nc < k) status = LAP_ENOCONV;
         for (int j = 0; j < k; ++j) {
             evals[(size_t)g * k + j] = j < nc ? hl[(size_t)g * k + j] : NAN;
             if (res) res[(size_t)g * k + j] = j < nc ? hr[(size_t)g * k + j] : NAN;
-        }
-        if (evecs) {
-            const double *src = hv.data() + gd[g].out_vec;
-            double *dst = evecs + gd[g].out_vec;
-            const std::vector<int> &pm = B->perm[g];
-            for (int j = 0; j < k; ++j) {
-                double *y = dst + (size_t)j * n;
-                if (j >= nc) {
-                    for (int i = 0; i < n; ++i) y[i] = 0.0;
-                    continue;
-                }
-                const double *x = src + (size_t)j * n;
-                for (int i = 0; i < n; ++i) y[i] = x[pm[i]];
-                int best = 0;
-                for (int i = 1; i < n; ++i)
-                    if (std::fabs(y[i]) > std::fabs(y[best])) best = i;
-                if (y[best] < 0.0)
-                    for (int i = 0; i < n; ++i) y[i] = -y[i];
-            }
         }
         if (infos) {
             infos[g].nconv = nc;

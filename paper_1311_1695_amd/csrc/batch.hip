@@ -732,6 +732,59 @@ __global__ void k_batch_reset(unsigned *queue) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
 }
 
+// Eigenvector blocks into the caller's vertex order (dst[i] = src[perm[i]])
+// with the sign convention of the single-graph solver: the entry of largest
+// magnitude is positive, the first such entry in caller order deciding;
+// columns past a graph's nconv are zero.  One workgroup per graph.
+__global__ __launch_bounds__(kBT) void k_batch_unpack(const BGraph *__restrict__ graphs,
+                                                      const BResult *__restrict__ results,
+                                                      const int *__restrict__ perm_all,
+                                                      const long long *__restrict__ perm_off, int ngraphs,
+                                                      const double *__restrict__ src, double *__restrict__ dst) {
+    __shared__ double wbest[kBW];
+    __shared__ int widx[kBW];
+    __shared__ double sgn;
+    const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+    for (int gi = blockIdx.x; gi < ngraphs; gi += gridDim.x) {
+        const BGraph G = graphs[gi];
+        const int n = G.n, k = G.k;
+        const int nc = min(results[gi].nconv, k);
+        const int *pm = perm_all + perm_off[gi];
+        for (int j = 0; j < k; ++j) {
+            const double *x = src + G.out_vec + (long long)j * n;
+            double *y = dst + G.out_vec + (long long)j * n;
+            if (j >= nc) {
+                for (int i = tid; i < n; i += kBT) y[i] = 0.0;
+                continue;
+            }
+            double best = -1.0;
+            int bi = n;
+            for (int i = tid; i < n; i += kBT) {
+                const double v = fabs(x[pm[i]]);
+                if (v > best) { best = v; bi = i; }  // i grows: the first maximum of this thread
+            }
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o, kWave);
+                const int oi = __shfl_xor(bi, o, kWave);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (lane == 0) { wbest[wv] = best; widx[wv] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                double b = wbest[0];
+                int i0 = widx[0];
+                for (int w = 1; w < kBW; ++w)
+                    if (wbest[w] > b || (wbest[w] == b && widx[w] < i0)) { b = wbest[w]; i0 = widx[w]; }
+                sgn = (i0 < n && x[pm[i0]] < 0.0) ? -1.0 : 1.0;
+            }
+            __syncthreads();
+            const double sg = sgn;
+            for (int i = tid; i < n; i += kBT) y[i] = sg * x[pm[i]];
+            __syncthreads();
+        }
+    }
+}
+
 // The solver's product on every graph of the batch (y = G x, graph g's
 // vectors at voff[g]), one workgroup per graph as in the solver, for timing
 // the row-class threshold candidates.
@@ -800,6 +853,13 @@ void batch_spmv_launch(const BGraph *graphs, int ngraphs, const long long *voff,
             hipLaunchKernelGGL((k_batch_spmv<double, false>), dim3(grid), dim3(kBT), 0, s, graphs, ngraphs, voff,
                                rowptr, col, w32, w64, (const double *)x, (double *)y);
     }
+    LAP_HIP(hipGetLastError());
+}
+
+void batch_unpack_launch(const BGraph *graphs, const BResult *results, const int *perm_all, const long long *perm_off,
+                         int ngraphs, const double *src, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_unpack, dim3(std::min(ngraphs, 4 * device_cu_count())), dim3(kBT), 0, s, graphs,
+                       results, perm_all, perm_off, ngraphs, src, dst);
     LAP_HIP(hipGetLastError());
 }
 

@@ -41,6 +41,10 @@ struct BatchArgs {
 };
 
 void batch_launch(const BatchArgs &a, bool mixed, bool weighted, int grid, hipStream_t s);
+// eigenvector blocks (src, plan order) into the caller's order with the sign
+// convention; perm_all + perm_off[g]: graph g's caller -> plan map
+void batch_unpack_launch(const BGraph *graphs, const BResult *results, const int *perm_all, const long long *perm_off,
+                         int ngraphs, const double *src, double *dst, hipStream_t s);
 // y = G x on every graph with the solver's row engine (x, y: FP32 when mixed,
 // else FP64; graph g's entries at voff[g]); w32 non-null for weighted batches
 void batch_spmv_launch(const BGraph *graphs, int ngraphs, const long long *voff, const int *rowptr, const int *col,
