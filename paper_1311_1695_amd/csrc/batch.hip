@@ -38,6 +38,8 @@ struct Shared {
     double coef[kBM + kBK + 2];
     double cs[kBM / 2], sn[kBM / 2];
     int pp[kBM / 2], qq[kBM / 2];
+    double lam[kBK], rlock[kBK];  // locked pairs: Ritz value, certified residual
+    int order[kBK];               // locked pairs by ascending value
     int any_rot;
     int job;
 };
@@ -254,6 +256,25 @@ __device__ void wg_eig(int m, Shared &sh) {
     __syncthreads();
 }
 
+// B(:, c) = sum_j B(:, j) Yc(j, c) for c < nc (B n x m column-major, ld n;
+// Yc columns kBM apart): each thread rotates its rows in place, holding one
+// row of B in registers, the columns summed in index order.
+__device__ __forceinline__ void rotate_rows(int n, int m, double *B, const double *Yc, int nc) {
+    for (int i = threadIdx.x; i < n; i += kBT) {
+        double br[kBM];
+#pragma unroll
+        for (int j = 0; j < kBM; ++j)
+            if (j < m) br[j] = B[(size_t)j * n + i];
+        for (int c = 0; c < nc; ++c) {
+            double sv = 0.0;
+#pragma unroll
+            for (int j = 0; j < kBM; ++j)
+                if (j < m) sv += br[j] * Yc[c * kBM + j];
+            B[(size_t)c * n + i] = sv;
+        }
+    }
+}
+
 __device__ __forceinline__ double splitmix_b(unsigned long long seed, unsigned long long idx) {
     unsigned long long z = seed + (idx + 1ULL) * 0x9e3779b97f4a7c15ULL;
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -282,7 +303,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
     T *res = t + n, *p = res + n, *s = p + n, *y = s + n;
     // the PCG direction, which every product gathers from, in LDS as far as it fits
     const SplitVec<T> pv{lds, p, n < a.lds_elems ? n : a.lds_elems};
-    double lam[kBK], rlock[kBK];
+    double *lam = sh.lam, *rlock = sh.rlock;
     // zero pair: e / sqrt(n) (connected graph)
     const double e0 = 1.0 / sqrt((double)n);
     for (int i = tid; i < n; i += kBT) {
@@ -290,8 +311,10 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
         Q[(size_t)i * k] = (T)e0;
         v[i] = splitmix_b(a.seed, ((unsigned long long)gid << 32) + (unsigned long long)i);
     }
-    lam[0] = 0.0;
-    rlock[0] = 0.0;
+    if (tid == 0) {
+        lam[0] = 0.0;
+        rlock[0] = 0.0;
+    }
     int nx = 1, m = 0, it = 0;
     long long mvp = 0, inner = 0;
     bool from_t = false;
@@ -443,27 +466,17 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             if (!(cr <= a.tol * fmin(ct, 1.0))) break;
             // lock: X(:, nx) = u / ||u||; V <- V Y(:, 2..m), W <- W Y(:, 2..m)
             const double us = 1.0 / sqrt(un2);
-            for (int i = tid; i < n; i += kBT) {
-                double vr[kBM], wr[kBM];
-#pragma unroll
-                for (int j = 0; j < kBM; ++j)
-                    if (j < m) { vr[j] = V[(size_t)j * n + i]; wr[j] = W[(size_t)j * n + i]; }
-                X[(size_t)nx * n + i] = u[i] * us;
-                for (int c = 1; c < m; ++c) {
-                    double sv = 0.0, sw = 0.0;
-#pragma unroll
-                    for (int j = 0; j < kBM; ++j)
-                        if (j < m) { sv += vr[j] * sh.Y[c * kBM + j]; sw += wr[j] * sh.Y[c * kBM + j]; }
-                    V[(size_t)(c - 1) * n + i] = sv;
-                    W[(size_t)(c - 1) * n + i] = sw;
-                }
-            }
+            for (int i = tid; i < n; i += kBT) X[(size_t)nx * n + i] = u[i] * us;
+            rotate_rows(n, m, V, sh.Y + kBM, m - 1);
+            rotate_rows(n, m, W, sh.Y + kBM, m - 1);
             if (tid < kBM * kBM) {
                 const int i = tid / kBM, j = tid % kBM;
                 sh.H[tid] = (i == j && i < m - 1) ? sh.theta[i + 1] : 0.0;
             }
-            lam[nx] = ct;
-            rlock[nx] = cr;
+            if (tid == 0) {
+                lam[nx] = ct;
+                rlock[nx] = cr;
+            }
             ++nx;
             --m;
             __syncthreads();
@@ -481,20 +494,8 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
         if (!need_pcg) continue;
         // restart: keep the m_min Ritz vectors of smallest Ritz value
         if (m >= mmax) {
-            for (int i = tid; i < n; i += kBT) {
-                double vr[kBM], wr[kBM];
-#pragma unroll
-                for (int j = 0; j < kBM; ++j)
-                    if (j < m) { vr[j] = V[(size_t)j * n + i]; wr[j] = W[(size_t)j * n + i]; }
-                for (int c = 0; c < mmin; ++c) {
-                    double sv = 0.0, sw = 0.0;
-#pragma unroll
-                    for (int j = 0; j < kBM; ++j)
-                        if (j < m) { sv += vr[j] * sh.Y[c * kBM + j]; sw += wr[j] * sh.Y[c * kBM + j]; }
-                    V[(size_t)c * n + i] = sv;
-                    W[(size_t)c * n + i] = sw;
-                }
-            }
+            rotate_rows(n, m, V, sh.Y, mmin);
+            rotate_rows(n, m, W, sh.Y, mmin);
             if (tid < kBM * kBM) {
                 const int i = tid / kBM, j = tid % kBM;
                 sh.H[tid] = (i == j && i < mmin) ? sh.theta[i] : 0.0;
@@ -686,14 +687,18 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             __syncthreads();
         }
     }
-    // results: sort the locked pairs (insertion sort, done by every thread alike)
-    int order[kBK];
-    for (int j = 0; j < nx; ++j) order[j] = j;
-    for (int j = 1; j < nx; ++j) {
-        int x = order[j], i = j - 1;
-        while (i >= 0 && lam[order[i]] > lam[x]) { order[i + 1] = order[i]; --i; }
-        order[i + 1] = x;
+    // results: sort the locked pairs (insertion sort, one thread, in LDS)
+    int *order = sh.order;
+    __syncthreads();
+    if (tid == 0) {
+        for (int j = 0; j < nx; ++j) order[j] = j;
+        for (int j = 1; j < nx; ++j) {
+            int x = order[j], i = j - 1;
+            while (i >= 0 && lam[order[i]] > lam[x]) { order[i + 1] = order[i]; --i; }
+            order[i + 1] = x;
+        }
     }
+    __syncthreads();
     double *ov = a.out_vec + G.out_vec;
     for (int j = 0; j < nx; ++j)
         for (int i = tid; i < n; i += kBT) ov[(size_t)j * n + i] = X[(size_t)order[j] * n + i];
