@@ -167,7 +167,16 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
     // work on a stream of our own (capturable even when the caller uses the
     // default stream), ordered after the caller's pending work
     LAP_HIP(hipStreamSynchronize(P->stream));
-    const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
+    // the pcg_breakdown hook solves every correction equation with a shift
+    // above the spectrum (launched directly: the captured graphs hold theta)
+    const bool brk_fault = fault_enabled("pcg_breakdown");
+    DevBuf<double> theta_fault;
+    if (brk_fault) {
+        const double v = fault_breakdown_shift(*P);
+        theta_fault.alloc(1);
+        LAP_HIP(hipMemcpy(theta_fault.get(), &v, sizeof(double), hipMemcpyHostToDevice));
+    }
+    const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr && !brk_fault;
     const int mmax = o.m_max, mmin = o.m_min;
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
     LAP_REQUIRE(k + mmax <= kMaxBasis, LAP_EUNSUPPORTED,
@@ -227,6 +236,10 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
         DevBuf<double> tmp((size_t)n * o.init_cols);
         LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * o.init_cols,
                                 o.init_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        if (fault_enabled("nan_init")) {
+            static const double qnan = NAN;
+            LAP_HIP(hipMemcpyAsync(tmp.get(), &qnan, sizeof(double), hipMemcpyHostToDevice, s));
+        }
         for (int c = 0; c < o.init_cols; ++c)
             permute_rows<double>(P->d_perm.get(), n, 1, tmp.get() + (size_t)c * n, init_dev.get() + (size_t)c * n, s);
         LAP_HIP(hipStreamSynchronize(s));
@@ -339,8 +352,8 @@ lap_status jd_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double
             const bool inc = q == pcg_q;
             pcg_q = q;
             auto enqueue = [&]() {
-                pcg_enqueue<T>(*P, theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw, o.itmax, o.rtol_pcg, s, inc,
-                               fsai);
+                pcg_enqueue<T>(*P, brk_fault ? theta_fault.get() : theta.get(), Q.get(), ldq, q, r.get(), t.get(), pw,
+                               o.itmax, o.rtol_pcg, s, inc, fsai);
             };
             if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(2 * q + (inc ? 1 : 0), s, enqueue), s));
             else enqueue();

@@ -117,7 +117,15 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
     LAP_REQUIRE(k + mmax <= 128, LAP_EUNSUPPORTED, "k + m_max above 128");
     const int kmax = o.kmax > 0 ? o.kmax : 1000 * k;
     LAP_HIP(hipStreamSynchronize(P->stream));
-    const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr;
+    // the pcg_breakdown hook (see fault_enabled): shifts above the spectrum
+    const bool brk_fault = fault_enabled("pcg_breakdown");
+    DevBuf<double> theta_fault;
+    if (brk_fault) {
+        const std::vector<double> v(kMaxBlock, fault_breakdown_shift(*P));
+        theta_fault.alloc(kMaxBlock);
+        LAP_HIP(hipMemcpy(theta_fault.get(), v.data(), sizeof(double) * kMaxBlock, hipMemcpyHostToDevice));
+    }
+    const bool use_graph = std::getenv("LAPEIG_NO_GRAPH") == nullptr && !brk_fault;
     ts_prepare<double>();
     ts_prepare<T>();
     auto *cache = dynamic_cast<JdbWork<T> *>(P->jdb_cache.get());
@@ -176,6 +184,10 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         DevBuf<int> bad(c0);
         LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * c0,
                                 o.init_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        if (fault_enabled("nan_init")) {
+            static const double qnan = NAN;
+            LAP_HIP(hipMemcpyAsync(tmp.get(), &qnan, sizeof(double), hipMemcpyHostToDevice, s));
+        }
         LAP_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int) * c0, s));
         blk_nonfinite_cols(n, c0, tmp.get(), bad.get(), s);
         std::vector<int> hbad(c0);
@@ -313,7 +325,8 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         {
             const int q = nx + bu;
             auto enqueue = [&]() {
-                bpcg_enqueue<T>(*P, bu, theta.get(), Q.get(), ldq, q, R.get(), b, Tt.get(), pw, bs, o.itmax,
+                bpcg_enqueue<T>(*P, bu, brk_fault ? theta_fault.get() : theta.get(), Q.get(), ldq, q, R.get(), b,
+                                Tt.get(), pw, bs, o.itmax,
                                 o.rtol_pcg, s);
             };
             if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, bu, s, enqueue), s));

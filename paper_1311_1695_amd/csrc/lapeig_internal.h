@@ -271,6 +271,20 @@ template <typename T>
 void spmm_part(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, T *part,
                hipStream_t s);
 
+// Failure-path test hooks, read from the environment variable LAPEIG_FAULT
+// (comma-separated names) at each solve:
+//   nan_init       the first entry of the caller's start block becomes NaN
+//                  once it is on the device, so the solver's own check drops
+//                  the column and the seeded start takes its place;
+//   pcg_breakdown  every correction equation is solved with the shift moved
+//                  above the spectrum (4 max_i d_i + 1), so the projected
+//                  operator is negative definite and the PCG stops at its
+//                  first iteration on p'(G - theta I)p <= 0 and returns M(-r).
+// Both force the condition from the host; every kernel runs as usual.
+bool fault_enabled(const char *name);
+// the shift of the pcg_breakdown hook for the plan's graph
+double fault_breakdown_shift(const lap_plan &P);
+
 // Reduction scratch: per-block partial sums and a completion counter.
 struct ReduceScratch {
     DevBuf<double> partial;      // >= max_blocks * max_values doubles

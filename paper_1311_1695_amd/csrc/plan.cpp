@@ -1,6 +1,7 @@
 // Plan creation: host-side validation of the Laplacian, degree renumbering,
 // row classification, sliced layout, connected components, and upload.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <numeric>
 
@@ -295,6 +296,29 @@ void build_layout(lap_plan *P, int long_threshold, int huge_threshold) {
     P->g.chunk_off = P->d_chunk_off.get();
     // partial sums of chunked rows for block products of up to 64 double columns
     P->chunk_part.alloc(std::max<size_t>(crow.size(), 1) * 64 * sizeof(double));
+}
+
+bool fault_enabled(const char *name) {
+    const char *v = std::getenv("LAPEIG_FAULT");
+    if (!v) return false;
+    const std::string all(v), want(name);
+    size_t pos = 0;
+    while (pos <= all.size()) {
+        const size_t end = std::min(all.find(',', pos), all.size());
+        if (all.compare(pos, end - pos, want) == 0) return true;
+        pos = end + 1;
+    }
+    return false;
+}
+
+double fault_breakdown_shift(const lap_plan &P) {
+    double dmax = 0.0;
+    for (int i = 0; i < P.n; ++i) {
+        double d = 0.0;
+        for (int e = P.h_rowptr[i]; e < P.h_rowptr[i + 1]; ++e) d += P.h_w.empty() ? 1.0 : P.h_w[e];
+        dmax = std::max(dmax, d);
+    }
+    return 4.0 * dmax + 1.0;  // above 2 max_i d_i >= lambda_max (Gershgorin)
 }
 
 int device_cu_count() {
