@@ -541,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__rest
     for (; t < tot; t += stride) P[t] = Z[t] + beta * P[t];
 }
 
-// ------------------------------------------- fused block PCG (b, q <= 16)
+// ------------------------------------------- fused block PCG (b, q <= 32)
 // Same iteration, same per-column state and stop rules, with the residual
 // carried as R~: the step subtracts alpha S (not alpha (I-QQ')S) and the
 // projection is taken once per iteration afterwards.  With W = Q'D^{-1}Q
@@ -555,105 +555,148 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_p(int n, int b, const T *__rest
 //       P = (D^{-1}Res - Q C2) + beta P = (I-QQ')D^{-1}Res + beta P;  R~ = Res
 // R~ starts each iteration orthogonal to Q, so C1 holds one step's drift
 // (alpha Q'S, small beside Res while Q holds Ritz vectors) and the two
-// expansions lose nothing to cancellation.  The per-workgroup partials of
-// KT form a (2*16 + 2) x 16 matrix (rows: G1, G2, R~'R~, R~'D^{-1}R~),
-// added by k_ts_reduce in a fixed order into kFusedLd-row totals.
-constexpr int kFusedLd = 34;
+// expansions lose nothing to cancellation.  Q has up to TI x 16 columns, the
+// block up to TJ x 16.  The per-workgroup partials of KT form a
+// (2 PI + 2) x PJ matrix (rows: G1, G2, R~'R~, R~'D^{-1}R~; PI = 16 TI,
+// PJ = 16 TJ), added by k_ts_reduce in a fixed order into totals with
+// 2 PI + 2 rows.
+template <int TI>
+constexpr int fused_ld() { return 2 * 16 * TI + 2; }
 
 // KT (WM = false) and, with WM, the same pass over [Q | D^{-1}Q] that gives
-// W in rows 16..31 of the totals.
-template <typename T, bool WM>
+// W in rows PI .. 2 PI - 1 of the totals (TJ = TI then).
+template <typename T, bool WM, int TI, int TJ>
 __global__ __launch_bounds__(kBlock) void k_bpcg_kt(int n, int b, int q, T *__restrict__ X, T *__restrict__ R,
                                                     const T *__restrict__ P, const T *__restrict__ S,
                                                     const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
                                                     T *__restrict__ part, BPcgState<T> *st, int it) {
     using V4 = typename Mfma<T>::v4;
-    constexpr int PS = kFusedLd * 16;
+    constexpr int PI = 16 * TI, PJ = 16 * TJ;
+    constexpr int PS = (2 * PI + 2) * PJ;
     __shared__ T red[PS];
     const int lane = lane_id(), wave = wave_id();
     const int mi = lane & 15, kk = lane >> 4;
-    T alpha = T(0);
-    bool step = false, brk1 = false;
+    T alpha[TJ];
+    bool step[TJ], brk1[TJ];
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) { alpha[tj] = T(0); step[tj] = false; brk1[tj] = false; }
     if (!WM) {
         if (!any_active(st, 0, b)) {
             if (blockIdx.x == 0 && (int)threadIdx.x < b) st->act[1][threadIdx.x] = 0;
             return;
         }
-        if (mi < b) {
-            const int act = st->act[0][mi];
-            const T pap = st->tot_a[mi];
-            const bool brk = act && !(pap > T(0));  // the projected operator is indefinite along p
-            step = act && !brk;
-            brk1 = brk && it == 1;
-            alpha = step ? st->rho[(it + 1) & 1][mi] / pap : T(0);
-            if (blockIdx.x == 0 && (int)threadIdx.x < b) {  // wavefront 0, kk = 0: thread c owns column c
-                st->act[1][mi] = step;
-                if (brk) st->brk[mi] = it;
-                if (step) st->its[mi] = it;
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+            const int c = tj * 16 + mi;
+            if (c < b) {
+                const int act = st->act[0][c];
+                const T pap = st->tot_a[c];
+                const bool brk = act && !(pap > T(0));  // the projected operator is indefinite along p
+                step[tj] = act && !brk;
+                brk1[tj] = brk && it == 1;
+                alpha[tj] = step[tj] ? st->rho[(it + 1) & 1][c] / pap : T(0);
+                // wavefront 0, kk = 0: lane mi (with tj) owns column c
+                if (blockIdx.x == 0 && wave == 0 && kk == 0) {
+                    st->act[1][c] = step[tj];
+                    if (brk) st->brk[c] = it;
+                    if (step[tj]) st->its[c] = it;
+                }
             }
         }
     }
-    V4 acc1 = V4{T(0), T(0), T(0), T(0)}, acc2 = acc1;
-    T s1 = T(0), s2 = T(0);
-    constexpr int U = 4;  // 4-row chunks per pass, all loads issued first
+    V4 acc1[TI][TJ], acc2[TI][TJ];
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) acc1[ti][tj] = acc2[ti][tj] = V4{T(0), T(0), T(0), T(0)};
+    T s1[TJ], s2[TJ];
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) s1[tj] = s2[tj] = T(0);
+    constexpr int U = TI * TJ == 1 ? 4 : 2;  // 4-row chunks per pass, all loads issued first
     const int stride = gridDim.x * kWavesPerBlock * 4;
     for (int k0 = (blockIdx.x * kWavesPerBlock + wave) * 4; k0 < n; k0 += U * stride) {
-        T a[U], v[U], d[U], x[U], p[U], sv[U];
+        T a[U][TI], v[U][TJ], d[U], x[U][TJ], p[U][TJ], sv[U][TJ];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int row = k0 + u * stride + kk;
             const bool ok = row < n;
-            a[u] = (ok && mi < q) ? Q[(size_t)row * ldq + mi] : T(0);
+#pragma unroll
+            for (int ti = 0; ti < TI; ++ti) {
+                const int col = ti * 16 + mi;
+                a[u][ti] = (ok && col < q) ? Q[(size_t)row * ldq + col] : T(0);
+            }
             d[u] = ok ? dinv[row] : T(0);
-            if (WM) {
-                v[u] = a[u];
-            } else {
-                const bool in = ok && mi < b;
-                const size_t e = (size_t)row * b + mi;
-                v[u] = in ? R[e] : T(0);
-                x[u] = (in && step) ? X[e] : T(0);
-                p[u] = (in && (step || brk1)) ? P[e] : T(0);
-                sv[u] = (in && step) ? S[e] : T(0);
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj) {
+                const int c = tj * 16 + mi;
+                if (WM) {
+                    v[u][tj] = (ok && c < q) ? Q[(size_t)row * ldq + c] : T(0);
+                } else {
+                    const bool in = ok && c < b;
+                    const size_t e = (size_t)row * b + c;
+                    v[u][tj] = in ? R[e] : T(0);
+                    x[u][tj] = (in && step[tj]) ? X[e] : T(0);
+                    p[u][tj] = (in && (step[tj] || brk1[tj])) ? P[e] : T(0);
+                    sv[u][tj] = (in && step[tj]) ? S[e] : T(0);
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!WM) {
-                const int row = k0 + u * stride + kk;
-                if (row < n && mi < b) {
-                    const size_t e = (size_t)row * b + mi;
-                    if (step) {
-                        X[e] = x[u] + alpha * p[u];
-                        v[u] = v[u] - alpha * sv[u];
-                        R[e] = v[u];
-                    } else if (brk1) {
-                        X[e] = p[u];  // no step was taken before the breakdown: M(-r)
+            const int row = k0 + u * stride + kk;
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj) {
+                if (!WM) {
+                    const int c = tj * 16 + mi;
+                    if (row < n && c < b) {
+                        const size_t e = (size_t)row * b + c;
+                        if (step[tj]) {
+                            X[e] = x[u][tj] + alpha[tj] * p[u][tj];
+                            v[u][tj] = v[u][tj] - alpha[tj] * sv[u][tj];
+                            R[e] = v[u][tj];
+                        } else if (brk1[tj]) {
+                            X[e] = p[u][tj];  // no step was taken before the breakdown: M(-r)
+                        }
                     }
                 }
+                const T dv = d[u] * v[u][tj];
+#pragma unroll
+                for (int ti = 0; ti < TI; ++ti) {
+                    acc1[ti][tj] = Mfma<T>::mac(a[u][ti], v[u][tj], acc1[ti][tj]);
+                    acc2[ti][tj] = Mfma<T>::mac(a[u][ti], dv, acc2[ti][tj]);
+                }
+                s1[tj] += v[u][tj] * v[u][tj];
+                s2[tj] += v[u][tj] * dv;
             }
-            const T dv = d[u] * v[u];
-            acc1 = Mfma<T>::mac(a[u], v[u], acc1);
-            acc2 = Mfma<T>::mac(a[u], dv, acc2);
-            s1 += v[u] * v[u];
-            s2 += v[u] * dv;
         }
     }
-    s1 += __shfl_xor(s1, 16, kWave);
-    s1 += __shfl_xor(s1, 32, kWave);
-    s2 += __shfl_xor(s2, 16, kWave);
-    s2 += __shfl_xor(s2, 32, kWave);
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) {
+        s1[tj] += __shfl_xor(s1[tj], 16, kWave);
+        s1[tj] += __shfl_xor(s1[tj], 32, kWave);
+        s2[tj] += __shfl_xor(s2[tj], 16, kWave);
+        s2[tj] += __shfl_xor(s2[tj], 32, kWave);
+    }
     // the four wavefronts in a fixed order
     for (int w = 0; w < kWavesPerBlock; ++w) {
         if (wave == w) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = Mfma<T>::row(lane, r), j = lane & 15;
-                red[i * 16 + j] = (w == 0 ? T(0) : red[i * 16 + j]) + acc1[r];
-                red[(16 + i) * 16 + j] = (w == 0 ? T(0) : red[(16 + i) * 16 + j]) + acc2[r];
-            }
+            for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = ti * 16 + Mfma<T>::row(lane, r), j = tj * 16 + (lane & 15);
+                        red[i * PJ + j] = (w == 0 ? T(0) : red[i * PJ + j]) + acc1[ti][tj][r];
+                        red[(PI + i) * PJ + j] = (w == 0 ? T(0) : red[(PI + i) * PJ + j]) + acc2[ti][tj][r];
+                    }
             if (kk == 0) {
-                red[32 * 16 + mi] = (w == 0 ? T(0) : red[32 * 16 + mi]) + s1;
-                red[33 * 16 + mi] = (w == 0 ? T(0) : red[33 * 16 + mi]) + s2;
+#pragma unroll
+                for (int tj = 0; tj < TJ; ++tj) {
+                    const int j = tj * 16 + mi;
+                    red[2 * PI * PJ + j] = (w == 0 ? T(0) : red[2 * PI * PJ + j]) + s1[tj];
+                    red[(2 * PI + 1) * PJ + j] = (w == 0 ? T(0) : red[(2 * PI + 1) * PJ + j]) + s2[tj];
+                }
             }
         }
         __syncthreads();
@@ -662,44 +705,48 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_kt(int n, int b, int q, T *__re
     for (int t = threadIdx.x; t < PS; t += blockDim.x) out[t] = red[t];
 }
 
-// KN.  tot: totals of KT (element (i, j) at i + j kFusedLd); totw: those of
+// KN.  tot: totals of KT (element (i, j) at i + j (2 PI + 2)); totw: those of
 // the W pass.  Reads flags of slot 1, writes slot 0.
-template <typename T>
+template <typename T, int TI, int TJ>
 __global__ __launch_bounds__(kBlock) void k_bpcg_kn(int n, int b, int q, T *__restrict__ R, T *__restrict__ P,
                                                     const T *__restrict__ dinv, const T *__restrict__ Q, int ldq,
                                                     const T *__restrict__ tot, const T *__restrict__ totw,
                                                     BPcgState<T> *st, int it, T rtol) {
     using V4 = typename Mfma<T>::v4;
-    constexpr int LD = kFusedLd;
-    __shared__ T c1s[16 * 16], c2s[16 * 16];  // [k][j]: Q column k, block column j
-    __shared__ T betas[16];
-    __shared__ int gos[16];
+    constexpr int PI = 16 * TI, PJ = 16 * TJ;
+    constexpr int LD = 2 * PI + 2;
+    __shared__ T c1s[PI * PJ], c2s[PI * PJ];  // [k][j]: Q column k, block column j
+    __shared__ T betas[PJ];
+    __shared__ int gos[PJ];
     if (!any_active(st, 1, b)) {
         if (blockIdx.x == 0 && (int)threadIdx.x < b) st->act[0][threadIdx.x] = 0;
         return;
     }
-    const int t = threadIdx.x;
-    const int kq = t >> 4, jc = t & 15;
-    const bool kin = kq < q && jc < b;
-    c1s[t] = kin ? tot[kq + jc * LD] : T(0);
-    __syncthreads();
-    T c2 = T(0);
-    if (kin) {
-        c2 = tot[16 + kq + jc * LD];
-        for (int m = 0; m < q; ++m) c2 -= totw[16 + kq + m * LD] * c1s[m * 16 + jc];
+    for (int t = threadIdx.x; t < PI * PJ; t += blockDim.x) {
+        const int kq = t / PJ, jc = t % PJ;
+        c1s[t] = (kq < q && jc < b) ? tot[kq + jc * LD] : T(0);
     }
-    c2s[t] = c2;
     __syncthreads();
-    if (t < 16) {
+    for (int t = threadIdx.x; t < PI * PJ; t += blockDim.x) {
+        const int kq = t / PJ, jc = t % PJ;
+        T c2 = T(0);
+        if (kq < q && jc < b) {
+            c2 = tot[PI + kq + jc * LD];
+            for (int m = 0; m < q; ++m) c2 -= totw[PI + kq + m * LD] * c1s[m * PJ + jc];
+        }
+        c2s[t] = c2;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < PJ) {
+        const int c = threadIdx.x;
         bool go = false;
         T beta = T(0);
-        if (t < b) {
-            const int c = t;
-            T rr = tot[32 + c * LD], rho_new = tot[33 + c * LD];
+        if (c < b) {
+            T rr = tot[2 * PI + c * LD], rho_new = tot[2 * PI + 1 + c * LD];
             for (int k = 0; k < q; ++k) {
-                const T g1 = c1s[k * 16 + c];
+                const T g1 = c1s[k * PJ + c];
                 rr -= g1 * g1;
-                rho_new -= g1 * (tot[16 + k + c * LD] + c2s[k * 16 + c]);
+                rho_new -= g1 * (tot[PI + k + c * LD] + c2s[k * PJ + c]);
             }
             const T rn = sqrt(rr > T(0) ? rr : T(0));
             go = st->act[1][c] && !(rn <= rtol * st->r0[c]);
@@ -709,8 +756,8 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_kn(int n, int b, int q, T *__re
                 if (go) st->rho[it & 1][c] = rho_new;
             }
         }
-        gos[t] = go;
-        betas[t] = beta;
+        gos[c] = go;
+        betas[c] = beta;
     }
     __syncthreads();
     const int lane = lane_id();
@@ -720,24 +767,31 @@ __global__ __launch_bounds__(kBlock) void k_bpcg_kn(int n, int b, int q, T *__re
         const int r0 = rb * 16;
         const int row = r0 + mi;
         const bool rok = row < n;
-        V4 acc1 = V4{T(0), T(0), T(0), T(0)}, acc2 = acc1;
+        V4 acc1[TJ], acc2[TJ];
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) acc1[tj] = acc2[tj] = V4{T(0), T(0), T(0), T(0)};
         for (int k0 = 0; k0 < q; k0 += 4) {
             const int kc = k0 + kk;
             const T a = (rok && kc < q) ? Q[(size_t)row * ldq + kc] : T(0);
-            acc1 = Mfma<T>::mac(a, c1s[kc * 16 + mi], acc1);
-            acc2 = Mfma<T>::mac(a, c2s[kc * 16 + mi], acc2);
-        }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = r0 + Mfma<T>::row(lane, r), j = lane & 15;
-            if (i < n && j < b && gos[j]) {
-                const size_t e = (size_t)i * b + j;
-                const T res = R[e] - acc1[r];
-                R[e] = res;
-                const T z = dinv[i] * res - acc2[r];
-                P[e] = z + betas[j] * P[e];
+            for (int tj = 0; tj < TJ; ++tj) {
+                acc1[tj] = Mfma<T>::mac(a, c1s[kc * PJ + tj * 16 + mi], acc1[tj]);
+                acc2[tj] = Mfma<T>::mac(a, c2s[kc * PJ + tj * 16 + mi], acc2[tj]);
             }
         }
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = r0 + Mfma<T>::row(lane, r), j = tj * 16 + (lane & 15);
+                if (i < n && j < b && gos[j]) {
+                    const size_t e = (size_t)i * b + j;
+                    const T res = R[e] - acc1[tj][r];
+                    R[e] = res;
+                    const T z = dinv[i] * res - acc2[tj][r];
+                    P[e] = z + betas[j] * P[e];
+                }
+            }
     }
 }
 
@@ -893,17 +947,26 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         Zy = Z;
     }
     hipLaunchKernelGGL((k_bpcg_p0<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
-    const bool fused = b <= 16 && q <= 16;
+    // the fused iteration for projectors and blocks of up to 32 columns
+    const bool fused = q <= 32;
+    const int ti = q <= 16 ? 1 : 2, tj = b <= 16 ? 1 : 2;
     const int gt = ts_grid(n);
-    const int rgrid = std::min((kFusedLd * 16 + kWavesPerBlock - 1) / kWavesPerBlock, 4 * device_cu_count());
     const int gn = std::min((n + 63) / 64, 8 * device_cu_count());
+    auto reduce = [&](int rows, int cols, T *out) {
+        const int rg = std::min((rows * cols + kWavesPerBlock - 1) / kWavesPerBlock, 4 * device_cu_count());
+        hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rg), dim3(kBlock), 0, s, gt, w.kt_part.get(), cols, rows * cols, rows,
+                           cols, out, rows, nullptr, 0, 0, T(1));
+    };
     if (fused) {
-        LAP_REQUIRE(w.kt_part.n >= (size_t)gt * kFusedLd * 16, LAP_EDEVICE, "block PCG work area too small");
-        // W = Q'D^{-1}Q, rows 16..31 of the totals
-        hipLaunchKernelGGL((k_bpcg_kt<T, true>), dim3(gt), dim3(kBlock), 0, s, n, b, q, nullptr, nullptr, nullptr,
-                           nullptr, dinv, Q, ldq, w.kt_part.get(), st, 0);
-        hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rgrid), dim3(kBlock), 0, s, gt, w.kt_part.get(), 16,
-                           kFusedLd * 16, kFusedLd, 16, w.kt_w.get(), kFusedLd, nullptr, 0, 0, T(1));
+        LAP_REQUIRE(w.kt_part.n >= (size_t)gt * kFusedMax, LAP_EDEVICE, "block PCG work area too small");
+        // W = Q'D^{-1}Q: rows PI .. 2 PI - 1 of the totals
+        if (ti == 1)
+            hipLaunchKernelGGL((k_bpcg_kt<T, true, 1, 1>), dim3(gt), dim3(kBlock), 0, s, n, b, q, nullptr, nullptr,
+                               nullptr, nullptr, dinv, Q, ldq, w.kt_part.get(), st, 0);
+        else
+            hipLaunchKernelGGL((k_bpcg_kt<T, true, 2, 2>), dim3(gt), dim3(kBlock), 0, s, n, b, q, nullptr, nullptr,
+                               nullptr, nullptr, dinv, Q, ldq, w.kt_part.get(), st, 0);
+        reduce(ti == 1 ? fused_ld<1>() : fused_ld<2>(), 16 * ti, w.kt_w.get());
     }
     for (int it = 1; it <= itmax; ++it) {
         // S = G P - P diag(theta);  Z = (I - QQ') S
@@ -911,13 +974,24 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         if (fused) {
             hipLaunchKernelGGL((k_bpcg_pap<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.p.get(), w.s.get(), part, st);
             fold(b, st->tot_a);
-            hipLaunchKernelGGL((k_bpcg_kt<T, false>), dim3(gt), dim3(kBlock), 0, s, n, b, q, X, w.res.get(),
-                               w.p.get(), w.s.get(), dinv, Q, ldq, w.kt_part.get(), st, it);
+#define LAP_KT(TI_, TJ_)                                                                                       \
+    hipLaunchKernelGGL((k_bpcg_kt<T, false, TI_, TJ_>), dim3(gt), dim3(kBlock), 0, s, n, b, q, X, w.res.get(), \
+                       w.p.get(), w.s.get(), dinv, Q, ldq, w.kt_part.get(), st, it)
+#define LAP_KN(TI_, TJ_)                                                                                      \
+    hipLaunchKernelGGL((k_bpcg_kn<T, TI_, TJ_>), dim3(gn), dim3(kBlock), 0, s, n, b, q, w.res.get(), w.p.get(), \
+                       dinv, Q, ldq, w.kt_tot.get(), w.kt_w.get(), st, it, (T)rtol)
+            if (ti == 1 && tj == 1) LAP_KT(1, 1);
+            else if (ti == 1) LAP_KT(1, 2);
+            else if (tj == 1) LAP_KT(2, 1);
+            else LAP_KT(2, 2);
             if (it == itmax) break;
-            hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rgrid), dim3(kBlock), 0, s, gt, w.kt_part.get(), 16,
-                               kFusedLd * 16, kFusedLd, 16, w.kt_tot.get(), kFusedLd, nullptr, 0, 0, T(1));
-            hipLaunchKernelGGL((k_bpcg_kn<T>), dim3(gn), dim3(kBlock), 0, s, n, b, q, w.res.get(), w.p.get(), dinv,
-                               Q, ldq, w.kt_tot.get(), w.kt_w.get(), st, it, (T)rtol);
+            reduce(ti == 1 ? fused_ld<1>() : fused_ld<2>(), 16 * tj, w.kt_tot.get());
+            if (ti == 1 && tj == 1) LAP_KN(1, 1);
+            else if (ti == 1) LAP_KN(1, 2);
+            else if (tj == 1) LAP_KN(2, 1);
+            else LAP_KN(2, 2);
+#undef LAP_KT
+#undef LAP_KN
             continue;
         }
         const T *Zs = w.s.get();

@@ -8,6 +8,9 @@
 namespace lapeig {
 
 constexpr int kMaxBlock = 32;
+// largest per-workgroup partial matrix of the fused block-PCG pass (and of
+// its totals): (2 x 32 + 2) rows of 32 columns
+constexpr int kFusedMax = (2 * 32 + 2) * 32;
 
 // Partial tiles of the tall-skinny products: up to 2 x CUs workgroups,
 // 128 x 32 entries each.
@@ -39,8 +42,8 @@ struct BPcgState {
 template <typename T>
 struct BPcgWork {
     DevBuf<T> res, p, s, y, z, C, part;
-    // fused iteration (b, q <= 16): per-workgroup partial tiles, their
-    // totals, and the totals of the W = Q'D^{-1}Q pass (34 x 16 each)
+    // fused iteration (b, q <= 32): per-workgroup partial tiles, their
+    // totals, and the totals of the W = Q'D^{-1}Q pass (kFusedMax each)
     DevBuf<T> kt_part, kt_tot, kt_w;
     DevBuf<BPcgState<T>> st;
     void ensure(int n, int b, int qmax) {
@@ -49,9 +52,9 @@ struct BPcgWork {
         z.alloc((size_t)n * b);
         C.alloc((size_t)(qmax + 1) * b);
         part.alloc((size_t)(4 * device_cu_count() + kMaxBlock) * 64);
-        kt_part.alloc((size_t)2 * device_cu_count() * 34 * 16);
-        kt_tot.alloc(34 * 16);
-        kt_w.alloc(34 * 16);
+        kt_part.alloc((size_t)2 * device_cu_count() * kFusedMax);
+        kt_tot.alloc(kFusedMax);
+        kt_w.alloc(kFusedMax);
         st.alloc(1);
     }
 };
