@@ -62,6 +62,29 @@ __device__ void wg_sum(const T (&acc)[NV], int nv, Shared &sh) {
     __syncthreads();
 }
 
+// wg_sum of nv values and one more FP64 value, in one pair of barriers:
+// sh.out[0..nv) as wg_sum gives them, sh.out[nv] the sum of `extra`
+template <typename T, int NV>
+__device__ void wg_sum_x(const T (&acc)[NV], int nv, double extra, Shared &sh) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        if (j < nv) {
+            const double s = (double)wave_sum(acc[j]);
+            if (lane_id() == 0) sh.red[wave_id()][j] = s;
+        }
+    {
+        const double e = wave_sum(extra);
+        if (lane_id() == 0) sh.red[wave_id()][nv] = e;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= nv) {
+        double s = 0.0;
+        for (int w = 0; w < kBW; ++w) s += sh.red[w][threadIdx.x];
+        sh.out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // pk[0..q) = proj, pk[q] = scalar (static register indexing only)
 template <typename T, int NV>
 __device__ __forceinline__ void pack_q(const T (&proj)[kBK], int q, T scalar, T (&pk)[NV]) {
@@ -622,7 +645,14 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                     break;
                 }
                 const T alpha = rho / pap;
-                // t += alpha p; res -= alpha (s - Q c2)
+                // one pass: t += alpha p; res -= alpha (s - Q c2); y = D^-1 res;
+                // partial sums of Q'y and res'y (PCG precision) and ||res||^2
+                // (FP64), each thread adding its rows in the same order as the
+                // separate update, preconditioner and norm passes did
+                T acc[kBK], rr = T(0);
+#pragma unroll
+                for (int j = 0; j < kBK; ++j) acc[j] = T(0);
+                double nrm = 0.0;
                 row_pass<T>(
                     n,
                     [&](int i) {
@@ -633,6 +663,8 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                         o.b = s[i];
                         o.c = res[i];
                         o.d = t[i];
+                        o.e0 = gv.rp[i];
+                        o.e1 = gv.rp[i + 1];
                         return o;
                     },
                     [&](int i, const RowQ<T> &o) {
@@ -641,23 +673,31 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                         for (int j = 0; j < kBK; ++j)
                             if (j < q) proj += o.q[j] * c2[j];
                         t[i] = o.d + alpha * o.a;
-                        res[i] = o.c - alpha * (o.b - proj);
-                    });
-                __syncthreads();
-                T zero[kBK];
+                        const T ri = o.c - alpha * (o.b - proj);
+                        res[i] = ri;
+                        T dsum = T(0);
+                        if (WT) {
+                            for (int e = o.e0; e < o.e1; ++e) dsum += sizeof(T) == 4 ? (T)gv.w32[e] : (T)gv.w64[e];
+                        } else {
+                            dsum = (T)(o.e1 - o.e0);
+                        }
+                        const T yi = dsum > T(0) ? ri / dsum : ri;
+                        y[i] = yi;
+                        rr += ri * yi;
 #pragma unroll
-                for (int j = 0; j < kBK; ++j) zero[j] = T(0);
-                T rho_new = T(0);
-                precond(zero, rho_new);
+                        for (int j = 0; j < kBK; ++j)
+                            if (j < q) acc[j] += o.q[j] * yi;
+                        nrm += (double)ri * (double)ri;
+                    });
+                {
+                    T pk[kBK + 2];
+                    pack_q<T, kBK + 2>(acc, q, rr, pk);
+                    wg_sum_x<T, kBK + 2>(pk, q + 1, nrm, sh);
+                }
+                const T rho_new = (T)sh.out[q];
 #pragma unroll
                 for (int j = 0; j < kBK; ++j) c1[j] = j < q ? (T)sh.out[j] : T(0);
-                __syncthreads();
-                double a2[1] = {0.0};
-                row_pass<T>(
-                    n, [&](int i) { return res[i]; },
-                    [&](int, T ri) { a2[0] += (double)ri * (double)ri; });
-                wg_sum<double, 1>(a2, 1, sh);
-                const T rn2 = (T)sqrt(sh.out[0]);
+                const T rn2 = (T)sqrt(sh.out[q + 1]);
                 __syncthreads();
                 its = pit;
                 if (rn2 <= (T)a.rtol_pcg * r0 || pit == a.itmax) break;
