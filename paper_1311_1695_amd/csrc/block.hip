@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_ts_reduce(int G, const T *__restrict
     }
 }
 
-template <typename T, int TJ>
+template <typename T, int TJ, int KS>
 __global__ __launch_bounds__(kBlock) void k_ts_nn(int n, const T *A, int lda, int ka, const T *__restrict__ C,
                                                   int ldc, int kb, T *Out, int ldo, const T *addend, int ldadd,
                                                   T alpha, T beta) {
@@ -126,17 +126,26 @@ __global__ __launch_bounds__(kBlock) void k_ts_nn(int n, const T *A, int lda, in
     const int nrb = (n + 15) / 16;
     for (int rb = blockIdx.x * kWavesPerBlock + wave_id(); rb < nrb; rb += gridDim.x * kWavesPerBlock) {
         const int r0 = rb * 16;
+        const int row = r0 + mi;
+        const bool rok = row < n;
+        // every load of the 16-row block (KS 4-column steps cover ka) is
+        // issued before the first multiply
+        T a[KS];
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            const int kc = 4 * t + kk;
+            a[t] = (rok && kc < ka) ? A[(size_t)row * lda + kc] : T(0);
+        }
         V4 acc[TJ];
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) acc[tj] = V4{T(0), T(0), T(0), T(0)};
-        const int row = r0 + mi;
-        const bool rok = row < n;
-        for (int k0 = 0; k0 < kap; k0 += 4) {
-            const int kc = k0 + kk;
-            const T a = (rok && kc < ka) ? A[(size_t)row * lda + kc] : T(0);
 #pragma unroll
-            for (int tj = 0; tj < TJ; ++tj) acc[tj] = Mfma<T>::mac(a, Cs[(k0 + kk) * PJ + tj * 16 + mi], acc[tj]);
-        }
+        for (int t = 0; t < KS; ++t)
+            if (4 * t < kap) {
+#pragma unroll
+                for (int tj = 0; tj < TJ; ++tj)
+                    acc[tj] = Mfma<T>::mac(a[t], Cs[(4 * t + kk) * PJ + tj * 16 + mi], acc[tj]);
+            }
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj)
 #pragma unroll
@@ -203,19 +212,24 @@ void ts_tn(int n, const T *A, int lda, int ka, const T *B, int ldb, int kb, T *o
     else throw Failure{LAP_EUNSUPPORTED, "tall-skinny product with more than 32 right-hand columns"};
 }
 
+template <typename T, int TJ>
+void ts_nn_attr() {
+    const int bytes = 128 * TJ * 16 * (int)sizeof(T);
+    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, TJ, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, TJ, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, TJ, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, TJ, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+}
+
 template <typename T>
 void ts_prepare() {
     // LDS above 64 KB needs an opt-in per kernel; done once, outside any capture
     static bool done = false;
     if (done) return;
-    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 16 * (int)sizeof(T)));
-    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 32 * (int)sizeof(T)));
-    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 64 * (int)sizeof(T)));
-    LAP_HIP(hipFuncSetAttribute((const void *)k_ts_nn<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 128 * (int)sizeof(T)));
+    ts_nn_attr<T, 1>();
+    ts_nn_attr<T, 2>();
+    ts_nn_attr<T, 4>();
+    ts_nn_attr<T, 8>();
     done = true;
 }
 template void ts_prepare<float>();
@@ -235,8 +249,15 @@ void ts_nn(int n, const T *A, int lda, int ka, const T *C, int ldc, int kb, T *O
     auto launch = [&](auto tjc) {
         constexpr int TJ = decltype(tjc)::value;
         const size_t lds = (size_t)kap * TJ * 16 * sizeof(T);
-        hipLaunchKernelGGL((k_ts_nn<T, TJ>), dim3(grid), dim3(kBlock), lds, s, n, A, lda, ka, C, ldc, kb, Out, ldo,
-                           addend, ldadd, alpha, beta);
+        auto go = [&](auto ksc) {
+            constexpr int KS = decltype(ksc)::value;
+            hipLaunchKernelGGL((k_ts_nn<T, TJ, KS>), dim3(grid), dim3(kBlock), lds, s, n, A, lda, ka, C, ldc, kb, Out,
+                               ldo, addend, ldadd, alpha, beta);
+        };
+        if (kap <= 16) go(std::integral_constant<int, 4>{});
+        else if (kap <= 32) go(std::integral_constant<int, 8>{});
+        else if (kap <= 64) go(std::integral_constant<int, 16>{});
+        else go(std::integral_constant<int, 32>{});
     };
     if (kb <= 16) launch(std::integral_constant<int, 1>{});
     else if (kb <= 32) launch(std::integral_constant<int, 2>{});
