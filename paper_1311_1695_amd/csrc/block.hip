@@ -937,8 +937,10 @@ void blk_random(int n, int b, uint64_t seed, long long colbase, const int *iperm
 
 template <typename T>
 void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q, int ldq, int q, const double *R,
-                  int ldr, T *X, BPcgWork<T> &w, BlockScratch &bs, int itmax, double rtol, hipStream_t s) {
+                  int ldr, T *X, BPcgWork<T> &w, BlockScratch &bs, int itmax, int it_first, int it_last, double rtol,
+                  hipStream_t s) {
     LAP_REQUIRE(b >= 1 && b <= kMaxBlock, LAP_EUNSUPPORTED, "block wider than 32");
+    LAP_REQUIRE(it_first >= 1 && it_first <= it_last && it_last <= itmax, LAP_EINVAL, "bad PCG iteration range");
     const int n = P.n;
     const int gc = cgrid(n, b);
     LAP_REQUIRE(w.part.n >= (size_t)gc * 64, LAP_EDEVICE, "block PCG work area too small");
@@ -951,23 +953,26 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         const int fg = std::min((nv + kWavesPerBlock - 1) / kWavesPerBlock, 16);
         hipLaunchKernelGGL((k_bfold<T>), dim3(fg), dim3(kBlock), 0, s, part, gc, nv, totals);
     };
-    hipLaunchKernelGGL((k_bpcg_init1<T>), dim3(gc), dim3(kBlock), 0, s, n, b, R, ldr, w.res.get(), X, part);
-    fold(b, st->tot_a);
-    // Res <- (I - QQ')Res
-    if (q > 0) {
-        ts_tn<T>(n, Q, ldq, q, w.res.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
-        ts_nn<T>(n, Q, ldq, q, C, q, b, w.res.get(), b, nullptr, 0, T(-1), T(1), s);
+    if (it_first == 1) {
+        hipLaunchKernelGGL((k_bpcg_init1<T>), dim3(gc), dim3(kBlock), 0, s, n, b, R, ldr, w.res.get(), X, part);
+        fold(b, st->tot_a);
+        // Res <- (I - QQ')Res
+        if (q > 0) {
+            ts_tn<T>(n, Q, ldq, q, w.res.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
+            ts_nn<T>(n, Q, ldq, q, C, q, b, w.res.get(), b, nullptr, 0, T(-1), T(1), s);
+        }
+        hipLaunchKernelGGL((k_bpcg_init2<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.res.get(), w.y.get(), dinv, part,
+                           st);
+        fold(b, st->tot_b);
+        // P = (I - QQ') Y
+        const T *Zy = w.y.get();
+        if (q > 0) {
+            ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
+            ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.y.get(), b, T(-1), T(0), s);
+            Zy = Z;
+        }
+        hipLaunchKernelGGL((k_bpcg_p0<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
     }
-    hipLaunchKernelGGL((k_bpcg_init2<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.res.get(), w.y.get(), dinv, part, st);
-    fold(b, st->tot_b);
-    // P = (I - QQ') Y
-    const T *Zy = w.y.get();
-    if (q > 0) {
-        ts_tn<T>(n, Q, ldq, q, w.y.get(), b, b, C, q, nullptr, 0, T(1), bs, s);
-        ts_nn<T>(n, Q, ldq, q, C, q, b, Z, b, w.y.get(), b, T(-1), T(0), s);
-        Zy = Z;
-    }
-    hipLaunchKernelGGL((k_bpcg_p0<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
     // the fused iteration for projectors and blocks of up to 32 columns
     const bool fused = q <= 32;
     const int ti = q <= 16 ? 1 : 2, tj = b <= 16 ? 1 : 2;
@@ -978,8 +983,8 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         hipLaunchKernelGGL((k_ts_reduce<T>), dim3(rg), dim3(kBlock), 0, s, gt, w.kt_part.get(), cols, rows * cols, rows,
                            cols, out, rows, nullptr, 0, 0, T(1));
     };
-    if (fused) {
-        LAP_REQUIRE(w.kt_part.n >= (size_t)gt * kFusedMax, LAP_EDEVICE, "block PCG work area too small");
+    if (fused) LAP_REQUIRE(w.kt_part.n >= (size_t)gt * kFusedMax, LAP_EDEVICE, "block PCG work area too small");
+    if (fused && it_first == 1) {
         // W = Q'D^{-1}Q: rows PI .. 2 PI - 1 of the totals
         if (ti == 1)
             hipLaunchKernelGGL((k_bpcg_kt<T, true, 1, 1>), dim3(gt), dim3(kBlock), 0, s, n, b, q, nullptr, nullptr,
@@ -989,7 +994,7 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
                                nullptr, nullptr, dinv, Q, ldq, w.kt_part.get(), st, 0);
         reduce(ti == 1 ? fused_ld<1>() : fused_ld<2>(), 16 * ti, w.kt_w.get());
     }
-    for (int it = 1; it <= itmax; ++it) {
+    for (int it = it_first; it <= it_last; ++it) {
         // S = G P - P diag(theta);  Z = (I - QQ') S
         spmm<T>(P, b, w.p.get(), b, w.s.get(), b, theta_dev, s);
         if (fused) {
@@ -1039,8 +1044,8 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
     LAP_HIP(hipGetLastError());
 }
 template void bpcg_enqueue<float>(const lap_plan &, int, const double *, const float *, int, int, const double *, int,
-                                  float *, BPcgWork<float> &, BlockScratch &, int, double, hipStream_t);
+                                  float *, BPcgWork<float> &, BlockScratch &, int, int, int, double, hipStream_t);
 template void bpcg_enqueue<double>(const lap_plan &, int, const double *, const double *, int, int, const double *,
-                                   int, double *, BPcgWork<double> &, BlockScratch &, int, double, hipStream_t);
+                                   int, double *, BPcgWork<double> &, BlockScratch &, int, int, int, double, hipStream_t);
 
 }  // namespace lapeig

@@ -92,9 +92,13 @@ template <typename S>
 void blk_to_f64(int n, int b, const S *in, int ldi, double *out, int ldo, hipStream_t s);
 void blk_random(int n, int b, uint64_t seed, long long colbase, const int *iperm, double *out, int ldo,
                 hipStream_t s);
+// Enqueues iterations it_first .. it_last (of at most itmax) of the block
+// PCG; it_first == 1 also enqueues its set-up.  After a segment that ends
+// before itmax, w.st->act[0][0..b) flags the columns still iterating.
 template <typename T>
 void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q, int ldq, int q, const double *R,
-                  int ldr, T *X, BPcgWork<T> &w, BlockScratch &bs, int itmax, double rtol, hipStream_t s);
+                  int ldr, T *X, BPcgWork<T> &w, BlockScratch &bs, int itmax, int it_first, int it_last, double rtol,
+                  hipStream_t s);
 
 lap_status jd_block_solve(lap_plan *P, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
                           int evecs_on_device, double *res, lap_eigs_info *info);

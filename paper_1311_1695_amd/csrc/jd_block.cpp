@@ -8,6 +8,7 @@
 // JDsismorethanone; m_min/m_max of Section 3.2), applied to the leading Ritz
 // pair.  Basis storage is row-major: [X | V] is n x (k + m_max), W n x m_max.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -39,15 +40,15 @@ struct PinnedB {
     ~PinnedB() { if (h) (void)hipHostFree(h); }
 };
 
-// graphs of the block PCG keyed by (q, b)
+// graphs of the block PCG keyed by (q, b, first iteration, last iteration)
 struct GraphCache {
-    std::map<std::pair<int, int>, hipGraphExec_t> exec;
+    std::map<std::array<int, 4>, hipGraphExec_t> exec;
     ~GraphCache() {
         for (auto &e : exec)
             if (e.second) (void)hipGraphExecDestroy(e.second);
     }
-    hipGraphExec_t get(int q, int b, hipStream_t s, const std::function<void()> &enqueue) {
-        auto key = std::make_pair(q, b);
+    hipGraphExec_t get(int q, int b, int it_first, int it_last, hipStream_t s, const std::function<void()> &enqueue) {
+        const std::array<int, 4> key{q, b, it_first, it_last};
         auto it = exec.find(key);
         if (it != exec.end()) return it->second;
         hipGraph_t g = nullptr;
@@ -206,13 +207,17 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
     bool pcg_pending = false;
     int pcg_cols = 0;
 
+    int pcg_last = 3;  // iterations of the last block PCG (its longest column)
     auto account_pcg = [&]() {
         if (!pcg_pending) return;
+        int longest = 0;
         for (int c = 0; c < pcg_cols; ++c) {
             const int its = hp.h->brk[c] ? hp.h->brk[c] : hp.h->its[c];
             inner += its;
             mvp += its;
+            longest = std::max(longest, its);
         }
+        pcg_last = longest;
         pcg_pending = false;
     };
 
@@ -321,16 +326,30 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
             m = keep;
             y_rows = 0;
         }
-        // block PCG on the bu correction equations, Q = [X U]
+        // block PCG on the bu correction equations, Q = [X U], in up to two
+        // segments: the first ends two iterations past the length of the
+        // previous block PCG (all itmax when that one used them all); the
+        // second runs only if some column is still iterating after it, so
+        // equations that stop early do not pay for the whole itmax
         {
             const int q = nx + bu;
-            auto enqueue = [&]() {
-                bpcg_enqueue<T>(*P, bu, brk_fault ? theta_fault.get() : theta.get(), Q.get(), ldq, q, R.get(), b,
-                                Tt.get(), pw, bs, o.itmax,
-                                o.rtol_pcg, s);
+            const int split = std::min(o.itmax, pcg_last + 2);
+            auto segment = [&](int i0, int i1) {
+                auto enqueue = [&]() {
+                    bpcg_enqueue<T>(*P, bu, brk_fault ? theta_fault.get() : theta.get(), Q.get(), ldq, q, R.get(), b,
+                                    Tt.get(), pw, bs, o.itmax, i0, i1, o.rtol_pcg, s);
+                };
+                if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, bu, i0, i1, s, enqueue), s));
+                else enqueue();
             };
-            if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, bu, s, enqueue), s));
-            else enqueue();
+            segment(1, split);
+            if (split < o.itmax) {
+                LAP_HIP(hipMemcpyAsync(hp.h->act[0], pw.st.get()->act[0], sizeof(int) * bu, hipMemcpyDeviceToHost, s));
+                LAP_HIP(hipStreamSynchronize(s));
+                bool any = false;
+                for (int c = 0; c < bu; ++c) any |= hp.h->act[0][c] != 0;
+                if (any) segment(split + 1, o.itmax);
+            }
         }
         pcg_pending = true;
         pcg_cols = bu;
