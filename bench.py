@@ -502,6 +502,8 @@ def main():
                          "(for profiling)")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the headline solves, no training (random start; for profiling)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="train the network, then three timed headline steps (network start; for profiling)")
     ap.add_argument("--block-only", action="store_true",
                     help="only block JD (b = 20, mixed) on the 330k-vertex graph (for profiling)")
     ap.add_argument("--sweep", action="store_true",
@@ -597,6 +599,16 @@ def main():
     net, net_info = train_network(lap, torch, gg, np)
     print(f"bench: network trained, loss {net_info['loss_first']} -> {net_info['loss_last']}",
           file=sys.stderr, flush=True)
+    if args.headline_only:
+        def one():
+            V0 = net.infer(plan, feature_seed=1)
+            return lap.lap_eigs(plan, K_PAIRS, TOL, precision="mixed", seed=1, init=V0, evecs_on_device=True,
+                                **HEADLINE)
+        one()
+        dt, _, r = median_time(one, 3, torch)
+        print(json.dumps({"solver": HEADLINE, "start": "network", "s": dt, "outer": r.outer, "mvp": r.mvp}),
+              flush=True)
+        return
 
     def step(precision="mixed"):
         V0 = net.infer(plan, feature_seed=1)
