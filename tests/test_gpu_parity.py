@@ -666,6 +666,34 @@ def test_eigs_block_zero_space_and_weighted():
     check_against_reference(r.evals, r.evecs, w2, V2, val_rtol=1e-8, angle_tol=1e-6)
 
 
+@pytest.mark.parametrize("name,b", [("cl30k", 8), ("pa5k", 4)])
+def test_eigs_block_segments_replay_matches_eager(monkeypatch, name, b):
+    # the block PCG is captured in two segments per correction equation
+    # (the second launched only while a column still iterates) and cached
+    # per (q, b, iteration range); from the random start the first equations
+    # stop early and later ones run to ITMAX, so both branches are taken.
+    # Eager launches, a first graph run and a replay from the cache must
+    # agree bit for bit, with the same counts
+    L = graph(name)
+    plan = lap.Plan(L)
+    kw = dict(precision="mixed", block=b, m_min=max(b, 6), m_max=max(b, 6) + 2 * b + 4, kmax=400, seed=3)
+    a = lap.lap_eigs(plan, 10, 1e-8, **kw)
+    monkeypatch.setenv("LAPEIG_NO_GRAPH", "1")
+    e = lap.lap_eigs(plan, 10, 1e-8, **kw)
+    monkeypatch.delenv("LAPEIG_NO_GRAPH")
+    c = lap.lap_eigs(plan, 10, 1e-8, **kw)
+    assert a.nconv == 10
+    _certified(L, a, 1e-8)
+    for r in (e, c):
+        assert np.array_equal(a.evals, r.evals) and np.array_equal(a.evecs, r.evecs)
+        assert (a.mvp, a.inner, a.outer) == (r.mvp, r.inner, r.outer)
+    # some correction equations stopped before ITMAX (20), so the second
+    # segment was skipped at least once, and the products count only
+    # iterations that ran
+    assert a.inner < a.outer * b * 20
+    plan.close()
+
+
 def test_eigs_block_rejects_bad_sizes():
     plan = lap.Plan(graph("pa5k"))
     with pytest.raises(lap.LapError) as e:
