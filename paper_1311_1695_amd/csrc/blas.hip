@@ -485,6 +485,13 @@ constexpr int kRRMax = 96;  // 2 * 96^2 doubles of LDS (147 KB) at most
 // against four wavefronts), and the register budget of 2 per SIMD leaves
 // the one-wavefront arrowhead path unspilled.
 constexpr int kRRThreads = 512;
+// Rotation items per thread: (me / 2)^2 blocks of A and me (me / 2) items of
+// Z over the launch (kRRThreads, or one wavefront for me <= 32)
+constexpr int kRRItemsA = 5, kRRItemsZ = 9;
+static_assert((kRRMax / 2) * (kRRMax / 2) <= kRRItemsA * kRRThreads && 16 * 16 <= kRRItemsA * kWave,
+              "A items per thread");
+static_assert(kRRMax * (kRRMax / 2) <= kRRItemsZ * kRRThreads && 32 * 16 <= kRRItemsZ * kWave,
+              "Z items per thread");
 
 // The last column of H from the border kernel's partial rows (brows <= 4 x 64
 // rows, stride bld, m <= kDeferBorderMax values wanted) in one wavefront:
@@ -668,7 +675,25 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_eig(int m, double *Hin, int l
         __syncthreads();
     }
     const double tol = 2.220446049250313e-16 * sqrt(fro2) / (double)me;
-    const int half = me / 2;
+    const int half = me / 2, m1 = me - 1;
+    // The items of every round are the same: this thread's 2x2 blocks of A
+    // (pair k rows, pair l columns) and (row, pair) items of Z, taken once
+    // here, packed as (k << 8) | l and (row << 8) | k
+    const int nA = half * half, nZ = me * half, bd = (int)blockDim.x;
+    int itA[kRRItemsA], itZ[kRRItemsZ];
+    int na = 0, nz = 0;
+#pragma unroll
+    for (int j = 0; j < kRRItemsA; ++j) {
+        const int e = tid + j * bd;
+        itA[j] = e < nA ? ((e / half) << 8) | (e % half) : 0;
+        na += e < nA;
+    }
+#pragma unroll
+    for (int j = 0; j < kRRItemsZ; ++j) {
+        const int e = tid + j * bd;
+        itZ[j] = e < nZ ? ((e / half) << 8) | (e % half) : 0;
+        nz += e < nZ;
+    }
     int sweeps = 0;
     for (; sweeps < 60 && me > 1; ++sweeps) {
         // A sweep rotates exactly the pairs with |a_pq| > tol, so when no
@@ -693,7 +718,11 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_eig(int m, double *Hin, int l
             if (tid < kWave) {  // the pairs of a round (half <= 48) sit in the first wavefront
                 bool rot = false;
                 if (tid < half) {
-                    auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
+                    auto player = [&](int pos) {
+                        if (pos == 0) return 0;
+                        const int x = pos - 1 + round;  // < 2 (me - 1)
+                        return 1 + (x >= m1 ? x - m1 : x);
+                    };
                     int a = player(tid), b = player(me - 1 - tid);
                     int p = a < b ? a : b, q = a < b ? b : a;
                     double c = 1.0, s = 0.0;
@@ -728,12 +757,12 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_eig(int m, double *Hin, int l
             // Items e = tid, tid + blockDim.x, ... in pairs: both items'
             // parameters and entries are read before either is computed, so
             // a thread waits for LDS once per pair of items.
-            const int nA = half * half, nZ = me * half, bd = (int)blockDim.x;
-            for (int e = tid; e < nA; e += 2 * bd) {
-                const int e2 = e + bd;
-                const bool two = e2 < nA;
-                const int ka = e / half, la = e - ka * half;
-                const int kb = two ? e2 / half : ka, lb = two ? e2 - kb * half : la;
+#pragma unroll
+            for (int j = 0; j < kRRItemsA; j += 2) {
+                if (j >= na) break;
+                const bool two = j + 1 < na;
+                const int ka = itA[j] >> 8, la = itA[j] & 255;
+                const int kb = two ? itA[j + 1] >> 8 : ka, lb = two ? itA[j + 1] & 255 : la;
                 const double ska = sn[ka], sla = sn[la], cka = cs[ka], cla = cs[la];
                 const double skb = sn[kb], slb = sn[lb], ckb = cs[kb], clb = cs[lb];
                 const int pa = pp[ka], qa = qq[ka], ra = pp[la], ca = qq[la];
@@ -749,11 +778,12 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_eig(int m, double *Hin, int l
                     A[pb * me + rb] = b0; A[pb * me + cb] = b1; A[qb * me + rb] = b2; A[qb * me + cb] = b3;
                 }
             }
-            for (int e = tid; e < nZ; e += 2 * bd) {
-                const int e2 = e + bd;
-                const bool two = e2 < nZ;
-                const int ia = e / half, ka = e - ia * half;
-                const int ib = two ? e2 / half : ia, kb = two ? e2 - ib * half : ka;
+#pragma unroll
+            for (int j = 0; j < kRRItemsZ; j += 2) {
+                if (j >= nz) break;
+                const bool two = j + 1 < nz;
+                const int ia = itZ[j] >> 8, ka = itZ[j] & 255;
+                const int ib = two ? itZ[j + 1] >> 8 : ia, kb = two ? itZ[j + 1] & 255 : ka;
                 const double ska = sn[ka], cka = cs[ka], skb = sn[kb], ckb = cs[kb];
                 const int pa = pp[ka], qa = qq[ka], pb = pp[kb], qb = qq[kb];
                 const double zpa = Z[ia * me + pa], zqa = Z[ia * me + qa];

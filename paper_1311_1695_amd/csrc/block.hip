@@ -296,11 +296,14 @@ __global__ void k_svqb(int b, const double *__restrict__ lam, const double *__re
     }
     __syncthreads();
     const int f = first;
-    // kept columns in descending eigenvalue order (the best-conditioned first)
-    for (int t = threadIdx.x; t < b * (b - f); t += blockDim.x) {
+    // kept columns in descending eigenvalue order (the best-conditioned first),
+    // then zero columns up to b, so a caller that does not wait for the kept
+    // count can apply all b columns (the dropped directions come out as zero
+    // columns, which the next SVQB drops in turn)
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
         const int i = t % b, jj = t / b;
         const int j = b - 1 - jj;
-        M[i + (size_t)jj * ldm] = Z[i + (size_t)j * ldz] / sqrt(lam[j]);
+        M[i + (size_t)jj * ldm] = jj < b - f ? Z[i + (size_t)j * ldz] / sqrt(lam[j]) : 0.0;
     }
 }
 

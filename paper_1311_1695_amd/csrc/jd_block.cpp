@@ -221,11 +221,18 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         pcg_pending = false;
     };
 
-    // SVQB of Vn's `cur` columns; result into dest (ld); returns the kept count
-    auto svqb = [&](int cur, double rel, double abs_thr, double *dest, int lddest) -> int {
+    // SVQB of Vn's `cur` columns; result into dest (ld); returns the kept
+    // count.  Without `wait` the host does not read that count: all `cur`
+    // columns are formed (the dropped ones as zero columns) and `cur` is
+    // returned; the last SVQB of a block waits and compacts.
+    auto svqb = [&](int cur, double rel, double abs_thr, double *dest, int lddest, bool wait) -> int {
         ts_tn<double>(n, Vn.get(), b, cur, Vn.get(), b, cur, S.get(), b, nullptr, 0, 1.0, bs, s);
         jd_rr(cur, S.get(), b, Sth.get(), Sz.get(), b, nullptr, s, 0, nullptr, true);
         blk_svqb(cur, Sth.get(), Sz.get(), b, rel, abs_thr, M.get(), b, bst.get(), s);
+        if (!wait) {
+            ts_nn<double>(n, Vn.get(), b, cur, M.get(), b, cur, dest, lddest, nullptr, 0, 1.0, 0.0, s);
+            return cur;
+        }
         LAP_HIP(hipMemcpyAsync(hb.h, bst.get(), sizeof(BlockStatus), hipMemcpyDeviceToHost, s));
         if (pcg_pending) LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
         LAP_HIP(hipStreamSynchronize(s));
@@ -245,8 +252,10 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         ++it;
         if (src_is_t) blk_to_f64<T>(n, src_cols, Tt.get(), src_cols, Vn.get(), b, s);
         // orthonormalize the new block: SVQB (scale), then twice
-        // [classical Gram-Schmidt against [X V]; SVQB]
-        int cur = svqb(src_cols, 1e-20, 0.0, Vn.get(), b);
+        // [classical Gram-Schmidt against [X V]; SVQB]; only the last SVQB
+        // waits for its kept count (columns dropped before it stay as zero
+        // columns until then)
+        int cur = svqb(src_cols, 1e-20, 0.0, Vn.get(), b, false);
         for (int pass = 0; pass < 2 && cur > 0; ++pass) {
             const int nb = nx + m;
             if (nb > 0) {
@@ -255,7 +264,7 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
             }
             double *dest = pass == 1 ? XV.get() + nx + m : Vn.get();
             const int ld = pass == 1 ? ldb : b;
-            cur = svqb(cur, 1e-20, 1e-20, dest, ld);
+            cur = svqb(cur, 1e-20, 1e-20, dest, ld, pass == 1);
         }
         if (cur == 0) {  // the corrections lay in span[X V]
             random_block();
