@@ -307,6 +307,104 @@ __global__ void k_svqb(int b, const double *__restrict__ lam, const double *__re
     }
 }
 
+// CholQR of a block V with b <= 32 columns from its Gram matrix S = V'V
+// (column-major, ld lds), in one wavefront: pivoted Cholesky P'SP = R'R, the
+// pivot each step the largest remaining diagonal, stopping at the first pivot
+// not above max(rel * (largest diagonal of S), abs_thr, 0); then M = P R^-1
+// on the kept columns and zero elsewhere (b x b, ld ldm), so that V M has
+// `kept` orthonormal columns spanning what V spans above the threshold, then
+// zero columns.  st->kept = the number kept.
+__global__ __launch_bounds__(kWave) void k_cholqr(int b, const double *__restrict__ S, int lds, double rel,
+                                                  double abs_thr, double *__restrict__ M, int ldm,
+                                                  BlockStatus *st) {
+    __shared__ double A[32][33];  // the trailing Schur complement (row-major); later R^-1
+    __shared__ double R[32][33];
+    __shared__ int piv[32];
+    const int lane = threadIdx.x;
+    for (int t = lane; t < 32 * 32; t += kWave) {
+        const int i = t >> 5, j = t & 31;
+        A[i][j] = (i < b && j < b) ? S[i + (size_t)j * lds] : 0.0;
+        R[i][j] = 0.0;
+    }
+    if (lane < 32) piv[lane] = lane;
+    __syncthreads();
+    double dmax = lane < b ? A[lane][lane] : 0.0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
+    const double thr = fmax(rel * dmax, abs_thr);
+    int rank = 0;
+    for (int j = 0; j < b; ++j) {
+        // pivot: the largest remaining diagonal (ties to the smaller index)
+        double v = (lane >= j && lane < b) ? A[lane][lane] : -1.0;
+        int idx = lane;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(v, o, kWave);
+            const int oi = __shfl_xor(idx, o, kWave);
+            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+        }
+        if (!(v > thr) || !(v > 0.0)) break;
+        const int p = idx;
+        if (p != j) {
+            if (lane < b) {
+                const double t0 = A[j][lane];
+                A[j][lane] = A[p][lane];
+                A[p][lane] = t0;
+            }
+            __syncthreads();
+            if (lane < b) {
+                const double t0 = A[lane][j];
+                A[lane][j] = A[lane][p];
+                A[lane][p] = t0;
+            }
+            if (lane < j) {
+                const double t0 = R[lane][j];
+                R[lane][j] = R[lane][p];
+                R[lane][p] = t0;
+            }
+            if (lane == 0) {
+                const int t0 = piv[j];
+                piv[j] = piv[p];
+                piv[p] = t0;
+            }
+            __syncthreads();
+        }
+        const double rjj = sqrt(A[j][j]);
+        if (lane == j) R[j][j] = rjj;
+        else if (lane > j && lane < b) R[j][lane] = A[j][lane] / rjj;
+        __syncthreads();
+        const int w = b - j - 1;
+        for (int t = lane; t < w * w; t += kWave) {
+            const int i = j + 1 + t / w, k = j + 1 + t % w;
+            A[i][k] -= R[j][i] * R[j][k];
+        }
+        __syncthreads();
+        rank = j + 1;
+    }
+    // R^-1 (upper triangular, rank x rank) into A: lane c takes column c
+    if (lane < rank) {
+        const int c = lane;
+        A[c][c] = 1.0 / R[c][c];
+        for (int i = c - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (int k = i + 1; k <= c; ++k) acc += R[i][k] * A[k][c];
+            A[i][c] = -acc / R[i][i];
+        }
+    }
+    __syncthreads();
+    // M = P R^-1: row piv[i] of column c holds R^-1[i][c]
+    for (int t = lane; t < b * b; t += kWave) {
+        const int r = t % b, c = t / b;
+        M[r + (size_t)c * ldm] = 0.0;
+    }
+    __syncthreads();
+    for (int t = lane; t < b * b; t += kWave) {
+        const int i = t % b, c = t / b;
+        if (c < rank && i <= c) M[piv[i] + (size_t)c * ldm] = A[i][c];
+    }
+    if (lane == 0) st->kept = rank;
+}
+
 template <typename T, int NQ>
 __device__ __forceinline__ void col_partials(const T (&acc)[NQ], int b, T *__restrict__ part) {
     __shared__ T red[NQ][kBlock];
@@ -880,6 +978,13 @@ void blk_svqb(int b, const double *lam, const double *Z, int ldz, double rel, do
     hipLaunchKernelGGL(k_svqb, dim3(1), dim3(kBlock), 0, s, b, lam, Z, ldz, rel, abs_thr, M, ldm, st);
     LAP_HIP(hipGetLastError());
 }
+void blk_cholqr(int b, const double *S, int lds, double rel, double abs_thr, double *M, int ldm, BlockStatus *st,
+                hipStream_t s) {
+    LAP_REQUIRE(b >= 1 && b <= 32, LAP_EUNSUPPORTED, "CholQR of more than 32 columns");
+    hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kWave), 0, s, b, S, lds, rel, abs_thr, M, ldm, st);
+    LAP_HIP(hipGetLastError());
+}
+
 
 template <typename T>
 void blk_resid(int n, int bu, const double *U, const double *GU, int ldu, const double *theta, double *R, T *Q,

@@ -77,6 +77,11 @@ void ts_nn(int n, const T *A, int lda, int ka, const T *C, int ldc, int kb, T *O
 // SVQB scaling: keep eigenvalues above max(rel lam_max, abs_thr)
 void blk_svqb(int b, const double *lam, const double *Z, int ldz, double rel, double abs_thr, double *M, int ldm,
               BlockStatus *st, hipStream_t s);
+// CholQR coefficients of a block from its Gram matrix S (b x b, ld lds, b <=
+// 32): M (b x b, ld ldm) such that V M has st->kept orthonormal columns
+// (pivoted Cholesky, the same drop thresholds as blk_svqb), then zero columns
+void blk_cholqr(int b, const double *S, int lds, double rel, double abs_thr, double *M, int ldm, BlockStatus *st,
+                hipStream_t s);
 template <typename T>
 void blk_zero_space(int n, int nz, const int *comp, const double *isz, double *XV, int ldb, T *Q, int ldq,
                     hipStream_t s);

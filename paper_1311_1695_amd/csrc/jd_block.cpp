@@ -223,16 +223,20 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
 
     // SVQB of Vn's `cur` columns; result into dest (ld); returns the kept
     // count.  Without `wait` the host does not read that count: all `cur`
-    // columns are formed (the dropped ones as zero columns) and `cur` is
-    // returned; the last SVQB of a block waits and compacts.
+    // columns are formed by CholQR (the dropped ones as zero columns) and
+    // `cur` is returned; the last pass of a block is an SVQB that waits and
+    // compacts.
     auto svqb = [&](int cur, double rel, double abs_thr, double *dest, int lddest, bool wait) -> int {
         ts_tn<double>(n, Vn.get(), b, cur, Vn.get(), b, cur, S.get(), b, nullptr, 0, 1.0, bs, s);
-        jd_rr(cur, S.get(), b, Sth.get(), Sz.get(), b, nullptr, s, 0, nullptr, true);
-        blk_svqb(cur, Sth.get(), Sz.get(), b, rel, abs_thr, M.get(), b, bst.get(), s);
         if (!wait) {
+            // the passes before the last: CholQR (pivoted Cholesky of the
+            // Gram matrix, one wavefront) instead of its eigen-decomposition
+            blk_cholqr(cur, S.get(), b, rel, abs_thr, M.get(), b, bst.get(), s);
             ts_nn<double>(n, Vn.get(), b, cur, M.get(), b, cur, dest, lddest, nullptr, 0, 1.0, 0.0, s);
             return cur;
         }
+        jd_rr(cur, S.get(), b, Sth.get(), Sz.get(), b, nullptr, s, 0, nullptr, true);
+        blk_svqb(cur, Sth.get(), Sz.get(), b, rel, abs_thr, M.get(), b, bst.get(), s);
         LAP_HIP(hipMemcpyAsync(hb.h, bst.get(), sizeof(BlockStatus), hipMemcpyDeviceToHost, s));
         if (pcg_pending) LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
         LAP_HIP(hipStreamSynchronize(s));
