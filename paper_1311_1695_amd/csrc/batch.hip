@@ -129,6 +129,12 @@ __device__ __forceinline__ void row_pass(int n, Ld &&ld, Op &&op) {
     }
 }
 
+// a row of the projector Q (the product's operands of a row)
+template <typename T>
+struct QRow {
+    T q[kBK];
+};
+
 // operands of one row of a PCG pass
 template <typename T>
 struct RowQ {
@@ -137,13 +143,21 @@ struct RowQ {
     int e0, e1;
 };
 
+// row operands a wg_rows caller loads nothing for
+struct NoRow {};
+struct NoPre {
+    __device__ __forceinline__ NoRow operator()(int) const { return NoRow{}; }
+};
+
 // y_i = sum_j w_ij (x_i - x_j) for the rows of one graph: rows [0, nlong)
-// one wavefront each, the rest one thread each.  f(i, x_i, y_i, q_i).
+// one wavefront each, the rest one thread each.  pre(i) loads the caller's
+// operands of row i, f(i, x_i, y_i, q_i, pre(i)) uses them.
 // x: a pointer, or any vector with operator[] (the split PCG direction)
-template <typename T, bool WT, bool QF, class X, class F>
-__device__ void wg_rows(const GView &g, const X &x, F &&f) {
+template <typename T, bool WT, bool QF, class X, class Pre, class F>
+__device__ void wg_rows(const GView &g, const X &x, Pre &&pre, F &&f) {
     const int lane = lane_id();
     for (int r = wave_id(); r < g.nlong; r += kBW) {
+        const auto op = pre(r);  // loaded before the edges (every lane, one address)
         const T xi = x[r];
         T acc = T(0), aq = T(0);
         for (int e = g.rp[r] + lane; e < g.rp[r + 1]; e += kWave) {
@@ -155,18 +169,19 @@ __device__ void wg_rows(const GView &g, const X &x, F &&f) {
         }
         acc = wave_sum(acc);
         if (QF) aq = wave_sum(aq);
-        if (lane == 0) f(r, xi, acc, aq);
+        if (lane == 0) f(r, xi, acc, aq, op);
     }
-    // one row per thread: the next row's offsets are loaded before this row's
-    // edges, and the edges go four at a time (indices, then gathers), so a
-    // row costs about one memory round trip per four edges; the sum is still
-    // taken in edge order
+    // one row per thread: the next row's offsets and this row's operands are
+    // loaded before its edges, and the edges go four at a time (indices,
+    // then gathers), so a row costs about one memory round trip per four
+    // edges; the sum is still taken in edge order
     auto wt_of = [&](int e) -> T { return WT ? (sizeof(T) == 4 ? (T)g.w32[e] : (T)g.w64[e]) : T(1); };
     int r = g.nlong + threadIdx.x;
     int e0 = r < g.n ? g.rp[r] : 0, e1 = r < g.n ? g.rp[r + 1] : 0;
     for (; r < g.n; r += kBT) {
         const int rn = r + kBT;
         const int n0 = rn < g.n ? g.rp[rn] : 0, n1 = rn < g.n ? g.rp[rn + 1] : 0;
+        const auto op = pre(r);
         const T xi = x[r];
         T acc = T(0), aq = T(0);
         int e = e0;
@@ -189,7 +204,7 @@ __device__ void wg_rows(const GView &g, const X &x, F &&f) {
             acc += wt * d;
             if (QF) aq += wt * d * d;
         }
-        f(r, xi, acc, aq);
+        f(r, xi, acc, aq, op);
         e0 = n0;
         e1 = n1;
     }
@@ -407,7 +422,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             const double sc = 1.0 / vn;
             for (int i = tid; i < n; i += kBT) vc[i] = v[i] * sc;
             __syncthreads();
-            wg_rows<double, WT, false>(gv, vc, [&](int i, double, double yi, double) { wc[i] = yi; });
+            wg_rows<double, WT, false>(gv, vc, NoPre{}, [&](int i, double, double yi, double, NoRow) { wc[i] = yi; });
             ++mvp;
             __syncthreads();
             // step 4: H border
@@ -469,7 +484,7 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
             if (!(rn <= a.tol * fmin(th, 1.0))) break;
             // certificate: fresh G u, theta from eq. (1)
             double c2[2] = {0.0, 0.0};
-            wg_rows<double, WT, true>(gv, u, [&](int i, double xi, double yi, double qi) {
+            wg_rows<double, WT, true>(gv, u, NoPre{}, [&](int i, double xi, double yi, double qi, NoRow) {
                 gu[i] = yi;
                 c2[0] += qi;
                 c2[1] += xi * xi;
@@ -618,14 +633,22 @@ __device__ void solve_graph(const BatchArgs &a, int gid, Shared &sh, T *lds) {
                 T a1[kBK], pa = T(0);
 #pragma unroll
                 for (int j = 0; j < kBK; ++j) a1[j] = T(0);
-                wg_rows<T, WT, false>(gv, pv, [&](int i, T pi, T yi, T) {
-                    const T si = yi - th * pi;
-                    s[i] = si;
-                    pa += pi * si;
+                wg_rows<T, WT, false>(
+                    gv, pv,
+                    [&](int i) {
+                        QRow<T> o;
 #pragma unroll
-                    for (int j = 0; j < kBK; ++j)
-                        if (j < q) a1[j] += Q[(size_t)i * k + j] * si;
-                });
+                        for (int j = 0; j < kBK; ++j) o.q[j] = j < q ? Q[(size_t)i * k + j] : T(0);
+                        return o;
+                    },
+                    [&](int i, T pi, T yi, T, const QRow<T> &o) {
+                        const T si = yi - th * pi;
+                        s[i] = si;
+                        pa += pi * si;
+#pragma unroll
+                        for (int j = 0; j < kBK; ++j)
+                            if (j < q) a1[j] += o.q[j] * si;
+                    });
                 {
                     T pk[kBK + 2];
                     pack_q<T, kBK + 2>(a1, q, pa, pk);
@@ -845,7 +868,7 @@ __global__ __launch_bounds__(kBT) void k_batch_spmv(const BGraph *__restrict__ g
                        w64 ? w64 + G.ci : nullptr};
         const T *xg = x + voff[gi];
         T *yg = y + voff[gi];
-        wg_rows<T, WT, false>(gv, xg, [&](int i, T, T yi, T) { yg[i] = yi; });
+        wg_rows<T, WT, false>(gv, xg, NoPre{}, [&](int i, T, T yi, T, NoRow) { yg[i] = yi; });
         __syncthreads();
     }
 }
