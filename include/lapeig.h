@@ -366,7 +366,9 @@ lap_status lap_pinv_apply(int n, int k, const double *evals, const double *evecs
  * graphs for the k smallest pairs each:
  *   evals: host, nb x k (graph g's values at g*k, ascending);
  *   evecs: host or NULL, graph g's n_g x k column-major block at offset
- *          k * (n_0 + ... + n_{g-1}), in the caller's vertex order;
+ *          k * (n_0 + ... + n_{g-1}), in the caller's vertex order
+ *          (lap_batch_eigs_ex: host when evecs_on_device = 0, device
+ *          memory of the batch's GPU when 1);
  *   res:   host or NULL, nb x k certified residual norms;
  *   infos: host or NULL, nb entries.
  * Pairs a graph did not certify within kmax are NaN (evals, res) and zero
@@ -391,6 +393,9 @@ lap_status lap_batch_autotune(lap_batch *batch, int precision, int32_t *long_thr
 lap_status lap_batch_layout(const lap_batch *batch, int precision, int32_t *long_threshold, int32_t *tuned);
 lap_status lap_batch_eigs(lap_batch *batch, int k, double tol, const lap_eigs_opts *opts, double *evals,
                           double *evecs, double *res, lap_eigs_info *infos, void *stream);
+lap_status lap_batch_eigs_ex(lap_batch *batch, int k, double tol, const lap_eigs_opts *opts, double *evals,
+                             double *evecs, int evecs_on_device, double *res, lap_eigs_info *infos,
+                             void *stream);
 lap_status lap_eigs_batch(const lap_csr *Ls, int nb, int k, double tol, const lap_eigs_opts *opts,
                           double *evals, double *evecs, double *res, lap_eigs_info *infos, void *stream);
 

@@ -48,8 +48,8 @@ EXPORTED = ["lap_eigs_default_opts", "lap_plan_create", "lap_plan_create_ex", "l
             "lap_mpnn_set_params", "lap_mpnn_infer", "lap_mpnn_loss_grad", "lap_mpnn_train_step",
             "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config", "lap_fiedler_bisect", "lap_pinv_apply",
             "lap_eigs", "lap_eigs_csr", "lap_eigs_dacg", "lap_eigs_irlm", "lap_spmv", "lap_spmv_noalloc", "lap_orth", "lap_sym_eig", "lap_pcg", "lap_batch_create",
-            "lap_batch_destroy", "lap_batch_total_n", "lap_batch_autotune", "lap_batch_layout", "lap_batch_eigs", "lap_eigs_batch",
-            "lap_status_string", "lap_last_error"]
+            "lap_batch_destroy", "lap_batch_total_n", "lap_batch_autotune", "lap_batch_layout", "lap_batch_eigs", "lap_batch_eigs_ex",
+            "lap_eigs_batch", "lap_status_string", "lap_last_error"]
 
 
 class LapError(RuntimeError):
@@ -134,6 +134,8 @@ def load_library():
     lib.lap_batch_layout.argtypes = [vp, ctypes.c_int, i32p, i32p]
     lib.lap_batch_total_n.restype = ctypes.c_int32
     lib.lap_batch_eigs.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p, f64p, P(_Info), vp]
+    lib.lap_batch_eigs_ex.argtypes = [vp, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, vp, ctypes.c_int, f64p,
+                                      P(_Info), vp]
     lib.lap_eigs_batch.argtypes = [P(_Csr), ctypes.c_int, ctypes.c_int, ctypes.c_double, P(_Opts), f64p, f64p,
                                    f64p, P(_Info), vp]
     lib.lap_mpnn_create.argtypes = [P(_MpnnConfig), P(vp)]
@@ -157,7 +159,7 @@ def load_library():
     lib.lap_last_error.argtypes = []
     lib.lap_last_error.restype = ctypes.c_char_p
     for name in ["lap_plan_create", "lap_plan_create_ex", "lap_plan_perm", "lap_eigs", "lap_eigs_csr", "lap_spmv", "lap_orth", "lap_sym_eig",
-                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
+                 "lap_pcg", "lap_batch_create", "lap_batch_eigs", "lap_batch_eigs_ex", "lap_eigs_batch", "lap_spmv_noalloc", "lap_mpnn_save", "lap_mpnn_load", "lap_mpnn_get_config",
                  "lap_fiedler_bisect", "lap_pinv_apply", "lap_eigs_dacg", "lap_eigs_irlm", "lap_batch_autotune",
                  "lap_batch_layout"]:
         getattr(lib, name).restype = ctypes.c_int
@@ -547,28 +549,39 @@ def lap_batch_create(graphs) -> Batch:
     return Batch(graphs)
 
 
-def lap_batch_eigs(batch: Batch, k: int, tol: float, *, allow_noconv=False, stream=None, **kw):
+def lap_batch_eigs(batch: Batch, k: int, tol: float, *, evecs_on_device=False, allow_noconv=False, stream=None,
+                   **kw):
     """The k smallest pairs of every graph of the batch; returns a list of
-    EigResult (evecs as numpy n x k arrays in each graph's vertex order)."""
+    EigResult (evecs as numpy n x k arrays in each graph's vertex order, or,
+    with evecs_on_device, (k, n) float64 views of one device tensor)."""
     lib = load_library()
     o, keep = _opts(**kw)
     nb = len(batch.ns)
     ev = np.zeros(nb * k)
     res = np.zeros(nb * k)
-    X = np.zeros(k * sum(batch.ns))
+    total = k * sum(batch.ns)
+    if evecs_on_device:
+        import torch
+        X = torch.zeros(total, dtype=torch.float64, device="cuda")
+        xp = ctypes.c_void_p(X.data_ptr())
+    else:
+        X = np.zeros(total)
+        xp = ctypes.c_void_p(X.ctypes.data)
     infos = (_Info * nb)()
-    code = lib.lap_batch_eigs(batch._h, int(k), float(tol), ctypes.byref(o),
-                              ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), infos, _stream_handle(stream))
+    code = lib.lap_batch_eigs_ex(batch._h, int(k), float(tol), ctypes.byref(o),
+                                 ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), xp, int(bool(evecs_on_device)),
+                                 res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), infos, _stream_handle(stream))
     if code != LAP_OK and not (allow_noconv and code == LAP_ENOCONV):
         _check(code)
     out, off = [], 0
     for g, n in enumerate(batch.ns):
         inf = infos[g]
         nc = inf.nconv
-        blk = X[off:off + n * k].reshape(k, n).T
-        out.append(EigResult(ev[g * k:g * k + nc].copy(), blk[:, :nc].copy(), res[g * k:g * k + nc].copy(), nc,
+        if evecs_on_device:
+            vec = X[off:off + n * k].view(k, n)[:nc]
+        else:
+            vec = X[off:off + n * k].reshape(k, n).T[:, :nc].copy()
+        out.append(EigResult(ev[g * k:g * k + nc].copy(), vec, res[g * k:g * k + nc].copy(), nc,
                              inf.ncomp, inf.outer, inf.inner, int(inf.mvp), inf.seconds, code))
         off += n * k
     return out

@@ -273,6 +273,7 @@ void batch_layout(const lap_batch *B, bool mixed, int *long_threshold, int *tune
 int batch_total_n(const lap_batch *B) { return B ? (int)B->total_n : 0; }
 
 lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
+                       int evecs_on_device,
                        double *res, lap_eigs_info *infos, hipStream_t user) {
     const auto t0 = std::chrono::steady_clock::now();
     LAP_REQUIRE(k >= 1 && k <= kBatchMaxK, LAP_EUNSUPPORTED, "the batched solver supports 1 <= k <= 8");
@@ -389,7 +390,9 @@ lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, 
     LAP_HIP(hipMemcpyAsync(hres.data(), W.dres.get(), sizeof(BResult) * nb, hipMemcpyDeviceToHost, s));
     LAP_HIP(hipMemcpyAsync(hl.data(), W.outl.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
     LAP_HIP(hipMemcpyAsync(hr.data(), W.outr.get(), sizeof(double) * nb * k, hipMemcpyDeviceToHost, s));
-    if (evecs) LAP_HIP(hipMemcpyAsync(evecs, W.unp.get(), sizeof(double) * W.ov, hipMemcpyDeviceToHost, s));
+    if (evecs)
+        LAP_HIP(hipMemcpyAsync(evecs, W.unp.get(), sizeof(double) * W.ov,
+                               evecs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     LAP_HIP(hipStreamSynchronize(s));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     lap_status status = LAP_OK;

@@ -535,6 +535,11 @@ lap_status lap_batch_layout(const lap_batch *b, int precision, int32_t *long_thr
 
 lap_status lap_batch_eigs(lap_batch *b, int k, double tol, const lap_eigs_opts *opts, double *evals, double *evecs,
                           double *res, lap_eigs_info *infos, void *stream) {
+    return lap_batch_eigs_ex(b, k, tol, opts, evals, evecs, 0, res, infos, stream);
+}
+
+lap_status lap_batch_eigs_ex(lap_batch *b, int k, double tol, const lap_eigs_opts *opts, double *evals,
+                             double *evecs, int evecs_on_device, double *res, lap_eigs_info *infos, void *stream) {
     LAP_GUARD_BEGIN
     LAP_REQUIRE(b != nullptr, LAP_EINVAL, "batch is NULL");
     LAP_REQUIRE(tol > 0.0 && std::isfinite(tol), LAP_EINVAL, "tol must be > 0");
@@ -543,7 +548,7 @@ lap_status lap_batch_eigs(lap_batch *b, int k, double tol, const lap_eigs_opts *
     if (opts) o = *opts;
     else lap_eigs_default_opts(&o);
     check_opts(o, 0);
-    return lapeig::batch_solve(b, k, tol, o, evals, evecs, res, infos, (hipStream_t)stream);
+    return lapeig::batch_solve(b, k, tol, o, evals, evecs, evecs_on_device, res, infos, (hipStream_t)stream);
     LAP_GUARD_END
 }
 

@@ -335,6 +335,6 @@ void batch_layout(const lap_batch *B, bool mixed, int *long_threshold, int *tune
 void batch_destroy(lap_batch *B);
 int batch_total_n(const lap_batch *B);
 lap_status batch_solve(lap_batch *B, int k, double tol, const lap_eigs_opts &o, double *evals, double *evecs,
-                       double *res, lap_eigs_info *infos, hipStream_t user);
+                       int evecs_on_device, double *res, lap_eigs_info *infos, hipStream_t user);
 
 }  // namespace lapeig

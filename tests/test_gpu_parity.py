@@ -748,6 +748,22 @@ def test_batch_weighted_and_reuse():
         assert np.allclose(r.evals, w, rtol=1e-8, atol=1e-13)
 
 
+def test_batch_evecs_on_device_match_host():
+    # lap_batch_eigs_ex with the vectors left in device memory: the same
+    # values and, bit for bit, the same vectors as the host copy; each
+    # graph's block is a (k, n) view of one device tensor
+    graphs = small_batch()[:4]
+    b = lap.lap_batch_create(graphs)
+    host = lap.lap_batch_eigs(b, 5, 1e-8)
+    dev = lap.lap_batch_eigs(b, 5, 1e-8, evecs_on_device=True)
+    for L, h, d in zip(graphs, host, dev):
+        assert d.evecs.is_cuda and tuple(d.evecs.shape) == (h.nconv, L.n)
+        assert np.array_equal(h.evals, d.evals)
+        assert np.array_equal(h.evecs, d.evecs.cpu().numpy().T)
+        _certified(L, h, 1e-8)
+    b.close()
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_batch_autotuned_row_classes(precision):
     # the first solve in a precision times the row-class thresholds and keeps
