@@ -355,7 +355,15 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
                 if (use_graph) LAP_HIP(hipGraphLaunch(graphs.get(q, bu, i0, i1, s, enqueue), s));
                 else enqueue();
             };
-            segment(1, split);
+            if (split == o.itmax && o.itmax > 2) {
+                // one segment: launched as two graphs back to back, so the
+                // device starts on the first two iterations while the host
+                // still submits the rest
+                segment(1, 2);
+                segment(3, o.itmax);
+            } else {
+                segment(1, split);
+            }
             if (split < o.itmax) {
                 LAP_HIP(hipMemcpyAsync(hp.h->act[0], pw.st.get()->act[0], sizeof(int) * bu, hipMemcpyDeviceToHost, s));
                 LAP_HIP(hipStreamSynchronize(s));
