@@ -80,6 +80,8 @@ struct JdbWork : SolverCache {
     DevBuf<T> Q, Tt;
     DevBuf<BlockStatus> bst;
     DevBuf<JDStatus> jst;
+    DevBuf<double> init_tmp;  // a caller's start block (taken on its first use)
+    DevBuf<int> init_bad;
     PinnedB<BlockStatus> hb;
     PinnedB<JDStatus> hj;
     PinnedB<BPcgState<T>> hp;
@@ -181,8 +183,12 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         // random columns; a column with a non-finite entry is left out (its
         // place keeps a random column)
         const int c0 = std::min(o.init_cols, b);
-        DevBuf<double> tmp((size_t)n * c0);
-        DevBuf<int> bad(c0);
+        if (!wk.init_tmp.get()) {
+            wk.init_tmp.alloc((size_t)n * b);
+            wk.init_bad.alloc(b);
+        }
+        DevBuf<double> &tmp = wk.init_tmp;
+        DevBuf<int> &bad = wk.init_bad;
         LAP_HIP(hipMemcpyAsync(tmp.get(), o.init, sizeof(double) * n * c0,
                                 o.init_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         if (fault_enabled("nan_init")) {
@@ -198,7 +204,6 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         LAP_HIP(hipStreamSynchronize(s));
         for (int c = 0; c < c0; ++c)
             if (!hbad[c]) blk_cm_to_rm(n, 1, tmp.get() + (size_t)c * n, P->d_perm.get(), Vn.get() + init_used++, b, s);
-        LAP_HIP(hipStreamSynchronize(s));
         src_cols = b;
         src_is_t = false;
     } else if (nx < k) {
