@@ -71,6 +71,12 @@ def test_batch_autotune_and_layout_argument_checks():
     assert lib.lap_batch_layout(None, lap.LAP_PREC_MIXED, ctypes.byref(thr), ctypes.byref(tuned)) == lap.LAP_EINVAL
     with pytest.raises(lap.LapError):
         lap._precision_code("bf16")
+    # the solve entry points reject a NULL batch before touching the device,
+    # with the eigenvectors asked for on the host or on the device
+    ev = (ctypes.c_double * 10)()
+    for on_device in (0, 1):
+        assert lib.lap_batch_eigs_ex(None, 5, 1e-8, None, ev, None, on_device, None, None, None) == lap.LAP_EINVAL
+    assert lib.lap_batch_eigs(None, 5, 1e-8, None, ev, None, None, None, None) == lap.LAP_EINVAL
 
 
 def test_plan_order_argument_checked_before_hip():
