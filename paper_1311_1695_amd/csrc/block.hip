@@ -442,24 +442,25 @@ __global__ __launch_bounds__(kBlock) void k_bfold(const T *__restrict__ part, in
 }
 
 // R = GU - U diag(theta);  U also into Q (type T, columns qoff..) and
-// column 0 of U into u0 (for the certificate).  Column grid over the n x ldu
+// column 0 of U into u0 (for the certificate).  U, GU and R are row-major
+// with leading dimensions ldu, ldg and ldr.  Column grid over the n x ldr
 // blocks (columns c >= bu are skipped); partials ||R_c||^2, ||U_c||^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_block_resid(int n, int bu, const double *__restrict__ U,
-                                                        const double *__restrict__ GU, int ldu,
+__global__ __launch_bounds__(kBlock) void k_block_resid(int n, int bu, const double *__restrict__ U, int ldu,
+                                                        const double *__restrict__ GU, int ldg, int ldr,
                                                         const double *__restrict__ theta, double *__restrict__ R,
                                                         T *__restrict__ Q, int ldq, int qoff, double *__restrict__ u0,
                                                         double *__restrict__ part) {
-    const size_t tot = (size_t)n * ldu, stride = (size_t)gridDim.x * blockDim.x;
+    const size_t tot = (size_t)n * ldr, stride = (size_t)gridDim.x * blockDim.x;
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = (int)(t % ldu);
+    const int c = (int)(t % ldr);
     double acc[2] = {0.0, 0.0};
     if (c < bu) {
         const double th = theta[c];
         for (; t < tot; t += stride) {
-            const size_t i = t / ldu;
-            const double uv = U[t];
-            const double rv = GU[t] - th * uv;
+            const size_t i = t / ldr;
+            const double uv = U[i * ldu + c];
+            const double rv = GU[i * ldg + c] - th * uv;
             R[t] = rv;
             Q[i * ldq + qoff + c] = (T)uv;
             if (c == 0) u0[i] = uv;
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_block_resid(int n, int bu, const dou
             acc[1] += uv * uv;
         }
     }
-    col_partials<double, 2>(acc, ldu, part);
+    col_partials<double, 2>(acc, ldr, part);
 }
 
 // Ritz residual norms of the block from the folded sums
@@ -987,23 +988,24 @@ void blk_cholqr(int b, const double *S, int lds, double rel, double abs_thr, dou
 
 
 template <typename T>
-void blk_resid(int n, int bu, const double *U, const double *GU, int ldu, const double *theta, double *R, T *Q,
-               int ldq, int qoff, double *u0, ReduceScratch &rs, BlockStatus *st, hipStream_t s) {
-    LAP_REQUIRE(bu <= 32 && ldu <= 32 && bu <= ldu, LAP_EUNSUPPORTED, "block wider than 32");
-    const int grid = cgrid(n, ldu);
+void blk_resid(int n, int bu, const double *U, int ldu, const double *GU, int ldg, int ldr, const double *theta,
+               double *R, T *Q, int ldq, int qoff, double *u0, ReduceScratch &rs, BlockStatus *st, hipStream_t s) {
+    LAP_REQUIRE(bu <= 32 && ldr <= 32 && bu <= ldr && bu <= ldu && bu <= ldg, LAP_EUNSUPPORTED,
+                "block wider than 32");
+    const int grid = cgrid(n, ldr);
     rs.ensure(grid + 1, 64);
     double *part = rs.partial.get();
     double *tot = part + (size_t)grid * 64;  // one more row for the totals
-    hipLaunchKernelGGL((k_block_resid<T>), dim3(grid), dim3(kBlock), 0, s, n, bu, U, GU, ldu, theta, R, Q, ldq, qoff,
-                       u0, part);
+    hipLaunchKernelGGL((k_block_resid<T>), dim3(grid), dim3(kBlock), 0, s, n, bu, U, ldu, GU, ldg, ldr, theta, R, Q,
+                       ldq, qoff, u0, part);
     hipLaunchKernelGGL((k_bfold<double>), dim3(16), dim3(kBlock), 0, s, part, grid, 64, tot);
     hipLaunchKernelGGL(k_block_resid_status, dim3(1), dim3(64), 0, s, bu, theta, tot, st);
     LAP_HIP(hipGetLastError());
 }
-template void blk_resid<float>(int, int, const double *, const double *, int, const double *, double *, float *, int,
-                               int, double *, ReduceScratch &, BlockStatus *, hipStream_t);
-template void blk_resid<double>(int, int, const double *, const double *, int, const double *, double *, double *,
-                                int, int, double *, ReduceScratch &, BlockStatus *, hipStream_t);
+template void blk_resid<float>(int, int, const double *, int, const double *, int, int, const double *, double *,
+                               float *, int, int, double *, ReduceScratch &, BlockStatus *, hipStream_t);
+template void blk_resid<double>(int, int, const double *, int, const double *, int, int, const double *, double *,
+                                double *, int, int, double *, ReduceScratch &, BlockStatus *, hipStream_t);
 
 template <typename S>
 void blk_to_f64(int n, int b, const S *in, int ldi, double *out, int ldo, hipStream_t s) {

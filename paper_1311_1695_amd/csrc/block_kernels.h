@@ -91,8 +91,8 @@ void blk_nonfinite_cols(int n, int b, const double *in, int *flags_dev, hipStrea
 // out[map[i] * ldo + c] = in[i + c n] (map NULL: identity)
 void blk_cm_to_rm(int n, int b, const double *in, const int *map, double *out, int ldo, hipStream_t s);
 template <typename T>
-void blk_resid(int n, int bu, const double *U, const double *GU, int ldu, const double *theta, double *R, T *Q,
-               int ldq, int qoff, double *u0, ReduceScratch &rs, BlockStatus *st, hipStream_t s);
+void blk_resid(int n, int bu, const double *U, int ldu, const double *GU, int ldg, int ldr, const double *theta,
+               double *R, T *Q, int ldq, int qoff, double *u0, ReduceScratch &rs, BlockStatus *st, hipStream_t s);
 template <typename S>
 void blk_to_f64(int n, int b, const S *in, int ldi, double *out, int ldo, hipStream_t s);
 void blk_random(int n, int b, uint64_t seed, long long colbase, const int *iperm, double *out, int ldo,

@@ -290,16 +290,26 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
 
         bool need_pcg = true;
         int bu = 0;
+        // H diagonal with ascending entries (as a lock leaves it): Rayleigh-Ritz
+        // then returns Y = I exactly (no rotation, ranks in index order), so
+        // U = V Y, GU = W Y and the rotations V Y, W Y(:, keep) are the
+        // leading columns as they stand and are not formed
+        bool y_ident = false;
         for (;;) {
             // warm start when theta and Y still diagonalize the leading block
             jd_rr(m, H.get(), ldh, theta.get(), Y.get(), mmax, nullptr, s, y_rows < m ? y_rows : 0, nullptr, true);
             y_rows = m;
             Vb = XV.get() + nx;
             bu = std::min(std::min(b, m), k - nx);
-            ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, bu, U.get(), b, nullptr, 0, 1.0, 0.0, s);
-            ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, bu, GU.get(), b, nullptr, 0, 1.0, 0.0, s);
-            blk_resid<T>(n, bu, U.get(), GU.get(), b, theta.get(), R.get(), Q.get(), ldq, nx, u0.get(), rs, bst.get(),
-                         s);
+            if (y_ident) {
+                blk_resid<T>(n, bu, Vb, ldb, W.get(), mmax, b, theta.get(), R.get(), Q.get(), ldq, nx, u0.get(), rs,
+                             bst.get(), s);
+            } else {
+                ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, bu, U.get(), b, nullptr, 0, 1.0, 0.0, s);
+                ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, bu, GU.get(), b, nullptr, 0, 1.0, 0.0, s);
+                blk_resid<T>(n, bu, U.get(), b, GU.get(), b, b, theta.get(), R.get(), Q.get(), ldq, nx, u0.get(), rs,
+                             bst.get(), s);
+            }
             LAP_HIP(hipMemcpyAsync(hb.h, bst.get(), sizeof(BlockStatus), hipMemcpyDeviceToHost, s));
             if (pcg_pending)
                 LAP_HIP(hipMemcpyAsync(hp.h, pw.st.get(), sizeof(BPcgState<T>), hipMemcpyDeviceToHost, s));
@@ -316,11 +326,12 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
             const double ct = hj.h->cert_theta, cr = hj.h->cert_rnorm;
             if (!converged_b(cr, ct, tol)) break;
             // lock: V <- V Y (the first column, u, joins X); W <- W Y(:, 2:m)
-            ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, m, Vb, ldb, nullptr, 0, 1.0, 0.0, s);
+            if (!y_ident) ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, m, Vb, ldb, nullptr, 0, 1.0, 0.0, s);
             if (m > 1)
                 ts_nn<double>(n, W.get(), mmax, m, Y.get() + mmax, mmax, m - 1, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
             jd_hdiag(H.get(), ldh, m - 1, theta.get(), 1, s);
             y_rows = 0;
+            y_ident = true;
             lam.push_back(ct);
             resid.push_back(cr);
             ++nx;
@@ -338,8 +349,10 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
         if (m + b > mmax) {
             const int keep = std::max(mmin, bu);
             Vb = XV.get() + nx;
-            ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, keep, Vb, ldb, nullptr, 0, 1.0, 0.0, s);
-            ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, keep, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
+            if (!y_ident) {
+                ts_nn<double>(n, Vb, ldb, m, Y.get(), mmax, keep, Vb, ldb, nullptr, 0, 1.0, 0.0, s);
+                ts_nn<double>(n, W.get(), mmax, m, Y.get(), mmax, keep, W.get(), mmax, nullptr, 0, 1.0, 0.0, s);
+            }
             jd_hdiag(H.get(), ldh, keep, theta.get(), 0, s);
             m = keep;
             y_rows = 0;
