@@ -441,6 +441,58 @@ __global__ __launch_bounds__(kBlock) void k_bfold(const T *__restrict__ part, in
     }
 }
 
+// First stage of a fold of many partial rows (64 values each): workgroup g
+// adds rows [g per, (g + 1) per), wavefront w rows w, w + 4, ... of them
+// (lane l value l), then the four wavefront sums in order, into row g of out.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bfold_rows(const T *__restrict__ part, int nb, int per,
+                                                       T *__restrict__ out) {
+    __shared__ T ws[kWavesPerBlock][kWave];
+    const int lane = lane_id(), w = wave_id();
+    const int r1 = min((blockIdx.x + 1) * per, nb);
+    T s = T(0);
+    int r = blockIdx.x * per + w;
+    for (; r + 3 * kWavesPerBlock < r1; r += 4 * kWavesPerBlock) {
+        const T a0 = part[(size_t)r * 64 + lane], a1 = part[(size_t)(r + kWavesPerBlock) * 64 + lane];
+        const T a2 = part[(size_t)(r + 2 * kWavesPerBlock) * 64 + lane];
+        const T a3 = part[(size_t)(r + 3 * kWavesPerBlock) * 64 + lane];
+        s += a0; s += a1; s += a2; s += a3;
+    }
+    for (; r < r1; r += kWavesPerBlock) s += part[(size_t)r * 64 + lane];
+    ws[w][lane] = s;
+    __syncthreads();
+    if (w == 0) {
+        T t = T(0);
+        for (int i = 0; i < kWavesPerBlock; ++i) t += ws[i][lane];
+        out[(size_t)blockIdx.x * 64 + lane] = t;
+    }
+}
+
+// k_bfold for many rows: one workgroup per value, its four wavefronts add
+// interleaved rows (lane l of wavefront w: rows w 64 + l, then + 256, ...),
+// then the wavefront sums in wavefront order
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bfold_wide(const T *__restrict__ part, int nb, T *__restrict__ totals) {
+    __shared__ T ws[kWavesPerBlock];
+    const int v = blockIdx.x;
+    T s = T(0);
+    int g = threadIdx.x;
+    for (; g + 3 * kBlock < nb; g += 4 * kBlock) {
+        const T a0 = part[(size_t)g * 64 + v], a1 = part[(size_t)(g + kBlock) * 64 + v];
+        const T a2 = part[(size_t)(g + 2 * kBlock) * 64 + v], a3 = part[(size_t)(g + 3 * kBlock) * 64 + v];
+        s += a0; s += a1; s += a2; s += a3;
+    }
+    for (; g < nb; g += kBlock) s += part[(size_t)g * 64 + v];
+    s = wave_sum(s);
+    if (lane_id() == 0) ws[wave_id()] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T t = T(0);
+        for (int w = 0; w < kWavesPerBlock; ++w) t += ws[w];
+        totals[v] = t;
+    }
+}
+
 // R = GU - U diag(theta);  U also into Q (type T, columns qoff..) and
 // column 0 of U into u0 (for the certificate).  U, GU and R are row-major
 // with leading dimensions ldu, ldg and ldr.  Column grid over the n x ldr
@@ -1083,6 +1135,8 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         }
         hipLaunchKernelGGL((k_bpcg_p0<T>), dim3(gc), dim3(kBlock), 0, s, n, b, Zy, w.p.get(), st);
     }
+    constexpr int kFoldRows = 1024;
+    LAP_REQUIRE(w.part.n >= (size_t)kFoldRows * 64, LAP_EDEVICE, "block PCG work area too small");
     // the fused iteration for projectors and blocks of up to 32 columns
     const bool fused = q <= 32;
     const int ti = q <= 16 ? 1 : 2, tj = b <= 16 ? 1 : 2;
@@ -1105,11 +1159,15 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
         reduce(ti == 1 ? fused_ld<1>() : fused_ld<2>(), 16 * ti, w.kt_w.get());
     }
     for (int it = it_first; it <= it_last; ++it) {
-        // S = G P - P diag(theta);  Z = (I - QQ') S
-        spmm<T>(P, b, w.p.get(), b, w.s.get(), b, theta_dev, s);
         if (fused) {
-            hipLaunchKernelGGL((k_bpcg_pap<T>), dim3(gc), dim3(kBlock), 0, s, n, b, w.p.get(), w.s.get(), part, st);
-            fold(b, st->tot_a);
+            // S = G P - P diag(theta) with the column sums p'S (p'Ap) in the same pass
+            const int rows = spmm_dot<T>(P, b, w.p.get(), w.s.get(), theta_dev, w.dpart.get(), w.dpart.n / 64, s);
+            // the product leaves a row per workgroup (tens of thousands on
+            // large graphs): added in two stages, through at most 1024 rows
+            const int per = (rows + kFoldRows - 1) / kFoldRows;
+            const int f1 = (rows + per - 1) / per;
+            hipLaunchKernelGGL((k_bfold_rows<T>), dim3(f1), dim3(kBlock), 0, s, w.dpart.get(), rows, per, part);
+            hipLaunchKernelGGL((k_bfold_wide<T>), dim3(b), dim3(kBlock), 0, s, part, f1, st->tot_a);
 #define LAP_KT(TI_, TJ_)                                                                                       \
     hipLaunchKernelGGL((k_bpcg_kt<T, false, TI_, TJ_>), dim3(gt), dim3(kBlock), 0, s, n, b, q, X, w.res.get(), \
                        w.p.get(), w.s.get(), dinv, Q, ldq, w.kt_part.get(), st, it)
@@ -1130,6 +1188,8 @@ void bpcg_enqueue(const lap_plan &P, int b, const double *theta_dev, const T *Q,
 #undef LAP_KN
             continue;
         }
+        // S = G P - P diag(theta);  Z = (I - QQ') S
+        spmm<T>(P, b, w.p.get(), b, w.s.get(), b, theta_dev, s);
         const T *Zs = w.s.get();
         if (q > 0) {
             ts_tn<T>(n, Q, ldq, q, w.s.get(), b, b, C, q, nullptr, 0, T(1), bs, s);

@@ -45,13 +45,20 @@ struct BPcgWork {
     // fused iteration (b, q <= 32): per-workgroup partial tiles, their
     // totals, and the totals of the W = Q'D^{-1}Q pass (kFusedMax each)
     DevBuf<T> kt_part, kt_tot, kt_w;
+    // the block product's rows of p'Ap partials (spmm_dot), 64 values a row
+    DevBuf<T> dpart;
     DevBuf<BPcgState<T>> st;
+    void ensure_dot(size_t rows) {
+        if (dpart.n < rows * 64) dpart.alloc(rows * 64);
+    }
     void ensure(int n, int b, int qmax) {
         if (res.get()) return;
         res.alloc((size_t)n * b); p.alloc((size_t)n * b); s.alloc((size_t)n * b); y.alloc((size_t)n * b);
         z.alloc((size_t)n * b);
         C.alloc((size_t)(qmax + 1) * b);
-        part.alloc((size_t)(4 * device_cu_count() + kMaxBlock) * 64);
+        // per-workgroup partial rows, also the 1024 first-stage rows of the
+        // product's p'Ap sums
+        part.alloc((size_t)std::max(4 * device_cu_count() + kMaxBlock, 1024) * 64);
         kt_part.alloc((size_t)2 * device_cu_count() * kFusedMax);
         kt_tot.alloc(kFusedMax);
         kt_w.alloc(kFusedMax);

@@ -135,6 +135,8 @@ lap_status jdb_run(lap_plan *P, int k, double tol, const lap_eigs_opts &o, doubl
     if (!cache || !cache->fits(n, k, b, mmax, o.itmax, o.rtol_pcg)) {
         P->jdb_cache.reset();
         P->jdb_cache.reset(cache = new JdbWork<T>(n, k, b, mmax, o.itmax, o.rtol_pcg));
+        // sized for this plan's layout (a new layout drops the cache)
+        cache->pw.ensure_dot((size_t)spmm_dot_rows(*P, b));
     }
     JdbWork<T> &wk = *cache;
     hipStream_t s = wk.own.s;

@@ -270,6 +270,14 @@ void spmm(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const do
 template <typename T>
 void spmm_part(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, T *part,
                hipStream_t s);
+// Y = G X - X diag(shift) for n x b blocks (ld b, b <= 32), and the column
+// sums of X o Y as rows of 64 partials (columns past b zero) in dpart; returns
+// the number of rows written, at most spmm_dot_rows(P, b), which dpart_rows
+// must cover.  The rows add up in a fixed order (k_bfold).
+template <typename T>
+int spmm_dot(const lap_plan &P, int b, const T *X, T *Y, const double *shift_dev, T *dpart, size_t dpart_rows,
+             hipStream_t s);
+int spmm_dot_rows(const lap_plan &P, int b);
 
 // Failure-path test hooks, read from the environment variable LAPEIG_FAULT
 // (comma-separated names) at each solve:

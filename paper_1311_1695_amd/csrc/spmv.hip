@@ -37,11 +37,18 @@ __device__ __forceinline__ void store_pack(T *p, const Pack<T, V> &x) {
 //     written directly, longer rows leave per-chunk partial sums that
 //     k_spmm_combine adds in chunk order (deterministic);
 //   slice rows: see below.
-template <typename T, bool W, int BL, int V>
+//   DOT: also the column sums of X o Y over the rows the workgroup writes,
+//     one row of 64 values per workgroup in dpart (columns past b zero),
+//     each added in a fixed lane and wavefront order.
+template <typename T, bool W, int BL, int V, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
                                                  const T *__restrict__ X, int ldx, T *__restrict__ Y, int ldy,
-                                                 const double *__restrict__ shift, T *__restrict__ part) {
+                                                 const double *__restrict__ shift, T *__restrict__ part,
+                                                 T *__restrict__ dpart) {
     constexpr int RPW = kWave / BL;  // row (or edge) slots per wavefront
+    T dch = T(0), dsl[V];  // X o Y sums: chunk rows (column c), slice rows (columns vc..)
+#pragma unroll
+    for (int e = 0; e < V; ++e) dsl[e] = T(0);
     const int lane = lane_id();
     const int c = lane % BL;
     const int sub = lane / BL;
@@ -75,7 +82,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
         if (sub == 0 && c < b) {
             if (nch == 1) {
                 const T sh = shift ? T(shift[c]) : T(0);
-                Y[(size_t)r * ldy + c] = acc - sh * xi;
+                const T yv = acc - sh * xi;
+                Y[(size_t)r * ldy + c] = yv;
+                if (DOT) dch += xi * yv;
             } else {
                 part[(size_t)u * b + c] = acc;
             }
@@ -141,6 +150,32 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
 #pragma unroll
         for (int e = 0; e < V; ++e) out.v[e] = acc.v[e] - (shift ? T(shift[vc + e]) : T(0)) * xi.v[e];
         store_pack<T, V>(Y + (size_t)r * ldy + vc, out);
+        if (DOT) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) dsl[e] += xi.v[e] * out.v[e];
+        }
+    }
+    if constexpr (DOT) {
+        __shared__ T red[kBlock * (V + 1)];
+#pragma unroll
+        for (int e = 0; e < V; ++e) red[threadIdx.x * (V + 1) + e] = dsl[e];
+        red[threadIdx.x * (V + 1) + V] = dch;
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            const int j = threadIdx.x;
+            T sum = T(0);
+            if (j < b) {
+                // chunk rows: lane j of each wavefront (sub 0, column j);
+                // slice rows: lanes (j / V) + gl t, t < spr, element j % V
+                const int lg = j / V, e = j % V;
+                for (int wv = 0; wv < kWavesPerBlock; ++wv) {
+                    const T *rw = red + (size_t)wv * kWave * (V + 1);
+                    sum += rw[j * (V + 1) + V];
+                    for (int t = 0; t < spr; ++t) sum += rw[(lg + gl * t) * (V + 1) + e];
+                }
+            }
+            dpart[(size_t)blockIdx.x * kWave + j] = sum;
+        }
     }
 }
 
@@ -148,14 +183,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm(Graph g, Weights<T> w, int b,
 // order) - shift * x.  Lane groups of b lanes, 64 / b rows per wavefront:
 // lane c of a group adds column c of its row's partials (nch x b,
 // contiguous), eight loads in flight, in chunk order.
-template <typename T>
+// DOT: the column sums of X o Y over these rows, as k_spmm leaves them.
+template <typename T, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm_combine(Graph g, int b, const T *__restrict__ X, int ldx,
                                                          T *__restrict__ Y, int ldy,
                                                          const double *__restrict__ shift,
-                                                         const T *__restrict__ part) {
+                                                         const T *__restrict__ part, T *__restrict__ dpart) {
     const int lane = lane_id();
     const int rpw = kWave / b;
     const int sub = lane / b, c = lane % b;
+    T dsum = T(0);
     const int gw = blockIdx.x * kWavesPerBlock + wave_id();
     const int nw = gridDim.x * kWavesPerBlock;
     const int units = (g.n_multi + rpw - 1) / rpw;
@@ -175,7 +212,23 @@ __global__ __launch_bounds__(kBlock) void k_spmm_combine(Graph g, int b, const T
         }
         for (; k < nch; ++k) acc += src[(size_t)k * b];
         const T sh = shift ? T(shift[c]) : T(0);
-        Y[(size_t)r * ldy + c] = acc - sh * X[(size_t)r * ldx + c];
+        const T xv = X[(size_t)r * ldx + c];
+        const T yv = acc - sh * xv;
+        Y[(size_t)r * ldy + c] = yv;
+        if (DOT) dsum += xv * yv;
+    }
+    if constexpr (DOT) {
+        __shared__ T red[kBlock];
+        red[threadIdx.x] = dsum;
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            const int j = threadIdx.x;
+            T sum = T(0);
+            if (j < b)
+                for (int wv = 0; wv < kWavesPerBlock; ++wv)
+                    for (int t = 0; t < rpw; ++t) sum += red[wv * kWave + j + b * t];
+            dpart[(size_t)blockIdx.x * kWave + j] = sum;
+        }
     }
 }
 
@@ -219,26 +272,39 @@ static int spmm_vec_width(int b, const T *X, int ldx, const T *Y, int ldy) {
     return 1;
 }
 
-template <typename T, int BL, int V>
-static void spmm_launch_v(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
-                          T *part, hipStream_t s) {
-    const Graph &g = P.g;
-    const int spr = kWave / (b / V);
+// workgroups of the block product: one unit (a chunk, or a group of slice
+// rows of spr rows) per wavefront
+static int spmm_grid(const Graph &g, int spr) {
     const long long sunits = ((long long)(g.n - g.n_long) + spr - 1) / spr;
     const long long units = std::max<long long>(sunits, g.nchunks);
-    const int grid = (int)std::max<long long>(1, std::min<long long>((units + kWavesPerBlock - 1) / kWavesPerBlock,
-                                                                     1 << 20));
-    if (P.weighted)
-        hipLaunchKernelGGL((k_spmm<T, true, BL, V>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X, ldx,
-                           Y, ldy, shift, part);
-    else
-        hipLaunchKernelGGL((k_spmm<T, false, BL, V>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
-                           ldx, Y, ldy, shift, part);
+    return (int)std::max<long long>(1, std::min<long long>((units + kWavesPerBlock - 1) / kWavesPerBlock, 1 << 20));
 }
 
-template <typename T, int BL>
-static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
-                        T *part_in, hipStream_t s) {
+
+// workgroups of the hub-row combine (rows of more than one chunk)
+static int combine_grid(const Graph &g, int b) {
+    const int rpw = kWave / b;
+    const int cunits = (g.n_multi + rpw - 1) / rpw;
+    return (cunits + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
+template <typename T, int BL, int V, bool DOT>
+static int spmm_launch_v(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
+                         T *part, T *dpart, hipStream_t s) {
+    const Graph &g = P.g;
+    const int grid = spmm_grid(g, kWave / (b / V));
+    if (P.weighted)
+        hipLaunchKernelGGL((k_spmm<T, true, BL, V, DOT>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
+                           ldx, Y, ldy, shift, part, dpart);
+    else
+        hipLaunchKernelGGL((k_spmm<T, false, BL, V, DOT>), dim3(grid), dim3(kBlock), 0, s, g, P.weights<T>(), b, X,
+                           ldx, Y, ldy, shift, part, dpart);
+    return grid;
+}
+
+template <typename T, int BL, bool DOT = false>
+static int spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift,
+                       T *part_in, hipStream_t s, T *dpart = nullptr) {
     const Graph &g = P.g;
     T *part = nullptr;
     if (g.nchunks > 0) {
@@ -252,16 +318,18 @@ static void spmm_launch(const lap_plan &P, int b, const T *X, int ldx, T *Y, int
         }
     }
     const int v = spmm_vec_width<T>(b, X, ldx, Y, ldy);
-    if (v == 4) spmm_launch_v<T, BL, 4>(P, b, X, ldx, Y, ldy, shift, part, s);
-    else if (v == 2) spmm_launch_v<T, BL, 2>(P, b, X, ldx, Y, ldy, shift, part, s);
-    else spmm_launch_v<T, BL, 1>(P, b, X, ldx, Y, ldy, shift, part, s);
+    int rows;
+    if (v == 4) rows = spmm_launch_v<T, BL, 4, DOT>(P, b, X, ldx, Y, ldy, shift, part, dpart, s);
+    else if (v == 2) rows = spmm_launch_v<T, BL, 2, DOT>(P, b, X, ldx, Y, ldy, shift, part, dpart, s);
+    else rows = spmm_launch_v<T, BL, 1, DOT>(P, b, X, ldx, Y, ldy, shift, part, dpart, s);
     if (g.n_multi > 0) {
-        const int rpw = kWave / b;
-        const int cunits = (g.n_multi + rpw - 1) / rpw;
-        hipLaunchKernelGGL((k_spmm_combine<T>), dim3((cunits + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock),
-                           0, s, g, b, X, ldx, Y, ldy, shift, part);
+        const int cg = combine_grid(g, b);
+        hipLaunchKernelGGL((k_spmm_combine<T, DOT>), dim3(cg), dim3(kBlock), 0, s, g, b, X, ldx, Y, ldy, shift, part,
+                           DOT ? dpart + (size_t)rows * kWave : nullptr);
+        rows += cg;
     }
     LAP_HIP(hipGetLastError());
+    return rows;
 }
 
 template <typename T>
@@ -279,6 +347,26 @@ void spmm_part(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, con
 template <typename T>
 void spmm(const lap_plan &P, int b, const T *X, int ldx, T *Y, int ldy, const double *shift_dev, hipStream_t s) {
     spmm_part<T>(P, b, X, ldx, Y, ldy, shift_dev, nullptr, s);
+}
+
+int spmm_dot_rows(const lap_plan &P, int b) {
+    // one value per lane (V = 1) gives the fewest rows per wavefront, hence
+    // the most workgroups, for every width up to b
+    const int bmax = std::max(1, std::min(b, kWave));
+    return spmm_grid(P.g, kWave / bmax) + (P.g.n_multi > 0 ? combine_grid(P.g, bmax) : 0);
+}
+
+template <typename T>
+int spmm_dot(const lap_plan &P, int b, const T *X, T *Y, const double *shift_dev, T *dpart, size_t dpart_rows,
+             hipStream_t s) {
+    LAP_REQUIRE(b >= 1 && b <= 32, LAP_EUNSUPPORTED, "block product with sums wider than 32");
+    LAP_REQUIRE((size_t)spmm_dot_rows(P, b) <= dpart_rows, LAP_EDEVICE, "block-product sum area too small");
+    if (b <= 1) return spmm_launch<T, 1, true>(P, b, X, b, Y, b, shift_dev, nullptr, s, dpart);
+    if (b <= 2) return spmm_launch<T, 2, true>(P, b, X, b, Y, b, shift_dev, nullptr, s, dpart);
+    if (b <= 4) return spmm_launch<T, 4, true>(P, b, X, b, Y, b, shift_dev, nullptr, s, dpart);
+    if (b <= 8) return spmm_launch<T, 8, true>(P, b, X, b, Y, b, shift_dev, nullptr, s, dpart);
+    if (b <= 16) return spmm_launch<T, 16, true>(P, b, X, b, Y, b, shift_dev, nullptr, s, dpart);
+    return spmm_launch<T, 32, true>(P, b, X, b, Y, b, shift_dev, nullptr, s, dpart);
 }
 
 template <typename T>
@@ -305,6 +393,10 @@ template void spmm_part<float>(const lap_plan &, int, const float *, int, float 
 template void spmm_part<double>(const lap_plan &, int, const double *, int, double *, int, const double *, double *,
                                 hipStream_t);
 template void spmm<double>(const lap_plan &, int, const double *, int, double *, int, const double *, hipStream_t);
+template int spmm_dot<float>(const lap_plan &, int, const float *, float *, const double *, float *, size_t,
+                             hipStream_t);
+template int spmm_dot<double>(const lap_plan &, int, const double *, double *, const double *, double *, size_t,
+                              hipStream_t);
 template void permute_rows<float>(const int *, int, int, const float *, float *, hipStream_t);
 template void permute_rows<double>(const int *, int, int, const double *, double *, hipStream_t);
 
